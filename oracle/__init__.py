@@ -1,0 +1,251 @@
+"""Plain FP64 CPU oracle for the MHM + PLM + HLLC patch-group step.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product path.  The arithmetic lives
+in ``mhm_oracle.cpp`` (C++17, templated over the scalar so that the same code
+also runs in dual numbers and in an operation-counting type); this module only
+marshals numpy arrays through ctypes.  It shares no code with the HIP library.
+
+Parity pins (what checks the oracle against something other than itself) are
+in ``tests/test_oracle_*.py``: the exact Riemann solution of a Sod tube
+(including Rankine-Hugoniot and isentrope checks of the exact solver), second
+order convergence on a smooth translating wave, conservation to round-off in a
+periodic box, uniform-flow and stationary-contact invariance, x/y/z cyclic and
+mirror symmetry, block-decomposition invariance, limiter special cases
+(theta = 1 minmod, theta = 2 MC), HLLC limiting cases, brute-force CFL, and
+dual-number JVPs against central finite differences.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mhm_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+SCHEME_MHM_PLM_HLLC = 1
+WAVESPEED_ROE = 0 << 8
+WAVESPEED_DAVIS = 1 << 8
+FIRST_ORDER = 1 << 10
+
+
+def build_library(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, OpenMP over groups, no FMA contraction)."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build_library()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    sig = {
+        "oracle_mhm_step": (i64, [P, P, i64, i32, f64, f64, f64, f64, i32]),
+        "oracle_mhm_step_block": (i64, [P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32]),
+        "oracle_dt": (i32, [P, i64, i32, f64, f64, f64, P]),
+        "oracle_fill_ghosts": (i32, [P, P, i32, i32, i32, i32, P]),
+        "oracle_rollout": (i64, [P, P, i32, i32, i32, i32, P, i32, f64, f64, f64, f64, f64, i32, P]),
+        "oracle_rollout_jvp": (i64, [P, P, P, P, i32, i32, i32, i32, P, i32, f64, f64, f64, f64, i32]),
+        "oracle_mhm_step_jvp": (i64, [P, P, P, P, i64, i32, f64, f64, f64, f64, i32]),
+        "oracle_hllc": (i32, [P, P, i32, f64, i32, P]),
+        "oracle_limited_slope": (f64, [f64, f64, f64, f64]),
+        "oracle_hancock_cell": (None, [P, P, P, f64, f64, f64, i32, P]),
+        "oracle_cons_to_prim": (None, [P, f64, P]),
+        "oracle_prim_to_cons": (None, [P, f64, P]),
+        "oracle_exact_star": (i32, [f64] * 7 + [P]),
+        "oracle_exact_sample": (i32, [f64] * 7 + [P, i64, P, P, P]),
+        "oracle_exact_residual": (f64, [f64] * 8),
+        "oracle_count_ops": (None, [P, P, P, P, P, P, f64, f64, f64, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _bc(bc: Sequence[int]) -> np.ndarray:
+    b = np.ascontiguousarray(bc, dtype=np.int32)
+    assert b.shape == (6,)
+    return b
+
+
+# ----------------------------------------------------------------- step API --
+
+def mhm_step(U_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """One MHM step of padded 16^3 groups U_pad[G,5,P,P,P] -> (U_out[G,5,16,16,16], n_bad)."""
+    U = _f64(U_pad)
+    G, nf, P = U.shape[0], U.shape[1], U.shape[2]
+    assert nf == 5 and U.shape[2:] == (P, P, P) and (P - 16) % 2 == 0
+    out = np.empty((G, 5, 16, 16, 16), np.float64)
+    n_bad = _load().oracle_mhm_step(_p(U), _p(out), G, (P - 16) // 2, dt, dx, gamma, theta, scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_mhm_step: bad arguments")
+    return out, int(n_bad)
+
+
+def mhm_step_block(U_pad, ghost, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """One MHM step of one padded block U_pad[5,nz+2g,ny+2g,nx+2g] -> (U_out[5,nz,ny,nx], n_bad)."""
+    U = _f64(U_pad)
+    nz, ny, nx = (s - 2 * ghost for s in U.shape[1:])
+    out = np.empty((5, nz, ny, nx), np.float64)
+    n_bad = _load().oracle_mhm_step_block(_p(U), _p(out), nx, ny, nz, ghost, dt, dx, gamma, theta, scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_mhm_step_block: bad arguments")
+    return out, int(n_bad)
+
+
+def mhm_step_jvp(U_pad, T_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """Dual-number JVP of one padded-group step: returns (U_out, T_out, n_bad)."""
+    U, T = _f64(U_pad), _f64(T_pad)
+    assert U.shape == T.shape
+    G, P = U.shape[0], U.shape[2]
+    out = np.empty((G, 5, 16, 16, 16), np.float64)
+    tout = np.empty_like(out)
+    n_bad = _load().oracle_mhm_step_jvp(_p(U), _p(T), _p(out), _p(tout), G, (P - 16) // 2, dt, dx, gamma,
+                                        theta, scheme)
+    return out, tout, int(n_bad)
+
+
+def dt_patch(U_pad, dx, gamma, c_cfl=0.5):
+    """Per-patch CFL time-step (Eq. 2) of padded groups: returns dt[G, 8]."""
+    U = _f64(U_pad)
+    G, P = U.shape[0], U.shape[2]
+    out = np.empty((G, 8), np.float64)
+    if _load().oracle_dt(_p(U), G, (P - 16) // 2, dx, gamma, c_cfl, _p(out)) != 0:
+        raise ValueError("oracle_dt: bad arguments")
+    return out
+
+
+def fill_ghosts(level, ng, ghost, bc):
+    """Group-major interiors level[G,5,16,16,16] -> padded groups [G,5,P,P,P]."""
+    L = _f64(level)
+    ngx, ngy, ngz = ng
+    G = ngx * ngy * ngz
+    assert L.shape == (G, 5, 16, 16, 16)
+    P = 16 + 2 * ghost
+    out = np.empty((G, 5, P, P, P), np.float64)
+    if _load().oracle_fill_ghosts(_p(L), _p(out), ngx, ngy, ngz, ghost, _p(_bc(bc))) != 0:
+        raise ValueError("oracle_fill_ghosts: bad arguments")
+    return out
+
+
+def rollout(level, ng, ghost, bc, n_steps, dx, gamma, dt=None, c_cfl=0.5, theta=1.5,
+            scheme=SCHEME_MHM_PLM_HLLC):
+    """n_steps MHM steps with ghost fill every step.  dt=None: CFL time-step each step.
+
+    Returns (level_out, dts[n_steps], n_bad)."""
+    L = _f64(level)
+    ngx, ngy, ngz = ng
+    out = np.empty_like(L)
+    dts = np.empty(n_steps, np.float64)
+    n_bad = _load().oracle_rollout(_p(L), _p(out), ngx, ngy, ngz, ghost, _p(_bc(bc)), n_steps,
+                                   -1.0 if dt is None else float(dt), c_cfl, dx, gamma, theta, scheme, _p(dts))
+    if n_bad < 0:
+        raise ValueError("oracle_rollout: bad arguments")
+    return out, dts, int(n_bad)
+
+
+def rollout_jvp(level, tangent, ng, ghost, bc, n_steps, dt, dx, gamma, theta=1.5,
+                scheme=SCHEME_MHM_PLM_HLLC):
+    """Exact JVP of a fixed-dt rollout (dual numbers): returns (level_out, tangent_out, n_bad)."""
+    L, T = _f64(level), _f64(tangent)
+    assert L.shape == T.shape
+    ngx, ngy, ngz = ng
+    out, tout = np.empty_like(L), np.empty_like(L)
+    n_bad = _load().oracle_rollout_jvp(_p(L), _p(T), _p(out), _p(tout), ngx, ngy, ngz, ghost, _p(_bc(bc)),
+                                       n_steps, dt, dx, gamma, theta, scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_rollout_jvp: bad arguments")
+    return out, tout, int(n_bad)
+
+
+# ------------------------------------------------------------ component API --
+
+def hllc(UL, UR, d, gamma, wavespeed=0):
+    """HLLC flux across a face normal to axis d; returns (F[5], bad)."""
+    l, r = _f64(UL), _f64(UR)
+    F = np.empty(5, np.float64)
+    bad = _load().oracle_hllc(_p(l), _p(r), d, gamma, wavespeed, _p(F))
+    return F, bool(bad)
+
+
+def limited_slope(qm, q0, qp, theta):
+    return _load().oracle_limited_slope(float(qm), float(q0), float(qp), float(theta))
+
+
+def hancock_cell(Wc, Wm, Wp, gamma, theta, half_dtdx, first_order=False):
+    """Six half-step-evolved face states of one cell: returns Ut[3, 2, 5]."""
+    c, m, p = _f64(Wc), _f64(Wm).reshape(3, 5), _f64(Wp).reshape(3, 5)
+    out = np.empty((3, 2, 5), np.float64)
+    _load().oracle_hancock_cell(_p(c), _p(m), _p(p), gamma, theta, half_dtdx, int(first_order), _p(out))
+    return out
+
+
+def cons_to_prim(U, gamma):
+    u, W = _f64(U), np.empty(5, np.float64)
+    _load().oracle_cons_to_prim(_p(u), gamma, _p(W))
+    return W
+
+
+def prim_to_cons(W, gamma):
+    w, U = _f64(W), np.empty(5, np.float64)
+    _load().oracle_prim_to_cons(_p(w), gamma, _p(U))
+    return U
+
+
+def exact_star(left, right, gamma):
+    """Star state of the exact Riemann problem: (p*, u*, rho*_L, rho*_R, newton_iterations)."""
+    out = np.empty(5, np.float64)
+    if _load().oracle_exact_star(*left, *right, gamma, _p(out)) != 0:
+        raise ValueError("vacuum-generating data")
+    return tuple(out[:4]) + (int(out[4]),)
+
+
+def exact_sample(left, right, gamma, xi):
+    """Exact self-similar solution (rho, u, p) at xi = x/t."""
+    x = _f64(xi).ravel()
+    r, u, p = (np.empty_like(x) for _ in range(3))
+    if _load().oracle_exact_sample(*left, *right, gamma, _p(x), x.size, _p(r), _p(u), _p(p)) != 0:
+        raise ValueError("vacuum-generating data")
+    return r, u, p
+
+
+def exact_residual(left, right, gamma, p):
+    return _load().oracle_exact_residual(*left, *right, gamma, float(p))
+
+
+def count_ops(U, Wc, Wm, Wp, UL, UR, gamma, theta, half_dtdx):
+    """Operation counts {add, mul, div, sqrt} of cons_to_prim, hancock_cell, hllc_flux, update."""
+    args = [_f64(a) for a in (U, Wc, Wm, Wp, UL, UR)]
+    ops = np.zeros(16, np.int64)
+    _load().oracle_count_ops(*[_p(a) for a in args], gamma, theta, half_dtdx, _p(ops))
+    names = ("cons_to_prim", "hancock_cell", "hllc_flux", "update")
+    return {n: dict(zip(("add", "mul", "div", "sqrt"), ops[4 * i:4 * i + 4].tolist())) for i, n in enumerate(names)}

@@ -1,0 +1,34 @@
+"""Test-side drivers that run the CPU oracle over time (no solver arithmetic here)."""
+
+import numpy as np
+
+import oracle
+
+
+def evolve_to(level, t_end, ghost=3, c_cfl=0.5, theta=1.5, scheme=oracle.SCHEME_MHM_PLM_HLLC, max_steps=100000):
+    """Advance a workloads.Level to t_end with the CFL time-step (Eq. 2), the
+    last step clipped to land on t_end.  Returns (U, n_steps, n_bad)."""
+    U = np.array(level.U, np.float64)
+    t, n, n_bad = 0.0, 0, 0
+    while t < t_end and n < max_steps:
+        pad = oracle.fill_ghosts(U, level.ng, ghost, level.bc)
+        dt = float(oracle.dt_patch(pad, level.dx, level.gamma, c_cfl).min())
+        if t + dt > t_end:
+            dt = t_end - t
+        U, nb = oracle.mhm_step(pad, dt, level.dx, level.gamma, theta, scheme)
+        n_bad += nb
+        t += dt
+        n += 1
+    return U, n, n_bad
+
+
+def field_scale_error(got, ref):
+    """max over cells of |g - o| / (|o| + ref_f), ref_f = max |o| of that field."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    f_axis = 1 if ref.ndim == 5 else 0
+    moved_r = np.moveaxis(ref, f_axis, 0).reshape(5, -1)
+    moved_g = np.moveaxis(got, f_axis, 0).reshape(5, -1)
+    scale = np.abs(moved_r).max(axis=1, keepdims=True)
+    scale = np.where(scale > 0, scale, 1.0)
+    return float((np.abs(moved_g - moved_r) / (np.abs(moved_r) + scale)).max())
