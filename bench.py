@@ -1,0 +1,163 @@
+"""Benchmark of the patch-group MHM hot path on one MI355X.
+
+A step is one pass of the whole per-level path over every patch group of the
+level: ghost fill (hydro_fill_ghosts), per-patch CFL time-step with the level
+minimum kept on the device (hydro_dt), and the MHM update that reads that
+time-step from device memory (hydro_advance).  The default workload is the
+256^3 periodic shear layer (4096 groups of 16^3 cells, 3 ghost zones,
+gamma = 1.4) advanced at CFL 0.5 in double precision; inputs are resident in
+HBM before the timed region starts.
+
+Prints one JSON line.  `value` is cell updates per second of the timed steps
+(whole job); `roofline` describes the dominant kernel (the MHM update), whose
+average duration is measured with HIP events on the stream it runs on;
+`cpu_baseline` is the CPU oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VEC_PEAK_TFLOPS = 78.6    # MI355X vector FP64
+FP32_VEC_PEAK_TFLOPS = 157.3   # MI355X vector FP32
+# Algorithmic HBM bytes per cell update of the MHM kernel: the stencil-reachable
+# input (7360 cells of a padded group: interior, 2-deep face slabs, 1-deep
+# edges) plus the 4096 interior outputs, 5 fields each, per 4096 cells updated.
+REACH_CELLS = 7360
+ALG_BYTES_PER_CELL = {"f64": (REACH_CELLS + 4096) * 5 * 8 / 4096, "f32": (REACH_CELLS + 4096) * 5 * 4 / 4096}
+# Algorithmic floating-point operations per cell update (add, mul, div, sqrt
+# each one), from the oracle's operation count of the four per-item stages
+# times their multiplicities per group (7360 primitive conversions, 5632
+# Hancock cells, 13056 HLLC faces, 4096 updates).
+ALG_FLOPS_PER_CELL = 880.2
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--n", type=int, default=256, help="grid cells per axis (multiple of 16)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the extra FP32 measurement")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def run_workload(hydro, torch, lv, dtype, steps, warmup):
+    """Time `steps` full steps; return (seconds, mean MHM kernel ms, solver, last dt, n_bad)."""
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, lv.bc, ghost=3, dtype=tdt)
+    U0 = torch.from_numpy(np.ascontiguousarray(lv.U.astype(np.float64 if dtype == "f64" else np.float32))).cuda()
+    solver.load_state(U0)
+    for _ in range(warmup):
+        solver.step()
+    solver.load_state(U0)
+    solver.n_bad.zero_()
+    # the MHM update is bracketed by HIP events on the stream it is launched on
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        solver.step(events=ev[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    dts = solver.dt_min.cpu().numpy()
+    return elapsed, kms, solver, dts, int(solver.n_bad.cpu()[0])
+
+
+def cpu_baseline(lv_factory, seconds):
+    """The oracle (fill + CFL + MHM step) on a bounded sample of the workload."""
+    import oracle
+    lv = lv_factory()
+    # sample: the first two z-layers of groups as their own periodic brick
+    ngx, ngy, _ = lv.ng
+    nsub = ngx * ngy * 2
+    U = np.ascontiguousarray(lv.U[:nsub])
+    ng = (ngx, ngy, 2)
+    cells = nsub * 4096
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        U, _, _ = oracle.rollout(U, ng, 3, lv.bc, 1, lv.dx, lv.gamma)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d steps (ghost fill + CFL + MHM) of %d groups (%dx%dx%d cells, a %dx%dx2-group slab of "
+                      "the workload as its own periodic brick), FP64, OpenMP over groups" %
+                      (steps, nsub, ngx * 16, ngy * 16, 32, ngx, ngy)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1712_07070_amd import hydro
+    from paper_1712_07070_amd import workloads as W
+    hydro.load()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    print("bench: building workload", file=sys.stderr, flush=True)
+    lv = W.shear_layer(args.n)
+    cells = lv.n_cells
+    print("bench: timing %s" % args.dtype, file=sys.stderr, flush=True)
+    el, kms, solver, dts, n_bad = run_workload(hydro, torch, lv, args.dtype, args.steps, args.warmup)
+    value = cells * args.steps / el
+    alg_b = ALG_BYTES_PER_CELL[args.dtype]
+    k_rate = cells / (kms * 1e-3)                       # cell updates/s of the MHM kernel alone
+    hbm_gbs = alg_b * k_rate / 1e9
+    peak_flops = FP64_VEC_PEAK_TFLOPS if args.dtype == "f64" else FP32_VEC_PEAK_TFLOPS
+    alu_tflops = ALG_FLOPS_PER_CELL * k_rate / 1e12
+    roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "mhm_fwd_kernel<%s>" % ("double" if args.dtype == "f64" else "float"),
+            "kernel_ms": round(kms, 4), "alg_bytes_per_cell": round(alg_b, 3), "cells_per_launch": cells,
+            "alu": {"achieved": round(alu_tflops, 2), "peak": peak_flops, "unit": "TFLOP/s",
+                    "frac": round(alu_tflops / peak_flops, 4), "alg_flops_per_cell": ALG_FLOPS_PER_CELL}}
+    extra = {"kernel_cell_updates_per_s": k_rate, "n_bad": n_bad, "dt_last_step": float(dts[0])}
+    if not args.no_f32 and args.dtype == "f64":
+        print("bench: timing f32", file=sys.stderr, flush=True)
+        el32, kms32, _, _, nb32 = run_workload(hydro, torch, lv, "f32", args.steps, args.warmup)
+        r32 = cells / (kms32 * 1e-3)
+        extra["f32"] = {"value": cells * args.steps / el32, "ms_per_step": el32 / args.steps * 1e3,
+                        "kernel_ms": kms32, "kernel_cell_updates_per_s": r32,
+                        "hbm_frac": ALG_BYTES_PER_CELL["f32"] * r32 / 1e9 / HBM_PEAK_GBS, "n_bad": nb32}
+    del solver
+    torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(lambda: W.shear_layer(args.n), args.cpu_seconds)
+    line = {
+        "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "shear-layer %d^3 periodic, %d patch groups of 16^3 (3 ghost zones), gamma=1.4, "
+                               "MHM+PLM+HLLC at CFL 0.5: ghost fill + CFL + update per step" % (args.n, lv.n_groups),
+                   "grid": args.n, "groups": lv.n_groups, "ghost": 3, "theta": 1.5},
+        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/* hydro.h -- C ABI of the MI355X patch-group Euler solver (libhydro.so).
+ *
+ * The library advances the patch groups of one AMR level with the
+ * dimensionally unsplit MUSCL-Hancock scheme (MHM: PLM reconstruction with a
+ * generalized minmod limiter, HLLC Riemann solver, conservative update) and
+ * computes the per-patch CFL time-step, following Schive et al. 2018
+ * (GAMER-2), Sec. 2.2 (hydrodynamic schemes, Riemann solvers, limiters,
+ * boundary conditions), Sec. 2.6 Eq. 2 (CFL condition for MHM), Sec. 3.1 and
+ * Sec. 3.4 (patch groups of 2x2x2 sibling 8^3 patches, ghost zones allocated
+ * only for the groups being solved).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers named *_dev are DEVICE pointers (HIP device memory of the current
+ * device); pointers named *_host are host memory.  The caller allocates and
+ * frees every buffer; the library keeps no pointer after a call returns.
+ *
+ * Fields: 5 conserved variables per cell in this order: rho, m_x, m_y, m_z, E
+ * (mass density, momentum density, total energy density).  Ideal gas,
+ * p = (gamma-1) (E - |m|^2 / (2 rho)).  Cubic cells of width dx.
+ *
+ * Level storage ("group-major"): float array [G][5][16][16][16], x fastest;
+ * group g = (gz*NGy + gy)*NGx + gx on an NGx x NGy x NGz lattice of groups.
+ *
+ * Padded groups: float array [G][5][P][P][P], P = 16 + 2*ghost, x fastest; the
+ * group interior sits at offsets ghost..ghost+15 on each axis.  The MHM step
+ * reads the inner 2 ghost layers only (the stencil of PLM + Hancock + HLLC),
+ * so ghost >= 2; configurations of the paper's CTU/PPM kind carry 3.
+ *
+ * dtype: HYDRO_F64 (double) or HYDRO_F32 (float) for every state array of a
+ * call.  Time-steps are always double.
+ *
+ * Scheme word: bits 0-7 scheme id (HYDRO_SCHEME_MHM_PLM_HLLC), bits 8-9 HLLC
+ * wave-speed estimate (HYDRO_WAVESPEED_ROE: Einfeldt/Roe-averaged, default;
+ * HYDRO_WAVESPEED_DAVIS), bit 10 HYDRO_FIRST_ORDER (zero slopes: Godunov with
+ * HLLC).  theta is the generalized-minmod parameter, 1 <= theta <= 2.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
+ * Every call is asynchronous on it; argument errors are reported
+ * synchronously by the return value and nothing is launched.
+ *
+ * Status: HYDRO_OK (0) or a negative error code; hydro_strerror() names it.
+ * HYDRO_EDEVICE means a HIP call failed; hydro_last_hip_error() returns it.
+ *
+ * Determinism: for the same inputs, arguments and device the outputs are
+ * bitwise identical from run to run (no floating-point atomics).
+ */
+#ifndef HYDRO_H_
+#define HYDRO_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRO_OK 0
+#define HYDRO_EINVAL (-1)   /* bad shape, ghost, dtype, null pointer, aliasing, dt/dx/gamma/theta */
+#define HYDRO_EDEVICE (-2)  /* a HIP runtime call failed */
+
+#define HYDRO_F64 0
+#define HYDRO_F32 1
+
+#define HYDRO_SCHEME_MHM_PLM_HLLC 1
+#define HYDRO_WAVESPEED_ROE (0 << 8)
+#define HYDRO_WAVESPEED_DAVIS (1 << 8)
+#define HYDRO_FIRST_ORDER (1 << 10)
+
+#define HYDRO_BC_PERIODIC 0
+#define HYDRO_BC_OUTFLOW 1
+
+/* hydro_advance -- one MHM step of G padded patch groups (Sec. 2.2: MHM with
+ * PLM on primitive variables, generalized minmod limiter, HLLC solver, and the
+ * conservative flux-difference update).
+ *   U_pad_dev  [G][5][P^3] input state with filled ghost zones (not modified)
+ *   U_out_dev  [G][5][16^3] output interiors (level storage); must not overlap
+ *              U_pad_dev
+ *   n_groups   G >= 0 (0 launches nothing)
+ *   ghost      2..16
+ *   dt, dx     > 0; if dt_dev is non-NULL the step reads dt from that device
+ *              double instead (lets a CFL time-step stay on the device)
+ *   gamma > 1, scheme, theta in [1, 2]: see above
+ *   n_bad_dev  optional device int32 (may be NULL): the kernel ADDS the
+ *              number of unphysical items (HLLC faces whose two input states
+ *              are not both rho > 0 and p > 0, plus updated cells with rho <= 0
+ *              or p <= 0).  No floors or fallbacks are applied.
+ */
+int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost,
+                  int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                  double theta, const double* dt_dev, int32_t* n_bad_dev, void* stream);
+
+/* hydro_dt -- per-patch CFL time-step, Sec. 2.6 Eq. 2 (the form for MHM):
+ * dt_patch = (c_cfl * dx) / max over the patch's 8^3 cells of
+ * (|u| + |v| + |w| + 3 c_s), c_s = sqrt(gamma p / rho), evaluated in double
+ * precision for both dtypes (FP32 states are widened first).
+ *   U_pad_dev       [G][5][P^3] (only interiors are read; ghost 0..16)
+ *   dt_patch_dev    [G][8] double output; patch p = (pz*2 + py)*2 + px of a group
+ *   dt_min_dev      optional device double (may be NULL): receives the minimum
+ *                   over all patches (the level time-step); written, not
+ *                   accumulated.
+ */
+int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dtype, double dx,
+             double gamma, double c_cfl, double* dt_patch_dev, double* dt_min_dev, void* stream);
+
+/* hydro_fill_ghosts -- build padded groups from level storage (Sec. 3.4: ghost
+ * zones exist only for the groups being solved; Sec. 2.2 boundary conditions).
+ * Every padded cell copies the level cell whose index along each axis is the
+ * padded index mapped independently per axis: inside the domain unchanged,
+ * beyond a periodic face wrapped, beyond an outflow face clamped to the
+ * nearest interior cell.
+ *   level_dev   [G][5][16^3], G = ngx*ngy*ngz
+ *   U_pad_dev   [G][5][P^3] output, must not overlap level_dev
+ *   ghost       0..16
+ *   bc_host     6 ints on the host: x-, x+, y-, y+, z-, z+ faces
+ */
+int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                      int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream);
+
+/* Name of a status code (static string). */
+const char* hydro_strerror(int status);
+
+/* hipError_t of the last failed HIP call made by the library on this thread. */
+int hydro_last_hip_error(void);
+
+/* Library ABI version (increases when an entry point changes). */
+int hydro_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRO_H_ */

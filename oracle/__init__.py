@@ -74,6 +74,7 @@ def _load():
         "oracle_exact_sample": (i32, [f64] * 7 + [P, i64, P, P, P]),
         "oracle_exact_residual": (f64, [f64] * 8),
         "oracle_count_ops": (None, [P, P, P, P, P, P, f64, f64, f64, P]),
+        "oracle_num_threads": (i32, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -240,6 +241,11 @@ def exact_sample(left, right, gamma, xi):
 
 def exact_residual(left, right, gamma, p):
     return _load().oracle_exact_residual(*left, *right, gamma, float(p))
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's loops over groups."""
+    return int(_load().oracle_num_threads())
 
 
 def count_ops(U, Wc, Wm, Wp, UL, UR, gamma, theta, half_dtdx):

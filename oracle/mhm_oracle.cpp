@@ -36,6 +36,8 @@
 // algorithmic flop count per cell update).  Branch decisions always use the
 // value part.  Built with -ffp-contract=off: every operation rounds once.
 
+#include <omp.h>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -686,6 +688,9 @@ int64_t oracle_mhm_step_jvp(const double* Upad, const double* Tpad, double* Uout
   }
   return n_bad;
 }
+
+// Number of OpenMP threads the oracle's parallel loops use.
+int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 // Single HLLC flux (tests): UL, UR conserved, d = normal axis.  Returns 1 if an
 // input state is unphysical.

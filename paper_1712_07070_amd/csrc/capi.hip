@@ -1,0 +1,137 @@
+// extern "C" entry points of libhydro: argument validation and dispatch to
+// the kernels.  Declarations and documentation: include/hydro.h.
+
+#include <cmath>
+#include <cstdint>
+
+#include "hydro.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+int device_status(hipError_t e) {
+  if (e == hipSuccess) return HYDRO_OK;
+  g_last_hip_error = int(e);
+  return HYDRO_EDEVICE;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+size_t dtype_size(int32_t dtype) { return dtype == HYDRO_F64 ? 8 : 4; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+bool valid_scheme(int32_t scheme, double theta) {
+  if ((scheme & 0xff) != HYDRO_SCHEME_MHM_PLM_HLLC) return false;
+  const int ws = (scheme >> 8) & 3;
+  if (ws > 1) return false;
+  if (scheme & ~(0xff | (3 << 8) | HYDRO_FIRST_ORDER)) return false;
+  return std::isfinite(theta) && theta >= 1.0 && theta <= 2.0;
+}
+
+template <typename T>
+gh::Gas<T> make_gas(double gamma, double theta, double dt, double dx) {
+  gh::Gas<T> g;
+  g.gamma = T(gamma);
+  g.gm1 = T(gamma - 1.0);
+  g.inv_gm1 = T(1.0 / (gamma - 1.0));
+  g.theta = T(theta);
+  g.dtdx = T(dt / dx);
+  g.half_dtdx = T(0.5 * (dt / dx));
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_version(void) { return 1; }
+
+int hydro_last_hip_error(void) { return g_last_hip_error; }
+
+const char* hydro_strerror(int status) {
+  switch (status) {
+    case HYDRO_OK:
+      return "ok";
+    case HYDRO_EINVAL:
+      return "invalid argument";
+    case HYDRO_EDEVICE:
+      return "HIP runtime error";
+    default:
+      return "unknown status";
+  }
+}
+
+int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
+                  double dt, double dx, double gamma, int32_t scheme, double theta, const double* dt_dev,
+                  int32_t* n_bad_dev, void* stream) {
+  if (n_groups < 0 || ghost < 2 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
+    return HYDRO_EINVAL;
+  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
+  if (n_groups == 0) return HYDRO_OK;
+  if (U_pad_dev == nullptr || U_out_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t P = 16 + 2 * ghost;
+  const size_t es = dtype_size(dtype);
+  if (overlap(U_pad_dev, size_t(n_groups) * 5 * P * P * P * es, U_out_dev, size_t(n_groups) * 5 * 4096 * es))
+    return HYDRO_EINVAL;
+  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
+  const int ws = (scheme >> 8) & 3;
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_mhm_fwd(static_cast<const double*>(U_pad_dev), static_cast<double*>(U_out_dev), n_groups, ghost,
+                           make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, s);
+  else
+    e = gh::launch_mhm_fwd(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups, ghost,
+                           make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, s);
+  return device_status(e);
+}
+
+int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dtype, double dx, double gamma,
+             double c_cfl, double* dt_patch_dev, double* dt_min_dev, void* stream) {
+  if (n_groups < 0 || ghost < 0 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !finite_pos(c_cfl) || !(std::isfinite(gamma) && gamma > 1.0)) return HYDRO_EINVAL;
+  if (n_groups > 0 && (U_pad_dev == nullptr || dt_patch_dev == nullptr)) return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_cfl_dt(static_cast<const double*>(U_pad_dev), n_groups, ghost, dx, gamma, c_cfl, dt_patch_dev,
+                          dt_min_dev, s);
+  else
+    e = gh::launch_cfl_dt(static_cast<const float*>(U_pad_dev), n_groups, ghost, dx, gamma, c_cfl, dt_patch_dev,
+                          dt_min_dev, s);
+  return device_status(e);
+}
+
+int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32_t ngy, int32_t ngz, int32_t ghost,
+                      int32_t dtype, const int32_t* bc_host, void* stream) {
+  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  int bc[6];
+  for (int i = 0; i < 6; ++i) {
+    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
+    bc[i] = bc_host[i];
+  }
+  if (level_dev == nullptr || U_pad_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t G = int64_t(ngx) * ngy * ngz, P = 16 + 2 * ghost;
+  const size_t es = dtype_size(dtype);
+  if (overlap(level_dev, size_t(G) * 5 * 4096 * es, U_pad_dev, size_t(G) * 5 * P * P * P * es)) return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_fill_ghosts(static_cast<const double*>(level_dev), static_cast<double*>(U_pad_dev), ngx, ngy, ngz,
+                               ghost, bc, s);
+  else
+    e = gh::launch_fill_ghosts(static_cast<const float*>(level_dev), static_cast<float*>(U_pad_dev), ngx, ngy, ngz,
+                               ghost, bc, s);
+  return device_status(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// Device-side arithmetic of the MHM + PLM + HLLC step (GAMER-2, Sec. 2.2).
+//
+// Everything here is __device__ __forceinline__ and templated on the floating
+// type T (double or float).  Values are carried in registers; the kernels in
+// mhm_fwd.hip decide what is staged in LDS.  Every expression has a single
+// source form, and the library is built with -ffp-contract=on, so each
+// inlined copy of a function rounds identically: a face computed by two
+// workgroups (the shared face of neighbouring groups) gets bitwise-identical
+// flux, which keeps the update conservative to round-off.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gh {
+
+// ------------------------------------------------------------ numerics ----
+template <typename T> struct Fp;
+
+template <> struct Fp<double> {
+  // IEEE-correct division and square root: the FP64 path is meant to agree
+  // with an FP64 reference to ~1e-15 per operation.
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
+};
+
+template <> struct Fp<float> {
+  // Hardware reciprocal and square root (about 1 ulp): the FP32 path is
+  // held to 1e-5 relative, far above their error.
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
+// Constants of one launch, already converted to T.
+template <typename T> struct Gas {
+  T gamma;      // adiabatic index
+  T gm1;        // gamma - 1
+  T inv_gm1;    // 1 / (gamma - 1)
+  T theta;      // generalized minmod parameter
+  T dtdx;       // dt / dx
+  T half_dtdx;  // dt / (2 dx)
+};
+
+// ------------------------------------------------- a1: cons -> primitive --
+// W = (rho, u, v, w, p), p = (gamma-1) (E - (m.u)/2).
+template <typename T>
+__device__ __forceinline__ void cons_to_prim(const T U[5], const Gas<T>& g, T W[5]) {
+  const T inv = Fp<T>::rcp(U[0]);
+  W[0] = U[0];
+  W[1] = U[1] * inv;
+  W[2] = U[2] * inv;
+  W[3] = U[3] * inv;
+  W[4] = g.gm1 * (U[4] - T(0.5) * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3]));
+}
+
+// ------------------------------------------- a2: generalized minmod slope --
+// dm = q0 - qm, dp = qp - q0, dc = (qp - qm)/2.  If dm and dp are strictly of
+// one sign: sgn(dc) * min(theta|dm|, |dc|, theta|dp|); else 0.
+template <typename T>
+__device__ __forceinline__ T gminmod(T qm, T q0, T qp, T theta) {
+  const T dm = q0 - qm;
+  const T dp = qp - q0;
+  const T dc = T(0.5) * (qp - qm);
+  T m = __builtin_fmin(theta * __builtin_fabs(dm), __builtin_fabs(dc));
+  m = __builtin_fmin(m, theta * __builtin_fabs(dp));
+  const bool mono = (dm > T(0) && dp > T(0)) || (dm < T(0) && dp < T(0));
+  return mono ? __builtin_copysign(m, dc) : T(0);
+}
+
+// ----------------------------------------- a3 + a4: Hancock face states ---
+// Given the primitive state of a cell (Wc) and of its six axis neighbours
+// (Wn[d][0] at -e_d, Wn[d][1] at +e_d), return the six face states advanced
+// by half a step in conserved form, Ut[d][0] on the low face and Ut[d][1] on
+// the high face of axis d:
+//   W_{d,-+} = Wc -+ dW_d / 2;   U_{d,-+} = cons(W_{d,-+})
+//   dU = dt/(2dx) sum_d [F_d(U_{d,-}) - F_d(U_{d,+})];   Ut = U + dU
+template <typename T>
+__device__ __forceinline__ void hancock_states(const T Wc[5], const T Wn[3][2][5], const Gas<T>& g,
+                                               bool first_order, T Ut[3][2][5]) {
+  T s[5];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T dF[5];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      T W[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T sl = first_order ? T(0) : gminmod(Wn[d][0][q], Wc[q], Wn[d][1][q], g.theta);
+        W[q] = side == 0 ? Wc[q] - T(0.5) * sl : Wc[q] + T(0.5) * sl;
+      }
+      T* U = Ut[d][side];
+      U[0] = W[0];
+      U[1] = W[0] * W[1];
+      U[2] = W[0] * W[2];
+      U[3] = W[0] * W[3];
+      U[4] = W[4] * g.inv_gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+      // physical flux along d of this face state
+      const T un = W[1 + d];
+      T F[5];
+      F[0] = U[0] * un;
+      F[1] = U[1] * un;
+      F[2] = U[2] * un;
+      F[3] = U[3] * un;
+      F[1 + d] = F[1 + d] + W[4];
+      F[4] = (U[4] + W[4]) * un;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) dF[q] = side == 0 ? F[q] : dF[q] - F[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s[q] = d == 0 ? dF[q] : s[q] + dF[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const T dU = g.half_dtdx * s[q];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Ut[d][0][q] = Ut[d][0][q] + dU;
+      Ut[d][1][q] = Ut[d][1][q] + dU;
+    }
+  }
+}
+
+// Minimum / maximum that keep the first argument unless the second is
+// strictly smaller / larger.  Unlike fmin/fmax (where a NaN operand loses),
+// a NaN first argument propagates, so unphysical states give the same wave
+// speeds, fluxes and unphysical counts as an evaluation written this way.
+template <typename T>
+__device__ __forceinline__ T min_first(T a, T b) { return b < a ? b : a; }
+template <typename T>
+__device__ __forceinline__ T max_first(T a, T b) { return b > a ? b : a; }
+
+// ------------------------------------------------------------- a5: HLLC ---
+// HLLC flux across a face normal to axis D between left state L and right
+// state R (conserved).  Normal frame (n, t1, t2) = (D, D+1, D+2) mod 3.
+// Wave speeds: Einfeldt / Roe-averaged (ws == 0) or Davis (ws == 1).
+// Star state U*_K = r_K (rho_K, rho_K S*, m_t1, m_t2,
+//                        E_K + (S* - u_K)(rho_K S* + p_K / (S_K - u_K))),
+// r_K = (S_K - u_K) / (S_K - S*).  Returns true when an input state has
+// rho <= 0 or p <= 0 (or is NaN); the flux is evaluated regardless.
+template <int D, typename T>
+__device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<T>& g, int ws, T F[5]) {
+  constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
+  const T rL = L[0], rR = R[0];
+  const T iL = Fp<T>::rcp(rL), iR = Fp<T>::rcp(rR);
+  const T uL = L[n] * iL, vL = L[t1] * iL, wL = L[t2] * iL;
+  const T uR = R[n] * iR, vR = R[t1] * iR, wR = R[t2] * iR;
+  const T pL = g.gm1 * (L[4] - T(0.5) * (L[n] * uL + L[t1] * vL + L[t2] * wL));
+  const T pR = g.gm1 * (R[4] - T(0.5) * (R[n] * uR + R[t1] * vR + R[t2] * wR));
+  const bool bad = !(rL > T(0) && pL > T(0) && rR > T(0) && pR > T(0));
+  const T cL = Fp<T>::sqrt(g.gamma * pL * iL);
+  const T cR = Fp<T>::sqrt(g.gamma * pR * iR);
+
+  T SL, SR;
+  if (ws == 1) {
+    SL = min_first(uL - cL, uR - cR);
+    SR = max_first(uL + cL, uR + cR);
+  } else {
+    const T sL = Fp<T>::sqrt(rL), sR = Fp<T>::sqrt(rR);
+    const T iw = Fp<T>::rcp(sL + sR);
+    const T ua = (sL * uL + sR * uR) * iw;
+    const T va = (sL * vL + sR * vR) * iw;
+    const T wa = (sL * wL + sR * wR) * iw;
+    const T Ha = (sL * ((L[4] + pL) * iL) + sR * ((R[4] + pR) * iR)) * iw;  // H = (E + p)/rho
+    const T ca = Fp<T>::sqrt(g.gm1 * (Ha - T(0.5) * (ua * ua + va * va + wa * wa)));
+    SL = min_first(uL - cL, ua - ca);
+    SR = max_first(uR + cR, ua + ca);
+  }
+  const T aL = SL - uL, aR = SR - uR;
+  const T Ss = Fp<T>::div(pR - pL + rL * uL * aL - rR * uR * aR, rL * aL - rR * aR);
+
+  // branch order: S_L >= 0 -> F_L; else S* >= 0 -> F*_L; else S_R > 0 -> F*_R; else F_R
+  T Fn[5];
+  if (SL >= T(0)) {
+    Fn[0] = L[n];
+    Fn[1] = L[n] * uL + pL;
+    Fn[2] = L[t1] * uL;
+    Fn[3] = L[t2] * uL;
+    Fn[4] = (L[4] + pL) * uL;
+  } else if (!(Ss >= T(0)) && !(SR > T(0))) {
+    Fn[0] = R[n];
+    Fn[1] = R[n] * uR + pR;
+    Fn[2] = R[t1] * uR;
+    Fn[3] = R[t2] * uR;
+    Fn[4] = (R[4] + pR) * uR;
+  } else {
+    // subsonic: one of the two star fluxes F_K + S_K (U*_K - U_K)
+    const bool left = Ss >= T(0);
+    const T r = left ? rL : rR, u = left ? uL : uR, p = left ? pL : pR;
+    const T mn = left ? L[n] : R[n], m1 = left ? L[t1] : R[t1], m2 = left ? L[t2] : R[t2];
+    const T E = left ? L[4] : R[4];
+    const T S = left ? SL : SR, a = left ? aL : aR;
+    const T rr = Fp<T>::div(a, S - Ss);
+    const T Us0 = rr * r;
+    const T Us1 = rr * (r * Ss);
+    const T Us2 = rr * m1;
+    const T Us3 = rr * m2;
+    const T Us4 = rr * (E + (Ss - u) * (r * Ss + Fp<T>::div(p, a)));
+    Fn[0] = mn + S * (Us0 - r);
+    Fn[1] = (mn * u + p) + S * (Us1 - mn);
+    Fn[2] = m1 * u + S * (Us2 - m1);
+    Fn[3] = m2 * u + S * (Us3 - m2);
+    Fn[4] = (E + p) * u + S * (Us4 - E);
+  }
+  F[0] = Fn[0];
+  F[n] = Fn[1];
+  F[t1] = Fn[2];
+  F[t2] = Fn[3];
+  F[4] = Fn[4];
+  return bad;
+}
+
+// True when a conserved state has rho <= 0 or p <= 0 (or NaN).
+template <typename T>
+__device__ __forceinline__ bool unphysical(const T U[5], const Gas<T>& g) {
+  const T inv = Fp<T>::rcp(U[0]);
+  const T p = g.gm1 * (U[4] - T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * inv);
+  return !(U[0] > T(0) && p > T(0));
+}
+
+}  // namespace gh

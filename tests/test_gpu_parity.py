@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: bit-exact for the ghost fill (a copy), the CFL time-step (the same IEEE
+operations in the same order, uncontracted, in double) and the unphysical
+count; for the MHM step |g - o| <= tol (|o| + ref_f) per cell, ref_f the
+largest |o| of that field, with tol = 1e-12 (FP64) and 1e-5 (FP32, the oracle
+started from the FP32-rounded state)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_07070_amd import workloads as W
+from tests.oracle_runs import field_scale_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {np.float64: 1e-12, np.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1712_07070_amd import hydro as h
+    h.load()
+    return h
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else a.astype(dtype))
+    return torch.from_numpy(a).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def cfl_dt_of(lv, ghost=3, c=0.5):
+    pad = oracle.fill_ghosts(lv.U, lv.ng, ghost, lv.bc)
+    return float(oracle.dt_patch(pad, lv.dx, lv.gamma, c).min())
+
+
+# ------------------------------------------------------------- ghost fill --
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("ghost", [0, 2, 3, 5])
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (1, 1, 0, 0, 0, 0), (1, 0, 0, 1, 1, 1)])
+def test_fill_ghosts_bitwise(hydro, dtype, ghost, bc):
+    say("fill_ghosts", dtype.__name__, ghost, bc)
+    rng = np.random.default_rng(ghost)
+    ng = (3, 2, 2)
+    level = rng.normal(size=(12, 5, 16, 16, 16)).astype(dtype)
+    ref = oracle.fill_ghosts(level.astype(np.float64), ng, ghost, bc).astype(dtype)
+    got = host(hydro.fill_ghosts(dev(level), ng, ghost, bc))
+    assert np.array_equal(got, ref)
+
+
+# --------------------------------------------------------------------- CFL --
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_cfl_dt_bitwise(hydro, dtype):
+    say("cfl_dt", dtype.__name__)
+    lv = W.white_noise(64)
+    U = lv.U.astype(dtype)
+    pad = oracle.fill_ghosts(U.astype(np.float64), lv.ng, 3, lv.bc)
+    ref = oracle.dt_patch(pad, lv.dx, lv.gamma, 0.5)
+    dt_min = torch.empty(1, dtype=torch.float64, device="cuda")
+    got = host(hydro.cfl_dt(dev(pad.astype(dtype)), lv.dx, lv.gamma, 0.5, dt_min=dt_min))
+    assert np.array_equal(got, ref)
+    assert host(dt_min)[0] == ref.min()
+
+
+# -------------------------------------------------------------- MHM step ---
+
+def run_step(hydro, lv, dtype, dt, ghost=3, theta=1.5, scheme=1, U=None):
+    U = lv.U if U is None else U
+    U = U.astype(dtype)
+    pad = oracle.fill_ghosts(U.astype(np.float64), lv.ng, ghost, lv.bc)
+    ref, nb_ref = oracle.mhm_step(pad, dt, lv.dx, lv.gamma, theta, scheme)
+    n_bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got = hydro.advance(dev(pad.astype(dtype)), dt, lv.dx, lv.gamma, theta, scheme, n_bad=n_bad)
+    return host(got), ref, int(host(n_bad)[0]), nb_ref
+
+
+CASES = {
+    "white-noise": dict(),
+    "theta=1": dict(theta=1.0),
+    "theta=2": dict(theta=2.0),
+    "theta=1.37": dict(theta=1.37),
+    "davis": dict(scheme=1 | (1 << 8)),
+    "first-order": dict(scheme=1 | (1 << 10)),
+    "ghost=2": dict(ghost=2),
+}
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", list(CASES))
+def test_advance_white_noise(hydro, dtype, case):
+    say("advance white-noise 64^3", dtype.__name__, case)
+    lv = W.white_noise(64)
+    dt = cfl_dt_of(lv)
+    got, ref, nb, nb_ref = run_step(hydro, lv, dtype, dt, **CASES[case])
+    assert nb == nb_ref == 0
+    assert field_scale_error(got, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_advance_sod_tube(hydro, dtype, axis):
+    say("advance sod", dtype.__name__, axis)
+    lv = W.sod_tube(128, axis=axis)
+    got, ref, nb, nb_ref = run_step(hydro, lv, dtype, cfl_dt_of(lv))
+    assert nb == nb_ref == 0
+    assert field_scale_error(got, ref) <= TOL[dtype]
+
+
+def test_advance_hllc_branches(hydro):
+    """Supersonic flow in +x and -x halves, stagnation in between: every HLLC
+    branch (F_L, F*_L, F*_R, F_R) occurs."""
+    say("advance hllc branches")
+    n = 32
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.5, 2.0, X.shape)
+    vx = np.where(X < 0.5, 4.0, -4.0) + rng.normal(0, 0.2, X.shape)
+    vy = np.where(Y < 0.5, 3.0, -3.0)
+    vz = rng.normal(0, 0.5, X.shape)
+    p = rng.uniform(0.5, 2.0, X.shape)
+    lv = W.Level(W.grid_to_groups(W.conserved(rho, vx, vy, vz, p, 5 / 3)), (2, 2, 2), 1 / n, 5 / 3)
+    got, ref, nb, nb_ref = run_step(hydro, lv, np.float64, 0.3 * cfl_dt_of(lv))
+    assert nb == nb_ref
+    assert field_scale_error(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_unphysical_count_matches_oracle(hydro, dtype):
+    say("unphysical count", dtype.__name__)
+    lv = W.white_noise(32)
+    U = lv.U.copy()
+    U[3, 4, 7, 9, 2] = -1.0      # E < 0 -> p < 0 in one interior cell
+    U[5, 0, 0, 0, 15] = -0.5     # rho < 0 on a group corner
+    got, ref, nb, nb_ref = run_step(hydro, lv, dtype, 1e-3, U=U)
+    assert nb_ref > 0
+    assert nb == nb_ref
+
+
+def test_zero_and_single_group(hydro):
+    say("zero / single group")
+    empty = torch.empty((0, 5, 22, 22, 22), dtype=torch.float64, device="cuda")
+    assert hydro.advance(empty, 1e-3, 0.1, 1.4).shape == (0, 5, 16, 16, 16)
+    lv = W.white_noise(16)
+    got, ref, nb, nb_ref = run_step(hydro, lv, np.float64, cfl_dt_of(lv))
+    assert field_scale_error(got, ref) <= 1e-12
+
+
+def test_dt_from_device_memory(hydro):
+    say("dt from device")
+    lv = W.white_noise(32)
+    pad = dev(oracle.fill_ghosts(lv.U, lv.ng, 3, lv.bc))
+    dt = cfl_dt_of(lv)
+    a = hydro.advance(pad, dt, lv.dx, lv.gamma)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    b = hydro.advance(pad, 123.0, lv.dx, lv.gamma, dt_dev=dt_dev)
+    assert torch.equal(a, b)
+
+
+# --------------------------------------------------------- determinism -----
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_bitwise_reproducible(hydro, dtype):
+    say("determinism", dtype.__name__)
+    lv = W.white_noise(64)
+    pad = dev(oracle.fill_ghosts(lv.U, lv.ng, 3, lv.bc).astype(dtype))
+    dt = cfl_dt_of(lv)
+    outs = [hydro.advance(pad, dt, lv.dx, lv.gamma).clone() for _ in range(5)]
+    dts = [hydro.cfl_dt(pad, lv.dx, lv.gamma).clone() for _ in range(3)]
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+    assert all(torch.equal(dts[0], d) for d in dts[1:])
+
+
+# ------------------------------------------------------------ invariants ---
+
+def test_uniform_flow_and_stationary_contact_bitwise(hydro):
+    say("invariants")
+    n = 32
+    g = 5 / 3
+    uni = W.grid_to_groups(W.conserved(np.full((n, n, n), 1.3), 0.7, -0.4, 0.25, 0.8, g))
+    pad = dev(oracle.fill_ghosts(uni, (2, 2, 2), 3, (0,) * 6))
+    assert np.array_equal(host(hydro.advance(pad, 2e-3, 1 / n, g)), uni)
+    rho = np.random.default_rng(7).uniform(0.2, 3.0, (n, n, n))
+    con = W.grid_to_groups(W.conserved(rho, 0.0, 0.0, 0.0, 1.7, g))
+    pad = dev(oracle.fill_ghosts(con, (2, 2, 2), 3, (0,) * 6))
+    assert np.array_equal(host(hydro.advance(pad, 2e-3, 1 / n, g)), con)
+
+
+def test_one_dimensional_symmetry_bitwise(hydro):
+    say("1d symmetry")
+    outs = []
+    for axis in range(3):
+        lv = W.sod_tube(64, axis=axis)
+        pad = dev(oracle.fill_ghosts(lv.U, lv.ng, 3, lv.bc))
+        grid = W.groups_to_grid(host(hydro.advance(pad, 1e-3, lv.dx, lv.gamma)), lv.ng)
+        # bring the tube axis to x and its momentum to slot 1
+        if axis == 1:
+            grid = grid.transpose(0, 1, 3, 2)[[0, 2, 1, 3, 4]]
+        elif axis == 2:
+            grid = grid.transpose(0, 3, 2, 1)[[0, 3, 2, 1, 4]]
+        outs.append(grid)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_conservation_on_gpu(hydro):
+    say("conservation")
+    lv = W.white_noise(64)
+    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma)
+    solver.load_state(dev(lv.U))
+    for _ in range(3):
+        solver.step()
+    U = host(solver.state)
+    s0, s1 = lv.U.sum(axis=(0, 2, 3, 4)), U.sum(axis=(0, 2, 3, 4))
+    tol = 10 * lv.n_cells * np.finfo(float).eps * np.abs(lv.U).sum(axis=(0, 2, 3, 4))
+    assert np.all(np.abs(s1 - s0) <= tol)
+    assert int(host(solver.n_bad)[0]) == 0
+
+
+# ---------------------------------------------------------------- rollout ---
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_rollout_matches_oracle(hydro, dtype):
+    say("rollout", dtype.__name__)
+    lv = W.shear_layer(64)
+    U0 = lv.U.astype(dtype)
+    ref, dts, nb = oracle.rollout(U0.astype(np.float64), lv.ng, 3, lv.bc, 4, lv.dx, lv.gamma)
+    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, dtype=torch.float64 if dtype == np.float64 else torch.float32)
+    solver.load_state(dev(U0))
+    got_dts = []
+    for _ in range(4):
+        solver.step()
+        got_dts.append(float(host(solver.dt_min)[0]))
+    np.testing.assert_allclose(got_dts, dts, rtol=1e-13 if dtype == np.float64 else 1e-5)
+    assert field_scale_error(host(solver.state), ref) <= (1e-12 if dtype == np.float64 else 2e-5)
+
+
+# ----------------------------------------------------- full-size, sampled ---
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_shear_layer_256_sampled(hydro, dtype):
+    """Full 256^3 (4096 groups) in the launch configuration the benchmark times;
+    16 sampled groups are checked against the oracle."""
+    say("shear 256^3 sampled", dtype.__name__)
+    lv = W.shear_layer(256)
+    U = lv.U.astype(dtype)
+    del lv.U
+    t = dev(U)
+    pad = hydro.fill_ghosts(t, lv.ng, 3, lv.bc)
+    dt_min = torch.empty(1, dtype=torch.float64, device="cuda")
+    hydro.cfl_dt(pad, lv.dx, lv.gamma, 0.5, dt_min=dt_min)
+    out = hydro.advance(pad, 1.0, lv.dx, lv.gamma, dt_dev=dt_min)
+    dt = float(host(dt_min)[0])
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(lv.n_groups, 16, replace=False))
+    opad = oracle.fill_ghosts(U.astype(np.float64), lv.ng, 3, lv.bc)[sample]
+    assert dt == float(oracle.dt_patch(oracle.fill_ghosts(U.astype(np.float64), lv.ng, 3, lv.bc), lv.dx,
+                                       lv.gamma).min())
+    ref, _ = oracle.mhm_step(opad, dt, lv.dx, lv.gamma)
+    got = host(out)[sample]
+    assert field_scale_error(got, ref) <= TOL[dtype]
