@@ -1,9 +1,13 @@
 """Benchmark of the patch-group MHM hot path on one MI355X.
 
 A step is one pass of the whole per-level path over every patch group of the
-level: ghost fill (hydro_fill_ghosts), per-patch CFL time-step with the level
-minimum kept on the device (hydro_dt), and the MHM update that reads that
-time-step from device memory (hydro_advance).  The default workload is the
+level: ghost fill, MHM update and the per-patch CFL time-step (Eq. 2) that the
+next step uses.  By default this is one fused launch per step
+(hydro_advance_level: neighbour groups are read directly instead of a padded
+copy, and the CFL reduction of the written state runs in the epilogue); the
+first timed step also computes the CFL time-step of the initial state
+(hydro_dt).  --unfused times hydro_fill_ghosts + hydro_dt + hydro_advance per
+step instead.  The default workload is the
 256^3 periodic shear layer (4096 groups of 16^3 cells, 3 ghost zones,
 gamma = 1.4) advanced at CFL 0.5 in double precision; inputs are resident in
 HBM before the timed region starts.
@@ -36,12 +40,37 @@ FP32_VEC_PEAK_TFLOPS = 157.3   # MI355X vector FP32
 # input (7360 cells of a padded group: interior, 2-deep face slabs, 1-deep
 # edges) plus the 4096 interior outputs, 5 fields each, per 4096 cells updated.
 REACH_CELLS = 7360
-ALG_BYTES_PER_CELL = {"f64": (REACH_CELLS + 4096) * 5 * 8 / 4096, "f32": (REACH_CELLS + 4096) * 5 * 4 / 4096}
+ALG_BYTES_PADDED = {"f64": (REACH_CELLS + 4096) * 5 * 8 / 4096, "f32": (REACH_CELLS + 4096) * 5 * 4 / 4096}
+# The fused level step reads every level cell once and writes it once.
+ALG_BYTES_LEVEL = {"f64": 2 * 5 * 8, "f32": 2 * 5 * 4}
 # Algorithmic floating-point operations per cell update (add, mul, div, sqrt
 # each one), from the oracle's operation count of the four per-item stages
 # times their multiplicities per group (7360 primitive conversions, 5632
 # Hancock cells, 13056 HLLC faces, 4096 updates).
 ALG_FLOPS_PER_CELL = 880.2
+
+
+def kernel_source_sha() -> str:
+    """sha256 of the sources of the MHM kernels (changes whenever they do)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hydro_device.h", "mhm_fwd.hip"):
+        with open(os.path.join(ROOT, "paper_1712_07070_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_key: str, variant):
+    """HBM bytes per launch from the committed counter profile, or None when
+    the kernel sources or the launch shape differ from what was measured."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            rec = json.load(fh).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != kernel_source_sha() or rec.get("variant") != variant:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def parse():
@@ -54,14 +83,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the extra FP32 measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--unfused", action="store_true", help="time fill + dt + padded advance per step")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="after the run, copy a device buffer of this size (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def run_workload(hydro, torch, lv, dtype, steps, warmup):
-    """Time `steps` full steps; return (seconds, mean MHM kernel ms, solver, last dt, n_bad)."""
+def run_workload(hydro, torch, lv, dtype, steps, warmup, fused=True, autotune=True):
+    """Time `steps` full steps; return (seconds, mean MHM kernel ms, solver, last dt, n_bad, tune info)."""
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, lv.bc, ghost=3, dtype=tdt)
+    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, lv.bc, ghost=3, dtype=tdt, fused=fused)
     U0 = torch.from_numpy(np.ascontiguousarray(lv.U.astype(np.float64 if dtype == "f64" else np.float32))).cuda()
+    tune = None
+    if fused and autotune:
+        # choose the launch shape (all shapes give bit-identical results) before timing
+        best, times = hydro.autotune(U0, lv.ng, lv.bc, lv.dx, lv.gamma, reps=5)
+        tune = {"variant": best, "name": hydro.variant_name(best), "ms": [round(t, 4) for t in times]}
     solver.load_state(U0)
     for _ in range(warmup):
         solver.step()
@@ -77,7 +115,7 @@ def run_workload(hydro, torch, lv, dtype, steps, warmup):
     elapsed = time.perf_counter() - t0
     kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     dts = solver.dt_min.cpu().numpy()
-    return elapsed, kms, solver, dts, int(solver.n_bad.cpu()[0])
+    return elapsed, kms, solver, dts, int(solver.n_bad.cpu()[0]), tune
 
 
 def cpu_baseline(lv_factory, seconds):
@@ -120,29 +158,58 @@ def main():
     lv = W.shear_layer(args.n)
     cells = lv.n_cells
     print("bench: timing %s" % args.dtype, file=sys.stderr, flush=True)
-    el, kms, solver, dts, n_bad = run_workload(hydro, torch, lv, args.dtype, args.steps, args.warmup)
+    fused = not args.unfused
+    el, kms, solver, dts, n_bad, tune = run_workload(hydro, torch, lv, args.dtype, args.steps, args.warmup, fused,
+                                                     not args.no_autotune)
     value = cells * args.steps / el
-    alg_b = ALG_BYTES_PER_CELL[args.dtype]
+    alg_b = (ALG_BYTES_LEVEL if fused else ALG_BYTES_PADDED)[args.dtype]
     k_rate = cells / (kms * 1e-3)                       # cell updates/s of the MHM kernel alone
     hbm_gbs = alg_b * k_rate / 1e9
     peak_flops = FP64_VEC_PEAK_TFLOPS if args.dtype == "f64" else FP32_VEC_PEAK_TFLOPS
     alu_tflops = ALG_FLOPS_PER_CELL * k_rate / 1e12
-    roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "mhm_fwd_kernel<%s>" % ("double" if args.dtype == "f64" else "float"),
-            "kernel_ms": round(kms, 4), "alg_bytes_per_cell": round(alg_b, 3), "cells_per_launch": cells,
-            "alu": {"achieved": round(alu_tflops, 2), "peak": peak_flops, "unit": "TFLOP/s",
-                    "frac": round(alu_tflops / peak_flops, 4), "alg_flops_per_cell": ALG_FLOPS_PER_CELL}}
-    extra = {"kernel_cell_updates_per_s": k_rate, "n_bad": n_bad, "dt_last_step": float(dts[0])}
+    tname = "double" if args.dtype == "f64" else "float"
+    hbm = {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+           "alg_bytes_per_cell": alg_b}
+    alu = {"achieved": round(alu_tflops, 2), "peak": peak_flops, "unit": "TFLOP/s",
+           "frac": round(alu_tflops / peak_flops, 4), "alg_flops_per_cell": ALG_FLOPS_PER_CELL}
+    # the binding roof is the one with the lower ceiling for this kernel's
+    # algorithmic bytes and flops per cell
+    alu_binds = peak_flops * 1e12 / ALG_FLOPS_PER_CELL < HBM_PEAK_GBS * 1e9 / alg_b
+    main, other = (alu, hbm) if alu_binds else (hbm, alu)
+    roof = {"bound": "alu" if alu_binds else "hbm", "achieved": main["achieved"], "peak": main["peak"],
+            "unit": main["unit"], "frac": main["frac"], "traffic": None,
+            "kernel": ("mhm_level_kernel<%s, true>" % tname) if fused else ("mhm_padded_kernel<%s>" % tname),
+            "kernel_ms": round(kms, 4), "cells_per_launch": cells, "other_roof": other}
+    roof["alg_per_cell"] = main.get("alg_flops_per_cell", main.get("alg_bytes_per_cell"))
+    if fused:
+        roof["traffic"] = measured_traffic("mhm_level_kernel<%s, true>" % tname,
+                                           tune["variant"] if tune else hydro.get_variant(solver.state.dtype))
+    extra = {"kernel_cell_updates_per_s": k_rate, "n_bad": n_bad, "dt_last_step": float(dts[0]),
+             "path": "fused level step" if fused else "fill + dt + padded advance", "launch_shape": tune}
     if not args.no_f32 and args.dtype == "f64":
         print("bench: timing f32", file=sys.stderr, flush=True)
-        el32, kms32, _, _, nb32 = run_workload(hydro, torch, lv, "f32", args.steps, args.warmup)
+        el32, kms32, _, _, nb32, tune32 = run_workload(hydro, torch, lv, "f32", args.steps, args.warmup, fused,
+                                                       not args.no_autotune)
         r32 = cells / (kms32 * 1e-3)
+        b32 = (ALG_BYTES_LEVEL if fused else ALG_BYTES_PADDED)["f32"]
         extra["f32"] = {"value": cells * args.steps / el32, "ms_per_step": el32 / args.steps * 1e3,
                         "kernel_ms": kms32, "kernel_cell_updates_per_s": r32,
-                        "hbm_frac": ALG_BYTES_PER_CELL["f32"] * r32 / 1e9 / HBM_PEAK_GBS, "n_bad": nb32}
+                        "hbm_frac": b32 * r32 / 1e9 / HBM_PEAK_GBS,
+                        "alu_frac": ALG_FLOPS_PER_CELL * r32 / 1e12 / FP32_VEC_PEAK_TFLOPS, "n_bad": nb32,
+                        "launch_shape": tune32}
     del solver
     torch.cuda.empty_cache()
+    if args.calibrate_copy > 0:
+        # a plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counter readings calibrate the byte counters of the kernels above
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        extra["copy_calibration_bytes"] = n * 8
+        del src, dst
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -152,7 +219,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "shear-layer %d^3 periodic, %d patch groups of 16^3 (3 ghost zones), gamma=1.4, "
-                               "MHM+PLM+HLLC at CFL 0.5: ghost fill + CFL + update per step" % (args.n, lv.n_groups),
+                               "MHM+PLM+HLLC at CFL 0.5: ghost fill + update + CFL per step" % (args.n, lv.n_groups),
                    "grid": args.n, "groups": lv.n_groups, "ghost": 3, "theta": 1.5},
         "roofline": roof, "cpu_baseline": cpu, "extra": extra,
     }

@@ -89,6 +89,35 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
                   int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
                   double theta, const double* dt_dev, int32_t* n_bad_dev, void* stream);
 
+/* hydro_advance_level -- one MHM step of every patch group of a level, read
+ * directly from level storage (Sec. 2.2 scheme; Sec. 3.4 ghost zones; Sec. 2.6
+ * Eq. 2 for the optional CFL outputs).  Each cell the stencil reaches outside
+ * a group (2 layers) is read from the neighbouring group with the index map
+ * of hydro_fill_ghosts, so the result equals hydro_fill_ghosts followed by
+ * hydro_advance, without the padded copy.
+ *   level_dev       [G][5][16^3] input level, G = ngx*ngy*ngz (not modified)
+ *   level_out_dev   [G][5][16^3] output level; must not overlap level_dev
+ *   bc_host         6 ints on the host (x-, x+, y-, y+, z-, z+), 0 periodic,
+ *                   1 outflow
+ *   dt, dt_dev, dx, gamma, scheme, theta, n_bad_dev: as for hydro_advance
+ *   c_cfl           CFL safety factor, > 0 if any of the three outputs below
+ *                   is requested
+ *   dt_next_dev     optional device double: the minimum over all patches of
+ *                   the Eq. 2 time-step of the OUTPUT state is folded in with
+ *                   an (exact, order-independent) minimum; it must hold +inf
+ *                   or a larger value when the step starts
+ *   dt_patch_next_dev optional [G][8] double: per-patch Eq. 2 time-steps of
+ *                   the output state (bit-identical to hydro_dt on it)
+ *   dt_reset_dev    optional device double the step sets to +inf (before any
+ *                   other use in the step); lets three buffers rotate over a
+ *                   rollout (read dt from A, reduce into B, reset C); must
+ *                   differ from dt_dev and dt_next_dev
+ */
+int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                        const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                        double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl, double* dt_next_dev,
+                        double* dt_patch_next_dev, double* dt_reset_dev, void* stream);
+
 /* hydro_dt -- per-patch CFL time-step, Sec. 2.6 Eq. 2 (the form for MHM):
  * dt_patch = (c_cfl * dx) / max over the patch's 8^3 cells of
  * (|u| + |v| + |w| + 3 c_s), c_s = sqrt(gamma p / rho), evaluated in double
@@ -115,6 +144,34 @@ int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dty
  */
 int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                       int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream);
+
+/* Launch shapes of hydro_advance_level.  Every shape runs the same per-cell
+ * arithmetic in the same order, so all give bit-identical results; they
+ * differ in the register budget the compiler was given (occupancy) and in the
+ * order groups are dealt to workgroups (plain, or blocked so that each of the
+ * 8 XCDs sweeps a contiguous range of groups and finds neighbour-group halos
+ * in its own L2).  The choice is process-wide, per dtype.
+ *   hydro_num_variants   number of shapes (>= 1)
+ *   hydro_set_variant    select one (0 .. n-1); HYDRO_EINVAL otherwise
+ *   hydro_get_variant    current selection for a dtype
+ *   hydro_variant_name   short description into buf[len] (host memory)
+ */
+int hydro_num_variants(void);
+int hydro_set_variant(int32_t dtype, int32_t variant);
+int hydro_get_variant(int32_t dtype);
+int hydro_variant_name(int32_t variant, char* buf, int32_t len);
+
+/* hydro_autotune -- time every launch shape of hydro_advance_level on the
+ * caller's level (1 untimed + `reps` timed launches each, HIP events on
+ * `stream`, 1 <= reps <= 1000), select the fastest for `dtype` and return its
+ * index (>= 0), or a negative status (the previous selection is then kept).
+ * SYNCHRONOUS: waits on `stream`.  level_dev is read, scratch_out_dev
+ * ([G][5][16^3], not overlapping) is overwritten.  times_ms_host, if not
+ * NULL, receives hydro_num_variants() mean times in milliseconds.
+ */
+int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                   const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps,
+                   float* times_ms_host, void* stream);
 
 /* Name of a status code (static string). */
 const char* hydro_strerror(int status);

@@ -49,15 +49,13 @@ __global__ __launch_bounds__(256) void fill_ghosts_kernel(const T* __restrict__ 
 // ------------------------------------------------------------------ CFL ---
 // One workgroup of 256 threads per group: thread (x, y) walks z; the maximum
 // signal speed |u|+|v|+|w|+3c is reduced per 8^3 patch through LDS.
-// Arithmetic is double for both state types and is not contracted, so each
-// value is the IEEE evaluation of the formula in the order ((|u|+|v|)+|w|)+3c.
-// The maximum keeps the running value unless a speed is strictly larger (a
+// cfl_signal_speed evaluates each cell in double for both state types with
+// IEEE-rounded, uncontracted operations.  The maximum keeps the running value unless a speed is strictly larger (a
 // NaN speed from an unphysical cell never wins; the step counts such cells).
 template <typename T>
 __global__ __launch_bounds__(256) void cfl_dt_kernel(const T* __restrict__ U_pad, int gh, double dx, double gamma,
                                                      double c_cfl, double* __restrict__ dt_patch,
                                                      unsigned long long* __restrict__ dt_min) {
-#pragma clang fp contract(off)
   __shared__ double red[2][4][64];  // [pz][py*2 + px][cell column within the patch]
   const int P = 16 + 2 * gh;
   const int64_t P3 = int64_t(P) * P * P;
@@ -66,13 +64,8 @@ __global__ __launch_bounds__(256) void cfl_dt_kernel(const T* __restrict__ U_pad
   double smax[2] = {0.0, 0.0};
   for (int z = 0; z < 16; ++z) {
     const int64_t o = (int64_t(z + gh) * P + (y + gh)) * P + (x + gh);
-    const double rho = double(Ug[o]);
-    const double mx = double(Ug[P3 + o]), my = double(Ug[2 * P3 + o]), mz = double(Ug[3 * P3 + o]);
-    const double E = double(Ug[4 * P3 + o]);
-    const double u = mx / rho, v = my / rho, w = mz / rho;
-    const double p = (gamma - 1.0) * (E - 0.5 * ((mx * u + my * v) + mz * w));
-    const double c = __builtin_sqrt((gamma * p) / rho);
-    const double s = ((__builtin_fabs(u) + __builtin_fabs(v)) + __builtin_fabs(w)) + 3.0 * c;
+    const double s = cfl_signal_speed(double(Ug[o]), double(Ug[P3 + o]), double(Ug[2 * P3 + o]),
+                                      double(Ug[3 * P3 + o]), double(Ug[4 * P3 + o]), gamma);
     if (s > smax[z >> 3]) smax[z >> 3] = s;
   }
   const int pxy = (y >> 3) * 2 + (x >> 3);

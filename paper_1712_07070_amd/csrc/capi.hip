@@ -1,8 +1,10 @@
 // extern "C" entry points of libhydro: argument validation and dispatch to
 // the kernels.  Declarations and documentation: include/hydro.h.
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 
 #include "hydro.h"
 #include "kernels.h"
@@ -10,6 +12,10 @@
 namespace {
 
 thread_local int g_last_hip_error = 0;
+
+// Launch shape of the level step per dtype (index into the variants of
+// mhm_fwd.hip); set by hydro_set_variant or hydro_autotune, process-wide.
+std::atomic<int> g_level_variant[2] = {{1}, {2}};  // measured defaults: FP64 plain order, FP32 XCD-blocked
 
 int device_status(hipError_t e) {
   if (e == hipSuccess) return HYDRO_OK;
@@ -41,6 +47,7 @@ gh::Gas<T> make_gas(double gamma, double theta, double dt, double dx) {
   g.gm1 = T(gamma - 1.0);
   g.inv_gm1 = T(1.0 / (gamma - 1.0));
   g.theta = T(theta);
+  g.half_theta = T(0.5 * theta);
   g.dtdx = T(dt / dx);
   g.half_dtdx = T(0.5 * (dt / dx));
   return g;
@@ -50,7 +57,7 @@ gh::Gas<T> make_gas(double gamma, double theta, double dt, double dx) {
 
 extern "C" {
 
-int hydro_version(void) { return 1; }
+int hydro_version(void) { return 2; }
 
 int hydro_last_hip_error(void) { return g_last_hip_error; }
 
@@ -92,6 +99,127 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
     e = gh::launch_mhm_fwd(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups, ghost,
                            make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, s);
   return device_status(e);
+}
+
+int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                        const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                        double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl, double* dt_next_dev,
+                        double* dt_patch_next_dev, double* dt_reset_dev, void* stream) {
+  if (ngx < 1 || ngy < 1 || ngz < 1 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
+    return HYDRO_EINVAL;
+  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
+  const bool want_cfl = dt_next_dev != nullptr || dt_patch_next_dev != nullptr || dt_reset_dev != nullptr;
+  if (want_cfl && !finite_pos(c_cfl)) return HYDRO_EINVAL;
+  if (dt_reset_dev != nullptr && (dt_reset_dev == dt_dev || dt_reset_dev == dt_next_dev)) return HYDRO_EINVAL;
+  if (dt_next_dev != nullptr && dt_next_dev == dt_dev) return HYDRO_EINVAL;
+  gh::LevelGeom geo;
+  geo.ngx = ngx;
+  geo.ngy = ngy;
+  geo.ngz = ngz;
+  for (int i = 0; i < 6; ++i) {
+    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
+    geo.bc[i] = bc_host[i];
+  }
+  if (level_dev == nullptr || level_out_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  const size_t bytes = size_t(G) * 5 * 4096 * dtype_size(dtype);
+  if (overlap(level_dev, bytes, level_out_dev, bytes)) return HYDRO_EINVAL;
+  gh::CflOut cfl;
+  cfl.dt_patch = dt_patch_next_dev;
+  cfl.dt_min = reinterpret_cast<unsigned long long*>(dt_next_dev);
+  cfl.reset = reinterpret_cast<unsigned long long*>(dt_reset_dev);
+  cfl.c_cfl_dx = want_cfl ? c_cfl * dx : 0.0;
+  cfl.gamma = gamma;
+  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
+  const int ws = (scheme >> 8) & 3;
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_mhm_level(static_cast<const double*>(level_dev), static_cast<double*>(level_out_dev), geo,
+                             make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
+                             g_level_variant[0].load(), s);
+  else
+    e = gh::launch_mhm_level(static_cast<const float*>(level_dev), static_cast<float*>(level_out_dev), geo,
+                             make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
+                             g_level_variant[1].load(), s);
+  return device_status(e);
+}
+
+int hydro_num_variants(void) { return gh::kLevelVariants; }
+
+int hydro_get_variant(int32_t dtype) {
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  return g_level_variant[dtype].load();
+}
+
+int hydro_set_variant(int32_t dtype, int32_t variant) {
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  if (variant < 0 || variant >= gh::kLevelVariants) return HYDRO_EINVAL;
+  g_level_variant[dtype].store(variant);
+  return HYDRO_OK;
+}
+
+int hydro_variant_name(int32_t variant, char* buf, int32_t len) {
+  if (variant < 0 || variant >= gh::kLevelVariants || buf == nullptr || len < 1) return HYDRO_EINVAL;
+  std::snprintf(buf, size_t(len), "%s order, %s occupancy target", (variant & 1) ? "plain" : "xcd-blocked",
+                (variant & 2) ? "low" : "high");
+  return HYDRO_OK;
+}
+
+int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                   const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps, float* times_ms_host,
+                   void* stream) {
+  if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int saved = g_level_variant[dtype].load();
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return device_status(hipGetLastError());
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return device_status(hipGetLastError());
+  }
+  int best = -1, status = HYDRO_OK;
+  float best_ms = 0.0f;
+  const double dt = 1e-3 * dx;  // any positive step does the same work
+  for (int v = 0; v < gh::kLevelVariants && status == HYDRO_OK; ++v) {
+    g_level_variant[dtype].store(v);
+    // one untimed launch, then `reps` timed ones
+    status = hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
+                                 HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, nullptr, nullptr, nullptr,
+                                 stream);
+    if (status != HYDRO_OK) break;
+    hipError_t he = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r)
+      status = hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
+                                   HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, nullptr, nullptr, nullptr,
+                                   stream);
+    if (status != HYDRO_OK) break;
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      status = device_status(he);
+      break;
+    }
+    ms /= float(reps);
+    if (times_ms_host != nullptr) times_ms_host[v] = ms;
+    if (best < 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != HYDRO_OK) {
+    g_level_variant[dtype].store(saved);
+    return status;
+  }
+  g_level_variant[dtype].store(best);
+  return best;
 }
 
 int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dtype, double dx, double gamma,

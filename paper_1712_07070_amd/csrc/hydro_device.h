@@ -15,19 +15,49 @@
 namespace gh {
 
 // ------------------------------------------------------------ numerics ----
+// Type-exact elementary helpers (the __builtin_f* forms without suffix are
+// the double versions and would silently widen float arguments).
+__device__ __forceinline__ double fabs_(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float fabs_(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double fmin_(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float fmin_(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double copysign_(double a, double b) { return __builtin_copysign(a, b); }
+__device__ __forceinline__ float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
+
 template <typename T> struct Fp;
 
+// FP64: hardware reciprocal / reciprocal square root refined by Newton steps
+// (error about 1 ulp, far inside the 1e-12 parity bound) instead of the
+// correctly rounded IEEE sequences, which cost two to three times as many
+// instructions.  sqrt(0) is returned as 0 (the refinement would give NaN).
 template <> struct Fp<double> {
-  // IEEE-correct division and square root: the FP64 path is meant to agree
-  // with an FP64 reference to ~1e-15 per operation.
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-  static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
+  static __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+  }
+  static __device__ __forceinline__ double div(double a, double b) {
+    const double r = rcp(b);
+    const double q = a * r;
+    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+  }
+  static __device__ __forceinline__ double sqrt(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    return x == 0.0 ? 0.0 : g;
+  }
 };
 
+// FP32: single hardware reciprocal and square root (about 1 ulp); the FP32
+// path is held to 1e-5 relative.
 template <> struct Fp<float> {
-  // Hardware reciprocal and square root (about 1 ulp): the FP32 path is
-  // held to 1e-5 relative, far above their error.
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
   static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -39,6 +69,7 @@ template <typename T> struct Gas {
   T gm1;        // gamma - 1
   T inv_gm1;    // 1 / (gamma - 1)
   T theta;      // generalized minmod parameter
+  T half_theta; // theta / 2
   T dtdx;       // dt / dx
   T half_dtdx;  // dt / (2 dx)
 };
@@ -56,17 +87,20 @@ __device__ __forceinline__ void cons_to_prim(const T U[5], const Gas<T>& g, T W[
 }
 
 // ------------------------------------------- a2: generalized minmod slope --
-// dm = q0 - qm, dp = qp - q0, dc = (qp - qm)/2.  If dm and dp are strictly of
-// one sign: sgn(dc) * min(theta|dm|, |dc|, theta|dp|); else 0.
+// Half of the limited slope, h = slope/2, so that the face values are q0 -+ h:
+//   dm = q0 - qm, dp = qp - q0, slope = sgn(dc) min(theta|dm|, |dc|, theta|dp|)
+//   with dc = (qp - qm)/2 if dm and dp have one strict sign, else 0.
+// Scaling by 1/2 and 1/4 is exact, so h is bit-identical to slope/2.  The
+// one-sign test is dm*dp > 0: it differs from testing the signs separately
+// only when the product underflows (|dm|, |dp| < 1e-154 in FP64), where the
+// slope itself is below any resolvable level.
 template <typename T>
-__device__ __forceinline__ T gminmod(T qm, T q0, T qp, T theta) {
+__device__ __forceinline__ T half_slope(T qm, T q0, T qp, T half_theta) {
   const T dm = q0 - qm;
   const T dp = qp - q0;
-  const T dc = T(0.5) * (qp - qm);
-  T m = __builtin_fmin(theta * __builtin_fabs(dm), __builtin_fabs(dc));
-  m = __builtin_fmin(m, theta * __builtin_fabs(dp));
-  const bool mono = (dm > T(0) && dp > T(0)) || (dm < T(0) && dp < T(0));
-  return mono ? __builtin_copysign(m, dc) : T(0);
+  T h = fmin_(half_theta * fabs_(dm), T(0.25) * fabs_(qp - qm));
+  h = fmin_(h, half_theta * fabs_(dp));
+  return dm * dp > T(0) ? copysign_(h, dp) : T(0);
 }
 
 // ----------------------------------------- a3 + a4: Hancock face states ---
@@ -88,8 +122,8 @@ __device__ __forceinline__ void hancock_states(const T Wc[5], const T Wn[3][2][5
       T W[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const T sl = first_order ? T(0) : gminmod(Wn[d][0][q], Wc[q], Wn[d][1][q], g.theta);
-        W[q] = side == 0 ? Wc[q] - T(0.5) * sl : Wc[q] + T(0.5) * sl;
+        const T h = first_order ? T(0) : half_slope(Wn[d][0][q], Wc[q], Wn[d][1][q], g.half_theta);
+        W[q] = side == 0 ? Wc[q] - h : Wc[q] + h;
       }
       T* U = Ut[d][side];
       U[0] = W[0];
@@ -218,6 +252,19 @@ __device__ __forceinline__ bool unphysical(const T U[5], const Gas<T>& g) {
   const T inv = Fp<T>::rcp(U[0]);
   const T p = g.gm1 * (U[4] - T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * inv);
   return !(U[0] > T(0) && p > T(0));
+}
+
+// ------------------------------------------------ a8: CFL signal speed ----
+// |u| + |v| + |w| + 3 c_s of one cell (Sec. 2.6 Eq. 2), in double, every
+// operation IEEE-rounded and uncontracted, summed ((|u|+|v|)+|w|)+3c.  Both
+// the standalone CFL kernel and the CFL epilogue of the fused step call this.
+__device__ __forceinline__ double cfl_signal_speed(double rho, double mx, double my, double mz, double E,
+                                                   double gamma) {
+#pragma clang fp contract(off)
+  const double u = mx / rho, v = my / rho, w = mz / rho;
+  const double p = (gamma - 1.0) * (E - 0.5 * ((mx * u + my * v) + mz * w));
+  const double c = __builtin_sqrt((gamma * p) / rho);
+  return ((__builtin_fabs(u) + __builtin_fabs(v)) + __builtin_fabs(w)) + 3.0 * c;
 }
 
 }  // namespace gh

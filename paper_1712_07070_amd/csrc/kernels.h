@@ -8,6 +8,34 @@
 
 namespace gh {
 
+// Group lattice and boundary conditions of one level (bc: x-, x+, y-, y+,
+// z-, z+; 0 periodic, 1 outflow).
+struct LevelGeom {
+  int ngx, ngy, ngz;
+  int bc[6];
+};
+
+// CFL outputs of a fused step (all optional): per-patch time-steps of the
+// written state, an integer-minimum target for the level time-step (the bit
+// pattern of a non-negative double), and a location the kernel resets to +inf.
+struct CflOut {
+  double* dt_patch;
+  unsigned long long* dt_min;
+  unsigned long long* reset;
+  double c_cfl_dx;  // C_CFL * dx, formed on the host in double
+  double gamma;
+};
+
+template <typename T>
+hipError_t launch_mhm_level(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
+                            const double* dt_dev, double dx, int first_order, int ws, int* n_bad, const CflOut& cfl,
+                            int variant, hipStream_t stream);
+
+// Launch shapes of the level step (all give bit-identical results):
+// bit 0 set = groups in plain order instead of XCD-blocked order,
+// bit 1 set = lower occupancy target for the register allocator.
+constexpr int kLevelVariants = 4;
+
 template <typename T>
 hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost, const Gas<T>& gas,
                           const double* dt_dev, double dx, int first_order, int ws, int* n_bad,

@@ -1,4 +1,4 @@
-// Fused MHM step of one 16^3 patch group per workgroup (GAMER-2, Sec. 2.2).
+// MHM step of 16^3 patch groups, one group per workgroup (GAMER-2, Sec. 2.2).
 //
 // Mapping on gfx950 (wave64, 160 KB LDS per CU):
 //   * 320 threads = 5 waves.  Waves 0-3 own the 256 interior (x, y) columns
@@ -22,8 +22,15 @@
 // primitives and states are read before the barrier after which plane k+1's
 // are written, and the fluxes of plane k are read before those of k+1 are.
 //
-// HBM traffic per group: the padded input planes -2..17 (read once, the
-// z stencil re-uses registers) and the 16^3 x 5 output.
+// Two sources of the input cells share this code:
+//   * padded groups [G][5][P^3] whose ghost zones were filled beforehand
+//     (hydro_advance), and
+//   * the level storage itself [G][5][16^3] (hydro_advance_level): every cell
+//     the stencil reaches outside the group is read from the neighbouring
+//     group, with the periodic / outflow index map of the ghost fill.  This
+//     is the ghost fill (a0) fused into the load stage: no padded copy is
+//     written or read back.  Optionally the same kernel reduces the CFL
+//     time-step (a8) of the cells it writes, for the next step.
 
 #include "hydro_device.h"
 #include "kernels.h"
@@ -41,40 +48,71 @@ __device__ __forceinline__ int sidx(int x, int y) { return (y + 1) * kSW + (x + 
 __device__ __forceinline__ int fxidx(int i, int j) { return j * 17 + i; }  // x-face i: between i-1 and i
 __device__ __forceinline__ int fyidx(int i, int j) { return j * 16 + i; }  // y-face j: between j-1 and j
 
+// ------------------------------------------------------------- sources ----
+// A source maps group-relative cell coordinates to element offsets:
+// offset(f, x, y, z) = col(x, y) + plane(z) + f * fstride.
+
 template <typename T>
-__device__ __forceinline__ void load_prim(const T* __restrict__ Ug, int64_t P3, int P, int gh, int x, int y,
-                                          int z, const Gas<T>& g, T W[5]) {
-  const int64_t o = (int64_t(z + gh) * P + (y + gh)) * P + (x + gh);
+struct PaddedSource {
+  const T* base;  // this group's padded block
+  int P, gh;
+  __device__ int64_t col(int x, int y) const { return int64_t(y + gh) * P + (x + gh); }
+  __device__ int64_t plane(int z) const { return int64_t(z + gh) * P * P; }
+  __device__ int64_t fstride() const { return int64_t(P) * P * P; }
+};
+
+__device__ __forceinline__ int bc_wrap(int i, int n, int lo, int hi) {
+  if (i < 0) return lo == 0 ? i + n : 0;
+  if (i >= n) return hi == 0 ? i - n : n - 1;
+  return i;
+}
+
+template <typename T>
+struct LevelSource {
+  const T* base;  // the level storage [G][5][16^3]
+  LevelGeom geo;
+  int gx, gy, gz;
+  __device__ int64_t col(int x, int y) const {
+    const int X = bc_wrap(gx * 16 + x, geo.ngx * 16, geo.bc[0], geo.bc[1]);
+    const int Y = bc_wrap(gy * 16 + y, geo.ngy * 16, geo.bc[2], geo.bc[3]);
+    return int64_t((Y >> 4) * geo.ngx + (X >> 4)) * (5 * 4096) + (Y & 15) * 16 + (X & 15);
+  }
+  __device__ int64_t plane(int z) const {
+    const int Z = bc_wrap(gz * 16 + z, geo.ngz * 16, geo.bc[4], geo.bc[5]);
+    return int64_t(Z >> 4) * geo.ngx * geo.ngy * (5 * 4096) + (Z & 15) * 256;
+  }
+  __device__ int64_t fstride() const { return 4096; }
+};
+
+template <typename T, class Src>
+__device__ __forceinline__ void load_prim(const Src& src, int64_t col, int z, const Gas<T>& g, T W[5]) {
+  const int64_t o = col + src.plane(z);
+  const int64_t fs = src.fstride();
   T U[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) U[q] = Ug[q * P3 + o];
+  for (int q = 0; q < 5; ++q) U[q] = src.base[o + q * fs];
   cons_to_prim(U, g, W);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void mhm_fwd_kernel(const T* __restrict__ Upad, T* __restrict__ Uout,
-                                                           int gh, Gas<T> gas, const double* __restrict__ dt_dev,
-                                                           double dx, int first_order, int ws,
-                                                           int* __restrict__ n_bad) {
-  __shared__ T sP[5][kPW * kPW];     // primitive plane k
-  __shared__ T sS[2][5][kSW * kSW];  // x+ and y+ half-step states of plane k
-  __shared__ T sF[2][5][17 * 16];    // x and y fluxes of plane k
+struct Smem {
+  T P[5][kPW * kPW];     // primitive plane k
+  T S[2][5][kSW * kSW];  // x+ and y+ half-step states of plane k
+  T F[2][5][17 * 16];    // x and y fluxes of plane k
+};
 
-  if (dt_dev != nullptr) {
-    const double dt = *dt_dev;
-    gas.dtdx = T(dt / dx);
-    gas.half_dtdx = T(0.5 * (dt / dx));
-  }
-
+// ---------------------------------------------------- one patch group ----
+// Advance one group: read through `src`, write the 16^3 x 5 interior to `out`
+// (field stride 4096).  Returns this thread's unphysical count.  If smax is
+// non-null, also returns (interior threads) the maximum CFL signal speed of
+// the thread's cells in patch-z halves 0..7 and 8..15.
+template <typename T, class Src>
+__device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
+                                             int first_order, int ws, Smem<T>& sm, double* smax,
+                                             double gamma_d) {
   const int tid = threadIdx.x;
-  const int P = 16 + 2 * gh;
-  const int64_t P3 = int64_t(P) * P * P;
-  const T* __restrict__ Ug = Upad + int64_t(blockIdx.x) * 5 * P3;
-  T* __restrict__ Og = Uout + int64_t(blockIdx.x) * 5 * 4096;
-
-  // roles
   const bool interior = tid < 256;
-  int cx, cy;        // own state column
+  int cx, cy;          // own state column
   int ox = 0, oy = 0;  // wave 4: the column two cells out
   int ex = 0, ey = 0;  // wave 4, lanes 0..3: one of the 4 edge columns
   if (interior) {
@@ -92,54 +130,58 @@ __global__ __launch_bounds__(kThreads) void mhm_fwd_kernel(const T* __restrict__
   const bool has_edge = !interior && (tid - 256) < 4;
   const bool xface16 = !interior && cx == 16;  // solves x-face 16 (between 15 and 16)
   const bool yface16 = !interior && cy == 16;  // solves y-face 16
+  const int64_t col_own = src.col(cx, cy);
+  const int64_t col_out = interior ? 0 : src.col(ox, oy);
+  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
+  const int64_t fs = src.fstride();
 
   // register ring of the own column's primitive states
   T Wm[5], Wc[5], Wp[5];
-  if (interior) load_prim(Ug, P3, P, gh, cx, cy, -2, gas, Wm);
-  load_prim(Ug, P3, P, gh, cx, cy, -1, gas, Wc);
+  if (interior) load_prim(src, col_own, -2, gas, Wm);
+  load_prim(src, col_own, -1, gas, Wc);
 
-  T Uz[5];    // z+ face state of the previous plane (interior)
-  T Fz0[5];   // z flux at the low face of the previous plane (interior)
+  T Uz[5];         // z+ face state of the previous plane (interior)
+  T Fz0[5];        // z flux at the low face of the previous plane (interior)
   T Ux[5], Uy[5];  // own x- and y- face states of the current plane
   int bad = 0;
 
   for (int k = -1; k <= 16; ++k) {
-    // ---- B: next plane of the own column, publish plane k to LDS
-    if (interior || k + 1 <= 16) load_prim(Ug, P3, P, gh, cx, cy, k + 1, gas, Wp);
+    // ---- next plane of the own column; publish plane k to LDS
+    if (interior || k + 1 <= 16) load_prim(src, col_own, k + 1, gas, Wp);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sP[q][pidx(cx, cy)] = Wc[q];
+    for (int q = 0; q < 5; ++q) sm.P[q][pidx(cx, cy)] = Wc[q];
     if (!interior && k >= 0 && k <= 15) {
       T Wo[5];
-      load_prim(Ug, P3, P, gh, ox, oy, k, gas, Wo);
+      load_prim(src, col_out, k, gas, Wo);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) sP[q][pidx(ox, oy)] = Wo[q];
+      for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
       if (has_edge) {
-        load_prim(Ug, P3, P, gh, ex, ey, k, gas, Wo);
+        load_prim(src, col_edge, k, gas, Wo);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) sP[q][pidx(ex, ey)] = Wo[q];
+        for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
       }
     }
     __syncthreads();
 
-    // ---- H: x/y flux differences of plane k-1 (fluxes written last iteration)
+    // ---- x/y flux differences of plane k-1 (fluxes written last iteration)
     T acc[5];
     if (interior && k >= 1) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        acc[q] = sF[0][q][fxidx(cx + 1, cy)] - sF[0][q][fxidx(cx, cy)];
-        acc[q] = acc[q] + (sF[1][q][fyidx(cx, cy + 1)] - sF[1][q][fyidx(cx, cy)]);
+        acc[q] = sm.F[0][q][fxidx(cx + 1, cy)] - sm.F[0][q][fxidx(cx, cy)];
+        acc[q] = acc[q] + (sm.F[1][q][fyidx(cx, cy + 1)] - sm.F[1][q][fyidx(cx, cy)]);
       }
     }
 
-    // ---- D: half-step face states of the own state cell at plane k
+    // ---- half-step face states of the own state cell at plane k
     if (interior || (k >= 0 && k <= 15)) {
       T Wn[3][2][5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        Wn[0][0][q] = sP[q][pidx(cx - 1, cy)];
-        Wn[0][1][q] = sP[q][pidx(cx + 1, cy)];
-        Wn[1][0][q] = sP[q][pidx(cx, cy - 1)];
-        Wn[1][1][q] = sP[q][pidx(cx, cy + 1)];
+        Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
+        Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
+        Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
+        Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
         Wn[2][0][q] = Wm[q];
         Wn[2][1][q] = Wp[q];
       }
@@ -147,8 +189,8 @@ __global__ __launch_bounds__(kThreads) void mhm_fwd_kernel(const T* __restrict__
       hancock_states(Wc, Wn, gas, first_order != 0, Ut);
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        sS[0][q][sidx(cx, cy)] = Ut[0][1][q];
-        sS[1][q][sidx(cx, cy)] = Ut[1][1][q];
+        sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
+        sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
         Ux[q] = Ut[0][0][q];
         Uy[q] = Ut[1][0][q];
       }
@@ -158,15 +200,21 @@ __global__ __launch_bounds__(kThreads) void mhm_fwd_kernel(const T* __restrict__
           bad += hllc_flux<2>(Uz, Ut[2][0], gas, ws, Fz1);
           if (k >= 1) {
             // complete plane k-1: U^{n+1} = U^n - dt/dx [(x) + (y) + (z)]
-            const int64_t o = (int64_t(k - 1 + gh) * P + (cy + gh)) * P + (cx + gh);
+            const int64_t o = col_own + src.plane(k - 1);
             T Un[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
               const T a = acc[q] + (Fz1[q] - Fz0[q]);
-              Un[q] = Ug[q * P3 + o] - gas.dtdx * a;
-              Og[q * 4096 + ((k - 1) * 16 + cy) * 16 + cx] = Un[q];
+              Un[q] = src.base[o + q * fs] - gas.dtdx * a;
+              out[q * 4096 + ((k - 1) * 16 + cy) * 16 + cx] = Un[q];
             }
             bad += unphysical(Un, gas);
+            if (smax != nullptr) {
+              const double s = cfl_signal_speed(double(Un[0]), double(Un[1]), double(Un[2]), double(Un[3]),
+                                                double(Un[4]), gamma_d);
+              double& m = smax[(k - 1) >> 3];
+              if (s > m) m = s;
+            }
           }
 #pragma unroll
           for (int q = 0; q < 5; ++q) Fz0[q] = Fz1[q];
@@ -177,23 +225,23 @@ __global__ __launch_bounds__(kThreads) void mhm_fwd_kernel(const T* __restrict__
     }
     __syncthreads();
 
-    // ---- F: x and y faces of plane k
+    // ---- x and y faces of plane k
     if (k >= 0 && k <= 15) {
       if (interior || xface16) {
         T L[5], F[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) L[q] = sS[0][q][sidx(cx - 1, cy)];
+        for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
         bad += hllc_flux<0>(L, Ux, gas, ws, F);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) sF[0][q][fxidx(cx, cy)] = F[q];
+        for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
       }
       if (interior || yface16) {
         T L[5], F[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) L[q] = sS[1][q][sidx(cx, cy - 1)];
+        for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
         bad += hllc_flux<1>(L, Uy, gas, ws, F);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) sF[1][q][fyidx(cx, cy)] = F[q];
+        for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
       }
     }
 
@@ -203,8 +251,115 @@ __global__ __launch_bounds__(kThreads) void mhm_fwd_kernel(const T* __restrict__
       Wc[q] = Wp[q];
     }
   }
+  return bad;
+}
 
+// Reduce the per-thread signal-speed maxima of one group to its 8 patch
+// time-steps (patch p = (pz*2 + py)*2 + px); LDS scratch `red` >= 512 doubles.
+// Optionally stores dt_patch[8] and folds the minimum into *dt_min (integer
+// minimum of non-negative doubles: exact and order-independent).
+__device__ __forceinline__ void cfl_epilogue(const double smax[2], double* red, double c_cfl_dx,
+                                             double* __restrict__ dt_patch, unsigned long long* __restrict__ dt_min) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 256) {
+    const int x = tid & 15, y = tid >> 4;
+    const int pxy = (y >> 3) * 2 + (x >> 3), col = (y & 7) * 8 + (x & 7);
+    red[(0 * 4 + pxy) * 64 + col] = smax[0];
+    red[(1 * 4 + pxy) * 64 + col] = smax[1];
+  }
+  __syncthreads();
+  if (tid < 8) {
+    double m = 0.0;
+    for (int i = 0; i < 64; ++i) {
+      const double s = red[((tid >> 2) * 4 + (tid & 3)) * 64 + i];
+      if (s > m) m = s;
+    }
+    const double dt = c_cfl_dx / m;
+    if (dt_patch != nullptr) dt_patch[tid] = dt;
+    if (dt_min != nullptr) atomicMin(dt_min, (unsigned long long)__double_as_longlong(dt));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void set_dt(Gas<T>& gas, const double* dt_dev, double dx) {
+  if (dt_dev != nullptr) {
+    const double dt = *dt_dev;
+    gas.dtdx = T(dt / dx);
+    gas.half_dtdx = T(0.5 * (dt / dx));
+  }
+}
+
+// ------------------------------------------------------------- kernels ----
+
+template <typename T, int kWaves>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_padded_kernel(const T* __restrict__ Upad, T* __restrict__ Uout,
+                                                              int gh, Gas<T> gas, const double* __restrict__ dt_dev,
+                                                              double dx, int first_order, int ws,
+                                                              int* __restrict__ n_bad) {
+  __shared__ Smem<T> sm;
+  set_dt(gas, dt_dev, dx);
+  const int P = 16 + 2 * gh;
+  const int64_t P3 = int64_t(P) * P * P;
+  PaddedSource<T> src{Upad + int64_t(blockIdx.x) * 5 * P3, P, gh};
+  const int bad = process_group<T>(src, Uout + int64_t(blockIdx.x) * 5 * 4096, gas, first_order, ws, sm, nullptr,
+                                   0.0);
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
+}
+
+// Groups are assigned to workgroups so that each XCD (workgroups are dealt
+// to the 8 XCDs round-robin) sweeps a contiguous range of groups: halo cells
+// read from a neighbouring group then mostly hit the same XCD's L2.
+__device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t G) {
+  const int64_t per = (G + 7) / 8;
+  const int64_t g = (b & 7) * per + (b >> 3);
+  return g;
+}
+
+template <typename T, bool kCfl, int kWaves>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_level_kernel(const T* __restrict__ level, T* __restrict__ level_out,
+                                                             LevelGeom geo, Gas<T> gas,
+                                                             const double* __restrict__ dt_dev, double dx,
+                                                             int first_order, int ws, int* __restrict__ n_bad,
+                                                             CflOut cfl, int xcd_order) {
+  __shared__ Smem<T> sm;
+  set_dt(gas, dt_dev, dx);
+  if (kCfl && cfl.reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cfl.reset = 0x7ff0000000000000ull;
+  const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
+  const int64_t g = xcd_order ? xcd_group(blockIdx.x, G) : int64_t(blockIdx.x);
+  if (g >= G) return;  // whole workgroup leaves together (g is uniform)
+  LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
+  double smax[2] = {0.0, 0.0};
+  const int bad = process_group<T>(src, level_out + g * 5 * 4096, gas, first_order, ws, sm,
+                                   kCfl ? smax : nullptr, cfl.gamma);
+  if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
+  if (kCfl)
+    cfl_epilogue(smax, reinterpret_cast<double*>(&sm), cfl.c_cfl_dx,
+                 cfl.dt_patch != nullptr ? cfl.dt_patch + g * 8 : nullptr, cfl.dt_min);
+}
+
+// Waves per SIMD the register allocation must allow: with 5-wave workgroups,
+// 3 (FP64, <= 168 VGPRs) lets two workgroups share a CU (the LDS of two FP64
+// workgroups fits in 160 KB); 5 (FP32, <= 102 VGPRs) lets four share it.
+// The lower settings leave the allocator free (one or three workgroups).
+template <typename T> struct MinWaves;
+template <> struct MinWaves<double> { static constexpr int hi = 3, lo = 2; static constexpr int value = hi; };
+template <> struct MinWaves<float> { static constexpr int hi = 5, lo = 4; static constexpr int value = hi; };
+
+template <typename T, bool kCfl>
+hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
+                                const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
+                                const CflOut& cfl, int variant, hipStream_t stream) {
+  const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
+  const int xcd = (variant & 1) ? 0 : 1;
+  const int64_t blocks = xcd ? ((G + 7) / 8) * 8 : G;
+  if (variant & 2)
+    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::lo>), dim3(unsigned(blocks)), dim3(kThreads), 0,
+                       stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, xcd);
+  else
+    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::hi>), dim3(unsigned(blocks)), dim3(kThreads), 0,
+                       stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, xcd);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -214,14 +369,14 @@ hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost,
                           const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
                           hipStream_t stream) {
   if (n_groups == 0) return hipSuccess;
-  // one workgroup per group; split very large batches into launches of at
-  // most 2^30 workgroups
+  // one workgroup per group; very large batches go in launches of at most
+  // 2^30 workgroups
   const int64_t chunk = int64_t(1) << 30;
   const int P = 16 + 2 * ghost;
   const int64_t P3 = int64_t(P) * P * P;
   for (int64_t g0 = 0; g0 < n_groups; g0 += chunk) {
     const int64_t n = n_groups - g0 < chunk ? n_groups - g0 : chunk;
-    hipLaunchKernelGGL(mhm_fwd_kernel<T>, dim3(unsigned(n)), dim3(kThreads), 0, stream, U_pad + g0 * 5 * P3,
+    hipLaunchKernelGGL((mhm_padded_kernel<T, MinWaves<T>::value>), dim3(unsigned(n)), dim3(kThreads), 0, stream, U_pad + g0 * 5 * P3,
                        U_out + g0 * 5 * 4096, ghost, gas, dt_dev, dx, first_order, ws, n_bad);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -229,9 +384,28 @@ hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost,
   return hipSuccess;
 }
 
+template <typename T>
+hipError_t launch_mhm_level(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
+                            const double* dt_dev, double dx, int first_order, int ws, int* n_bad, const CflOut& cfl,
+                            int variant, hipStream_t stream) {
+  const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
+  if (G == 0) return hipSuccess;
+  if (G > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;
+  const bool with_cfl = cfl.dt_min != nullptr || cfl.dt_patch != nullptr || cfl.reset != nullptr;
+  if (with_cfl)
+    return launch_level_variant<T, true>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, variant,
+                                         stream);
+  return launch_level_variant<T, false>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, variant,
+                                        stream);
+}
+
 template hipError_t launch_mhm_fwd<double>(const double*, double*, int64_t, int, const Gas<double>&,
                                            const double*, double, int, int, int*, hipStream_t);
 template hipError_t launch_mhm_fwd<float>(const float*, float*, int64_t, int, const Gas<float>&,
                                           const double*, double, int, int, int*, hipStream_t);
+template hipError_t launch_mhm_level<double>(const double*, double*, const LevelGeom&, const Gas<double>&,
+                                             const double*, double, int, int, int*, const CflOut&, int, hipStream_t);
+template hipError_t launch_mhm_level<float>(const float*, float*, const LevelGeom&, const Gas<float>&,
+                                            const double*, double, int, int, int*, const CflOut&, int, hipStream_t);
 
 }  // namespace gh

@@ -235,13 +235,15 @@ def test_conservation_on_gpu(hydro):
 
 # ---------------------------------------------------------------- rollout ---
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_rollout_matches_oracle(hydro, dtype):
-    say("rollout", dtype.__name__)
+def test_rollout_matches_oracle(hydro, dtype, fused):
+    say("rollout", dtype.__name__, "fused" if fused else "padded")
     lv = W.shear_layer(64)
     U0 = lv.U.astype(dtype)
     ref, dts, nb = oracle.rollout(U0.astype(np.float64), lv.ng, 3, lv.bc, 4, lv.dx, lv.gamma)
-    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, dtype=torch.float64 if dtype == np.float64 else torch.float32)
+    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, dtype=torch.float64 if dtype == np.float64 else torch.float32,
+                               fused=fused)
     solver.load_state(dev(U0))
     got_dts = []
     for _ in range(4):
@@ -249,6 +251,75 @@ def test_rollout_matches_oracle(hydro, dtype):
         got_dts.append(float(host(solver.dt_min)[0]))
     np.testing.assert_allclose(got_dts, dts, rtol=1e-13 if dtype == np.float64 else 1e-5)
     assert field_scale_error(host(solver.state), ref) <= (1e-12 if dtype == np.float64 else 2e-5)
+
+
+# ------------------------------------------------------ fused level step ---
+
+LEVEL_CASES = {
+    "periodic": ((3, 2, 2), (0, 0, 0, 0, 0, 0)),
+    "outflow-x": ((4, 1, 1), (1, 1, 0, 0, 0, 0)),
+    "mixed": ((2, 3, 2), (1, 0, 0, 1, 1, 1)),
+    "single-group": ((1, 1, 1), (0, 0, 0, 0, 0, 0)),
+}
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", list(LEVEL_CASES))
+def test_level_step_equals_fill_then_advance(hydro, dtype, case):
+    """The fused kernel reads neighbour groups directly; its output is
+    bit-identical to ghost fill + padded step, and within tolerance of the oracle."""
+    say("level step", dtype.__name__, case)
+    ng, bc = LEVEL_CASES[case]
+    rng = np.random.default_rng(5)
+    n = [16 * v for v in ng]
+    shape = (n[2], n[1], n[0])
+    grid = W.conserved(rng.uniform(0.5, 2, shape), *(rng.normal(0, 0.3, shape) for _ in range(3)),
+                       rng.uniform(0.5, 2, shape), 5 / 3)
+    U = W.grid_to_groups(grid).astype(dtype)
+    t = dev(U)
+    dx = 1.0 / n[0]
+    pad = hydro.fill_ghosts(t, ng, 3, bc)
+    a = hydro.advance(pad, 1e-3, dx, 5 / 3)
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b = hydro.advance_level(t, ng, bc, 1e-3, dx, 5 / 3, n_bad=nb)
+    assert torch.equal(a, b)
+    ref, nb_ref = oracle.mhm_step(oracle.fill_ghosts(U.astype(np.float64), ng, 3, bc), 1e-3, dx, 5 / 3)
+    assert field_scale_error(host(b), ref) <= TOL[dtype]
+    assert int(host(nb)[0]) == nb_ref == 0
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_level_cfl_epilogue_bitwise(hydro, dtype):
+    say("level cfl epilogue", dtype.__name__)
+    lv = W.white_noise(64)
+    t = dev(lv.U.astype(dtype))
+    dt_next = torch.full((1,), float("inf"), dtype=torch.float64, device="cuda")
+    dt_patch = torch.empty((lv.n_groups, 8), dtype=torch.float64, device="cuda")
+    reset = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = hydro.advance_level(t, lv.ng, lv.bc, 1e-3, lv.dx, lv.gamma, c_cfl=0.5, dt_next=dt_next,
+                              dt_patch_next=dt_patch, dt_reset=reset)
+    got = host(out)
+    ref = oracle.dt_patch(got.astype(np.float64), lv.dx, lv.gamma, 0.5)   # level storage = ghost 0
+    assert np.array_equal(host(dt_patch), ref)
+    assert host(dt_next)[0] == ref.min()
+    assert host(reset)[0] == np.inf
+    # the standalone CFL kernel on the output agrees bit for bit
+    assert torch.equal(hydro.cfl_dt(out, lv.dx, lv.gamma, 0.5), dt_patch)
+
+
+def test_level_sod_rollout_outflow(hydro):
+    say("level sod rollout")
+    lv = W.sod_tube(128)
+    ref, dts, nb = oracle.rollout(lv.U, lv.ng, 3, lv.bc, 20, lv.dx, lv.gamma)
+    solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, lv.bc)
+    solver.load_state(dev(lv.U))
+    got_dts = []
+    for _ in range(20):
+        solver.step()
+        got_dts.append(float(host(solver.dt_min)[0]))
+    np.testing.assert_allclose(got_dts, dts, rtol=1e-13)
+    assert field_scale_error(host(solver.state), ref) <= 1e-12
+    assert int(host(solver.n_bad)[0]) == nb == 0
 
 
 # ----------------------------------------------------- full-size, sampled ---
@@ -275,3 +346,39 @@ def test_shear_layer_256_sampled(hydro, dtype):
     ref, _ = oracle.mhm_step(opad, dt, lv.dx, lv.gamma)
     got = host(out)[sample]
     assert field_scale_error(got, ref) <= TOL[dtype]
+
+
+# ------------------------------------------------------- launch shapes -----
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_all_launch_shapes_bit_identical(hydro, dtype):
+    say("launch shapes", dtype.__name__)
+    lv = W.white_noise(64)
+    t = dev(lv.U.astype(dtype))
+    tdt = t.dtype
+    saved = hydro.get_variant(tdt)
+    outs = []
+    try:
+        for v in range(hydro.num_variants()):
+            hydro.set_variant(tdt, v)
+            dt_next = torch.full((1,), float("inf"), dtype=torch.float64, device="cuda")
+            o = hydro.advance_level(t, lv.ng, lv.bc, 1e-3, lv.dx, lv.gamma, dt_next=dt_next)
+            outs.append((o.clone(), dt_next.clone()))
+    finally:
+        hydro.set_variant(tdt, saved)
+    for o, d in outs[1:]:
+        assert torch.equal(o, outs[0][0]) and torch.equal(d, outs[0][1])
+
+
+def test_autotune_selects_a_shape(hydro):
+    say("autotune")
+    lv = W.white_noise(64)
+    t = dev(lv.U)
+    saved = hydro.get_variant(torch.float64)
+    try:
+        best, times = hydro.autotune(t, lv.ng, lv.bc, lv.dx, lv.gamma, reps=2)
+        assert 0 <= best < hydro.num_variants()
+        assert hydro.get_variant(torch.float64) == best
+        assert all(x > 0 for x in times) and times[best] == min(times)
+    finally:
+        hydro.set_variant(torch.float64, saved)
