@@ -54,7 +54,7 @@ def kernel_source_sha() -> str:
     """sha256 of the sources of the MHM kernels (changes whenever they do)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("hydro_device.h", "mhm_fwd.hip"):
+    for f in ("hydro_device.h", "mhm_group.h", "mhm_fwd.hip"):
         with open(os.path.join(ROOT, "paper_1712_07070_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -85,6 +85,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--unfused", action="store_true", help="time fill + dt + padded advance per step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--no-amr", action="store_true", help="skip the batched multi-level measurement")
+    ap.add_argument("--amr-coarse-steps", type=int, default=4)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the fwd+adjoint rollout measurements")
+    ap.add_argument("--fd-samples", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="after the run, copy a device buffer of this size (reference for HBM byte counters)")
     return ap.parse_args()
@@ -116,6 +120,152 @@ def run_workload(hydro, torch, lv, dtype, steps, warmup, fused=True, autotune=Tr
     kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     dts = solver.dt_min.cpu().numpy()
     return elapsed, kms, solver, dts, int(solver.n_bad.cpu()[0]), tune
+
+
+def amr_workload(hydro, torch, W, coarse_steps):
+    """Three uneven levels (512 / 1536 / 3072 groups, dx and dt halving per
+    level, Sedov-like blast), FP64: W-cycle coarse steps as one persistent
+    launch per stage vs one launch per level per stage, both graph-captured."""
+    lvs = W.sedov_levels()
+    geo = [(lv.ng, lv.dx, lv.bc) for lv in lvs]
+    states = [torch.from_numpy(lv.U).cuda() for lv in lvs]
+    dt0 = float("inf")
+    for l, (lv, U) in enumerate(zip(lvs, states)):
+        dt0 = min(dt0, float(hydro.cfl_dt(U, lv.dx, lv.gamma, 0.5).min()) * 2 ** l)
+    res = {"workload": "3 levels of 512/1536/3072 groups (8x8x8, 8x8x24, 8x16x24), dx_l = dx_0/2^l, "
+                       "dt_l = dt_0/2^l, 1/2/4 substeps per coarse step, Sedov-like blast, FP64",
+           "dt0": dt0}
+    out = {}
+    for name, batched, graph in (("batched_graph", True, True), ("per_level_graph", False, True),
+                                 ("per_level_eager", False, False), ("batched_eager", True, False)):
+        ml = hydro.MultiLevel(geo, lvs[0].gamma, dt0, batched=batched)
+        for l, U in enumerate(states):
+            ml.load_state(l, U)
+        if batched and "batched_tune" not in res:
+            ent = ml._entries(range(ml.L))
+            best, times = hydro.autotune_batched(ent, lvs[0].gamma, ml.work, reps=3)
+            res["batched_tune"] = {"variant": best, "ms": [round(t, 4) for t in times]}
+            for l, U in enumerate(states):
+                ml.load_state(l, U)
+        n = max(2, coarse_steps - coarse_steps % 2)
+        g = ml.capture(2) if graph else None
+        run = (lambda: g.replay()) if graph else (lambda: (ml.coarse_step(), ml.coarse_step()))
+        run()                                   # warm-up (2 coarse steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n // 2):
+            run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"cell_updates_per_s": ml.cells_per_coarse_step() * n / el, "ms_per_coarse_step": el / n * 1e3,
+                     "n_bad": int(ml.n_bad.cpu()[0])}
+        if g is not None:
+            g.close()
+        res["cells_per_coarse_step"] = ml.cells_per_coarse_step()
+        del ml
+    res.update(out)
+    res["batched_over_per_level"] = out["batched_graph"]["cell_updates_per_s"] / out["per_level_graph"][
+        "cell_updates_per_s"]
+    return res
+
+
+def adjoint_rollout(hydro, torch, lv, dtype, n_steps, k_ckpt, dt, target=None, reps=3):
+    """Time a differentiable rollout (forward with checkpoints, backward with
+    segment replay and the step adjoint); returns timings and the gradient."""
+    U0 = torch.from_numpy(np.ascontiguousarray(lv.U.astype(dtype))).cuda()
+    tgt = None if target is None else torch.from_numpy(np.ascontiguousarray(target.astype(dtype))).cuda()
+    res = []
+    for _ in range(reps + 1):
+        x = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = hydro.Rollout.apply(x, lv.ng, lv.bc, n_steps, dt, lv.dx, lv.gamma, k_ckpt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if tgt is None:
+            gout = torch.ones_like(out)
+            out.backward(gout)
+        else:
+            loss = ((out[:, 0] - tgt) ** 2).sum()
+            loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res.append((t1 - t0, t2 - t1))
+    fwd = float(np.median([r[0] for r in res[1:] or res]))
+    bwd = float(np.median([r[1] for r in res[1:] or res]))
+    cell_steps = lv.n_cells * n_steps
+    return {"t_fwd_ms": fwd * 1e3, "t_bwd_ms": bwd * 1e3, "bwd_over_fwd": bwd / fwd,
+            "cell_steps_per_s_fwd_bwd": cell_steps / (fwd + bwd), "cell_steps_per_s_fwd": cell_steps / fwd}, x.grad
+
+
+def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171223, eps=1e-7):
+    """Central differences of the loss at sampled (cell, field) entries, each
+    perturbed by +-eps, against the adjoint gradient.  A sample is rejected
+    when its central differences at eps and eps/2 disagree (a limiter or
+    wave-speed switch lies within +-eps)."""
+    U0 = lv.U
+    tgt = torch.from_numpy(np.ascontiguousarray(target)).cuda()
+    rng = np.random.default_rng(seed)
+
+    def resid(U):
+        out = hydro.Rollout.apply(torch.from_numpy(U).cuda(), lv.ng, lv.bc, n_steps, dt, lv.dx, lv.gamma, n_steps)
+        return out[:, 0] - tgt
+
+    def central(idx, e):
+        up, um = U0.copy(), U0.copy()
+        up[idx] += e
+        um[idx] -= e
+        rp, rm = resid(up), resid(um)
+        return float(((rp - rm) * (rp + rm)).sum()) / (2 * e)
+
+    g = grad.cpu().numpy()
+    errs, rejected = [], 0
+    for _ in range(samples):
+        idx = tuple(int(rng.integers(0, s)) for s in U0.shape)
+        f1, f2 = central(idx, eps), central(idx, eps / 2)
+        if abs(f1 - f2) > 1e-6 * max(abs(f1), abs(f2), 1e-12):
+            rejected += 1
+            continue
+        errs.append(abs(f1 - g[idx]) / max(abs(f1), 1e-12))
+    errs = np.array(errs) if errs else np.array([np.nan])
+    return {"samples": samples, "rejected": rejected, "accepted": int(samples - rejected), "eps": eps,
+            "max_rel_err": float(np.nanmax(errs)), "median_rel_err": float(np.nanmedian(errs)),
+            "within_1e-6": int(np.sum(errs <= 1e-6))}
+
+
+def differentiation_workloads(hydro, torch, W, fd_samples):
+    out = {}
+    # 128^3 smooth wave, 512 groups, FP64, 8 steps at dt = 0.2 dx, checkpoint every 4
+    lv, target = W.smooth_wave(128)
+    dt = 0.2 * lv.dx
+    r, grad = adjoint_rollout(hydro, torch, lv, np.float64, 8, 4, dt, target)
+    r["workload"] = "smooth wave 128^3 (512 groups), FP64, 8 steps at dt = 0.2 dx, checkpoint every 4, " \
+                    "loss sum (rho_8 - rho_target)^2"
+    r["fd"] = fd_protocol(hydro, torch, lv, target, 8, dt, grad, fd_samples)
+    out["smooth128_f64"] = r
+    del grad
+    torch.cuda.empty_cache()
+    # the same protocol with v and p varying smoothly along every axis (1e-2),
+    # so that no velocity / pressure slope of the initial state is a round-off
+    # difference sitting on the limiter's kink
+    lvs, target_s = W.smooth_wave(128, smooth_vp=0.01)
+    _, grad = adjoint_rollout(hydro, torch, lvs, np.float64, 8, 4, dt, target_s, reps=0)
+    out["smooth128_f64"]["fd_smooth_vp"] = fd_protocol(hydro, torch, lvs, target_s, 8, dt, grad, fd_samples)
+    del grad
+    torch.cuda.empty_cache()
+    # 384^3 turbulence-like state, 13824 groups, FP32, 4 steps at the initial CFL time-step (FP64 reduction)
+    lv = W.turbulence(384).astype(np.float32)
+    U = torch.from_numpy(lv.U).cuda()
+    dt = float(hydro.cfl_dt(U, lv.dx, lv.gamma, 0.5).min())
+    del U
+    r, grad = adjoint_rollout(hydro, torch, lv, np.float32, 4, 4, dt, None, reps=2)
+    r["workload"] = "turbulence 384^3 (13824 groups), FP32 state, 4 steps at the initial CFL time-step " \
+                    "(FP64 reduction), checkpoint every 4, cotangent of ones"
+    r["dt"] = dt
+    out["turb384_f32"] = r
+    del grad
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(lv_factory, seconds):
@@ -199,6 +349,14 @@ def main():
                         "launch_shape": tune32}
     del solver
     torch.cuda.empty_cache()
+    if not args.no_amr:
+        print("bench: batched multi-level", file=sys.stderr, flush=True)
+        extra["amr"] = amr_workload(hydro, torch, W, args.amr_coarse_steps)
+        torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        print("bench: differentiation workloads", file=sys.stderr, flush=True)
+        extra["adjoint"] = differentiation_workloads(hydro, torch, W, args.fd_samples)
+        torch.cuda.empty_cache()
     if args.calibrate_copy > 0:
         # a plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
         # counter readings calibrate the byte counters of the kernels above

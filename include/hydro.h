@@ -118,6 +118,106 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
                         double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl, double* dt_next_dev,
                         double* dt_patch_next_dev, double* dt_reset_dev, void* stream);
 
+/* Adjoint (vector-Jacobian product) of one MHM step -- the transpose of the
+ * Jacobian of hydro_advance / hydro_advance_level with respect to its input
+ * state, applied to a cotangent of its output, at the same scheme, dt, dx,
+ * gamma and theta (dt fixed, not differentiated).  Recomputes the forward
+ * intermediates from the input state.  Derivatives at non-smooth points:
+ * limiter zero when the one-sided differences are not of one strict sign,
+ * otherwise through the argument attaining the minimum (the first on ties);
+ * min/max of wave speeds through the first argument unless the second is
+ * strictly smaller/larger; HLLC through the branch the forward takes.
+ * Deterministic: no floating-point atomics.
+ *
+ * hydro_adjoint_workspace_bytes -- bytes of scratch device memory the two
+ *   adjoint calls need for n_groups groups (level != 0: the level form); the
+ *   caller allocates it (HYDRO_EINVAL on bad arguments).
+ *
+ * hydro_advance_adjoint -- padded form.
+ *   U_pad_dev   [G][5][P^3] the step's input (not modified)
+ *   gU_out_dev  [G][5][16^3] cotangent of the step's output
+ *   gU_pad_dev  [G][5][P^3] receives the cotangent of U_pad (zero on cells
+ *               the step does not read)
+ *   work_dev, work_bytes  scratch of at least
+ *               hydro_adjoint_workspace_bytes(G, dtype, 0) bytes
+ *   No two of U_pad_dev, gU_out_dev, gU_pad_dev, work_dev may overlap.
+ *
+ * hydro_advance_level_adjoint -- level form (adjoint of hydro_advance_level,
+ *   including the ghost fill: cotangents of ghost copies are gathered back to
+ *   the cells they copy, in a fixed order).
+ *   level_dev        [G][5][16^3] the step's input level (not modified)
+ *   g_level_out_dev  [G][5][16^3] cotangent of the step's output level
+ *   g_level_in_dev   [G][5][16^3] receives the cotangent of the input level
+ *   work_dev, work_bytes  at least hydro_adjoint_workspace_bytes(G, dtype, 1)
+ *   dt_dev           optional device double read instead of dt
+ */
+int64_t hydro_adjoint_workspace_bytes(int64_t n_groups, int32_t dtype, int32_t level);
+int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* gU_pad_dev, int64_t n_groups,
+                          int32_t ghost, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                          double theta, void* work_dev, int64_t work_bytes, void* stream);
+int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
+                                int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx,
+                                double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
+                                int64_t work_bytes, void* stream);
+
+/* One level of a batched launch (hydro_advance_batched).  Pointers are
+ * device memory; bc holds the x-, x+, y-, y+, z-, z+ boundary conditions;
+ * dt is this level's time-step (dt_l = dt_0 / 2^l in the W-cycle of Sec. 2.1)
+ * unless dt_dev is non-NULL, in which case it is read from that device double;
+ * dx is this level's cell width. */
+typedef struct {
+  const void* level_dev;  /* [G_l][5][16^3] input level storage */
+  void* level_out_dev;    /* [G_l][5][16^3] output level storage */
+  int32_t ngx, ngy, ngz;  /* group lattice of the level */
+  int32_t bc[6];
+  double dt;
+  double dx;
+  const double* dt_dev;
+} hydro_level_t;
+
+/* hydro_advance_batched -- one MHM step of every group of n_levels levels in
+ * ONE persistent launch (Sec. 2.1: levels of an AMR hierarchy advance with
+ * their own dt; here their groups are pooled).  Workgroups take (level, group)
+ * items from a device work counter until all are done; results are
+ * bit-identical to one hydro_advance_level call per level.
+ *   levels_host  n_levels (1..8) entries in host memory; no output may overlap
+ *                any input or another output
+ *   dtype, gamma, scheme, theta, n_bad_dev: as for hydro_advance
+ *   work_dev     2 device uint32 owned by the caller: zero before the first
+ *                call; every call leaves them zero again.  Launches sharing a
+ *                work_dev must not run concurrently.
+ *   grid         persistent workgroups (0: two per compute unit in FP64,
+ *                four in FP32, capped at the item count)
+ * Launch shapes (process-wide per dtype): bit 0 item order (0: level 0
+ * first, 1: finest level first), bit 1 occupancy target;
+ * hydro_set_batched_variant / hydro_get_batched_variant select and read it,
+ * hydro_autotune_batched times all 4 on the given levels (SYNCHRONOUS; the
+ * outputs are overwritten) and keeps the fastest.
+ */
+int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
+                          int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
+                          void* stream);
+int hydro_set_batched_variant(int32_t dtype, int32_t variant);
+int hydro_get_batched_variant(int32_t dtype);
+int hydro_autotune_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
+                           uint32_t* work_dev, int32_t reps, float* times_ms_host, void* stream);
+
+/* Graph capture of a sequence of library calls (e.g. a level's substeps or
+ * the stages of a coarse step), replayed without per-launch host overhead.
+ *   hydro_graph_begin    start capturing `stream` (a non-NULL hipStream_t)
+ *   hydro_graph_end      stop capturing, instantiate; *graph_exec receives an
+ *                        opaque handle owned by the caller
+ *   hydro_graph_launch   replay the captured work on `stream`
+ *   hydro_graph_destroy  free a handle
+ * Calls made between begin and end are recorded, not executed; kernel
+ * arguments (pointers, dt values) are frozen at capture time, so buffers
+ * must stay allocated while the graph is used.  The library records no
+ * memset nodes. */
+int hydro_graph_begin(void* stream);
+int hydro_graph_end(void* stream, void** graph_exec);
+int hydro_graph_launch(void* graph_exec, void* stream);
+int hydro_graph_destroy(void* graph_exec);
+
 /* hydro_dt -- per-patch CFL time-step, Sec. 2.6 Eq. 2 (the form for MHM):
  * dt_patch = (c_cfl * dx) / max over the patch's 8^3 cells of
  * (|u| + |v| + |w| + 3 c_s), c_s = sqrt(gamma p / rho), evaluated in double

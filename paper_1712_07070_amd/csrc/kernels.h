@@ -31,6 +31,47 @@ hipError_t launch_mhm_level(const T* level, T* level_out, const LevelGeom& geo, 
                             const double* dt_dev, double dx, int first_order, int ws, int* n_bad, const CflOut& cfl,
                             int variant, hipStream_t stream);
 
+// One level of a batched launch: input / output level storage, geometry,
+// the level's dt/dx (or a device dt), and the index of its first work item.
+template <typename T>
+struct BatchLevel {
+  const T* in;
+  T* out;
+  LevelGeom geo;
+  long long g_begin;  // items [g_begin, next level's g_begin) are this level's groups
+  T dtdx, half_dtdx;
+  const double* dt_dev;
+  double dx;
+};
+
+constexpr int kMaxLevels = 8;
+
+template <typename T>
+struct BatchArgs {
+  BatchLevel<T> lv[kMaxLevels];
+  int n_levels;
+  long long total;  // number of work items (groups over all levels)
+};
+
+// work: 2 device uint32, zero before the first launch; every launch leaves
+// them zero.  grid: number of persistent workgroups.
+template <typename T>
+hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
+                              unsigned int* work, int variant, int grid, hipStream_t stream);
+
+// Adjoint of the step (mhm_adj.hip).  Workspace in elements of T:
+// adjoint_workspace_elems(G, level).
+size_t adjoint_workspace_elems(int64_t n_groups, bool level);
+
+template <typename T>
+hipError_t launch_mhm_adjoint_padded(const T* U_pad, const T* g_out, T* g_pad, int64_t G, int ghost, const Gas<T>& gas,
+                                     int first_order, int ws, T* work, hipStream_t stream);
+
+template <typename T>
+hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, const LevelGeom& geo, const Gas<T>& gas,
+                                    const double* dt_dev, double dx, int first_order, int ws, T* work,
+                                    hipStream_t stream);
+
 // Launch shapes of the level step (all give bit-identical results):
 // bit 0 set = groups in plain order instead of XCD-blocked order,
 // bit 1 set = lower occupancy target for the register allocator.

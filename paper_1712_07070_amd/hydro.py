@@ -30,6 +30,13 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 _lib = None
 
 
+class HydroLevel(ctypes.Structure):
+    """hydro_level_t of include/hydro.h."""
+    _fields_ = [("level_dev", ctypes.c_void_p), ("level_out_dev", ctypes.c_void_p), ("ngx", ctypes.c_int32),
+                ("ngy", ctypes.c_int32), ("ngz", ctypes.c_int32), ("bc", ctypes.c_int32 * 6), ("dt", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dt_dev", ctypes.c_void_p)]
+
+
 class HydroError(RuntimeError):
     def __init__(self, fn: str, status: int):
         lib = load()
@@ -60,6 +67,17 @@ def load():
         "hydro_get_variant": (i32, [i32]),
         "hydro_variant_name": (i32, [i32, ctypes.c_char_p, i32]),
         "hydro_autotune": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, i32, P, P]),
+        "hydro_advance_batched": (i32, [P, i32, i32, f64, i32, f64, P, P, i32, P]),
+        "hydro_set_batched_variant": (i32, [i32, i32]),
+        "hydro_get_batched_variant": (i32, [i32]),
+        "hydro_autotune_batched": (i32, [P, i32, i32, f64, P, i32, P, P]),
+        "hydro_graph_begin": (i32, [P]),
+        "hydro_graph_end": (i32, [P, ctypes.POINTER(ctypes.c_void_p)]),
+        "hydro_graph_launch": (i32, [P, P]),
+        "hydro_graph_destroy": (i32, [P]),
+        "hydro_adjoint_workspace_bytes": (i64, [i64, i32, i32]),
+        "hydro_advance_adjoint": (i32, [P, P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, i64, P]),
+        "hydro_advance_level_adjoint": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, i64, P]),
         "hydro_strerror": (ctypes.c_char_p, [i32]),
         "hydro_last_hip_error": (i32, []),
         "hydro_version": (i32, []),
@@ -158,6 +176,55 @@ def advance_level(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt:
     return out
 
 
+def adjoint_workspace(n_groups: int, dtype, level: bool, device=None) -> torch.Tensor:
+    """Scratch buffer for the adjoint calls (bytes from hydro_adjoint_workspace_bytes)."""
+    nbytes = load().hydro_adjoint_workspace_bytes(int(n_groups), F64 if dtype == torch.float64 else F32, int(level))
+    if nbytes < 0:
+        raise HydroError("hydro_adjoint_workspace_bytes", int(nbytes))
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def advance_adjoint(U_pad: torch.Tensor, gU_out: torch.Tensor, dt: float, dx: float, gamma: float,
+                    theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, out: Optional[torch.Tensor] = None,
+                    work: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Cotangent of U_pad given that of the step's output (hydro_advance_adjoint)."""
+    gh = ghost_of(U_pad)
+    G = U_pad.shape[0]
+    if gU_out.dtype != U_pad.dtype or tuple(gU_out.shape) != (G, 5, 16, 16, 16):
+        raise ValueError("gU_out must be [G,5,16,16,16] of the state dtype")
+    if out is None:
+        out = torch.empty_like(U_pad)
+    if work is None:
+        work = adjoint_workspace(G, U_pad.dtype, False, U_pad.device)
+    st = load().hydro_advance_adjoint(_dev(U_pad, "U_pad"), _dev(gU_out, "gU_out"), _dev(out, "out"), G, gh,
+                                      _dtype_code(U_pad), float(dt), float(dx), float(gamma), int(scheme), float(theta),
+                                      _dev(work, "work"), work.numel(), _stream())
+    _check(st, "hydro_advance_adjoint")
+    return out
+
+
+def advance_level_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt: float,
+                          dx: float, gamma: float, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC,
+                          out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None,
+                          dt_dev: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Cotangent of a level's input state given that of its stepped state (hydro_advance_level_adjoint)."""
+    ngx, ngy, ngz = (int(v) for v in ng)
+    G = ngx * ngy * ngz
+    if tuple(level.shape) != (G, 5, 16, 16, 16) or g_out.shape != level.shape or g_out.dtype != level.dtype:
+        raise ValueError("level and g_out must be [G,5,16,16,16] of one dtype")
+    if out is None:
+        out = torch.empty_like(level)
+    if work is None:
+        work = adjoint_workspace(G, level.dtype, True, level.device)
+    b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
+    st = load().hydro_advance_level_adjoint(_dev(level, "level"), _dev(g_out, "g_out"), _dev(out, "out"), ngx, ngy,
+                                            ngz, b, _dtype_code(level), float(dt), float(dx), float(gamma),
+                                            int(scheme), float(theta), _opt(dt_dev, "dt_dev", torch.float64),
+                                            _dev(work, "work"), work.numel(), _stream())
+    _check(st, "hydro_advance_level_adjoint")
+    return out
+
+
 def cfl_dt(U_pad: torch.Tensor, dx: float, gamma: float, c_cfl: float = 0.5, out: Optional[torch.Tensor] = None,
            dt_min: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Per-patch CFL time-step (hydro_dt): returns dt_patch[G, 8] (float64)."""
@@ -190,6 +257,172 @@ def fill_ghosts(level: torch.Tensor, ng: Sequence[int], ghost: int, bc: Sequence
                                   _dtype_code(level), b, _stream())
     _check(st, "hydro_fill_ghosts")
     return out
+
+
+def _levels_array(levels):
+    arr = (HydroLevel * len(levels))()
+    dtype = None
+    for i, L in enumerate(levels):
+        lin, lout, ng, bc, dt, dx = L[:6]
+        dt_dev = L[6] if len(L) > 6 else None
+        dtype = lin.dtype if dtype is None else dtype
+        if lin.dtype != dtype or lout.dtype != dtype or lin.shape != lout.shape:
+            raise ValueError("batched levels must share one dtype and match in/out shapes")
+        G = int(ng[0]) * int(ng[1]) * int(ng[2])
+        if tuple(lin.shape) != (G, 5, 16, 16, 16):
+            raise ValueError("level %d must be [G,5,16,16,16] with G = ngx*ngy*ngz" % i)
+        arr[i].level_dev = _dev(lin, "level")
+        arr[i].level_out_dev = _dev(lout, "level_out")
+        arr[i].ngx, arr[i].ngy, arr[i].ngz = (int(v) for v in ng)
+        for k in range(6):
+            arr[i].bc[k] = int(bc[k])
+        arr[i].dt = float(dt)
+        arr[i].dx = float(dx)
+        arr[i].dt_dev = _opt(dt_dev, "dt_dev", torch.float64)
+    return arr, dtype
+
+
+def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC,
+                    n_bad: Optional[torch.Tensor] = None, grid: int = 0) -> None:
+    """One step of several levels in one persistent launch (hydro_advance_batched).
+
+    levels: sequence of (level_in, level_out, ng, bc, dt, dx[, dt_dev]);
+    work: int32 device tensor of 2 zeros (re-armed by every launch)."""
+    if work.dtype != torch.int32 or work.numel() < 2:
+        raise ValueError("work must hold 2 int32")
+    arr, dtype = _levels_array(levels)
+    st = load().hydro_advance_batched(ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
+                                      float(gamma), int(scheme), float(theta), _opt(n_bad, "n_bad", torch.int32),
+                                      _dev(work, "work"), int(grid), _stream())
+    _check(st, "hydro_advance_batched")
+
+
+def autotune_batched(levels, gamma: float, work: torch.Tensor, reps: int = 5) -> Tuple[int, list]:
+    arr, dtype = _levels_array(levels)
+    times = (ctypes.c_float * 4)()
+    st = load().hydro_autotune_batched(ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
+                                       float(gamma), _dev(work, "work"), int(reps), times, _stream())
+    if st < 0:
+        raise HydroError("hydro_autotune_batched", st)
+    return int(st), list(times)
+
+
+def set_batched_variant(dtype, v: int) -> None:
+    _check(load().hydro_set_batched_variant(F64 if dtype == torch.float64 else F32, int(v)), "hydro_set_batched_variant")
+
+
+def get_batched_variant(dtype) -> int:
+    return int(load().hydro_get_batched_variant(F64 if dtype == torch.float64 else F32))
+
+
+class Graph:
+    """A captured sequence of library calls (hydro_graph_*), replayed on the
+    current stream.  Capture happens on a private non-default stream."""
+
+    def __init__(self):
+        self.handle = None
+        self.stream = torch.cuda.Stream()
+
+    def capture(self, fn) -> "Graph":
+        lib = load()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(self.stream):
+            _check(lib.hydro_graph_begin(self.stream.cuda_stream), "hydro_graph_begin")
+            err = None
+            try:
+                fn()
+            except BaseException as e:  # always end the capture
+                err = e
+            h = ctypes.c_void_p()
+            st = lib.hydro_graph_end(self.stream.cuda_stream, ctypes.byref(h))
+            if err is not None:
+                if st == HYDRO_OK:
+                    lib.hydro_graph_destroy(h)
+                raise err
+            _check(st, "hydro_graph_end")
+        self.handle = h
+        torch.cuda.synchronize()
+        return self
+
+    def replay(self) -> None:
+        _check(load().hydro_graph_launch(self.handle, _stream()), "hydro_graph_launch")
+
+    def close(self) -> None:
+        if self.handle is not None:
+            load().hydro_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MultiLevel:
+    """Levels of an AMR-shaped workload advanced in the W-cycle order of
+    Sec. 2.1 with dt_l = dt_0 / 2^l: per coarse step, level l takes 2^l
+    substeps; stage s of the 2^(L-1) stages advances every level l with
+    s % 2^(L-1-l) == 0.  batched=True runs each stage as one persistent launch
+    over the union of the stage's groups; batched=False launches
+    hydro_advance_level once per level per stage.  Levels are independent
+    periodic bricks (no coarse-fine coupling)."""
+
+    def __init__(self, levels, gamma: float, dt0: float, dtype=torch.float64, batched: bool = True,
+                 theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, device=None):
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        self.geo = [(tuple(int(v) for v in lv[0]), float(lv[1]), tuple(int(v) for v in lv[2])) for lv in levels]
+        self.L = len(self.geo)
+        self.gamma, self.dt0, self.batched = float(gamma), float(dt0), bool(batched)
+        self.theta, self.scheme = float(theta), int(scheme)
+        self.bufs = [[torch.empty((ng[0] * ng[1] * ng[2], 5, 16, 16, 16), dtype=dtype, device=dev) for _ in range(2)]
+                     for ng, _, _ in self.geo]
+        self.cur = [0] * self.L
+        self.work = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.n_bad = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def load_state(self, l: int, U: torch.Tensor):
+        self.bufs[l][self.cur[l]].copy_(U)
+
+    def state(self, l: int) -> torch.Tensor:
+        return self.bufs[l][self.cur[l]]
+
+    def cells_per_coarse_step(self) -> int:
+        return sum(ng[0] * ng[1] * ng[2] * 4096 * 2 ** l for l, (ng, _, _) in enumerate(self.geo))
+
+    def stage_levels(self, s: int):
+        return [l for l in range(self.L) if s % 2 ** (self.L - 1 - l) == 0]
+
+    def _entries(self, lvls):
+        out = []
+        for l in lvls:
+            ng, dx, bc = self.geo[l]
+            out.append((self.bufs[l][self.cur[l]], self.bufs[l][1 - self.cur[l]], ng, bc, self.dt0 / 2 ** l, dx))
+        return out
+
+    def stage(self, s: int) -> None:
+        lvls = self.stage_levels(s)
+        ent = self._entries(lvls)
+        if self.batched:
+            advance_batched(ent, self.gamma, self.work, self.theta, self.scheme, n_bad=self.n_bad)
+        else:
+            for lin, lout, ng, bc, dt, dx in ent:
+                advance_level(lin, ng, bc, dt, dx, self.gamma, self.theta, self.scheme, out=lout, n_bad=self.n_bad)
+        for l in lvls:
+            self.cur[l] = 1 - self.cur[l]
+
+    def coarse_step(self) -> None:
+        for s in range(2 ** (self.L - 1)):
+            self.stage(s)
+
+    def capture(self, n_coarse: int = 2) -> Graph:
+        """Graph of n_coarse coarse steps (an even count returns every level's
+        state to the buffer it started in, so the graph can be replayed)."""
+        start = list(self.cur)
+        g = Graph().capture(lambda: [self.coarse_step() for _ in range(n_coarse)])
+        if self.cur != start:
+            raise ValueError("captured steps must return every level to its starting buffer")
+        return g
 
 
 # ------------------------------------------------------------- launch shapes --
@@ -319,3 +552,47 @@ class LevelSolver:
             if events is not None:
                 events[1].record(stream)
         self.cur = 1 - self.cur
+
+
+# ------------------------------------------------------ differentiable rollout --
+
+class Rollout(torch.autograd.Function):
+    """n_steps fixed-dt MHM steps of a level as a differentiable function of
+    the initial state.  Forward keeps a checkpoint every k_ckpt steps; backward
+    replays each segment from its checkpoint and applies the hand-written
+    step adjoint (hydro_advance_level_adjoint) from the last step back.
+
+    Rollout.apply(U0, ng, bc, n_steps, dt, dx, gamma, k_ckpt, theta, scheme) -> U_N"""
+
+    @staticmethod
+    def forward(ctx, U0, ng, bc, n_steps, dt, dx, gamma, k_ckpt=4, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+        ng, bc = tuple(int(v) for v in ng), tuple(int(v) for v in bc)
+        k = max(1, int(k_ckpt))
+        ckpts = []
+        cur = U0.detach().contiguous()
+        nxt = torch.empty_like(cur)
+        for n in range(int(n_steps)):
+            if n % k == 0:
+                ckpts.append(cur.clone())
+            advance_level(cur, ng, bc, dt, dx, gamma, theta, scheme, out=nxt)
+            cur, nxt = nxt, cur
+        ctx.save_for_backward(*ckpts)
+        ctx.args = (ng, bc, int(n_steps), float(dt), float(dx), float(gamma), k, float(theta), int(scheme))
+        return cur.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        ng, bc, n_steps, dt, dx, gamma, k, theta, scheme = ctx.args
+        ckpts = ctx.saved_tensors
+        g = g.contiguous().clone()
+        gin = torch.empty_like(g)
+        work = adjoint_workspace(g.shape[0], g.dtype, True, g.device)
+        for s in range((n_steps + k - 1) // k - 1, -1, -1):
+            n0, n1 = s * k, min((s + 1) * k, n_steps)
+            states = [ckpts[s]]
+            for n in range(n0, n1 - 1):          # replay the segment
+                states.append(advance_level(states[-1], ng, bc, dt, dx, gamma, theta, scheme))
+            for n in range(n1 - 1, n0 - 1, -1):
+                advance_level_adjoint(states[n - n0], g, ng, bc, dt, dx, gamma, theta, scheme, out=gin, work=work)
+                g, gin = gin, g
+        return (g,) + (None,) * 9

@@ -185,16 +185,25 @@ def sedov_levels(ng_levels=AMR_LEVEL_GROUPS, dx0: float = 1.0 / 128, gamma: floa
 
 
 def smooth_wave(n: int = 128, config_id: int = 4, gamma: float = 5.0 / 3.0, amp: float = 0.01,
-                v=(0.1, 0.05, 0.0), p0: float = 1.0) -> Tuple[Level, np.ndarray]:
+                v=(0.1, 0.05, 0.0), p0: float = 1.0, smooth_vp: float = 0.0) -> Tuple[Level, np.ndarray]:
     """Workload 4: rho = 1 + amp sin(2 pi (x+y+z)), uniform v and p (an exact
     translating solution).  Returns the level and a seeded target density
-    rho_target = rho_0 + 0.01 N(0, 1) in group-major [G, 16, 16, 16]."""
+    rho_target = rho_0 + 0.01 N(0, 1) in group-major [G, 16, 16, 16].
+
+    smooth_vp > 0 adds smooth variations of that amplitude to v and p, each
+    varying along every axis (a variant for derivative checks: uniform fields
+    put every velocity / pressure slope on the limiter's kink)."""
     r = rng(config_id)
     dx = 1.0 / n
     x = cell_centres(n, dx)
     Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
     rho = 1.0 + amp * np.sin(2.0 * np.pi * (X + Y + Z))
-    U = grid_to_groups(conserved(rho, v[0], v[1], v[2], p0, gamma))
+    tp = 2.0 * np.pi
+    vx = v[0] + smooth_vp * np.sin(tp * (X + 2 * Y + Z) + 0.3)
+    vy = v[1] + smooth_vp * np.cos(tp * (2 * X - Y + Z) + 0.7)
+    vz = v[2] + smooth_vp * np.sin(tp * (X + Y - 2 * Z) + 1.1)
+    pp = p0 + smooth_vp * np.cos(tp * (X + Y - Z) + 0.5)
+    U = grid_to_groups(conserved(rho, vx, vy, vz, pp, gamma))
     target = rho + 0.01 * r.normal(0.0, 1.0, rho.shape)
     tgt = grid_to_groups(target[None])[:, 0]
     return Level(U, (n // N,) * 3, dx, gamma, meta={"name": "smooth-wave", "n": n, "v": v}), tgt

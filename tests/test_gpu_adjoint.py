@@ -1,0 +1,226 @@
+"""GPU adjoint: the hand-written VJP of the MHM step against the oracle.
+
+The oracle gives exact Jacobian-vector products J v (dual numbers through its
+own step); the HIP path gives J^T w.  For random v, w the two sides of
+<J v, w> = <v, J^T w> must agree to round-off (FP64: 1e-11 relative).  States
+vary smoothly along every axis so that no limiter / wave-speed branch sits at
+a switch (where the two codes could legitimately take different one-sided
+derivatives).  The rollout gradient is also checked against central finite
+differences of the GPU forward and for bitwise invariance under the
+checkpoint interval."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_07070_amd import workloads as W
+from tests.test_oracle_scheme import smooth_all_fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+G53 = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1712_07070_amd import hydro as h
+    h.load()
+    return h
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(a), abs(b), 1e-300)
+
+
+STEP_CASES = {
+    "full": dict(theta=1.5, scheme=1),
+    "first-order": dict(theta=1.5, scheme=1 | (1 << 10)),
+    "davis": dict(theta=1.5, scheme=1 | (1 << 8)),
+    "theta=1": dict(theta=1.0, scheme=1),
+    "theta=2": dict(theta=2.0, scheme=1),
+}
+
+
+@pytest.mark.parametrize("case", list(STEP_CASES))
+@pytest.mark.parametrize("state", ["smooth", "white-noise"])
+def test_step_adjoint_dot_product(hydro, case, state):
+    say("step adjoint", case, state)
+    if state == "smooth":
+        U, ng, dx = smooth_all_fields(32)
+    else:
+        lv = W.white_noise(32)
+        U, ng, dx = lv.U, lv.ng, lv.dx
+    kw = STEP_CASES[case]
+    pad = oracle.fill_ghosts(U, ng, 3, (0,) * 6)
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=pad.shape)
+    w = rng.normal(size=(pad.shape[0], 5, 16, 16, 16))
+    dt = 0.3 * dx
+    _, Jv, _ = oracle.mhm_step_jvp(pad, v, dt, dx, G53, kw["theta"], kw["scheme"])
+    JTw = host(hydro.advance_adjoint(dev(pad), dev(w), dt, dx, G53, kw["theta"], kw["scheme"]))
+    lhs, rhs = float(np.sum(Jv * w)), float(np.sum(v * JTw))
+    assert rel(lhs, rhs) <= 1e-11, (lhs, rhs)
+
+
+def test_step_adjoint_elementwise(hydro):
+    """(J^T w)_j = <J e_j, w> for input elements in the interior, on the
+    group boundary, in the 2-deep ghost slab and on a ghost edge."""
+    say("step adjoint elementwise")
+    U, ng, dx = smooth_all_fields(16)
+    pad = oracle.fill_ghosts(U, ng, 3, (0,) * 6)
+    w = np.random.default_rng(2).normal(size=(1, 5, 16, 16, 16))
+    dt = 0.3 * dx
+    JTw = host(hydro.advance_adjoint(dev(pad), dev(w), dt, dx, G53))
+    g = 3
+    picks = [(0, 7 + g, 5 + g, 9 + g), (4, 0 + g, 8 + g, 3 + g), (1, 15 + g, 15 + g, 15 + g), (2, -1 + g, 4 + g, 6 + g),
+             (3, 8 + g, -2 + g, 10 + g), (0, -1 + g, -1 + g, 7 + g), (4, 17 + g, 3 + g, 3 + g), (1, -3 + g, 4 + g, 4 + g)]
+    for q, z, y, x in picks:
+        e = np.zeros_like(pad)
+        e[0, q, z, y, x] = 1.0
+        _, Je, _ = oracle.mhm_step_jvp(pad, e, dt, dx, G53)
+        ref = float(np.sum(Je * w))
+        got = float(JTw[0, q, z, y, x])
+        assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), ((q, z, y, x), got, ref)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (1, 1, 0, 0, 1, 0)])
+def test_level_adjoint_dot_product(hydro, bc):
+    say("level adjoint", bc)
+    U, ng, dx = smooth_all_fields(32)
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=U.shape)
+    w = rng.normal(size=U.shape)
+    dt = 0.3 * dx
+    _, Jv, _ = oracle.rollout_jvp(U, v, ng, 3, bc, 1, dt, dx, G53)
+    JTw = host(hydro.advance_level_adjoint(dev(U), dev(w), ng, bc, dt, dx, G53))
+    lhs, rhs = float(np.sum(Jv * w)), float(np.sum(v * JTw))
+    assert rel(lhs, rhs) <= 1e-11, (lhs, rhs)
+
+
+def test_level_adjoint_single_group_and_two_groups(hydro):
+    """1 and 2 groups along an axis: periodic neighbours coincide with the group itself."""
+    say("level adjoint small lattices")
+    for n, ngs in ((16, (1, 1, 1)), (32, (2, 1, 1))):
+        x = (np.arange(n) + 0.5) / n
+        y = (np.arange(16) + 0.5) / 16
+        Z, Y, X = np.meshgrid(y, y, x, indexing="ij")
+        tp = 2 * np.pi
+        rho = 1 + 0.1 * np.sin(tp * (X + Y + Z) + 0.2)
+        u = 0.2 + 0.05 * np.cos(tp * (X - Y + 2 * Z) + 0.4)
+        # every field varies along every axis (a field constant along an axis sits on the limiter kink)
+        grid = W.conserved(rho, u, 0.1 * np.sin(tp * (X + 2 * Y + Z) + 0.9),
+                           0.05 + 0.02 * np.cos(tp * (Y + X - Z) + 0.3),
+                           1 + 0.05 * np.sin(tp * (X + Y - Z) + 0.1), G53)
+        U = W.grid_to_groups(grid)
+        rng = np.random.default_rng(n)
+        v, w = rng.normal(size=U.shape), rng.normal(size=U.shape)
+        dt = 0.2 / n
+        _, Jv, _ = oracle.rollout_jvp(U, v, ngs, 3, (0,) * 6, 1, dt, 1 / n, G53)
+        JTw = host(hydro.advance_level_adjoint(dev(U), dev(w), ngs, (0,) * 6, dt, 1 / n, G53))
+        assert rel(float(np.sum(Jv * w)), float(np.sum(v * JTw))) <= 1e-11
+
+
+def test_adjoint_fp32(hydro):
+    say("adjoint fp32")
+    U, ng, dx = smooth_all_fields(32)
+    U32 = U.astype(np.float32)
+    rng = np.random.default_rng(4)
+    v = rng.normal(size=U.shape)
+    w = rng.normal(size=U.shape).astype(np.float32)
+    dt = 0.3 * dx
+    _, Jv, _ = oracle.rollout_jvp(U32.astype(np.float64), v, ng, 3, (0,) * 6, 1, dt, dx, G53)
+    JTw = host(hydro.advance_level_adjoint(dev(U32), dev(w), ng, (0,) * 6, dt, dx, G53)).astype(np.float64)
+    assert rel(float(np.sum(Jv * w)), float(np.sum(v * JTw))) <= 1e-4
+
+
+def test_adjoint_deterministic(hydro):
+    say("adjoint determinism")
+    U, ng, dx = smooth_all_fields(32)
+    w = dev(np.random.default_rng(5).normal(size=U.shape))
+    t = dev(U)
+    outs = [hydro.advance_level_adjoint(t, w, ng, (0,) * 6, 1e-3, dx, G53).clone() for _ in range(3)]
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+
+
+# --------------------------------------------------------------- rollout ----
+
+def _loss_grad(hydro, U0, ng, dt, dx, target, n_steps, k):
+    x = dev(U0).requires_grad_(True)
+    out = hydro.Rollout.apply(x, ng, (0,) * 6, n_steps, dt, dx, G53, k)
+    loss = ((out[:, 0] - target) ** 2).sum()
+    loss.backward()
+    return float(loss), x.grad.detach()
+
+
+def test_rollout_gradient_matches_oracle_and_is_checkpoint_invariant(hydro):
+    say("rollout gradient")
+    U0, ng, dx = smooth_all_fields(32)
+    rng = np.random.default_rng(6)
+    target = dev(U0[:, 0] + 0.01 * rng.normal(size=U0[:, 0].shape))
+    dt = 0.2 * dx
+    grads = {}
+    for k in (1, 2, 4, 8):
+        _, grads[k] = _loss_grad(hydro, U0, ng, dt, dx, target, 8, k)
+    for k in (2, 4, 8):
+        assert torch.equal(grads[k], grads[1]), k
+    # dL/d(eps) along v from the oracle's exact JVP of the same rollout
+    v = rng.normal(size=U0.shape)
+    UN, Jv, _ = oracle.rollout_jvp(U0, v, ng, 3, (0,) * 6, 8, dt, dx, G53)
+    dLdv = float(np.sum(2 * (UN[:, 0] - host(target)) * Jv[:, 0]))
+    got = float(np.sum(host(grads[1]) * v))
+    assert rel(dLdv, got) <= 1e-10, (dLdv, got)
+
+
+def test_rollout_gradient_central_differences(hydro):
+    """Gradient entries against central differences of the GPU forward.  A
+    sample whose central differences at eps and eps/2 disagree (a limiter or
+    wave-speed switch lies within +-eps, where a one-sided slope changes) is
+    rejected; accepted samples agree to 1e-6."""
+    say("rollout fd")
+    U0, ng, dx = smooth_all_fields(32)
+    rng = np.random.default_rng(7)
+    target = dev(U0[:, 0] + 0.01 * rng.normal(size=U0[:, 0].shape))
+    dt = 0.2 * dx
+    _, grad = _loss_grad(hydro, U0, ng, dt, dx, target, 4, 2)
+    grad = host(grad)
+
+    def resid(U):
+        out = hydro.Rollout.apply(dev(U), ng, (0,) * 6, 4, dt, dx, G53, 2)
+        return out[:, 0] - target
+
+    def central(idx, eps):
+        up, um = U0.copy(), U0.copy()
+        up[idx] += eps
+        um[idx] -= eps
+        rp, rm = resid(up), resid(um)
+        # L+ - L- = sum (r+ - r-)(r+ + r-): avoids cancelling two large sums
+        return float(((rp - rm) * (rp + rm)).sum()) / (2 * eps)
+
+    accepted, errs = 0, []
+    for _ in range(32):
+        idx = tuple(int(rng.integers(0, s)) for s in U0.shape)
+        eps = 1e-6 * max(1.0, abs(U0[idx]))
+        f1, f2 = central(idx, eps), central(idx, eps / 2)
+        if abs(f1 - f2) > 1e-7 * max(abs(f1), abs(f2), 1e-8):
+            continue
+        accepted += 1
+        errs.append(abs(f2 - grad[idx]) / max(abs(f2), 1e-8))
+    assert accepted >= 24, accepted
+    assert max(errs) <= 1e-6, max(errs)

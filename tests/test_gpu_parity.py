@@ -382,3 +382,106 @@ def test_autotune_selects_a_shape(hydro):
         assert all(x > 0 for x in times) and times[best] == min(times)
     finally:
         hydro.set_variant(torch.float64, saved)
+
+
+# ------------------------------------------------- batched multi-level -----
+
+def _amr_levels(scale_ng=((2, 2, 2), (2, 2, 6), (2, 4, 6)), dtype=np.float64):
+    lvs = W.sedov_levels(scale_ng, dx0=1.0 / 32)
+    return [lv.astype(dtype) for lv in lvs]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batched_equals_per_level(hydro, dtype):
+    say("batched vs per-level", dtype.__name__)
+    lvs = _amr_levels(dtype=dtype)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    ins = [dev(lv.U) for lv in lvs]
+    dt0 = 0.3 * min(float(oracle.dt_patch(lv.U.astype(np.float64), lv.dx, lv.gamma).min()) * 2 ** l
+                    for l, lv in enumerate(lvs))
+    ref = [hydro.advance_level(t, lv.ng, lv.bc, dt0 / 2 ** l, lv.dx, lv.gamma) for l, (t, lv) in enumerate(zip(ins, lvs))]
+    work = torch.zeros(2, dtype=torch.int32, device="cuda")
+    saved = hydro.get_batched_variant(tdt)
+    try:
+        for v in range(4):
+            hydro.set_batched_variant(tdt, v)
+            outs = [torch.empty_like(t) for t in ins]
+            nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+            hydro.advance_batched([(t, o, lv.ng, lv.bc, dt0 / 2 ** l, lv.dx) for l, (t, o, lv) in
+                                   enumerate(zip(ins, outs, lvs))], lvs[0].gamma, work, n_bad=nb)
+            for o, r in zip(outs, ref):
+                assert torch.equal(o, r)
+            assert int(host(nb)[0]) == 0
+            assert host(work).tolist() == [0, 0]       # the queue re-arms itself
+    finally:
+        hydro.set_batched_variant(tdt, saved)
+    # and the per-level result is the oracle's
+    for l, (lv, r) in enumerate(zip(lvs, ref)):
+        o, _ = oracle.mhm_step(oracle.fill_ghosts(lv.U.astype(np.float64), lv.ng, 3, lv.bc), dt0 / 2 ** l, lv.dx,
+                               lv.gamma)
+        assert field_scale_error(host(r), o) <= TOL[dtype]
+
+
+def test_batched_small_grid_and_uneven_items(hydro):
+    """A persistent grid much smaller than the item count still covers every item once."""
+    say("batched small grid")
+    lvs = _amr_levels()
+    ins = [dev(lv.U) for lv in lvs]
+    work = torch.zeros(2, dtype=torch.int32, device="cuda")
+    a = [torch.empty_like(t) for t in ins]
+    b = [torch.empty_like(t) for t in ins]
+    ent = lambda outs: [(t, o, lv.ng, lv.bc, 1e-4 / 2 ** l, lv.dx) for l, (t, o, lv) in enumerate(zip(ins, outs, lvs))]
+    hydro.advance_batched(ent(a), 5 / 3, work, grid=3)
+    hydro.advance_batched(ent(b), 5 / 3, work, grid=0)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_wcycle_graph_replays_match_eager(hydro):
+    """Graph replays of two coarse steps equal the eager W-cycle, with eager
+    work and synchronizations between replays; batched and per-level agree."""
+    say("w-cycle graph")
+    lvs = _amr_levels()
+    geo = [(lv.ng, lv.dx, lv.bc) for lv in lvs]
+    dt0 = 0.3 * min(float(oracle.dt_patch(lv.U, lv.dx, lv.gamma).min()) * 2 ** l for l, lv in enumerate(lvs))
+    runs = {}
+    for name, batched, graph in (("eager-batched", True, False), ("eager-level", False, False),
+                                 ("graph-batched", True, True), ("graph-level", False, True)):
+        ml = hydro.MultiLevel(geo, 5 / 3, dt0, batched=batched)
+        for l, lv in enumerate(lvs):
+            ml.load_state(l, dev(lv.U))
+        snaps = []
+        if graph:
+            g = ml.capture(2)
+            for _ in range(3):
+                g.replay()
+                torch.cuda.synchronize()
+                snaps.append([ml.state(l).clone() for l in range(3)])
+                _ = torch.ones(1000, device="cuda").sum()       # unrelated eager work between replays
+            g.close()
+        else:
+            for _ in range(3):
+                ml.coarse_step()
+                ml.coarse_step()
+                snaps.append([ml.state(l).clone() for l in range(3)])
+        runs[name] = snaps
+        assert int(host(ml.n_bad)[0]) == 0
+    for name in runs:
+        for a, b in zip(runs[name], runs["eager-level"]):
+            assert all(torch.equal(x, y) for x, y in zip(a, b)), name
+
+
+def test_sedov_levels_mirror_symmetric(hydro):
+    say("sedov symmetry")
+    lvs = _amr_levels()
+    lv = lvs[1]
+    t = dev(lv.U)
+    dt = 0.3 * float(oracle.dt_patch(lv.U, lv.dx, lv.gamma).min())
+    out = t
+    for _ in range(4):
+        out = hydro.advance_level(out, lv.ng, lv.bc, dt, lv.dx, lv.gamma)
+    grid = W.groups_to_grid(host(out), lv.ng)
+    for ax in (1, 2, 3):          # z, y, x axes of the grid
+        m = np.flip(grid, axis=ax).copy()
+        m[4 - ax] *= -1           # the momentum along that axis changes sign
+        assert field_scale_error(m, grid) <= 1e-12
