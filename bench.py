@@ -198,7 +198,7 @@ def adjoint_rollout(hydro, torch, lv, dtype, n_steps, k_ckpt, dt, target=None, r
             "cell_steps_per_s_fwd_bwd": cell_steps / (fwd + bwd), "cell_steps_per_s_fwd": cell_steps / fwd}, x.grad
 
 
-def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171223, eps=1e-7):
+def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171223, eps=1e-6):
     """Central differences of the loss at sampled (cell, field) entries, each
     perturbed by +-eps, against the adjoint gradient.  A sample is rejected
     when its central differences at eps and eps/2 disagree (a limiter or

@@ -130,8 +130,10 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
  * Deterministic: no floating-point atomics.
  *
  * hydro_adjoint_workspace_bytes -- bytes of scratch device memory the two
- *   adjoint calls need for n_groups groups (level != 0: the level form); the
- *   caller allocates it (HYDRO_EINVAL on bad arguments).
+ *   adjoint calls need for n_groups groups (level != 0: the level form, which
+ *   stages each group's reachable-cell cotangents before the gather; the
+ *   padded form needs none and returns 0); the caller allocates it
+ *   (HYDRO_EINVAL on bad arguments).
  *
  * hydro_advance_adjoint -- padded form.
  *   U_pad_dev   [G][5][P^3] the step's input (not modified)
@@ -139,7 +141,8 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
  *   gU_pad_dev  [G][5][P^3] receives the cotangent of U_pad (zero on cells
  *               the step does not read)
  *   work_dev, work_bytes  scratch of at least
- *               hydro_adjoint_workspace_bytes(G, dtype, 0) bytes
+ *               hydro_adjoint_workspace_bytes(G, dtype, 0) bytes (may be NULL
+ *               when that is 0)
  *   No two of U_pad_dev, gU_out_dev, gU_pad_dev, work_dev may overlap.
  *
  * hydro_advance_level_adjoint -- level form (adjoint of hydro_advance_level,
@@ -183,17 +186,23 @@ typedef struct {
  *   levels_host  n_levels (1..8) entries in host memory; no output may overlap
  *                any input or another output
  *   dtype, gamma, scheme, theta, n_bad_dev: as for hydro_advance
- *   work_dev     2 device uint32 owned by the caller: zero before the first
- *                call; every call leaves them zero again.  Launches sharing a
- *                work_dev must not run concurrently.
+ *   work_dev     HYDRO_BATCH_WORK_WORDS device uint32 owned by the caller:
+ *                zero before the first call; every call leaves them zero
+ *                again.  Launches sharing a work_dev must not run
+ *                concurrently.
  *   grid         persistent workgroups (0: two per compute unit in FP64,
  *                four in FP32, capped at the item count)
- * Launch shapes (process-wide per dtype): bit 0 item order (0: level 0
- * first, 1: finest level first), bit 1 occupancy target;
+ * Launch shapes (process-wide per dtype, HYDRO_BATCHED_VARIANTS of them):
+ * bit 0 item order (0: level 0 first, 1: finest level first), bit 1
+ * occupancy target, bit 2 queues (0: one queue; 1: one queue per XCD, each
+ * serving one residue class of items mod 8, with stealing when it runs dry);
  * hydro_set_batched_variant / hydro_get_batched_variant select and read it,
- * hydro_autotune_batched times all 4 on the given levels (SYNCHRONOUS; the
- * outputs are overwritten) and keeps the fastest.
+ * hydro_autotune_batched times all of them on the given levels (SYNCHRONOUS;
+ * the outputs are overwritten; times_ms_host receives HYDRO_BATCHED_VARIANTS
+ * floats) and keeps the fastest.
  */
+#define HYDRO_BATCH_WORK_WORDS 16
+#define HYDRO_BATCHED_VARIANTS 8
 int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
                           int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
                           void* stream);
@@ -244,6 +253,21 @@ int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dty
  */
 int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                       int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream);
+
+/* hydro_gather_ghost_adjoint -- the adjoint (transpose) of hydro_fill_ghosts:
+ * every level cell receives the sum of the padded cotangents at all padded
+ * positions that copy it (its own interior position and each ghost position
+ * the fill maps to it), summed in a fixed order (deterministic).  With
+ * hydro_advance_adjoint it gives the cotangent of the level state of a step
+ * taken as hydro_fill_ghosts + hydro_advance (the reverse of Sec. 3.4's ghost
+ * preparation; the adjoint itself is not in the paper).
+ *   g_pad_dev    [G][5][P^3] padded cotangents, G = ngx*ngy*ngz (not modified)
+ *   g_level_dev  [G][5][16^3] output (overwritten), must not overlap g_pad_dev
+ *   ghost        0..16, as given to hydro_fill_ghosts
+ *   bc_host      6 ints on the host, as given to hydro_fill_ghosts
+ */
+int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                               int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream);
 
 /* Launch shapes of hydro_advance_level.  Every shape runs the same per-cell
  * arithmetic in the same order, so all give bit-identical results; they

@@ -22,10 +22,10 @@ thread_local int g_last_hip_error = 0;
 
 // Launch shape of the level step per dtype (index into the variants of
 // mhm_fwd.hip); set by hydro_set_variant or hydro_autotune, process-wide.
-std::atomic<int> g_level_variant[2] = {{1}, {2}};  // measured defaults: FP64 plain order, FP32 XCD-blocked
+std::atomic<int> g_level_variant[2] = {{3}, {2}};  // measured defaults: FP64 plain order, FP32 XCD-blocked; both low occupancy
 // Launch shape of the batched kernel per dtype (bit 0: item order, bit 1:
-// occupancy target).
-std::atomic<int> g_batched_variant[2] = {{0}, {0}};
+// occupancy target, bit 2: per-XCD queues).
+std::atomic<int> g_batched_variant[2] = {{6}, {6}};  // per-XCD queues, low occupancy
 
 // Compute units of the current device (persistent-grid size), cached per device.
 int device_cus() {
@@ -50,6 +50,7 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 size_t dtype_size(int32_t dtype) { return dtype == HYDRO_F64 ? 8 : 4; }
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (na == 0 || nb == 0) return false;
   const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
   return pa < pb + nb && pb < pa + na;
 }
@@ -320,7 +321,7 @@ int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, in
 
 int hydro_set_batched_variant(int32_t dtype, int32_t variant) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
-  if (variant < 0 || variant >= 4) return HYDRO_EINVAL;
+  if (variant < 0 || variant >= gh::kBatchedVariants) return HYDRO_EINVAL;
   g_batched_variant[dtype].store(variant);
   return HYDRO_OK;
 }
@@ -346,7 +347,7 @@ int hydro_autotune_batched(const hydro_level_t* levels_host, int32_t n_levels, i
   }
   int best = -1, status = HYDRO_OK;
   float best_ms = 0.0f;
-  for (int var = 0; var < 4 && status == HYDRO_OK; ++var) {
+  for (int var = 0; var < gh::kBatchedVariants && status == HYDRO_OK; ++var) {
     g_batched_variant[dtype].store(var);
     status = hydro_advance_batched(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr,
                                    work_dev, 0, stream);
@@ -422,11 +423,10 @@ int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* g
   if (!finite_pos(dt) || !finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
     return HYDRO_EINVAL;
   if (n_groups == 0) return HYDRO_OK;
-  if (U_pad_dev == nullptr || gU_out_dev == nullptr || gU_pad_dev == nullptr || work_dev == nullptr)
-    return HYDRO_EINVAL;
+  if (U_pad_dev == nullptr || gU_out_dev == nullptr || gU_pad_dev == nullptr) return HYDRO_EINVAL;
   const size_t es = dtype_size(dtype);
   const size_t need = gh::adjoint_workspace_elems(n_groups, false) * es;
-  if (work_bytes < 0 || size_t(work_bytes) < need) return HYDRO_EINVAL;
+  if (work_bytes < 0 || size_t(work_bytes) < need || (need > 0 && work_dev == nullptr)) return HYDRO_EINVAL;
   const int64_t P = 16 + 2 * ghost;
   const size_t pad = size_t(n_groups) * 5 * P * P * P * es, out = size_t(n_groups) * 5 * 4096 * es;
   if (overlap(gU_pad_dev, pad, U_pad_dev, pad) || overlap(gU_pad_dev, pad, gU_out_dev, out) ||
@@ -532,6 +532,33 @@ int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32
   else
     e = gh::launch_fill_ghosts(static_cast<const float*>(level_dev), static_cast<float*>(U_pad_dev), ngx, ngy, ngz,
                                ghost, bc, s);
+  return device_status(e);
+}
+
+int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                               int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream) {
+  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  gh::LevelGeom geo;
+  geo.ngx = ngx;
+  geo.ngy = ngy;
+  geo.ngz = ngz;
+  for (int i = 0; i < 6; ++i) {
+    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
+    geo.bc[i] = bc_host[i];
+  }
+  if (g_pad_dev == nullptr || g_level_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t G = int64_t(ngx) * ngy * ngz, P = 16 + 2 * ghost;
+  const size_t es = dtype_size(dtype);
+  if (overlap(g_level_dev, size_t(G) * 5 * 4096 * es, g_pad_dev, size_t(G) * 5 * P * P * P * es)) return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_gather_ghost_adjoint(static_cast<const double*>(g_pad_dev), static_cast<double*>(g_level_dev), geo,
+                                        ghost, s);
+  else
+    e = gh::launch_gather_ghost_adjoint(static_cast<const float*>(g_pad_dev), static_cast<float*>(g_level_dev), geo,
+                                        ghost, s);
   return device_status(e);
 }
 

@@ -65,32 +65,40 @@ __device__ __forceinline__ void half_slope_vjp(T qm, T q0, T qp, T half_theta, T
 }
 
 // ------------------------------------------- a3 + a4: Hancock states VJP ---
-// Forward: hancock_states(Wc, Wn, g, first_order, Ut).  Given gUt[3][2][5],
-// return gWc (the cell's own primitive state) and gWn[3][2][5] (its six
-// neighbours), overwriting both.
-template <typename T>
-__device__ __forceinline__ void hancock_states_vjp(const T Wc[5], const T Wn[3][2][5], const Gas<T>& g,
-                                                   bool first_order, const T gUt[3][2][5], T gWc[5],
-                                                   T gWn[3][2][5]) {
+// Forward: hancock_states(Wc, Wn, g, first_order, Ut).  Streaming form: the
+// neighbour states, the face-state cotangents and the neighbour outputs are
+// reached through callbacks, one direction at a time, so that a caller can
+// keep them in LDS and only one direction's values are live at once.
+//   getW(d, side, T W[5])   primitive state of neighbour (d, side)
+//   getG(d, side, T g[5])   cotangent gUt[d][side] (zero for unused faces)
+//   putN(d, side, T g[5])   receives the cotangent of neighbour (d, side)
+//   gWc                     receives the cotangent of the cell's own state
+template <typename T, class GetW, class GetG, class PutN>
+__device__ __forceinline__ void hancock_states_vjp_stream(const T Wc[5], const Gas<T>& g, bool first_order,
+                                                          GetW&& getW, GetG&& getG, PutN&& putN, T gWc[5]) {
   // dU = half_dtdx * sum_d (F_d(-) - F_d(+)); every face state receives dU
-  T gdU[5];
+  T gdU[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T a[5], b[5];
+    getG(d, 0, a);
+    getG(d, 1, b);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) gdU[q] = gdU[q] + (a[q] + b[q]);
+  }
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    T s = gUt[0][0][q] + gUt[0][1][q];
-    s = s + (gUt[1][0][q] + gUt[1][1][q]);
-    s = s + (gUt[2][0][q] + gUt[2][1][q]);
-    gdU[q] = g.half_dtdx * s;
+    gdU[q] = g.half_dtdx * gdU[q];
     gWc[q] = T(0);
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    T Wl[5], Wr[5];
+    getW(d, 0, Wl);
+    getW(d, 1, Wr);
     T h[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      h[q] = first_order ? T(0) : half_slope(Wn[d][0][q], Wc[q], Wn[d][1][q], g.half_theta);
-      gWn[d][0][q] = T(0);
-      gWn[d][1][q] = T(0);
-    }
+    for (int q = 0; q < 5; ++q) h[q] = first_order ? T(0) : half_slope(Wl[q], Wc[q], Wr[q], g.half_theta);
     T gh[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -102,16 +110,15 @@ __device__ __forceinline__ void hancock_states_vjp(const T Wc[5], const T Wn[3][
       const T U1 = rho * u, U2 = rho * v, U3 = rho * w;
       const T U4 = p * g.inv_gm1 + T(0.5) * rho * (u * u + v * v + w * w);
       const T un = W[1 + d];
+      T gUt[5];
+      getG(d, side, gUt);
       // cotangent of this face state's conserved variables: direct + via its flux
       T gF[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) gF[q] = sgn * gdU[q];
       T gU[5];
-      gU[0] = gUt[d][side][0] + gF[0] * un;
-      gU[1] = gUt[d][side][1] + gF[1] * un;
-      gU[2] = gUt[d][side][2] + gF[2] * un;
-      gU[3] = gUt[d][side][3] + gF[3] * un;
-      gU[4] = gUt[d][side][4] + gF[4] * un;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) gU[q] = gUt[q] + gF[q] * un;
       // flux: F = U * un (+ p on the normal momentum), F4 = (U4 + p) un
       T gW[5] = {T(0), T(0), T(0), T(0), T(0)};
       gW[1 + d] = gF[0] * rho + gF[1] * U1 + gF[2] * U2 + gF[3] * U3 + gF[4] * (U4 + p);
@@ -129,12 +136,37 @@ __device__ __forceinline__ void hancock_states_vjp(const T Wc[5], const T Wn[3][
         gh[q] = side == 0 ? gh[q] - gW[q] : gh[q] + gW[q];
       }
     }
+    T gl[5] = {T(0), T(0), T(0), T(0), T(0)}, gr[5] = {T(0), T(0), T(0), T(0), T(0)};
     if (!first_order) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q)
-        half_slope_vjp(Wn[d][0][q], Wc[q], Wn[d][1][q], g.half_theta, gh[q], gWn[d][0][q], gWc[q], gWn[d][1][q]);
+      for (int q = 0; q < 5; ++q) half_slope_vjp(Wl[q], Wc[q], Wr[q], g.half_theta, gh[q], gl[q], gWc[q], gr[q]);
     }
+    putN(d, 0, gl);
+    putN(d, 1, gr);
   }
+}
+
+// Array form: gWc (the cell's own primitive state) and gWn[3][2][5] (its six
+// neighbours), overwriting both.
+template <typename T>
+__device__ __forceinline__ void hancock_states_vjp(const T Wc[5], const T Wn[3][2][5], const Gas<T>& g,
+                                                   bool first_order, const T gUt[3][2][5], T gWc[5],
+                                                   T gWn[3][2][5]) {
+  hancock_states_vjp_stream(
+      Wc, g, first_order,
+      [&](int d, int side, T W[5]) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) W[q] = Wn[d][side][q];
+      },
+      [&](int d, int side, T G[5]) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) G[q] = gUt[d][side][q];
+      },
+      [&](int d, int side, const T G[5]) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gWn[d][side][q] = G[q];
+      },
+      gWc);
 }
 
 // ---------------------------------------------------------- a5: HLLC VJP ---

@@ -72,10 +72,23 @@ hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, con
                                     const double* dt_dev, double dx, int first_order, int ws, T* work,
                                     hipStream_t stream);
 
+// Adjoint of the ghost fill: g_level[cell] = sum of g_pad over every padded
+// position that copies the cell (mhm_adj.hip).
+template <typename T>
+hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGeom& geo, int ghost,
+                                       hipStream_t stream);
+
 // Launch shapes of the level step (all give bit-identical results):
 // bit 0 set = groups in plain order instead of XCD-blocked order,
 // bit 1 set = lower occupancy target for the register allocator.
 constexpr int kLevelVariants = 4;
+// Batched kernel: ticket queues (one per XCD of MI355X), launch-shape variants
+// (bit 0 item order, bit 1 occupancy target, bit 2 per-XCD queues) and the
+// uint32 words of its work buffer (kQueues tickets + 1 departure counter).
+constexpr int kQueues = 8;
+constexpr int kBatchedVariants = 8;
+constexpr int kBatchWorkWords = 16;
+static_assert(kQueues + 1 <= kBatchWorkWords, "work buffer too small");
 
 template <typename T>
 hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost, const Gas<T>& gas,

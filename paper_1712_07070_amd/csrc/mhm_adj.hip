@@ -4,23 +4,24 @@
 //   U'_c = U_c - dt/dx sum_faces (+-F_f),  F_f = HLLC(Ut_left, Ut_right),
 //   Ut = Hancock(W of the cell and its 6 neighbours),  W = prim(U).
 //
-// Three kernels, all deterministic (no floating-point atomics):
-//   A  (per group, z-march like the forward): recompute the half-step face
-//      states and, at every face, the HLLC VJP with gF = dt/dx (gU'_right -
-//      gU'_left) (the face flux leaves the left cell and enters the right one;
-//      gU' = 0 outside the interior); store the cotangent of each
-//      state cell's face states in the workspace gUt[g][face][q][18^3].
-//   B  (per group, z-march): recompute the Hancock inputs, reverse the
-//      predictor (fluxes, cons, limiter) into cotangents of the primitive
-//      states of the cell and its 6 neighbours; gather them per cell (in-plane
-//      through LDS, along z through registers with a one-plane lag), reverse
-//      cons -> prim and add the identity term gU' of interior cells.  Output:
-//      the cotangent of every stencil-reachable cell of the group, either on
-//      the [-2,17]^3 box (level path) or in the padded layout (padded path).
-//   C  (per level cell): sum the cotangents of all copies of the cell that the
-//      groups read (its own interior copy and the ghost copies in neighbouring
-//      groups), enumerated with the ghost-fill index map -- the adjoint of the
-//      ghost fill, written as a gather.
+// Two kernels, both deterministic (no floating-point atomics):
+//   fused (per group, z-march like the forward): recompute the half-step
+//      face states of plane k; take the HLLC VJP at every face with
+//      gF = dt/dx (gU'_right - gU'_left) (the face flux leaves the left cell
+//      and enters the right one; gU' = 0 outside the interior); one plane
+//      behind, reverse the Hancock predictor (fluxes, cons, limiter) of every
+//      state cell into cotangents of the primitive states of the cell and its
+//      6 neighbours, gather them per cell (in-plane through LDS, along z
+//      through a register ring), reverse cons -> prim and add the identity
+//      term gU' of interior cells.  Output: the cotangent of every
+//      stencil-reachable cell of the group, on the [-2,17]^3 box (level path)
+//      or in the padded layout (padded path).
+//   gather (per level cell): sum the cotangents of all copies of the cell
+//      that the groups read (its own interior copy and the ghost copies in
+//      neighbouring groups), enumerated in closed form from the ghost-fill
+//      index map -- the adjoint of the ghost fill, written as a gather.  The
+//      same kernel sums padded blocks of any ghost width
+//      (hydro_gather_ghost_adjoint).
 
 #include "hydro_adjoint.h"
 #include "mhm_group.h"
@@ -30,9 +31,7 @@ namespace gh {
 namespace {
 
 constexpr int kBox = 20;      // reachable box [-2, 17] per axis
-constexpr int kS3 = 18 * 18 * 18;
 
-__device__ __forceinline__ int s3idx(int x, int y, int z) { return ((z + 1) * 18 + (y + 1)) * 18 + (x + 1); }
 __device__ __forceinline__ int b3idx(int x, int y, int z) { return ((z + 2) * kBox + (y + 2)) * kBox + (x + 2); }
 
 // gU' (cotangent of the output interiors) of one group: [5][4096].
@@ -41,134 +40,7 @@ __device__ __forceinline__ T gout(const T* __restrict__ go, int q, int x, int y,
   return (x < 0 || x > 15 || y < 0 || y > 15 || z < 0 || z > 15) ? T(0) : go[q * 4096 + (z * 16 + y) * 16 + x];
 }
 
-// ------------------------------------------------------------ kernel A ----
-template <typename T, class Src>
-__device__ __forceinline__ void adjoint_faces(const Src& src, const T* __restrict__ go, T* __restrict__ gut,
-                                              const Gas<T>& gas, int first_order, int ws, Smem<T>& sm) {
-  const int tid = threadIdx.x;
-  const bool interior = tid < 256;
-  int cx, cy, ox = 0, oy = 0, ex = 0, ey = 0;
-  if (interior) {
-    cx = tid & 15;
-    cy = tid >> 4;
-  } else {
-    const int l = tid - 256, side = l >> 4, k = l & 15;
-    cx = side == 0 ? -1 : side == 1 ? 16 : k;
-    cy = side == 2 ? -1 : side == 3 ? 16 : k;
-    ox = side == 0 ? -2 : side == 1 ? 17 : k;
-    oy = side == 2 ? -2 : side == 3 ? 17 : k;
-    ex = (l & 1) ? 16 : -1;
-    ey = (l & 2) ? 16 : -1;
-  }
-  const bool has_edge = !interior && (tid - 256) < 4;
-  const bool xface16 = !interior && cx == 16;
-  const bool yface16 = !interior && cy == 16;
-  const int64_t col_own = src.col(cx, cy);
-  const int64_t col_out = interior ? 0 : src.col(ox, oy);
-  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
-  const T dtdx = gas.dtdx;
-
-  T Wm[5], Wc[5], Wp[5];
-  if (interior) load_prim(src, col_own, -2, gas, Wm);
-  load_prim(src, col_own, -1, gas, Wc);
-  T Uz[5];   // z+ face state of the previous plane
-  T Ux[5], Uy[5];
-
-  for (int k = -1; k <= 16; ++k) {
-    if (interior || k + 1 <= 16) load_prim(src, col_own, k + 1, gas, Wp);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) sm.P[q][pidx(cx, cy)] = Wc[q];
-    if (!interior && k >= 0 && k <= 15) {
-      T Wo[5];
-      load_prim(src, col_out, k, gas, Wo);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
-      if (has_edge) {
-        load_prim(src, col_edge, k, gas, Wo);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
-      }
-    }
-    __syncthreads();
-
-    if (interior || (k >= 0 && k <= 15)) {
-      T Wn[3][2][5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
-        Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
-        Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
-        Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
-        Wn[2][0][q] = Wm[q];
-        Wn[2][1][q] = Wp[q];
-      }
-      T Ut[3][2][5];
-      hancock_states(Wc, Wn, gas, first_order != 0, Ut);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
-        sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
-        Ux[q] = Ut[0][0][q];
-        Uy[q] = Ut[1][0][q];
-      }
-      if (interior) {
-        if (k >= 0) {
-          // z-face between planes k-1 and k
-          T gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)}, gR[5] = {T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-          for (int q = 0; q < 5; ++q) gF[q] = dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy, k - 1));
-          hllc_flux_vjp<2>(Uz, Ut[2][0], gas, ws, gF, gL, gR);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) {
-            gut[(5 * 5 + q) * kS3 + s3idx(cx, cy, k - 1)] = gL[q];  // z+ face of the cell below
-            gut[(4 * 5 + q) * kS3 + s3idx(cx, cy, k)] = gR[q];      // z- face of this cell
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) Uz[q] = Ut[2][1][q];
-      }
-    }
-    __syncthreads();
-
-    if (k >= 0 && k <= 15) {
-      if (interior || xface16) {
-        T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)}, gR[5] = {T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          L[q] = sm.S[0][q][sidx(cx - 1, cy)];
-          gF[q] = dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx - 1, cy, k));
-        }
-        hllc_flux_vjp<0>(L, Ux, gas, ws, gF, gL, gR);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          gut[(1 * 5 + q) * kS3 + s3idx(cx - 1, cy, k)] = gL[q];  // x+ face of the left cell
-          gut[(0 * 5 + q) * kS3 + s3idx(cx, cy, k)] = gR[q];      // x- face of this cell
-        }
-      }
-      if (interior || yface16) {
-        T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)}, gR[5] = {T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          L[q] = sm.S[1][q][sidx(cx, cy - 1)];
-          gF[q] = dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy - 1, k));
-        }
-        hllc_flux_vjp<1>(L, Uy, gas, ws, gF, gL, gR);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          gut[(3 * 5 + q) * kS3 + s3idx(cx, cy - 1, k)] = gL[q];
-          gut[(2 * 5 + q) * kS3 + s3idx(cx, cy, k)] = gR[q];
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      Wm[q] = Wc[q];
-      Wc[q] = Wp[q];
-    }
-  }
-}
-
-// ------------------------------------------------------------ kernel B ----
+// ------------------------------------------------------ cell helpers ----
 // Which faces of a state cell carry a cotangent (the others were not used by
 // the step): interior cells all six; the halo state cells only the face they
 // share with the interior; the two extra z planes only their inner z face.
@@ -182,12 +54,6 @@ __device__ __forceinline__ bool face_used(int x, int y, int z, int f) {
   if (z == -1) return f == 5;
   return f == 4;  // z == 16
 }
-
-template <typename T>
-struct SmemB {
-  T P[5][kPW * kPW];        // primitive plane k
-  T O[4][5][kSW * kSW];     // in-plane neighbour contributions of each state cell (x-, x+, y-, y+)
-};
 
 // Sink for the input cotangent of one group's reachable cells.
 template <typename T>
@@ -220,173 +86,324 @@ __device__ __forceinline__ void finalize_cell(const Src& src, int64_t col, int x
   for (int q = 0; q < 5; ++q) sink.put(q, x, y, z, gU[q]);
 }
 
-template <typename T, class Src, class Sink>
-__device__ __forceinline__ void adjoint_cells(const Src& src, const T* __restrict__ go, const T* __restrict__ gut,
-                                              const Gas<T>& gas, int first_order, SmemB<T>& sm, const Sink& sink) {
-  const int tid = threadIdx.x;
-  const bool interior = tid < 256;
-  int cx, cy, ox = 0, oy = 0, ex = 0, ey = 0;
-  if (interior) {
-    cx = tid & 15;
-    cy = tid >> 4;
-  } else {
-    const int l = tid - 256, side = l >> 4, k = l & 15;
-    cx = side == 0 ? -1 : side == 1 ? 16 : k;
-    cy = side == 2 ? -1 : side == 3 ? 16 : k;
-    ox = side == 0 ? -2 : side == 1 ? 17 : k;
-    oy = side == 2 ? -2 : side == 3 ? 17 : k;
-    ex = (l & 1) ? 16 : -1;
-    ey = (l & 2) ? 16 : -1;
-  }
-  const bool has_edge = !interior && (tid - 256) < 4;
-  const int64_t col_own = src.col(cx, cy);
-  const int64_t col_out = interior ? 0 : src.col(ox, oy);
-  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
-  // planes of the own column that are reachable cells
-  const int zlo = interior ? -2 : -1, zhi = interior ? 17 : 16;
+// ------------------------------------------------------- fused kernel ----
+// One z-march per group that does both halves with a one-plane lag: at
+// iteration k it recomputes the half-step states of plane k, takes the HLLC
+// VJPs of the z-face (k-1 | k) and of the x/y faces of plane k, and reverses
+// the Hancock predictor of plane k-1, whose six face cotangents are then
+// complete.  Face cotangents reach the cell that owns the face state through
+// registers (the faces a thread solves itself) or LDS (the x+/y+ faces, solved
+// by the neighbouring thread); the cell's cotangents for its in-plane
+// neighbours go through LDS, those along z stay in a register ring.
+//
+// Workgroup: 256 threads (4 waves, one per SIMD).  Every thread owns one
+// interior column; the 64 threads of wave 0 also own one halo column each (the
+// 4 x 16 columns just outside the faces, whose state cells feed the boundary
+// faces) with its 2-deep neighbour and, for 4 of them, an edge column, and run
+// that role after the interior one in every phase.  One wave per SIMD leaves
+// the whole register file (VGPRs and AGPRs) to each wave.
+constexpr int kAdjThreads = 256;
 
-  T Wm[5], Wc[5], Wp[5];
-  if (interior) load_prim(src, col_own, -2, gas, Wm);
-  load_prim(src, col_own, -1, gas, Wc);
-  // cotangent accumulators of the own column at planes k-1, k, k+1
-  T a0[5], a1[5], a2[5];
+template <typename T>
+struct SmemF {
+  T P[3][5][kPW * kPW];   // primitive planes, slot (k + 3) % 3
+  T S[2][5][kSW * kSW];   // x+ and y+ half-step states of plane k
+  T GL[2][5][kSW * kSW];  // cotangents of the x+ / y+ face states of plane k-1 cells
+  T O[4][5][kSW * kSW];   // in-plane neighbour contributions of plane k-1 cells (x-, x+, y-, y+)
+};
+
+__device__ __forceinline__ int pslot(int k) { return (k + 3) % 3; }
+
+// Is (x, y, z) a state cell (one whose half-step states the step computes)?
+__device__ __forceinline__ bool in_state_plane(int x, int y, int z) {
+  const bool in_x = x >= 0 && x <= 15, in_y = y >= 0 && y <= 15;
+  if (in_x && in_y) return z >= -1 && z <= 16;
+  const bool hx = (x == -1 || x == 16) && in_y, hy = (y == -1 || y == 16) && in_x;
+  return (hx || hy) && z >= 0 && z <= 15;
+}
+
+// Per-column state of one role (interior or halo column) across the march.
+template <typename T, bool kInterior>
+struct AdjCol {
+  static constexpr bool interior = kInterior;
+  static constexpr int zlo = kInterior ? -2 : -1, zhi = kInterior ? 17 : 16;  // reachable planes of the column
+  int cx, cy;
+  bool xface16, yface16;
+  int64_t col;
+  T Wm[5], Wc[5], Wp[5];      // W(k-1), W(k), W(k+1); W(k-2) is read back from LDS
+  T Uz[5];                    // z+ face state of plane k-1 (interior columns)
+  T Ux[5], Uy[5];             // own x- and y- face states of plane k
+  T gRx[5], gRy[5], gRz[5];   // cotangents of the own x-, y-, z- face states of plane k-1
+  T A0[5], A1[5], A2[5];      // input cotangents of the column at planes k-2, k-1, k
+};
+
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ void adj_col_init(AdjCol<T, kI>& c, const Src& src, int cx, int cy, const Gas<T>& gas,
+                                             SmemF<T>& sm) {
+  c.cx = cx;
+  c.cy = cy;
+  c.xface16 = !kI && cx == 16;
+  c.yface16 = !kI && cy == 16;
+  c.col = src.col(cx, cy);
+  if (kI) {
+    load_prim(src, c.col, -2, gas, c.Wm);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.P[pslot(-2)][q][pidx(cx, cy)] = c.Wm[q];
+  }
+  load_prim(src, c.col, -1, gas, c.Wc);
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    a0[q] = T(0);
-    a1[q] = T(0);
-    a2[q] = T(0);
+    c.gRx[q] = c.gRy[q] = c.gRz[q] = T(0);
+    c.A0[q] = c.A1[q] = c.A2[q] = T(0);
   }
-  auto in_state_plane = [&](int x, int y, int z) {  // does (x, y, z) hold a state cell?
-    const bool in_x = x >= 0 && x <= 15, in_y = y >= 0 && y <= 15;
-    if (in_x && in_y) return z >= -1 && z <= 16;
-    const bool hx = (x == -1 || x == 16) && in_y, hy = (y == -1 || y == 16) && in_x;
-    return (hx || hy) && z >= 0 && z <= 15;
-  };
+}
 
-  for (int k = -1; k <= 17; ++k) {
-    // a0: plane k-1 (complete after this iteration's z- contribution), a1: plane k, a2: plane k+1
-    if (k <= 16) {
-      if (interior || k + 1 <= 16) load_prim(src, col_own, k + 1, gas, Wp);
+// F1: next plane of the column; publish plane k.
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ void adj_col_publish(AdjCol<T, kI>& c, const Src& src, int k, const Gas<T>& gas,
+                                                SmemF<T>& sm) {
+  if (kI || k + 1 <= 16) load_prim(src, c.col, k + 1, gas, c.Wp);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) sm.P[q][pidx(cx, cy)] = Wc[q];
-      if (!interior && k >= 0 && k <= 15) {
-        T Wo[5];
-        load_prim(src, col_out, k, gas, Wo);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
-        if (has_edge) {
-          load_prim(src, col_edge, k, gas, Wo);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
-        }
-      }
-    }
-    __syncthreads();
+  for (int q = 0; q < 5; ++q) sm.P[pslot(k)][q][pidx(c.cx, c.cy)] = c.Wc[q];
+}
 
-    const bool state = k <= 16 && in_state_plane(cx, cy, k);
-    if (state) {
-      T Wn[3][2][5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
-        Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
-        Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
-        Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
-        Wn[2][0][q] = Wm[q];
-        Wn[2][1][q] = Wp[q];
-      }
-      T gUt[3][2][5];
-#pragma unroll
-      for (int f = 0; f < 6; ++f) {
-        const bool used = face_used(cx, cy, k, f);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) gUt[f >> 1][f & 1][q] = used ? gut[(f * 5 + q) * kS3 + s3idx(cx, cy, k)] : T(0);
-      }
-      T gWc[5], gWn[3][2][5];
-      hancock_states_vjp(Wc, Wn, gas, first_order != 0, gUt, gWc, gWn);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        a1[q] = a1[q] + gWc[q];
-        a0[q] = a0[q] + gWn[2][0][q];
-        a2[q] = a2[q] + gWn[2][1][q];
-        sm.O[0][q][sidx(cx, cy)] = gWn[0][0][q];
-        sm.O[1][q][sidx(cx, cy)] = gWn[0][1][q];
-        sm.O[2][q][sidx(cx, cy)] = gWn[1][0][q];
-        sm.O[3][q][sidx(cx, cy)] = gWn[1][1][q];
-      }
-    }
-    __syncthreads();
-
-    if (k <= 16) {
-      // in-plane gather: cell (x, y) receives the x+ contribution of (x-1, y),
-      // the x- contribution of (x+1, y), and likewise in y
-      auto gather = [&](int x, int y, T g[5]) {
-        const bool l = in_state_plane(x - 1, y, k), r = in_state_plane(x + 1, y, k);
-        const bool d = in_state_plane(x, y - 1, k), u = in_state_plane(x, y + 1, k);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          T s = g[q];
-          if (l) s = s + sm.O[1][q][sidx(x - 1, y)];
-          if (r) s = s + sm.O[0][q][sidx(x + 1, y)];
-          if (d) s = s + sm.O[3][q][sidx(x, y - 1)];
-          if (u) s = s + sm.O[2][q][sidx(x, y + 1)];
-          g[q] = s;
-        }
-      };
-      if (k >= zlo && k <= zhi) gather(cx, cy, a1);
-      if (!interior && k >= 0 && k <= 15) {
-        // the 2-deep and edge columns get only in-plane contributions
-        T g[5] = {T(0), T(0), T(0), T(0), T(0)};
-        gather(ox, oy, g);
-        finalize_cell(src, col_out, ox, oy, k, g, go, gas, sink);
-        if (has_edge) {
-          T e[5] = {T(0), T(0), T(0), T(0), T(0)};
-          gather(ex, ey, e);
-          finalize_cell(src, col_edge, ex, ey, k, e, go, gas, sink);
-        }
-      }
-    }
-    // plane k-1 of the own column is complete
-    if (k - 1 >= zlo && k - 1 <= zhi) finalize_cell(src, col_own, cx, cy, k - 1, a0, go, gas, sink);
-    if (k == 17 && k <= zhi) finalize_cell(src, col_own, cx, cy, 17, a1, go, gas, sink);
+// F2: half-step states of plane k and the z-face (k-1 | k) VJP; then the
+// reverse Hancock predictor of the state cell at plane k-1.
+template <typename T, bool kI>
+__device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T* __restrict__ go, const Gas<T>& gas,
+                                               bool fo, int ws, SmemF<T>& sm) {
+  const int cx = c.cx, cy = c.cy;
+  const int sk = pslot(k), sj = pslot(k - 1), si = pslot(k - 2);
+  T gLz[5] = {T(0), T(0), T(0), T(0), T(0)};   // cotangent of the z+ face state of plane k-1
+  T gRzn[5] = {T(0), T(0), T(0), T(0), T(0)};  // cotangent of the z- face state of plane k
+  if (k <= 16 && in_state_plane(cx, cy, k)) {
+    T Wn[3][2][5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      a0[q] = a1[q];
-      a1[q] = a2[q];
-      a2[q] = T(0);
-      Wm[q] = Wc[q];
-      Wc[q] = Wp[q];
+      Wn[0][0][q] = sm.P[sk][q][pidx(cx - 1, cy)];
+      Wn[0][1][q] = sm.P[sk][q][pidx(cx + 1, cy)];
+      Wn[1][0][q] = sm.P[sk][q][pidx(cx, cy - 1)];
+      Wn[1][1][q] = sm.P[sk][q][pidx(cx, cy + 1)];
+      Wn[2][0][q] = c.Wm[q];
+      Wn[2][1][q] = c.Wp[q];
     }
-    // no barrier needed here: the next writes to sm.P (publish) and sm.O
-    // (state phase, after the next barrier) cannot overlap this gather
+    T Ut[3][2][5];
+    hancock_states(c.Wc, Wn, gas, fo, Ut);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
+      sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
+      c.Ux[q] = Ut[0][0][q];
+      c.Uy[q] = Ut[1][0][q];
+    }
+    if (kI) {
+      if (k >= 0) {
+        T gF[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy, k - 1));
+        hllc_flux_vjp<2>(c.Uz, Ut[2][0], gas, ws, gF, gLz, gRzn);
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) c.Uz[q] = Ut[2][1][q];
+    }
+  }
+
+  const int j = k - 1;
+  if (j >= -1 && in_state_plane(cx, cy, j)) {
+    const bool u0 = face_used(cx, cy, j, 0), u1 = face_used(cx, cy, j, 1), u2 = face_used(cx, cy, j, 2);
+    const bool u3 = face_used(cx, cy, j, 3), u4 = face_used(cx, cy, j, 4), u5 = face_used(cx, cy, j, 5);
+    T gWc[5];
+    hancock_states_vjp_stream(
+        c.Wm, gas, fo,
+        [&](int d, int side, T W[5]) {
+          if (d == 2) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) W[q] = side == 0 ? sm.P[si][q][pidx(cx, cy)] : c.Wc[q];
+          } else {
+            const int x = d == 0 ? cx + (side ? 1 : -1) : cx, y = d == 1 ? cy + (side ? 1 : -1) : cy;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) W[q] = sm.P[sj][q][pidx(x, y)];
+          }
+        },
+        [&](int d, int side, T G[5]) {
+          const int f = 2 * d + side;
+          const bool used = f == 0 ? u0 : f == 1 ? u1 : f == 2 ? u2 : f == 3 ? u3 : f == 4 ? u4 : u5;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            T v;
+            if (f == 0) v = c.gRx[q];
+            else if (f == 1) v = sm.GL[0][q][sidx(cx, cy)];
+            else if (f == 2) v = c.gRy[q];
+            else if (f == 3) v = sm.GL[1][q][sidx(cx, cy)];
+            else if (f == 4) v = c.gRz[q];
+            else v = gLz[q];
+            G[q] = used ? v : T(0);
+          }
+        },
+        [&](int d, int side, const T G[5]) {
+          if (d == 2) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+              if (side == 0) c.A0[q] = c.A0[q] + G[q];
+              else c.A2[q] = c.A2[q] + G[q];
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.O[2 * d + side][q][sidx(cx, cy)] = G[q];
+          }
+        },
+        gWc);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c.A1[q] = c.A1[q] + gWc[q];
+  }
+  if (kI) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c.gRz[q] = gRzn[q];
+  }
+}
+
+// F3a: the x and y face VJPs this column solves at plane k (its x- face and
+// y- face; halo columns only the faces at x = 16 / y = 16).
+template <typename T, bool kI>
+__device__ __forceinline__ void adj_col_faces(AdjCol<T, kI>& c, int k, const T* __restrict__ go, const Gas<T>& gas,
+                                              int ws, SmemF<T>& sm) {
+  if (k < 0 || k > 15) return;
+  const int cx = c.cx, cy = c.cy;
+  if (kI || c.xface16) {
+    T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx - 1, cy, k));
+      c.gRx[q] = T(0);
+    }
+    hllc_flux_vjp<0>(L, c.Ux, gas, ws, gF, gL, c.gRx);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.GL[0][q][sidx(cx - 1, cy)] = gL[q];
+  }
+  if (kI || c.yface16) {
+    T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy - 1, k));
+      c.gRy[q] = T(0);
+    }
+    hllc_flux_vjp<1>(L, c.Uy, gas, ws, gF, gL, c.gRy);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.GL[1][q][sidx(cx, cy - 1)] = gL[q];
+  }
+}
+
+// In-plane gather at plane j into g: cell (x, y) receives the x+ contribution
+// of (x-1, y), the x- contribution of (x+1, y), and likewise in y.
+template <typename T>
+__device__ __forceinline__ void adj_gather_plane(int x, int y, int j, const SmemF<T>& sm, T g[5]) {
+  const bool l = in_state_plane(x - 1, y, j), r = in_state_plane(x + 1, y, j);
+  const bool d = in_state_plane(x, y - 1, j), u = in_state_plane(x, y + 1, j);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    T s = g[q];
+    if (l) s = s + sm.O[1][q][sidx(x - 1, y)];
+    if (r) s = s + sm.O[0][q][sidx(x + 1, y)];
+    if (d) s = s + sm.O[3][q][sidx(x, y - 1)];
+    if (u) s = s + sm.O[2][q][sidx(x, y + 1)];
+    g[q] = s;
+  }
+}
+
+// F3b: in-plane gather of plane k-1 into the column; finalize the planes that
+// are complete (k-2; after the last plane also k-1 and k); advance the rings.
+template <typename T, bool kI, class Src, class Sink>
+__device__ __forceinline__ void adj_col_finish(AdjCol<T, kI>& c, const Src& src, int k, const T* __restrict__ go,
+                                               const Gas<T>& gas, const SmemF<T>& sm, const Sink& sink) {
+  const int j = k - 1;
+  if (j >= c.zlo && j <= c.zhi) adj_gather_plane(c.cx, c.cy, j, sm, c.A1);
+  if (k - 2 >= c.zlo && k - 2 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, k - 2, c.A0, go, gas, sink);
+  if (k == 17) {
+    if (16 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, 16, c.A1, go, gas, sink);
+    if (17 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, 17, c.A2, go, gas, sink);
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    c.A0[q] = c.A1[q];
+    c.A1[q] = c.A2[q];
+    c.A2[q] = T(0);
+    c.Wm[q] = c.Wc[q];
+    c.Wc[q] = c.Wp[q];
+  }
+}
+
+template <typename T, class Src, class Sink>
+__device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restrict__ go, const Gas<T>& gas,
+                                              int first_order, int ws, SmemF<T>& sm, const Sink& sink) {
+  const int tid = threadIdx.x;
+  const bool halo = tid < 64;  // wave 0
+  const bool fo = first_order != 0;
+  // halo role of wave 0: side 0..3 = x-, x+, y-, y+; the column two cells out;
+  // lanes 0..3 also one of the 4 edge columns
+  const int side = tid >> 4, kk = tid & 15;
+  const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
+  const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
+  const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
+  const bool has_edge = halo && tid < 4;
+  const int64_t col_out = halo ? src.col(ox, oy) : 0;
+  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
+
+  AdjCol<T, true> ci;
+  AdjCol<T, false> ch;
+  adj_col_init(ci, src, tid & 15, tid >> 4, gas, sm);
+  if (halo) adj_col_init(ch, src, hx, hy, gas, sm);
+
+  for (int k = -1; k <= 17; ++k) {
+    const int sk = pslot(k);
+    if (k <= 16) {
+      adj_col_publish(ci, src, k, gas, sm);
+      if (halo) {
+        adj_col_publish(ch, src, k, gas, sm);
+        if (k >= 0 && k <= 15) {
+          T Wo[5];
+          load_prim(src, col_out, k, gas, Wo);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) sm.P[sk][q][pidx(ox, oy)] = Wo[q];
+          if (has_edge) {
+            load_prim(src, col_edge, k, gas, Wo);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.P[sk][q][pidx(ex, ey)] = Wo[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    adj_col_states(ci, k, go, gas, fo, ws, sm);
+    if (halo) adj_col_states(ch, k, go, gas, fo, ws, sm);
+    __syncthreads();
+    adj_col_faces(ci, k, go, gas, ws, sm);
+    if (halo) adj_col_faces(ch, k, go, gas, ws, sm);
+    adj_col_finish(ci, src, k, go, gas, sm, sink);
+    if (halo) {
+      adj_col_finish(ch, src, k, go, gas, sm, sink);
+      const int j = k - 1;
+      if (j >= 0 && j <= 15) {
+        // the 2-deep and edge columns get only in-plane contributions
+        T g[5] = {T(0), T(0), T(0), T(0), T(0)};
+        adj_gather_plane(ox, oy, j, sm, g);
+        finalize_cell(src, col_out, ox, oy, j, g, go, gas, sink);
+        if (has_edge) {
+          T e[5] = {T(0), T(0), T(0), T(0), T(0)};
+          adj_gather_plane(ex, ey, j, sm, e);
+          finalize_cell(src, col_edge, ex, ey, j, e, go, gas, sink);
+        }
+      }
+    }
+    // next writes: P slot k+1 held plane k-2 (last read in this iteration's
+    // states phase), S / O in the next states phase (after its first
+    // barrier), GL in the next faces phase (after the barrier that follows
+    // its reads)
   }
 }
 
 // ------------------------------------------------------------- kernels ----
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void adj_faces_padded(const T* __restrict__ Upad, const T* __restrict__ gout_,
-                                                             T* __restrict__ gut, int gh, Gas<T> gas, int first_order,
-                                                             int ws) {
-  __shared__ Smem<T> sm;
-  const int P = 16 + 2 * gh;
-  const int64_t g = blockIdx.x;
-  PaddedSource<T> src{Upad + g * 5 * int64_t(P) * P * P, P, gh};
-  adjoint_faces<T>(src, gout_ + g * 5 * 4096, gut + g * 30 * int64_t(kS3), gas, first_order, ws, sm);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void adj_cells_padded(const T* __restrict__ Upad, const T* __restrict__ gout_,
-                                                             const T* __restrict__ gut, T* __restrict__ gpad, int gh,
-                                                             Gas<T> gas, int first_order) {
-  __shared__ SmemB<T> sm;
-  const int P = 16 + 2 * gh;
-  const int64_t g = blockIdx.x;
-  const int64_t P3 = int64_t(P) * P * P;
-  PaddedSource<T> src{Upad + g * 5 * P3, P, gh};
-  PadSink<T> sink{gpad + g * 5 * P3, P, gh};
-  adjoint_cells<T>(src, gout_ + g * 5 * 4096, gut + g * 30 * int64_t(kS3), gas, first_order, sm, sink);
-}
 
 template <typename T>
 __device__ __forceinline__ void set_dt_adj(Gas<T>& gas, const double* dt_dev, double dx) {
@@ -398,29 +415,29 @@ __device__ __forceinline__ void set_dt_adj(Gas<T>& gas, const double* dt_dev, do
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void adj_faces_level(const T* __restrict__ level, const T* __restrict__ gout_,
-                                                            T* __restrict__ gut, LevelGeom geo, Gas<T> gas,
-                                                            const double* __restrict__ dt_dev, double dx,
-                                                            int first_order, int ws) {
-  __shared__ Smem<T> sm;
-  set_dt_adj(gas, dt_dev, dx);
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void adj_fused_padded(const T* __restrict__ Upad, const T* __restrict__ gout_,
+                                                             T* __restrict__ gpad, int gh, Gas<T> gas, int first_order,
+                                                             int ws) {
+  __shared__ SmemF<T> sm;
+  const int P = 16 + 2 * gh;
   const int64_t g = blockIdx.x;
-  LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
-  adjoint_faces<T>(src, gout_ + g * 5 * 4096, gut + g * 30 * int64_t(kS3), gas, first_order, ws, sm);
+  const int64_t P3 = int64_t(P) * P * P;
+  PaddedSource<T> src{Upad + g * 5 * P3, P, gh};
+  PadSink<T> sink{gpad + g * 5 * P3, P, gh};
+  adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void adj_cells_level(const T* __restrict__ level, const T* __restrict__ gout_,
-                                                            const T* __restrict__ gut, T* __restrict__ gbox,
-                                                            LevelGeom geo, Gas<T> gas,
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void adj_fused_level(const T* __restrict__ level, const T* __restrict__ gout_,
+                                                            T* __restrict__ gbox, LevelGeom geo, Gas<T> gas,
                                                             const double* __restrict__ dt_dev, double dx,
-                                                            int first_order) {
-  __shared__ SmemB<T> sm;
+                                                            int first_order, int ws) {
+  __shared__ SmemF<T> sm;
   set_dt_adj(gas, dt_dev, dx);
   const int64_t g = blockIdx.x;
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
-  adjoint_cells<T>(src, gout_ + g * 5 * 4096, gut + g * 30 * int64_t(kS3), gas, first_order, sm, sink);
+  adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
 }
 
 // ------------------------------------------------------------ kernel C ----
@@ -434,60 +451,94 @@ __device__ __forceinline__ bool reachable(int x, int y, int z) {
   return o == 0 || (o == 1 && m <= 2) || (o == 2 && m <= 1);
 }
 
-// All (group coordinate, box position) pairs along one axis whose cell maps to
-// level index X under the ghost-fill index map.  At most 6 entries.
-__device__ __forceinline__ int axis_copies(int X, int ng, int lo, int hi, int* gs, int* ps) {
-  const int n = ng * 16;
-  int c = 0;
-  const int g0 = X >> 4;
-  for (int dg = -1; dg <= 1; ++dg) {
-    int g = g0 + dg;
-    if (g < 0 || g >= ng) {
-      // a group beyond a periodic face is the wrapped one; beyond an outflow face there is none
-      const bool periodic = g < 0 ? lo == 0 : hi == 0;
-      if (!periodic || ng < 3) continue;  // with 1 or 2 groups the wrapped group is already in the loop
-      g = g < 0 ? g + ng : g - ng;
-    }
-    for (int p = -2; p <= 17; ++p) {
-      const int i = g * 16 + p;
-      int m = i;
-      if (i < 0) m = lo == 0 ? i + n : 0;
-      if (i >= n) m = hi == 0 ? i - n : n - 1;
-      if (m == X && c < 6) {
-        gs[c] = g;
-        ps[c] = p;
-        ++c;
-      }
-    }
+// Positions that copy level index X along one axis under the ghost-fill index
+// map with ghost width gh <= 16: position p in [-gh, 16 + gh) of group g
+// stands for index i = 16 g + p, kept if 0 <= i < n, else mapped by the face
+// it lies beyond (periodic: i -/+ n; outflow: the nearest interior index).
+// Solving map(i) = X gives, as runs of consecutive positions in one group
+// (at most five):
+//   inside the domain  i = X, seen by the group holding X and, within gh of
+//                      its faces, by the neighbouring group;
+//   below the low face (group 0, p < 0): periodic p = X - n if that is
+//                      >= -gh; outflow all gh positions when X = 0;
+//   above the high face (group ng-1, p >= 16): periodic p = X + 16 if X < gh;
+//                      outflow all gh positions when X = n - 1.
+struct Run {
+  int g, p, n;  // group along the axis, first position, number of positions
+};
+
+// The five run slots of one axis, each packed in one int (n: 5 bits, p + 64:
+// 7 bits, g: the rest) and selected arithmetically, so that a run-time slot
+// index keeps them in registers.
+struct Runs {
+  int v0, v1, v2, v3, v4;
+  __device__ static int pack(int g, int p, int n) { return (g << 12) | ((p + 64) << 5) | n; }
+  __device__ Run operator[](int k) const {
+    int v = v0;
+    v = k == 1 ? v1 : v;
+    v = k == 2 ? v2 : v;
+    v = k == 3 ? v3 : v;
+    v = k == 4 ? v4 : v;
+    return Run{v >> 12, ((v >> 5) & 127) - 64, v & 31};
   }
-  return c;
+};
+
+// Fixed slots (absent runs have n = 0): 0 the lower neighbour group, 1 the
+// group holding X, 2 the upper neighbour group, 3 below the low face, 4 above
+// the high face.
+__device__ __forceinline__ Runs axis_runs(int X, int ng, int lo, int hi, int gh) {
+  const int n = ng * 16, g0 = X >> 4, x = X & 15;
+  Runs r;
+  r.v0 = Runs::pack(g0 >= 1 ? g0 - 1 : 0, x + 16, (g0 >= 1 && x < gh) ? 1 : 0);
+  r.v1 = Runs::pack(g0, x, 1);
+  r.v2 = Runs::pack(g0 + 1, x - 16, (g0 + 1 < ng && x >= 16 - gh) ? 1 : 0);
+  r.v3 = lo == 0 ? Runs::pack(0, X - n >= -gh ? X - n : 0, X - n >= -gh ? 1 : 0) : Runs::pack(0, -gh, X == 0 ? gh : 0);
+  r.v4 = hi == 0 ? Runs::pack(ng - 1, X + 16, X < gh ? 1 : 0) : Runs::pack(ng - 1, 16, X == n - 1 ? gh : 0);
+  return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void adj_gather_level(const T* __restrict__ gbox, T* __restrict__ glevel,
-                                                        LevelGeom geo, int64_t ncells) {
+// Sum, per level cell, the cotangents of every copy of the cell: the adjoint
+// of the ghost fill, written as a gather (fixed order, no atomics).  kBoxSrc:
+// the source is the per-group [5][20^3] box of the level adjoint (positions
+// [-2, 17], only stencil-reachable ones hold values); otherwise a padded
+// [5][P^3] block per group with ghost width gh.
+template <typename T, bool kBoxSrc>
+__global__ __launch_bounds__(256) void adj_gather(const T* __restrict__ src, T* __restrict__ glevel, LevelGeom geo,
+                                                  int gh, int64_t ncells) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= ncells) return;
   // level cell (g, z, y, x) in group-major order
   const int x = int(i & 15), y = int((i >> 4) & 15), z = int((i >> 8) & 15);
   const int64_t g = i >> 12;
   const int gx = int(g % geo.ngx), gy = int((g / geo.ngx) % geo.ngy), gz = int(g / (int64_t(geo.ngx) * geo.ngy));
-  int gxs[6], pxs[6], gys[6], pys[6], gzs[6], pzs[6];
-  // with 1 or 2 groups along an axis the periodic neighbours coincide with
-  // groups already enumerated; enumerate them explicitly in that case
-  const int nx = axis_copies(gx * 16 + x, geo.ngx, geo.bc[0], geo.bc[1], gxs, pxs);
-  const int ny = axis_copies(gy * 16 + y, geo.ngy, geo.bc[2], geo.bc[3], gys, pys);
-  const int nz = axis_copies(gz * 16 + z, geo.ngz, geo.bc[4], geo.bc[5], gzs, pzs);
+  const int w = kBoxSrc ? 2 : gh;        // position offset of the source block
+  const int P = kBoxSrc ? kBox : 16 + 2 * gh;
+  const int64_t P3 = int64_t(P) * P * P;
+  const Runs rx = axis_runs(gx * 16 + x, geo.ngx, geo.bc[0], geo.bc[1], w);
+  const Runs ry = axis_runs(gy * 16 + y, geo.ngy, geo.bc[2], geo.bc[3], w);
+  const Runs rz = axis_runs(gz * 16 + z, geo.ngz, geo.bc[4], geo.bc[5], w);
   T s[5] = {T(0), T(0), T(0), T(0), T(0)};
-  for (int a = 0; a < nz; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nx; ++c) {
-        if (!reachable(pxs[c], pys[b], pzs[a])) continue;
-        const int64_t src_g = (int64_t(gzs[a]) * geo.ngy + gys[b]) * geo.ngx + gxs[c];
-        const T* base = gbox + src_g * 5 * int64_t(kBox * kBox * kBox) + b3idx(pxs[c], pys[b], pzs[a]);
+#pragma unroll 1
+  for (int a = 0; a < 5; ++a) {
+    const Run ra = rz[a];
+    for (int pz = ra.p; pz < ra.p + ra.n; ++pz)
+#pragma unroll 1
+      for (int b = 0; b < 5; ++b) {
+        const Run rb = ry[b];
+        for (int py = rb.p; py < rb.p + rb.n; ++py)
+#pragma unroll 1
+          for (int c = 0; c < 5; ++c) {
+            const Run rc = rx[c];
+            for (int px = rc.p; px < rc.p + rc.n; ++px) {
+              if (kBoxSrc && !reachable(px, py, pz)) continue;
+              const int64_t sg = (int64_t(ra.g) * geo.ngy + rb.g) * geo.ngx + rc.g;
+              const T* base = src + sg * 5 * P3 + (int64_t(pz + w) * P + (py + w)) * P + (px + w);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s[q] = s[q] + base[q * (kBox * kBox * kBox)];
+              for (int q = 0; q < 5; ++q) s[q] = s[q] + base[q * P3];
+            }
+          }
       }
+  }
 #pragma unroll
   for (int q = 0; q < 5; ++q) glevel[(g * 5 + q) * 4096 + (i & 4095)] = s[q];
 }
@@ -501,23 +552,22 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ p, int64_t n)
 }  // namespace
 
 size_t adjoint_workspace_elems(int64_t n_groups, bool level) {
-  return size_t(n_groups) * (30 * size_t(kS3) + (level ? 5 * size_t(kBox * kBox * kBox) : 0));
+  return level ? size_t(n_groups) * 5 * size_t(kBox * kBox * kBox) : 0;
 }
 
 template <typename T>
 hipError_t launch_mhm_adjoint_padded(const T* U_pad, const T* g_out, T* g_pad, int64_t G, int ghost, const Gas<T>& gas,
-                                     int first_order, int ws, T* work, hipStream_t stream) {
+                                     int first_order, int ws, T* /*work*/, hipStream_t stream) {
   if (G == 0) return hipSuccess;
   if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int P = 16 + 2 * ghost;
   const int64_t n = G * 5 * int64_t(P) * P * P;
   int64_t zb = (n + 255) / 256;
   if (zb > 65536) zb = 65536;
+  // positions the step does not read receive zero
   hipLaunchKernelGGL(zero_kernel<T>, dim3(unsigned(zb)), dim3(256), 0, stream, g_pad, n);
-  hipLaunchKernelGGL(adj_faces_padded<T>, dim3(unsigned(G)), dim3(kThreads), 0, stream, U_pad, g_out, work, ghost,
+  hipLaunchKernelGGL(adj_fused_padded<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, U_pad, g_out, g_pad, ghost,
                      gas, first_order, ws);
-  hipLaunchKernelGGL(adj_cells_padded<T>, dim3(unsigned(G)), dim3(kThreads), 0, stream, U_pad, g_out, work, g_pad,
-                     ghost, gas, first_order);
   return hipGetLastError();
 }
 
@@ -528,15 +578,26 @@ hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, con
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   if (G == 0) return hipSuccess;
   if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
-  T* gut = work;
-  T* gbox = work + G * 30 * int64_t(kS3);
-  hipLaunchKernelGGL(adj_faces_level<T>, dim3(unsigned(G)), dim3(kThreads), 0, stream, level, g_out, gut, geo, gas,
+  if (geo.ngx >= (1 << 19) || geo.ngy >= (1 << 19) || geo.ngz >= (1 << 19)) return hipErrorInvalidValue;
+  T* gbox = work;  // [G][5][20^3]; only reachable positions are written, and only those are read
+  hipLaunchKernelGGL(adj_fused_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, gbox, geo, gas,
                      dt_dev, dx, first_order, ws);
-  hipLaunchKernelGGL(adj_cells_level<T>, dim3(unsigned(G)), dim3(kThreads), 0, stream, level, g_out, gut, gbox, geo,
-                     gas, dt_dev, dx, first_order);
   const int64_t ncells = G * 4096;
-  hipLaunchKernelGGL(adj_gather_level<T>, dim3(unsigned((ncells + 255) / 256)), dim3(256), 0, stream, gbox, g_in, geo,
-                     ncells);
+  hipLaunchKernelGGL((adj_gather<T, true>), dim3(unsigned((ncells + 255) / 256)), dim3(256), 0, stream, gbox, g_in,
+                     geo, 2, ncells);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGeom& geo, int ghost,
+                                       hipStream_t stream) {
+  const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
+  if (G == 0) return hipSuccess;
+  if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
+  if (geo.ngx >= (1 << 19) || geo.ngy >= (1 << 19) || geo.ngz >= (1 << 19)) return hipErrorInvalidValue;
+  const int64_t ncells = G * 4096;
+  hipLaunchKernelGGL((adj_gather<T, false>), dim3(unsigned((ncells + 255) / 256)), dim3(256), 0, stream, g_pad,
+                     g_level, geo, ghost, ncells);
   return hipGetLastError();
 }
 
@@ -550,5 +611,7 @@ template hipError_t launch_mhm_adjoint_level<double>(const double*, const double
 template hipError_t launch_mhm_adjoint_level<float>(const float*, const float*, float*, const LevelGeom&,
                                                     const Gas<float>&, const double*, double, int, int, float*,
                                                     hipStream_t);
+template hipError_t launch_gather_ghost_adjoint<double>(const double*, double*, const LevelGeom&, int, hipStream_t);
+template hipError_t launch_gather_ghost_adjoint<float>(const float*, float*, const LevelGeom&, int, hipStream_t);
 
 }  // namespace gh

@@ -14,24 +14,57 @@ namespace gh {
 
 namespace {
 
+// Work counters: kQueues ticket counters, then the departure counter.
+// Layout mode 0: one queue, items in ticket order.  Mode 1: queue c serves the
+// items c, c + kQueues, c + 2 kQueues, ... and workgroup b starts at queue
+// b % kQueues, moving on to the next queue when its own is empty.  Workgroups
+// of a launch are dealt round-robin to the 8 XCDs, so mode 1 gives every XCD
+// the same residue class of items that a one-launch-per-level grid gives it
+// (its L2 then holds the ghost cells that neighbouring groups in that class
+// share).  Either mode hands every item out exactly once.
 template <typename T, int kWaves>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_batched_kernel(
     BatchArgs<T> args, Gas<T> gas, int first_order, int ws, int* __restrict__ n_bad,
-    unsigned int* __restrict__ work, int order) {
+    unsigned int* __restrict__ work, int order, int queues) {
   __shared__ Smem<T> sm;
-  __shared__ long long item_slot;
-  for (;;) {
-    if (threadIdx.x == 0) {
+  __shared__ long long item_slot[2];
+  __shared__ int tried;  // queues found empty so far (thread 0 only; kept in LDS, not in a register)
+  auto fetch = [&]() -> long long {
+    long long i = -1;
+    if (queues == 0) {
       const unsigned int t = atomicAdd(&work[0], 1u);
-      // order 1: items dealt from the last (finest, largest) level first
-      item_slot = t < args.total ? (order ? (args.total - 1 - (long long)t) : (long long)t) : -1;
+      if (t < args.total) i = (long long)t;
+    } else {
+      const int home = int(blockIdx.x % unsigned(kQueues));
+      for (int q = tried; q < kQueues; tried = ++q) {
+        const int c = (home + q) % kQueues;
+        const long long n_c = c < args.total ? (args.total - c + kQueues - 1) / kQueues : 0;
+        const unsigned int t = atomicAdd(&work[c], 1u);
+        if ((long long)t < n_c) {
+          i = c + (long long)kQueues * t;
+          break;
+        }
+      }
     }
-    __syncthreads();
-    // the slot is the same for every thread: make it wave-uniform so that the
+    // order 1 deals items from the last (finest, largest) level first
+    return i < 0 ? -1 : (order ? args.total - 1 - i : i);
+  };
+  if (threadIdx.x == 0) {
+    tried = 0;
+    item_slot[0] = fetch();
+  }
+  __syncthreads();
+  for (int slot = 0;; slot ^= 1) {
+    // the item is the same for every thread: make it wave-uniform so that the
     // level lookup and everything derived from it live in scalar registers
-    const long long item = (long long)__builtin_amdgcn_readfirstlane((int)(item_slot >> 32)) << 32 |
-                           (unsigned int)__builtin_amdgcn_readfirstlane((int)(item_slot & 0xffffffff));
+    const long long it = item_slot[slot];
+    const long long item = (long long)__builtin_amdgcn_readfirstlane((int)(it >> 32)) << 32 |
+                           (unsigned int)__builtin_amdgcn_readfirstlane((int)(it & 0xffffffff));
     if (item < 0) break;
+    // take the next ticket now; the barriers inside the group step order this
+    // write before the next iteration's read, and every thread has read the
+    // other slot before them
+    if (threadIdx.x == 0) item_slot[slot ^ 1] = fetch();
     int l = 0;
     while (l + 1 < args.n_levels && item >= args.lv[l + 1].g_begin) ++l;
     const BatchLevel<T>& L = args.lv[l];
@@ -46,15 +79,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     }
     const LevelGeom& geo = L.geo;
     LevelSource<T> src{L.in, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
-    const int bad = process_group<T>(src, L.out + g * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0);
+    // an opaque thread index per item keeps thread-derived addresses from
+    // being hoisted out of the item loop (they would stay live across the
+    // whole group step and cost registers / occupancy)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int bad = process_group<T>(src, L.out + g * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
     if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
   }
-  // the last workgroup to leave re-arms the queue for the next launch
+  // the last workgroup to leave re-arms the queues for the next launch
   if (threadIdx.x == 0) {
-    const unsigned int done = atomicAdd(&work[1], 1u);
+    const unsigned int done = atomicAdd(&work[kQueues], 1u);
     if (done == gridDim.x - 1) {
-      atomicExch(&work[0], 0u);
-      atomicExch(&work[1], 0u);
+      for (int c = 0; c <= kQueues; ++c) atomicExch(&work[c], 0u);
     }
   }
 }
@@ -65,13 +102,13 @@ template <typename T>
 hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
                               unsigned int* work, int variant, int grid, hipStream_t stream) {
   if (args.total == 0) return hipSuccess;
-  const int order = variant & 1;
+  const int order = variant & 1, queues = (variant >> 2) & 1;
   if (variant & 2)
     hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo>), dim3(unsigned(grid)), dim3(kThreads), 0, stream,
-                       args, gas, first_order, ws, n_bad, work, order);
+                       args, gas, first_order, ws, n_bad, work, order, queues);
   else
     hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi>), dim3(unsigned(grid)), dim3(kThreads), 0, stream,
-                       args, gas, first_order, ws, n_bad, work, order);
+                       args, gas, first_order, ws, n_bad, work, order, queues);
   return hipGetLastError();
 }
 

@@ -56,12 +56,17 @@ struct LevelSource {
 };
 
 template <typename T, class Src>
-__device__ __forceinline__ void load_prim(const Src& src, int64_t col, int z, const Gas<T>& g, T W[5]) {
+__device__ __forceinline__ void load_cons(const Src& src, int64_t col, int z, T U[5]) {
   const int64_t o = col + src.plane(z);
   const int64_t fs = src.fstride();
-  T U[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) U[q] = src.base[o + q * fs];
+}
+
+template <typename T, class Src>
+__device__ __forceinline__ void load_prim(const Src& src, int64_t col, int z, const Gas<T>& g, T W[5]) {
+  T U[5];
+  load_cons(src, col, z, U);
   cons_to_prim(U, g, W);
 }
 
@@ -76,12 +81,13 @@ struct Smem {
 // Advance one group: read through `src`, write the 16^3 x 5 interior to `out`
 // (field stride 4096).  Returns this thread's unphysical count.  If smax is
 // non-null, also returns (interior threads) the maximum CFL signal speed of
-// the thread's cells in patch-z halves 0..7 and 8..15.
+// the thread's cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's
+// index in the workgroup (a loop over groups passes it opaque, so that the
+// compiler keeps thread-derived addresses out of the loop's live set).
 template <typename T, class Src>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
                                              int first_order, int ws, Smem<T>& sm, double* smax,
-                                             double gamma_d) {
-  const int tid = threadIdx.x;
+                                             double gamma_d, int tid = threadIdx.x) {
   const bool interior = tid < 256;
   int cx, cy;          // own state column
   int ox = 0, oy = 0;  // wave 4: the column two cells out
@@ -106,10 +112,19 @@ __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out
   const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
   const int64_t fs = src.fstride();
 
-  // register ring of the own column's primitive states
+  // register ring of the own column's primitive states; the conserved
+  // values of the next plane to convert are loaded one iteration ahead
+  // (software prefetch: the load latency overlaps a whole plane's work)
   T Wm[5], Wc[5], Wp[5];
+  T Un[5];           // own column, plane k+1 (in flight during iteration k-1)
+  T Uo[5], Ue[5];    // wave 4: 2-deep and edge column, plane k
   if (interior) load_prim(src, col_own, -2, gas, Wm);
   load_prim(src, col_own, -1, gas, Wc);
+  load_cons(src, col_own, 0, Un);
+  if (!interior) {
+    load_cons(src, col_out, 0, Uo);
+    if (has_edge) load_cons(src, col_edge, 0, Ue);
+  }
 
   T Uz[5];         // z+ face state of the previous plane (interior)
   T Fz0[5];        // z flux at the low face of the previous plane (interior)
@@ -117,17 +132,22 @@ __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out
   int bad = 0;
 
   for (int k = -1; k <= 16; ++k) {
-    // ---- next plane of the own column; publish plane k to LDS
-    if (interior || k + 1 <= 16) load_prim(src, col_own, k + 1, gas, Wp);
+    // ---- next plane of the own column (prefetched); publish plane k to LDS
+    if (interior || k + 1 <= 16) {
+      cons_to_prim(Un, gas, Wp);
+      if (k + 2 <= (interior ? 17 : 16)) load_cons(src, col_own, k + 2, Un);
+    }
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.P[q][pidx(cx, cy)] = Wc[q];
     if (!interior && k >= 0 && k <= 15) {
       T Wo[5];
-      load_prim(src, col_out, k, gas, Wo);
+      cons_to_prim(Uo, gas, Wo);
+      if (k + 1 <= 15) load_cons(src, col_out, k + 1, Uo);
 #pragma unroll
       for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
       if (has_edge) {
-        load_prim(src, col_edge, k, gas, Wo);
+        cons_to_prim(Ue, gas, Wo);
+        if (k + 1 <= 15) load_cons(src, col_edge, k + 1, Ue);
 #pragma unroll
         for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
       }
@@ -264,9 +284,10 @@ __device__ __forceinline__ void set_dt(Gas<T>& gas, const double* dt_dev, double
 // Waves per SIMD the register allocation must allow: with 5-wave workgroups,
 // 3 (FP64, <= 168 VGPRs) lets two workgroups share a CU (the LDS of two FP64
 // workgroups fits in 160 KB); 5 (FP32, <= 102 VGPRs) lets four share it.
-// The lower settings leave the allocator free (one or three workgroups).
+// The lower settings leave the allocator room for the prefetched plane (one
+// FP64 or three FP32 workgroups per CU); `value` is the padded step's choice.
 template <typename T> struct MinWaves;
-template <> struct MinWaves<double> { static constexpr int hi = 3, lo = 2; static constexpr int value = hi; };
-template <> struct MinWaves<float> { static constexpr int hi = 5, lo = 4; static constexpr int value = hi; };
+template <> struct MinWaves<double> { static constexpr int hi = 3, lo = 2; static constexpr int value = lo; };
+template <> struct MinWaves<float> { static constexpr int hi = 5, lo = 4; static constexpr int value = lo; };
 
 }  // namespace gh

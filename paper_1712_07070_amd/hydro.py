@@ -26,6 +26,8 @@ WAVESPEED_ROE = 0 << 8
 WAVESPEED_DAVIS = 1 << 8
 FIRST_ORDER = 1 << 10
 BC_PERIODIC, BC_OUTFLOW = 0, 1
+BATCH_WORK_WORDS = 16       # uint32 words of the batched kernel's work buffer
+BATCHED_VARIANTS = 8        # launch shapes of the batched kernel
 
 _lib = None
 
@@ -62,6 +64,7 @@ def load():
                                       P]),
         "hydro_dt": (i32, [P, i64, i32, i32, f64, f64, f64, P, P, P]),
         "hydro_fill_ghosts": (i32, [P, P, i32, i32, i32, i32, i32, P, P]),
+        "hydro_gather_ghost_adjoint": (i32, [P, P, i32, i32, i32, i32, i32, P, P]),
         "hydro_num_variants": (i32, []),
         "hydro_set_variant": (i32, [i32, i32]),
         "hydro_get_variant": (i32, [i32]),
@@ -259,6 +262,26 @@ def fill_ghosts(level: torch.Tensor, ng: Sequence[int], ghost: int, bc: Sequence
     return out
 
 
+def gather_ghost_adjoint(g_pad: torch.Tensor, ng: Sequence[int], ghost: int, bc: Sequence[int],
+                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Padded cotangents [G,5,P,P,P] -> level cotangents [G,5,16,16,16], the
+    transpose of fill_ghosts (hydro_gather_ghost_adjoint)."""
+    ngx, ngy, ngz = (int(v) for v in ng)
+    G = ngx * ngy * ngz
+    P = 16 + 2 * int(ghost)
+    if tuple(g_pad.shape) != (G, 5, P, P, P):
+        raise ValueError("g_pad must be [G,5,P,P,P] with G = ngx*ngy*ngz, P = 16 + 2 ghost")
+    if out is None:
+        out = torch.empty((G, 5, 16, 16, 16), dtype=g_pad.dtype, device=g_pad.device)
+    if out.dtype != g_pad.dtype or tuple(out.shape) != (G, 5, 16, 16, 16):
+        raise ValueError("out must be [G,5,16,16,16] of the g_pad dtype")
+    b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
+    st = load().hydro_gather_ghost_adjoint(_dev(g_pad, "g_pad"), _dev(out, "out"), ngx, ngy, ngz, int(ghost),
+                                           _dtype_code(g_pad), b, _stream())
+    _check(st, "hydro_gather_ghost_adjoint")
+    return out
+
+
 def _levels_array(levels):
     arr = (HydroLevel * len(levels))()
     dtype = None
@@ -287,9 +310,9 @@ def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5
     """One step of several levels in one persistent launch (hydro_advance_batched).
 
     levels: sequence of (level_in, level_out, ng, bc, dt, dx[, dt_dev]);
-    work: int32 device tensor of 2 zeros (re-armed by every launch)."""
-    if work.dtype != torch.int32 or work.numel() < 2:
-        raise ValueError("work must hold 2 int32")
+    work: int32 device tensor of BATCH_WORK_WORDS zeros (re-armed by every launch)."""
+    if work.dtype != torch.int32 or work.numel() < BATCH_WORK_WORDS:
+        raise ValueError("work must hold %d int32" % BATCH_WORK_WORDS)
     arr, dtype = _levels_array(levels)
     st = load().hydro_advance_batched(ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
                                       float(gamma), int(scheme), float(theta), _opt(n_bad, "n_bad", torch.int32),
@@ -298,8 +321,10 @@ def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5
 
 
 def autotune_batched(levels, gamma: float, work: torch.Tensor, reps: int = 5) -> Tuple[int, list]:
+    if work.dtype != torch.int32 or work.numel() < BATCH_WORK_WORDS:
+        raise ValueError("work must hold %d int32" % BATCH_WORK_WORDS)
     arr, dtype = _levels_array(levels)
-    times = (ctypes.c_float * 4)()
+    times = (ctypes.c_float * BATCHED_VARIANTS)()
     st = load().hydro_autotune_batched(ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
                                        float(gamma), _dev(work, "work"), int(reps), times, _stream())
     if st < 0:
@@ -378,7 +403,7 @@ class MultiLevel:
         self.bufs = [[torch.empty((ng[0] * ng[1] * ng[2], 5, 16, 16, 16), dtype=dtype, device=dev) for _ in range(2)]
                      for ng, _, _ in self.geo]
         self.cur = [0] * self.L
-        self.work = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.work = torch.zeros(BATCH_WORK_WORDS, dtype=torch.int32, device=dev)
         self.n_bad = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def load_state(self, l: int, U: torch.Tensor):

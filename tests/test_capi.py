@@ -76,3 +76,18 @@ def test_dt_and_fill_reject_bad_arguments(lib):
     assert lib.hydro_fill_ghosts(P(4096), P(1 << 40), 1, 1, 1, 17, 0, bc, None) == -1
     assert lib.hydro_fill_ghosts(P(4096), P(1 << 40), 1, 1, 1, 3, 0, badbc, None) == -1
     assert lib.hydro_fill_ghosts(P(4096), P(4096 + 64), 1, 1, 1, 3, 0, bc, None) == -1
+
+
+def test_gather_ghost_adjoint_rejects_bad_arguments(lib):
+    P = ctypes.c_void_p
+    bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    badbc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 5)
+    f = lib.hydro_gather_ghost_adjoint
+    assert f(P(4096), P(1 << 40), 1, 0, 1, 3, 0, bc, None) == -1
+    assert f(P(4096), P(1 << 40), 1, 1, 1, -1, 0, bc, None) == -1
+    assert f(P(4096), P(1 << 40), 1, 1, 1, 17, 0, bc, None) == -1
+    assert f(P(4096), P(1 << 40), 1, 1, 1, 3, 2, bc, None) == -1
+    assert f(P(4096), P(1 << 40), 1, 1, 1, 3, 0, badbc, None) == -1
+    assert f(P(4096), P(1 << 40), 1, 1, 1, 3, 0, None, None) == -1
+    assert f(None, P(1 << 40), 1, 1, 1, 3, 0, bc, None) == -1
+    assert f(P(4096), P(4096 + 8), 1, 1, 1, 3, 0, bc, None) == -1   # output overlaps the input

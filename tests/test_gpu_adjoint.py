@@ -100,10 +100,11 @@ def test_step_adjoint_elementwise(hydro):
         assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), ((q, z, y, x), got, ref)
 
 
-@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (1, 1, 0, 0, 1, 0)])
-def test_level_adjoint_dot_product(hydro, bc):
-    say("level adjoint", bc)
-    U, ng, dx = smooth_all_fields(32)
+@pytest.mark.parametrize("n,bc", [(32, (0, 0, 0, 0, 0, 0)), (32, (1, 1, 0, 0, 1, 0)),
+                                  (48, (1, 0, 0, 1, 1, 0))])   # one-sided periodic faces, 3 groups per axis
+def test_level_adjoint_dot_product(hydro, n, bc):
+    say("level adjoint", n, bc)
+    U, ng, dx = smooth_all_fields(n)
     rng = np.random.default_rng(3)
     v = rng.normal(size=U.shape)
     w = rng.normal(size=U.shape)
@@ -112,6 +113,46 @@ def test_level_adjoint_dot_product(hydro, bc):
     JTw = host(hydro.advance_level_adjoint(dev(U), dev(w), ng, bc, dt, dx, G53))
     lhs, rhs = float(np.sum(Jv * w)), float(np.sum(v * JTw))
     assert rel(lhs, rhs) <= 1e-11, (lhs, rhs)
+
+
+GATHER_CASES = [((1, 1, 1), 3, (0, 0, 0, 0, 0, 0)), ((1, 1, 1), 16, (1, 1, 0, 1, 1, 0)),
+                 ((3, 2, 1), 3, (1, 0, 0, 1, 1, 1)), ((4, 1, 3), 2, (0, 1, 1, 0, 0, 0)),
+                 ((2, 3, 2), 0, (1, 1, 1, 1, 1, 1)), ((3, 3, 3), 5, (1, 0, 0, 1, 1, 0))]
+
+
+@pytest.mark.parametrize("ng,ghost,bc", GATHER_CASES)
+def test_gather_ghost_adjoint_is_transpose_of_fill(hydro, ng, ghost, bc):
+    """<fill(x), y> = <x, gather(y)>, with fill the oracle's ghost fill."""
+    say("gather transpose", ng, ghost, bc)
+    G = ng[0] * ng[1] * ng[2]
+    P = 16 + 2 * ghost
+    rng = np.random.default_rng(G * 100 + ghost)
+    x = rng.normal(size=(G, 5, 16, 16, 16))
+    y = rng.normal(size=(G, 5, P, P, P))
+    lhs = float(np.sum(oracle.fill_ghosts(x, ng, ghost, bc) * y))
+    gx = host(hydro.gather_ghost_adjoint(dev(y), ng, ghost, bc))
+    rhs = float(np.sum(x * gx))
+    assert rel(lhs, rhs) <= 1e-12, (lhs, rhs)
+    # FP32 sums the same copies
+    gx32 = host(hydro.gather_ghost_adjoint(dev(y.astype(np.float32)), ng, ghost, bc)).astype(np.float64)
+    assert np.max(np.abs(gx32 - gx)) <= 1e-5 * max(1.0, np.max(np.abs(gx)))
+
+
+@pytest.mark.parametrize("n,bc", [(32, (1, 1, 0, 0, 1, 0)), (48, (1, 0, 0, 1, 1, 0))])
+def test_level_adjoint_equals_padded_adjoint_plus_gather(hydro, n, bc):
+    """The level path (box + gather) and the padded path (hydro_advance_adjoint
+    on filled groups, then hydro_gather_ghost_adjoint) sum the same terms in
+    the same order."""
+    say("level == padded + gather", n, bc)
+    U, ng, dx = smooth_all_fields(n)
+    w = dev(np.random.default_rng(n).normal(size=U.shape))
+    dt = 0.3 * dx
+    t = dev(U)
+    a = hydro.advance_level_adjoint(t, w, ng, bc, dt, dx, G53)
+    pad = hydro.fill_ghosts(t, ng, 3, bc)
+    gpad = hydro.advance_adjoint(pad, w, dt, dx, G53)
+    b = hydro.gather_ghost_adjoint(gpad, ng, 3, bc)
+    assert torch.equal(a, b)
 
 
 def test_level_adjoint_single_group_and_two_groups(hydro):

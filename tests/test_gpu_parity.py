@@ -400,10 +400,10 @@ def test_batched_equals_per_level(hydro, dtype):
     dt0 = 0.3 * min(float(oracle.dt_patch(lv.U.astype(np.float64), lv.dx, lv.gamma).min()) * 2 ** l
                     for l, lv in enumerate(lvs))
     ref = [hydro.advance_level(t, lv.ng, lv.bc, dt0 / 2 ** l, lv.dx, lv.gamma) for l, (t, lv) in enumerate(zip(ins, lvs))]
-    work = torch.zeros(2, dtype=torch.int32, device="cuda")
+    work = torch.zeros(hydro.BATCH_WORK_WORDS, dtype=torch.int32, device="cuda")
     saved = hydro.get_batched_variant(tdt)
     try:
-        for v in range(4):
+        for v in range(hydro.BATCHED_VARIANTS):
             hydro.set_batched_variant(tdt, v)
             outs = [torch.empty_like(t) for t in ins]
             nb = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -412,7 +412,7 @@ def test_batched_equals_per_level(hydro, dtype):
             for o, r in zip(outs, ref):
                 assert torch.equal(o, r)
             assert int(host(nb)[0]) == 0
-            assert host(work).tolist() == [0, 0]       # the queue re-arms itself
+            assert not host(work).any()       # the queues re-arm themselves
     finally:
         hydro.set_batched_variant(tdt, saved)
     # and the per-level result is the oracle's
@@ -427,14 +427,22 @@ def test_batched_small_grid_and_uneven_items(hydro):
     say("batched small grid")
     lvs = _amr_levels()
     ins = [dev(lv.U) for lv in lvs]
-    work = torch.zeros(2, dtype=torch.int32, device="cuda")
+    work = torch.zeros(hydro.BATCH_WORK_WORDS, dtype=torch.int32, device="cuda")
     a = [torch.empty_like(t) for t in ins]
     b = [torch.empty_like(t) for t in ins]
     ent = lambda outs: [(t, o, lv.ng, lv.bc, 1e-4 / 2 ** l, lv.dx) for l, (t, o, lv) in enumerate(zip(ins, outs, lvs))]
-    hydro.advance_batched(ent(a), 5 / 3, work, grid=3)
-    hydro.advance_batched(ent(b), 5 / 3, work, grid=0)
-    for x, y in zip(a, b):
-        assert torch.equal(x, y)
+    saved = hydro.get_batched_variant(torch.float64)
+    try:
+        for v in (0, 4):   # one queue; per-XCD queues (3 and 5 workgroups steal from empty-handed queues)
+            hydro.set_batched_variant(torch.float64, v)
+            hydro.advance_batched(ent(b), 5 / 3, work, grid=0)
+            for grid in (3, 5):
+                hydro.advance_batched(ent(a), 5 / 3, work, grid=grid)
+                for x, y in zip(a, b):
+                    assert torch.equal(x, y)
+                assert not host(work).any()
+    finally:
+        hydro.set_batched_variant(torch.float64, saved)
 
 
 def test_wcycle_graph_replays_match_eager(hydro):
