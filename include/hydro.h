@@ -194,15 +194,16 @@ typedef struct {
  *                four in FP32, capped at the item count)
  * Launch shapes (process-wide per dtype, HYDRO_BATCHED_VARIANTS of them):
  * bit 0 item order (0: level 0 first, 1: finest level first), bit 1
- * occupancy target, bit 2 queues (0: one queue; 1: one queue per XCD, each
- * serving one residue class of items mod 8, with stealing when it runs dry);
+ * occupancy target, bits 2-3 work distribution (0: one queue; 1: one queue
+ * per XCD, each serving one residue class of items mod 8, with stealing when
+ * it runs dry; 2: static round-robin, workgroup b takes items b, b + grid, ...);
  * hydro_set_batched_variant / hydro_get_batched_variant select and read it,
  * hydro_autotune_batched times all of them on the given levels (SYNCHRONOUS;
  * the outputs are overwritten; times_ms_host receives HYDRO_BATCHED_VARIANTS
  * floats) and keeps the fastest.
  */
 #define HYDRO_BATCH_WORK_WORDS 16
-#define HYDRO_BATCHED_VARIANTS 8
+#define HYDRO_BATCHED_VARIANTS 12
 int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
                           int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
                           void* stream);

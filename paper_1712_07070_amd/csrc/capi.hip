@@ -22,10 +22,10 @@ thread_local int g_last_hip_error = 0;
 
 // Launch shape of the level step per dtype (index into the variants of
 // mhm_fwd.hip); set by hydro_set_variant or hydro_autotune, process-wide.
-std::atomic<int> g_level_variant[2] = {{3}, {2}};  // measured defaults: FP64 plain order, FP32 XCD-blocked; both low occupancy
+std::atomic<int> g_level_variant[2] = {{1}, {1}};  // measured defaults: plain order, high occupancy
 // Launch shape of the batched kernel per dtype (bit 0: item order, bit 1:
 // occupancy target, bit 2: per-XCD queues).
-std::atomic<int> g_batched_variant[2] = {{6}, {6}};  // per-XCD queues, low occupancy
+std::atomic<int> g_batched_variant[2] = {{0}, {0}};  // one queue, high occupancy
 
 // Compute units of the current device (persistent-grid size), cached per device.
 int device_cus() {

@@ -83,10 +83,11 @@ hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGe
 // bit 1 set = lower occupancy target for the register allocator.
 constexpr int kLevelVariants = 4;
 // Batched kernel: ticket queues (one per XCD of MI355X), launch-shape variants
-// (bit 0 item order, bit 1 occupancy target, bit 2 per-XCD queues) and the
-// uint32 words of its work buffer (kQueues tickets + 1 departure counter).
+// (bit 0 item order, bit 1 occupancy target, bits 2-3 queue mode: one queue,
+// per-XCD queues, static round-robin) and the uint32 words of its work buffer
+// (kQueues tickets + 1 departure counter).
 constexpr int kQueues = 8;
-constexpr int kBatchedVariants = 8;
+constexpr int kBatchedVariants = 12;
 constexpr int kBatchWorkWords = 16;
 static_assert(kQueues + 1 <= kBatchWorkWords, "work buffer too small");
 

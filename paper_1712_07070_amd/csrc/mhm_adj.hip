@@ -103,6 +103,11 @@ __device__ __forceinline__ void finalize_cell(const Src& src, int64_t col, int x
 // that role after the interior one in every phase.  One wave per SIMD leaves
 // the whole register file (VGPRs and AGPRs) to each wave.
 constexpr int kAdjThreads = 256;
+// Waves per SIMD the register allocation targets: FP64 takes the whole
+// register file (one workgroup per CU, which its LDS needs anyway); FP32 fits
+// two workgroups per CU (LDS 75 KB each) at a few spilled registers, which
+// measured faster than one workgroup with none.
+template <typename T> struct AdjWaves { static constexpr int value = sizeof(T) == 8 ? 1 : 2; };
 
 template <typename T>
 struct SmemF {
@@ -123,6 +128,10 @@ __device__ __forceinline__ bool in_state_plane(int x, int y, int z) {
 }
 
 // Per-column state of one role (interior or halo column) across the march.
+// The column's primitive states of planes k-2, k-1, k are read back from the
+// LDS planes (the column publishes its own values there); only W(k+1) lives
+// in registers.  A halo column solves at most one face (x = 16 or y = 16), so
+// its face state and face cotangent share the x slots.
 template <typename T, bool kInterior>
 struct AdjCol {
   static constexpr bool interior = kInterior;
@@ -130,7 +139,7 @@ struct AdjCol {
   int cx, cy;
   bool xface16, yface16;
   int64_t col;
-  T Wm[5], Wc[5], Wp[5];      // W(k-1), W(k), W(k+1); W(k-2) is read back from LDS
+  T Wp[5];                    // W(k+1) (becomes W(k) at the next publish)
   T Uz[5];                    // z+ face state of plane k-1 (interior columns)
   T Ux[5], Uy[5];             // own x- and y- face states of plane k
   T gRx[5], gRy[5], gRz[5];   // cotangents of the own x-, y-, z- face states of plane k-1
@@ -146,11 +155,12 @@ __device__ __forceinline__ void adj_col_init(AdjCol<T, kI>& c, const Src& src, i
   c.yface16 = !kI && cy == 16;
   c.col = src.col(cx, cy);
   if (kI) {
-    load_prim(src, c.col, -2, gas, c.Wm);
+    T W[5];
+    load_prim(src, c.col, -2, gas, W);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sm.P[pslot(-2)][q][pidx(cx, cy)] = c.Wm[q];
+    for (int q = 0; q < 5; ++q) sm.P[pslot(-2)][q][pidx(cx, cy)] = W[q];
   }
-  load_prim(src, c.col, -1, gas, c.Wc);
+  load_prim(src, c.col, -1, gas, c.Wp);  // published as plane -1 by the first iteration
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     c.gRx[q] = c.gRy[q] = c.gRz[q] = T(0);
@@ -158,13 +168,14 @@ __device__ __forceinline__ void adj_col_init(AdjCol<T, kI>& c, const Src& src, i
   }
 }
 
-// F1: next plane of the column; publish plane k.
+// F1: publish plane k (loaded last iteration); load plane k+1.  Interior
+// columns publish up to plane 17 (read back by the last reverse predictor).
 template <typename T, bool kI, class Src>
 __device__ __forceinline__ void adj_col_publish(AdjCol<T, kI>& c, const Src& src, int k, const Gas<T>& gas,
                                                 SmemF<T>& sm) {
-  if (kI || k + 1 <= 16) load_prim(src, c.col, k + 1, gas, c.Wp);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) sm.P[pslot(k)][q][pidx(c.cx, c.cy)] = c.Wc[q];
+  for (int q = 0; q < 5; ++q) sm.P[pslot(k)][q][pidx(c.cx, c.cy)] = c.Wp[q];
+  if (k + 1 <= c.zhi) load_prim(src, c.col, k + 1, gas, c.Wp);
 }
 
 // F2: half-step states of plane k and the z-face (k-1 | k) VJP; then the
@@ -177,24 +188,29 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
   T gLz[5] = {T(0), T(0), T(0), T(0), T(0)};   // cotangent of the z+ face state of plane k-1
   T gRzn[5] = {T(0), T(0), T(0), T(0), T(0)};  // cotangent of the z- face state of plane k
   if (k <= 16 && in_state_plane(cx, cy, k)) {
-    T Wn[3][2][5];
+    T Wc[5], Wn[3][2][5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
+      Wc[q] = sm.P[sk][q][pidx(cx, cy)];
       Wn[0][0][q] = sm.P[sk][q][pidx(cx - 1, cy)];
       Wn[0][1][q] = sm.P[sk][q][pidx(cx + 1, cy)];
       Wn[1][0][q] = sm.P[sk][q][pidx(cx, cy - 1)];
       Wn[1][1][q] = sm.P[sk][q][pidx(cx, cy + 1)];
-      Wn[2][0][q] = c.Wm[q];
+      Wn[2][0][q] = sm.P[sj][q][pidx(cx, cy)];
       Wn[2][1][q] = c.Wp[q];
     }
     T Ut[3][2][5];
-    hancock_states(c.Wc, Wn, gas, fo, Ut);
+    hancock_states(Wc, Wn, gas, fo, Ut);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
       sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
-      c.Ux[q] = Ut[0][0][q];
-      c.Uy[q] = Ut[1][0][q];
+      if (kI) {
+        c.Ux[q] = Ut[0][0][q];
+        c.Uy[q] = Ut[1][0][q];
+      } else {
+        c.Ux[q] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
+      }
     }
     if (kI) {
       if (k >= 0) {
@@ -212,13 +228,15 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
   if (j >= -1 && in_state_plane(cx, cy, j)) {
     const bool u0 = face_used(cx, cy, j, 0), u1 = face_used(cx, cy, j, 1), u2 = face_used(cx, cy, j, 2);
     const bool u3 = face_used(cx, cy, j, 3), u4 = face_used(cx, cy, j, 4), u5 = face_used(cx, cy, j, 5);
-    T gWc[5];
+    T Wj[5], gWc[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Wj[q] = sm.P[sj][q][pidx(cx, cy)];
     hancock_states_vjp_stream(
-        c.Wm, gas, fo,
+        Wj, gas, fo,
         [&](int d, int side, T W[5]) {
           if (d == 2) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) W[q] = side == 0 ? sm.P[si][q][pidx(cx, cy)] : c.Wc[q];
+            for (int q = 0; q < 5; ++q) W[q] = sm.P[side == 0 ? si : sk][q][pidx(cx, cy)];
           } else {
             const int x = d == 0 ? cx + (side ? 1 : -1) : cx, y = d == 1 ? cy + (side ? 1 : -1) : cy;
 #pragma unroll
@@ -233,7 +251,7 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
             T v;
             if (f == 0) v = c.gRx[q];
             else if (f == 1) v = sm.GL[0][q][sidx(cx, cy)];
-            else if (f == 2) v = c.gRy[q];
+            else if (f == 2) v = kI ? c.gRy[q] : c.gRx[q];
             else if (f == 3) v = sm.GL[1][q][sidx(cx, cy)];
             else if (f == 4) v = c.gRz[q];
             else v = gLz[q];
@@ -263,7 +281,7 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
 }
 
 // F3a: the x and y face VJPs this column solves at plane k (its x- face and
-// y- face; halo columns only the faces at x = 16 / y = 16).
+// y- face; halo columns only the face at x = 16 or y = 16).
 template <typename T, bool kI>
 __device__ __forceinline__ void adj_col_faces(AdjCol<T, kI>& c, int k, const T* __restrict__ go, const Gas<T>& gas,
                                               int ws, SmemF<T>& sm) {
@@ -282,14 +300,16 @@ __device__ __forceinline__ void adj_col_faces(AdjCol<T, kI>& c, int k, const T* 
     for (int q = 0; q < 5; ++q) sm.GL[0][q][sidx(cx - 1, cy)] = gL[q];
   }
   if (kI || c.yface16) {
+    T* Uy = kI ? c.Uy : c.Ux;
+    T* gRy = kI ? c.gRy : c.gRx;
     T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       L[q] = sm.S[1][q][sidx(cx, cy - 1)];
       gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy - 1, k));
-      c.gRy[q] = T(0);
+      gRy[q] = T(0);
     }
-    hllc_flux_vjp<1>(L, c.Uy, gas, ws, gF, gL, c.gRy);
+    hllc_flux_vjp<1>(L, Uy, gas, ws, gF, gL, gRy);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.GL[1][q][sidx(cx, cy - 1)] = gL[q];
   }
@@ -329,8 +349,6 @@ __device__ __forceinline__ void adj_col_finish(AdjCol<T, kI>& c, const Src& src,
     c.A0[q] = c.A1[q];
     c.A1[q] = c.A2[q];
     c.A2[q] = T(0);
-    c.Wm[q] = c.Wc[q];
-    c.Wc[q] = c.Wp[q];
   }
 }
 
@@ -357,8 +375,8 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
 
   for (int k = -1; k <= 17; ++k) {
     const int sk = pslot(k);
+    adj_col_publish(ci, src, k, gas, sm);
     if (k <= 16) {
-      adj_col_publish(ci, src, k, gas, sm);
       if (halo) {
         adj_col_publish(ch, src, k, gas, sm);
         if (k >= 0 && k <= 15) {
@@ -415,7 +433,7 @@ __device__ __forceinline__ void set_dt_adj(Gas<T>& gas, const double* dt_dev, do
 }
 
 template <typename T>
-__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void adj_fused_padded(const T* __restrict__ Upad, const T* __restrict__ gout_,
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(AdjWaves<T>::value, AdjWaves<T>::value))) void adj_fused_padded(const T* __restrict__ Upad, const T* __restrict__ gout_,
                                                              T* __restrict__ gpad, int gh, Gas<T> gas, int first_order,
                                                              int ws) {
   __shared__ SmemF<T> sm;
@@ -428,7 +446,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void adj_fused_level(const T* __restrict__ level, const T* __restrict__ gout_,
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(AdjWaves<T>::value, AdjWaves<T>::value))) void adj_fused_level(const T* __restrict__ level, const T* __restrict__ gout_,
                                                             T* __restrict__ gbox, LevelGeom geo, Gas<T> gas,
                                                             const double* __restrict__ dt_dev, double dx,
                                                             int first_order, int ws) {

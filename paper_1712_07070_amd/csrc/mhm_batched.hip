@@ -15,56 +15,68 @@ namespace gh {
 namespace {
 
 // Work counters: kQueues ticket counters, then the departure counter.
-// Layout mode 0: one queue, items in ticket order.  Mode 1: queue c serves the
+// Queue modes: 0, one queue, items in ticket order; 1, queue c serves the
 // items c, c + kQueues, c + 2 kQueues, ... and workgroup b starts at queue
-// b % kQueues, moving on to the next queue when its own is empty.  Workgroups
-// of a launch are dealt round-robin to the 8 XCDs, so mode 1 gives every XCD
-// the same residue class of items that a one-launch-per-level grid gives it
-// (its L2 then holds the ghost cells that neighbouring groups in that class
-// share).  Either mode hands every item out exactly once.
+// b % kQueues, moving on to the next queue when its own is empty; 2, no
+// queue: workgroup b takes items b, b + grid, b + 2 grid, ... (static).
+// Workgroups of a launch are dealt round-robin to the 8 XCDs, so modes 1 and
+// 2 give every XCD the same residue class of items that a one-launch-per-level
+// grid gives it (its L2 then holds the ghost cells that neighbouring groups in
+// that class share).  Every mode hands every item out exactly once.
+//
+// The ticket for the next item is taken when an item starts and decoded when
+// it ends, so the atomic's round trip overlaps the whole group step.
 template <typename T, int kWaves>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_batched_kernel(
     BatchArgs<T> args, Gas<T> gas, int first_order, int ws, int* __restrict__ n_bad,
     unsigned int* __restrict__ work, int order, int queues) {
   __shared__ Smem<T> sm;
-  __shared__ long long item_slot[2];
-  __shared__ int tried;  // queues found empty so far (thread 0 only; kept in LDS, not in a register)
-  auto fetch = [&]() -> long long {
-    long long i = -1;
-    if (queues == 0) {
-      const unsigned int t = atomicAdd(&work[0], 1u);
-      if (t < args.total) i = (long long)t;
+  __shared__ long long item_slot;
+  __shared__ int tried;  // queues found empty / static items taken (thread 0 only)
+  const int home = int(blockIdx.x % unsigned(kQueues));
+  auto queue_size = [&](int c) -> long long {
+    return c < args.total ? (args.total - c + kQueues - 1) / kQueues : 0;
+  };
+  // the queue the next ticket comes from (mode 0: the only one)
+  auto cur_queue = [&]() { return queues == 1 ? (home + tried) % kQueues : 0; };
+  // ticket t of the current queue -> item (or -1 if that queue is exhausted)
+  auto decode = [&](unsigned int t) -> long long {
+    if (queues == 0) return t < args.total ? (long long)t : -1;
+    const int c = cur_queue();
+    return (long long)t < queue_size(c) ? c + (long long)kQueues * t : -1;
+  };
+  // take a ticket (thread 0); for mode 2 the "ticket" is the static index
+  auto take = [&]() -> unsigned int {
+    if (queues == 2) return unsigned(tried++);
+    return atomicAdd(&work[cur_queue()], 1u);
+  };
+  // resolve a taken ticket into the next item, moving on through exhausted queues
+  auto resolve = [&](unsigned int t) -> long long {
+    long long i;
+    if (queues == 2) {
+      const long long c = (long long)blockIdx.x + (long long)t * gridDim.x;
+      i = c < args.total ? c : -1;
     } else {
-      const int home = int(blockIdx.x % unsigned(kQueues));
-      for (int q = tried; q < kQueues; tried = ++q) {
-        const int c = (home + q) % kQueues;
-        const long long n_c = c < args.total ? (args.total - c + kQueues - 1) / kQueues : 0;
-        const unsigned int t = atomicAdd(&work[c], 1u);
-        if ((long long)t < n_c) {
-          i = c + (long long)kQueues * t;
-          break;
-        }
-      }
+      i = decode(t);
+      while (i < 0 && queues == 1 && ++tried < kQueues) i = decode(atomicAdd(&work[cur_queue()], 1u));
     }
     // order 1 deals items from the last (finest, largest) level first
     return i < 0 ? -1 : (order ? args.total - 1 - i : i);
   };
   if (threadIdx.x == 0) {
     tried = 0;
-    item_slot[0] = fetch();
+    item_slot = resolve(take());
   }
   __syncthreads();
-  for (int slot = 0;; slot ^= 1) {
+  for (;;) {
     // the item is the same for every thread: make it wave-uniform so that the
     // level lookup and everything derived from it live in scalar registers
-    const long long it = item_slot[slot];
+    const long long it = item_slot;
     const long long item = (long long)__builtin_amdgcn_readfirstlane((int)(it >> 32)) << 32 |
                            (unsigned int)__builtin_amdgcn_readfirstlane((int)(it & 0xffffffff));
     if (item < 0) break;
-    // take the next ticket now; the barriers inside the group step order this
-    // write before the next iteration's read, and every thread has read the
-    // other slot before them
-    if (threadIdx.x == 0) item_slot[slot ^ 1] = fetch();
+    unsigned int ticket = 0;
+    if (threadIdx.x == 0) ticket = take();
     int l = 0;
     while (l + 1 < args.n_levels && item >= args.lv[l + 1].g_begin) ++l;
     const BatchLevel<T>& L = args.lv[l];
@@ -86,6 +98,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     asm volatile("" : "+v"(tid));
     const int bad = process_group<T>(src, L.out + g * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
     if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
+    // every thread has read item_slot (first barrier of the group step)
+    if (threadIdx.x == 0) item_slot = resolve(ticket);
+    __syncthreads();
   }
   // the last workgroup to leave re-arms the queues for the next launch
   if (threadIdx.x == 0) {
@@ -102,7 +117,7 @@ template <typename T>
 hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
                               unsigned int* work, int variant, int grid, hipStream_t stream) {
   if (args.total == 0) return hipSuccess;
-  const int order = variant & 1, queues = (variant >> 2) & 1;
+  const int order = variant & 1, queues = (variant >> 2) & 3;
   if (variant & 2)
     hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo>), dim3(unsigned(grid)), dim3(kThreads), 0, stream,
                        args, gas, first_order, ws, n_bad, work, order, queues);

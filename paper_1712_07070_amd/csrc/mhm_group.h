@@ -1,7 +1,7 @@
 // Per-group device code of the MHM step shared by the level kernels
 // (mhm_fwd.hip) and the batched persistent kernel (mhm_batched.hip): input
 // sources, the LDS layout, and the z-marching routine that advances one
-// 16^3 patch group with one 320-thread workgroup.  See mhm_fwd.hip for the
+// 16^3 patch group with one 256-thread workgroup.  See mhm_fwd.hip for the
 // mapping of threads to columns.
 #pragma once
 
@@ -10,7 +10,7 @@
 
 namespace gh {
 
-constexpr int kThreads = 320;
+constexpr int kThreads = 256;
 constexpr int kPW = 20;  // primitive plane tile: x, y in [-2, 17]
 constexpr int kSW = 18;  // state tile: x, y in [-1, 16]
 
@@ -78,169 +78,224 @@ struct Smem {
 };
 
 // ---------------------------------------------------- one patch group ----
+// Workgroup of 256 threads (4 waves; the hardware gives each wave of a
+// workgroup its own SIMD).  Every thread owns one interior (x, y) column; the
+// 64 threads of wave 0 also own one "halo" column one cell outside the
+// interior (x = -1, x = 16, y = -1, y = 16), whose half-step states feed the
+// faces on the group boundary, together with the column two cells out and,
+// for 4 of them, an edge column (both only read as neighbours).  Wave 0 runs
+// its halo role after its interior role in every phase.
+
+// Per-column state of one role across the z-march.
+template <typename T, bool kInterior>
+struct FwdCol {
+  static constexpr int zhi = kInterior ? 17 : 16;  // last plane of the column that is read
+  int cx, cy;
+  bool xface16, yface16;  // halo columns at x = 16 / y = 16 solve the last x / y face
+  int64_t col;
+  T Wm[5], Wc[5], Wp[5];  // primitive states at planes k-1, k, k+1
+  T Un[5];                // conserved values of the next plane to convert (in flight)
+  T Ux[5], Uy[5];         // own x- and y- face states of plane k (halo: Ux holds the one it uses)
+  T Uz[5], Fz0[5];        // interior: z+ face state of plane k-1; z flux at the low face of plane k-1
+};
+
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ void fwd_col_init(FwdCol<T, kI>& c, const Src& src, int cx, int cy, const Gas<T>& gas) {
+  c.cx = cx;
+  c.cy = cy;
+  c.xface16 = !kI && cx == 16;
+  c.yface16 = !kI && cy == 16;
+  c.col = src.col(cx, cy);
+  if (kI) load_prim(src, c.col, -2, gas, c.Wm);
+  load_prim(src, c.col, -1, gas, c.Wc);
+  load_cons(src, c.col, 0, c.Un);
+}
+
+// Next plane of the column (prefetched one iteration ahead); publish plane k.
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ void fwd_col_publish(FwdCol<T, kI>& c, const Src& src, int k, const Gas<T>& gas,
+                                                Smem<T>& sm) {
+  if (k + 1 <= c.zhi) {
+    cons_to_prim(c.Un, gas, c.Wp);
+    if (k + 2 <= c.zhi) load_cons(src, c.col, k + 2, c.Un);
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sm.P[q][pidx(c.cx, c.cy)] = c.Wc[q];
+}
+
+// Half-step face states of the column's state cell at plane k.  Interior
+// columns also solve the z-face k-1/2 and complete plane k-1.
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ int fwd_col_states(FwdCol<T, kI>& c, const Src& src, T* __restrict__ out, int k,
+                                              const Gas<T>& gas, int first_order, int ws, Smem<T>& sm, double* smax,
+                                              double gamma_d) {
+  const int cx = c.cx, cy = c.cy;
+  int bad = 0;
+  // x/y flux differences of plane k-1 (fluxes written last iteration)
+  T acc[5];
+  if (kI && k >= 1) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      acc[q] = sm.F[0][q][fxidx(cx + 1, cy)] - sm.F[0][q][fxidx(cx, cy)];
+      acc[q] = acc[q] + (sm.F[1][q][fyidx(cx, cy + 1)] - sm.F[1][q][fyidx(cx, cy)]);
+    }
+  }
+  if (!kI && (k < 0 || k > 15)) return 0;
+  T Wn[3][2][5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
+    Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
+    Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
+    Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
+    Wn[2][0][q] = c.Wm[q];
+    Wn[2][1][q] = c.Wp[q];
+  }
+  T Ut[3][2][5];
+  hancock_states(c.Wc, Wn, gas, first_order != 0, Ut);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
+    sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
+    if (kI) {
+      c.Ux[q] = Ut[0][0][q];
+      c.Uy[q] = Ut[1][0][q];
+    } else {
+      c.Ux[q] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
+    }
+  }
+  if (kI) {
+    if (k >= 0) {
+      T Fz1[5];
+      bad += hllc_flux<2>(c.Uz, Ut[2][0], gas, ws, Fz1);
+      if (k >= 1) {
+        // complete plane k-1: U^{n+1} = U^n - dt/dx [(x) + (y) + (z)]
+        const int64_t o = c.col + src.plane(k - 1);
+        const int64_t fs = src.fstride();
+        T Un[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const T a = acc[q] + (Fz1[q] - c.Fz0[q]);
+          Un[q] = src.base[o + q * fs] - gas.dtdx * a;
+          out[q * 4096 + ((k - 1) * 16 + cy) * 16 + cx] = Un[q];
+        }
+        bad += unphysical(Un, gas);
+        if (smax != nullptr) {
+          const double s = cfl_signal_speed(double(Un[0]), double(Un[1]), double(Un[2]), double(Un[3]),
+                                            double(Un[4]), gamma_d);
+          double& m = smax[(k - 1) >> 3];
+          if (s > m) m = s;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) c.Fz0[q] = Fz1[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c.Uz[q] = Ut[2][1][q];
+  }
+  return bad;
+}
+
+// x and y faces of plane k that the column solves: interior columns their
+// low x and low y face; halo columns at x = 16 / y = 16 the last face.
+template <typename T, bool kI>
+__device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI>& c, int k, const Gas<T>& gas, int ws, Smem<T>& sm) {
+  if (k < 0 || k > 15) return 0;
+  const int cx = c.cx, cy = c.cy;
+  int bad = 0;
+  if (kI || c.xface16) {
+    T L[5], F[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+    bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
+  }
+  if (kI || c.yface16) {
+    const T* Uy = kI ? c.Uy : c.Ux;
+    T L[5], F[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+    bad += hllc_flux<1>(L, Uy, gas, ws, F);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
+  }
+  return bad;
+}
+
+template <typename T, bool kI>
+__device__ __forceinline__ void fwd_col_shift(FwdCol<T, kI>& c) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    c.Wm[q] = c.Wc[q];
+    c.Wc[q] = c.Wp[q];
+  }
+}
+
 // Advance one group: read through `src`, write the 16^3 x 5 interior to `out`
 // (field stride 4096).  Returns this thread's unphysical count.  If smax is
-// non-null, also returns (interior threads) the maximum CFL signal speed of
-// the thread's cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's
-// index in the workgroup (a loop over groups passes it opaque, so that the
-// compiler keeps thread-derived addresses out of the loop's live set).
+// non-null, also returns the maximum CFL signal speed of the thread's interior
+// cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's index in the
+// workgroup (a loop over groups passes it opaque, so that the compiler keeps
+// thread-derived addresses out of the loop's live set).
 template <typename T, class Src>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
                                              int first_order, int ws, Smem<T>& sm, double* smax,
                                              double gamma_d, int tid = threadIdx.x) {
-  const bool interior = tid < 256;
-  int cx, cy;          // own state column
-  int ox = 0, oy = 0;  // wave 4: the column two cells out
-  int ex = 0, ey = 0;  // wave 4, lanes 0..3: one of the 4 edge columns
-  if (interior) {
-    cx = tid & 15;
-    cy = tid >> 4;
-  } else {
-    const int l = tid - 256, side = l >> 4, k = l & 15;
-    cx = side == 0 ? -1 : side == 1 ? 16 : k;
-    cy = side == 2 ? -1 : side == 3 ? 16 : k;
-    ox = side == 0 ? -2 : side == 1 ? 17 : k;
-    oy = side == 2 ? -2 : side == 3 ? 17 : k;
-    ex = (l & 1) ? 16 : -1;
-    ey = (l & 2) ? 16 : -1;
-  }
-  const bool has_edge = !interior && (tid - 256) < 4;
-  const bool xface16 = !interior && cx == 16;  // solves x-face 16 (between 15 and 16)
-  const bool yface16 = !interior && cy == 16;  // solves y-face 16
-  const int64_t col_own = src.col(cx, cy);
-  const int64_t col_out = interior ? 0 : src.col(ox, oy);
+  const bool halo = tid < 64;  // wave 0
+  // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
+  // 0..3 also one of the 4 edge columns
+  const int side = tid >> 4, kk = tid & 15;
+  const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
+  const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
+  const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
+  const bool has_edge = halo && tid < 4;
+  const int64_t col_out = halo ? src.col(ox, oy) : 0;
   const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
-  const int64_t fs = src.fstride();
 
-  // register ring of the own column's primitive states; the conserved
-  // values of the next plane to convert are loaded one iteration ahead
-  // (software prefetch: the load latency overlaps a whole plane's work)
-  T Wm[5], Wc[5], Wp[5];
-  T Un[5];           // own column, plane k+1 (in flight during iteration k-1)
-  T Uo[5], Ue[5];    // wave 4: 2-deep and edge column, plane k
-  if (interior) load_prim(src, col_own, -2, gas, Wm);
-  load_prim(src, col_own, -1, gas, Wc);
-  load_cons(src, col_own, 0, Un);
-  if (!interior) {
+  FwdCol<T, true> ci;
+  FwdCol<T, false> ch;
+  fwd_col_init(ci, src, tid & 15, tid >> 4, gas);
+  T Uo[5], Ue[5];  // halo role: 2-deep and edge column, plane k (in flight)
+  if (halo) {
+    fwd_col_init(ch, src, hx, hy, gas);
     load_cons(src, col_out, 0, Uo);
     if (has_edge) load_cons(src, col_edge, 0, Ue);
   }
-
-  T Uz[5];         // z+ face state of the previous plane (interior)
-  T Fz0[5];        // z flux at the low face of the previous plane (interior)
-  T Ux[5], Uy[5];  // own x- and y- face states of the current plane
   int bad = 0;
 
   for (int k = -1; k <= 16; ++k) {
-    // ---- next plane of the own column (prefetched); publish plane k to LDS
-    if (interior || k + 1 <= 16) {
-      cons_to_prim(Un, gas, Wp);
-      if (k + 2 <= (interior ? 17 : 16)) load_cons(src, col_own, k + 2, Un);
-    }
+    // ---- next planes (prefetched); publish plane k to LDS
+    fwd_col_publish(ci, src, k, gas, sm);
+    if (halo) {
+      fwd_col_publish(ch, src, k, gas, sm);
+      if (k >= 0 && k <= 15) {
+        T Wo[5];
+        cons_to_prim(Uo, gas, Wo);
+        if (k + 1 <= 15) load_cons(src, col_out, k + 1, Uo);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sm.P[q][pidx(cx, cy)] = Wc[q];
-    if (!interior && k >= 0 && k <= 15) {
-      T Wo[5];
-      cons_to_prim(Uo, gas, Wo);
-      if (k + 1 <= 15) load_cons(src, col_out, k + 1, Uo);
+        for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
+        if (has_edge) {
+          cons_to_prim(Ue, gas, Wo);
+          if (k + 1 <= 15) load_cons(src, col_edge, k + 1, Ue);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
-      if (has_edge) {
-        cons_to_prim(Ue, gas, Wo);
-        if (k + 1 <= 15) load_cons(src, col_edge, k + 1, Ue);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
+          for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
+        }
       }
     }
     __syncthreads();
 
-    // ---- x/y flux differences of plane k-1 (fluxes written last iteration)
-    T acc[5];
-    if (interior && k >= 1) {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        acc[q] = sm.F[0][q][fxidx(cx + 1, cy)] - sm.F[0][q][fxidx(cx, cy)];
-        acc[q] = acc[q] + (sm.F[1][q][fyidx(cx, cy + 1)] - sm.F[1][q][fyidx(cx, cy)]);
-      }
-    }
-
-    // ---- half-step face states of the own state cell at plane k
-    if (interior || (k >= 0 && k <= 15)) {
-      T Wn[3][2][5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
-        Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
-        Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
-        Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
-        Wn[2][0][q] = Wm[q];
-        Wn[2][1][q] = Wp[q];
-      }
-      T Ut[3][2][5];
-      hancock_states(Wc, Wn, gas, first_order != 0, Ut);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
-        sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
-        Ux[q] = Ut[0][0][q];
-        Uy[q] = Ut[1][0][q];
-      }
-      if (interior) {
-        if (k >= 0) {
-          T Fz1[5];
-          bad += hllc_flux<2>(Uz, Ut[2][0], gas, ws, Fz1);
-          if (k >= 1) {
-            // complete plane k-1: U^{n+1} = U^n - dt/dx [(x) + (y) + (z)]
-            const int64_t o = col_own + src.plane(k - 1);
-            T Un[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-              const T a = acc[q] + (Fz1[q] - Fz0[q]);
-              Un[q] = src.base[o + q * fs] - gas.dtdx * a;
-              out[q * 4096 + ((k - 1) * 16 + cy) * 16 + cx] = Un[q];
-            }
-            bad += unphysical(Un, gas);
-            if (smax != nullptr) {
-              const double s = cfl_signal_speed(double(Un[0]), double(Un[1]), double(Un[2]), double(Un[3]),
-                                                double(Un[4]), gamma_d);
-              double& m = smax[(k - 1) >> 3];
-              if (s > m) m = s;
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < 5; ++q) Fz0[q] = Fz1[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) Uz[q] = Ut[2][1][q];
-      }
-    }
+    // ---- half-step face states of plane k; z-face and update of plane k-1
+    bad += fwd_col_states(ci, src, out, k, gas, first_order, ws, sm, smax, gamma_d);
+    if (halo) bad += fwd_col_states(ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d);
     __syncthreads();
 
     // ---- x and y faces of plane k
-    if (k >= 0 && k <= 15) {
-      if (interior || xface16) {
-        T L[5], F[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
-        bad += hllc_flux<0>(L, Ux, gas, ws, F);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
-      }
-      if (interior || yface16) {
-        T L[5], F[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
-        bad += hllc_flux<1>(L, Uy, gas, ws, F);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
-      }
-    }
+    bad += fwd_col_faces(ci, k, gas, ws, sm);
+    if (halo) bad += fwd_col_faces(ch, k, gas, ws, sm);
 
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      Wm[q] = Wc[q];
-      Wc[q] = Wp[q];
-    }
+    fwd_col_shift(ci);
+    if (halo) fwd_col_shift(ch);
   }
   return bad;
 }
@@ -281,13 +336,12 @@ __device__ __forceinline__ void set_dt(Gas<T>& gas, const double* dt_dev, double
   }
 }
 
-// Waves per SIMD the register allocation must allow: with 5-wave workgroups,
-// 3 (FP64, <= 168 VGPRs) lets two workgroups share a CU (the LDS of two FP64
-// workgroups fits in 160 KB); 5 (FP32, <= 102 VGPRs) lets four share it.
-// The lower settings leave the allocator room for the prefetched plane (one
-// FP64 or three FP32 workgroups per CU); `value` is the padded step's choice.
+// Waves per SIMD the register allocation must allow.  Each wave of a 4-wave
+// workgroup gets its own SIMD, so this is also the number of workgroups per
+// CU the registers allow: FP64 2 (<= 256 VGPRs; two workgroups' LDS fits in
+// 160 KB) or 1; FP32 4 (<= 128 VGPRs) or 2.  `value` is the padded step's.
 template <typename T> struct MinWaves;
-template <> struct MinWaves<double> { static constexpr int hi = 3, lo = 2; static constexpr int value = lo; };
-template <> struct MinWaves<float> { static constexpr int hi = 5, lo = 4; static constexpr int value = lo; };
+template <> struct MinWaves<double> { static constexpr int hi = 2, lo = 1; static constexpr int value = hi; };
+template <> struct MinWaves<float> { static constexpr int hi = 4, lo = 2; static constexpr int value = hi; };
 
 }  // namespace gh

@@ -27,7 +27,7 @@ WAVESPEED_DAVIS = 1 << 8
 FIRST_ORDER = 1 << 10
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 BATCH_WORK_WORDS = 16       # uint32 words of the batched kernel's work buffer
-BATCHED_VARIANTS = 8        # launch shapes of the batched kernel
+BATCHED_VARIANTS = 12       # launch shapes of the batched kernel
 
 _lib = None
 
