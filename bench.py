@@ -233,14 +233,48 @@ def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171
             "within_1e-6": int(np.sum(errs <= 1e-6))}
 
 
+def step_ratio(hydro, torch, lv, dtype, dt, reps=10):
+    """One forward level step and one step adjoint on the same state, timed
+    with events on the stream they run on (median of reps)."""
+    U = torch.from_numpy(np.ascontiguousarray(lv.U.astype(dtype))).cuda()
+    O = torch.empty_like(U)
+    g = torch.ones_like(U)
+    gi = torch.empty_like(U)
+    work = hydro.adjoint_workspace(lv.n_groups, U.dtype, True)
+    fwd = time_events(torch, lambda: hydro.advance_level(U, lv.ng, lv.bc, dt, lv.dx, lv.gamma, out=O), reps)
+    adj = time_events(torch, lambda: hydro.advance_level_adjoint(U, g, lv.ng, lv.bc, dt, lv.dx, lv.gamma, out=gi,
+                                                                 work=work), reps)
+    del U, O, g, gi, work
+    torch.cuda.empty_cache()
+    return {"fwd_step_ms": fwd, "adjoint_step_ms": adj, "adjoint_over_fwd": adj / fwd}
+
+
+def time_events(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
 def differentiation_workloads(hydro, torch, W, fd_samples):
     out = {}
-    # 128^3 smooth wave, 512 groups, FP64, 8 steps at dt = 0.2 dx, checkpoint every 4
+    # 128^3 smooth wave, 512 groups, FP64, 8 steps at dt = 0.2 dx; every state
+    # checkpointed (k = 1, no replay: 8 x 84 MB), and k = 4 with segment replay
     lv, target = W.smooth_wave(128)
     dt = 0.2 * lv.dx
-    r, grad = adjoint_rollout(hydro, torch, lv, np.float64, 8, 4, dt, target)
-    r["workload"] = "smooth wave 128^3 (512 groups), FP64, 8 steps at dt = 0.2 dx, checkpoint every 4, " \
+    r, grad = adjoint_rollout(hydro, torch, lv, np.float64, 8, 1, dt, target)
+    r4, _ = adjoint_rollout(hydro, torch, lv, np.float64, 8, 4, dt, target)
+    r["workload"] = "smooth wave 128^3 (512 groups), FP64, 8 steps at dt = 0.2 dx, every state checkpointed, " \
                     "loss sum (rho_8 - rho_target)^2"
+    r["checkpoint_every_4"] = r4
+    r["step"] = step_ratio(hydro, torch, lv, np.float64, dt)
     r["fd"] = fd_protocol(hydro, torch, lv, target, 8, dt, grad, fd_samples)
     out["smooth128_f64"] = r
     del grad
@@ -258,13 +292,14 @@ def differentiation_workloads(hydro, torch, W, fd_samples):
     U = torch.from_numpy(lv.U).cuda()
     dt = float(hydro.cfl_dt(U, lv.dx, lv.gamma, 0.5).min())
     del U
-    r, grad = adjoint_rollout(hydro, torch, lv, np.float32, 4, 4, dt, None, reps=2)
+    r, grad = adjoint_rollout(hydro, torch, lv, np.float32, 4, 1, dt, None, reps=2)
     r["workload"] = "turbulence 384^3 (13824 groups), FP32 state, 4 steps at the initial CFL time-step " \
-                    "(FP64 reduction), checkpoint every 4, cotangent of ones"
+                    "(FP64 reduction), every state checkpointed, cotangent of ones"
     r["dt"] = dt
-    out["turb384_f32"] = r
     del grad
     torch.cuda.empty_cache()
+    r["step"] = step_ratio(hydro, torch, lv, np.float32, dt)
+    out["turb384_f32"] = r
     return out
 
 

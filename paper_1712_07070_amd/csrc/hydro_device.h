@@ -31,11 +31,11 @@ template <typename T> struct Fp;
 // correctly rounded IEEE sequences, which cost two to three times as many
 // instructions.  sqrt(0) is returned as 0 (the refinement would give NaN).
 template <> struct Fp<double> {
+  // the hardware reciprocal is good to about 2^-24; one Newton step gives
+  // about 2^-48 relative (div corrects its quotient once more)
   static __device__ __forceinline__ double rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
   }
   static __device__ __forceinline__ double div(double a, double b) {

@@ -281,37 +281,76 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
 }
 
 // F3a: the x and y face VJPs this column solves at plane k (its x- face and
-// y- face; halo columns only the face at x = 16 or y = 16).
+// y- face; halo columns only the face at x = 16 or y = 16, in one pass: a
+// y face is solved in the x-normal frame with its states and cotangents
+// rotated (m_y, m_z, m_x) -> (m_x, m_y, m_z), the same arithmetic on the same
+// values as the y-normal solver, and the results rotated back).
 template <typename T, bool kI>
 __device__ __forceinline__ void adj_col_faces(AdjCol<T, kI>& c, int k, const T* __restrict__ go, const Gas<T>& gas,
                                               int ws, SmemF<T>& sm) {
   if (k < 0 || k > 15) return;
   const int cx = c.cx, cy = c.cy;
-  if (kI || c.xface16) {
-    T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
+  if (kI) {
+    {
+      T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+        gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx - 1, cy, k));
+        c.gRx[q] = T(0);
+      }
+      hllc_flux_vjp<0>(L, c.Ux, gas, ws, gF, gL, c.gRx);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sm.GL[0][q][sidx(cx - 1, cy)] = gL[q];
+    }
+    {
+      T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+        gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy - 1, k));
+        c.gRy[q] = T(0);
+      }
+      hllc_flux_vjp<1>(L, c.Uy, gas, ws, gF, gL, c.gRy);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sm.GL[1][q][sidx(cx, cy - 1)] = gL[q];
+    }
+  } else if (c.xface16 || c.yface16) {
+    const bool yf = c.yface16;
+    const int lx = yf ? cx : cx - 1, ly = yf ? cy - 1 : cy;  // the cell on the low side of the face
+    const T* Sb = yf ? &sm.S[1][0][sidx(lx, ly)] : &sm.S[0][0][sidx(lx, ly)];
+    T L[5], gF[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      L[q] = sm.S[0][q][sidx(cx - 1, cy)];
-      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx - 1, cy, k));
-      c.gRx[q] = T(0);
+      L[q] = Sb[q * kSW * kSW];
+      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, lx, ly, k));
     }
-    hllc_flux_vjp<0>(L, c.Ux, gas, ws, gF, gL, c.gRx);
+    auto rot = [&](const T a[5], T r[5]) {  // axis frame -> x-normal frame of this face
+      r[0] = a[0];
+      r[1] = yf ? a[2] : a[1];
+      r[2] = yf ? a[3] : a[2];
+      r[3] = yf ? a[1] : a[3];
+      r[4] = a[4];
+    };
+    auto unrot = [&](const T r[5], T a[5]) {
+      a[0] = r[0];
+      a[1] = yf ? r[3] : r[1];
+      a[2] = yf ? r[1] : r[2];
+      a[3] = yf ? r[2] : r[3];
+      a[4] = r[4];
+    };
+    T Lr[5], Rr[5], gFr[5];
+    rot(L, Lr);
+    rot(c.Ux, Rr);
+    rot(gF, gFr);
+    T gLr[5] = {T(0), T(0), T(0), T(0), T(0)}, gRr[5] = {T(0), T(0), T(0), T(0), T(0)};
+    hllc_flux_vjp<0>(Lr, Rr, gas, ws, gFr, gLr, gRr);
+    T gL[5];
+    unrot(gLr, gL);
+    unrot(gRr, c.gRx);
+    T* Gb = yf ? &sm.GL[1][0][sidx(lx, ly)] : &sm.GL[0][0][sidx(lx, ly)];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sm.GL[0][q][sidx(cx - 1, cy)] = gL[q];
-  }
-  if (kI || c.yface16) {
-    T* Uy = kI ? c.Uy : c.Ux;
-    T* gRy = kI ? c.gRy : c.gRx;
-    T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      L[q] = sm.S[1][q][sidx(cx, cy - 1)];
-      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy - 1, k));
-      gRy[q] = T(0);
-    }
-    hllc_flux_vjp<1>(L, Uy, gas, ws, gF, gL, gRy);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) sm.GL[1][q][sidx(cx, cy - 1)] = gL[q];
+    for (int q = 0; q < 5; ++q) Gb[q * kSW * kSW] = gL[q];
   }
 }
 
@@ -515,11 +554,45 @@ __device__ __forceinline__ Runs axis_runs(int X, int ng, int lo, int hi, int gh)
   return r;
 }
 
+// Up to 4 copies along one axis for ghost width 2 (the level path), compacted
+// in slot order into packed (g, p) entries.  Four occur with an outflow face
+// on one side and a periodic one on the other (the cell itself, two outflow
+// ghost positions and the wrapped copy).
+struct Copies4 {
+  int v0, v1, v2, v3, n;
+  __device__ void push(bool ok, int v) {
+    v3 = ok ? v2 : v3;
+    v2 = ok ? v1 : v2;
+    v1 = ok ? v0 : v1;
+    v0 = ok ? v : v0;
+    n += ok ? 1 : 0;
+  }
+  // entry i in slot order (pushes shift older entries up)
+  __device__ int at(int i) const {
+    const int k = n - 1 - i;
+    return k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : v3;
+  }
+};
+
+__device__ __forceinline__ Copies4 axis_copies2(const Runs& r) {
+  Copies4 c{0, 0, 0, 0, 0};
+  const Run s0 = r[0], s1 = r[1], s2 = r[2], s3 = r[3], s4 = r[4];
+  c.push(s0.n > 0, Runs::pack(s0.g, s0.p, 1));
+  c.push(true, Runs::pack(s1.g, s1.p, 1));
+  c.push(s2.n > 0, Runs::pack(s2.g, s2.p, 1));
+  c.push(s3.n > 0, Runs::pack(s3.g, s3.p, 1));
+  c.push(s3.n > 1, Runs::pack(s3.g, s3.p + 1, 1));
+  c.push(s4.n > 0, Runs::pack(s4.g, s4.p, 1));
+  c.push(s4.n > 1, Runs::pack(s4.g, s4.p + 1, 1));
+  return c;
+}
+
 // Sum, per level cell, the cotangents of every copy of the cell: the adjoint
 // of the ghost fill, written as a gather (fixed order, no atomics).  kBoxSrc:
 // the source is the per-group [5][20^3] box of the level adjoint (positions
-// [-2, 17], only stencil-reachable ones hold values); otherwise a padded
-// [5][P^3] block per group with ghost width gh.
+// [-2, 17], only stencil-reachable ones hold values); the x copies of each
+// (z, y) pair are loaded together.  Otherwise a padded [5][P^3] block per
+// group with ghost width gh (runs of up to gh positions per face).
 template <typename T, bool kBoxSrc>
 __global__ __launch_bounds__(256) void adj_gather(const T* __restrict__ src, T* __restrict__ glevel, LevelGeom geo,
                                                   int gh, int64_t ncells) {
@@ -536,26 +609,52 @@ __global__ __launch_bounds__(256) void adj_gather(const T* __restrict__ src, T* 
   const Runs ry = axis_runs(gy * 16 + y, geo.ngy, geo.bc[2], geo.bc[3], w);
   const Runs rz = axis_runs(gz * 16 + z, geo.ngz, geo.bc[4], geo.bc[5], w);
   T s[5] = {T(0), T(0), T(0), T(0), T(0)};
+  if (kBoxSrc) {
+    const Copies4 cx = axis_copies2(rx), cy = axis_copies2(ry), cz = axis_copies2(rz);
 #pragma unroll 1
-  for (int a = 0; a < 5; ++a) {
-    const Run ra = rz[a];
-    for (int pz = ra.p; pz < ra.p + ra.n; ++pz)
+    for (int a = 0; a < cz.n; ++a) {
+      const int vz = cz.at(a);
+      const int gzs = vz >> 12, pz = ((vz >> 5) & 127) - 64;
 #pragma unroll 1
-      for (int b = 0; b < 5; ++b) {
-        const Run rb = ry[b];
-        for (int py = rb.p; py < rb.p + rb.n; ++py)
-#pragma unroll 1
-          for (int c = 0; c < 5; ++c) {
-            const Run rc = rx[c];
-            for (int px = rc.p; px < rc.p + rc.n; ++px) {
-              if (kBoxSrc && !reachable(px, py, pz)) continue;
-              const int64_t sg = (int64_t(ra.g) * geo.ngy + rb.g) * geo.ngx + rc.g;
-              const T* base = src + sg * 5 * P3 + (int64_t(pz + w) * P + (py + w)) * P + (px + w);
+      for (int b = 0; b < cy.n; ++b) {
+        const int vy = cy.at(b);
+        const int gys = vy >> 12, py = ((vy >> 5) & 127) - 64;
+        T v[4][5];
 #pragma unroll
-              for (int q = 0; q < 5; ++q) s[q] = s[q] + base[q * P3];
-            }
-          }
+        for (int c = 0; c < 4; ++c) {
+          const int vx = cx.at(c);
+          const int gxs = vx >> 12, px = ((vx >> 5) & 127) - 64;
+          const bool ok = c < cx.n && reachable(px, py, pz);
+          const int64_t sg = (int64_t(gzs) * geo.ngy + gys) * geo.ngx + gxs;
+          const T* base = src + sg * 5 * P3 + (int64_t(pz + w) * P + (py + w)) * P + (px + w);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) v[c][q] = ok ? base[q * P3] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s[q] = s[q] + v[0][q] + v[1][q] + v[2][q] + v[3][q];
       }
+    }
+  } else {
+#pragma unroll 1
+    for (int a = 0; a < 5; ++a) {
+      const Run ra = rz[a];
+      for (int pz = ra.p; pz < ra.p + ra.n; ++pz)
+#pragma unroll 1
+        for (int b = 0; b < 5; ++b) {
+          const Run rb = ry[b];
+          for (int py = rb.p; py < rb.p + rb.n; ++py)
+#pragma unroll 1
+            for (int c = 0; c < 5; ++c) {
+              const Run rc = rx[c];
+              for (int px = rc.p; px < rc.p + rc.n; ++px) {
+                const int64_t sg = (int64_t(ra.g) * geo.ngy + rb.g) * geo.ngx + rc.g;
+                const T* base = src + sg * 5 * P3 + (int64_t(pz + w) * P + (py + w)) * P + (px + w);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) s[q] = s[q] + base[q * P3];
+              }
+            }
+        }
+    }
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) glevel[(g * 5 + q) * 4096 + (i & 4095)] = s[q];

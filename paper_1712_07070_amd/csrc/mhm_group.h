@@ -197,28 +197,57 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI>& c, const Src& src, 
 }
 
 // x and y faces of plane k that the column solves: interior columns their
-// low x and low y face; halo columns at x = 16 / y = 16 the last face.
+// low x and low y face; halo columns at x = 16 / y = 16 the last face.  The
+// halo lanes solve their x and y faces in one pass: a y face is solved in the
+// x-normal frame with its states rotated (m_y, m_z, m_x) -> (m_x, m_y, m_z),
+// the same arithmetic on the same values as the y-normal solver, and the flux
+// rotated back.
 template <typename T, bool kI>
 __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI>& c, int k, const Gas<T>& gas, int ws, Smem<T>& sm) {
   if (k < 0 || k > 15) return 0;
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
-  if (kI || c.xface16) {
-    T L[5], F[5];
+  if (kI) {
+    {
+      T L[5], F[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
-    bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
+      for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+      bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
-  }
-  if (kI || c.yface16) {
-    const T* Uy = kI ? c.Uy : c.Ux;
-    T L[5], F[5];
+      for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
+    }
+    {
+      T L[5], F[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
-    bad += hllc_flux<1>(L, Uy, gas, ws, F);
+      for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+      bad += hllc_flux<1>(L, c.Uy, gas, ws, F);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
+      for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
+    }
+  } else if (c.xface16 || c.yface16) {
+    const bool yf = c.yface16;
+    const T* Sb = yf ? &sm.S[1][0][sidx(cx, cy - 1)] : &sm.S[0][0][sidx(cx - 1, cy)];
+    T L[5], Lr[5], Rr[5], F[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) L[q] = Sb[q * kSW * kSW];
+    // rotation of a y-face problem into the x-normal frame (identity for x faces)
+    Lr[0] = L[0];
+    Lr[1] = yf ? L[2] : L[1];
+    Lr[2] = yf ? L[3] : L[2];
+    Lr[3] = yf ? L[1] : L[3];
+    Lr[4] = L[4];
+    Rr[0] = c.Ux[0];
+    Rr[1] = yf ? c.Ux[2] : c.Ux[1];
+    Rr[2] = yf ? c.Ux[3] : c.Ux[2];
+    Rr[3] = yf ? c.Ux[1] : c.Ux[3];
+    Rr[4] = c.Ux[4];
+    bad += hllc_flux<0>(Lr, Rr, gas, ws, F);
+    T* Fb = yf ? &sm.F[1][0][fyidx(cx, cy)] : &sm.F[0][0][fxidx(cx, cy)];
+    Fb[0] = F[0];
+    Fb[1 * 17 * 16] = yf ? F[3] : F[1];
+    Fb[2 * 17 * 16] = yf ? F[1] : F[2];
+    Fb[3 * 17 * 16] = yf ? F[2] : F[3];
+    Fb[4 * 17 * 16] = F[4];
   }
   return bad;
 }
