@@ -163,6 +163,16 @@ int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_d
                                 double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
                                 int64_t work_bytes, void* stream);
 
+/* Form of the two adjoint calls (process-wide, per dtype); both give the same
+ * cotangents up to the summation order of the limiter / flux terms:
+ *   0  one fused z-march per group (face cotangents stay on chip);
+ *   1  two z-marches per group with the face cotangents in the workspace
+ *      (smaller LDS and register footprint: two workgroups per CU).
+ * hydro_set_adjoint_variant returns HYDRO_EINVAL for other values;
+ * hydro_get_adjoint_variant returns the current form. */
+int hydro_set_adjoint_variant(int32_t dtype, int32_t variant);
+int hydro_get_adjoint_variant(int32_t dtype);
+
 /* One level of a batched launch (hydro_advance_batched).  Pointers are
  * device memory; bc holds the x-, x+, y-, y+, z-, z+ boundary conditions;
  * dt is this level's time-step (dt_l = dt_0 / 2^l in the W-cycle of Sec. 2.1)

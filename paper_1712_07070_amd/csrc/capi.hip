@@ -23,6 +23,9 @@ thread_local int g_last_hip_error = 0;
 // Launch shape of the level step per dtype (index into the variants of
 // mhm_fwd.hip); set by hydro_set_variant or hydro_autotune, process-wide.
 std::atomic<int> g_level_variant[2] = {{1}, {1}};  // measured defaults: plain order, high occupancy
+// Form of the step adjoint per dtype: 0 fused single sweep, 1 two kernels
+// with a face workspace.
+std::atomic<int> g_adjoint_variant[2] = {{0}, {0}};  // measured: fused faster in both dtypes
 // Launch shape of the batched kernel per dtype (bit 0: item order, bit 1:
 // occupancy target, bit 2: per-XCD queues).
 std::atomic<int> g_batched_variant[2] = {{0}, {0}};  // one queue, high occupancy
@@ -441,12 +444,12 @@ int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* g
     e = gh::launch_mhm_adjoint_padded(static_cast<const double*>(U_pad_dev), static_cast<const double*>(gU_out_dev),
                                       static_cast<double*>(gU_pad_dev), n_groups, ghost,
                                       make_gas<double>(gamma, theta, dt, dx), first_order, ws,
-                                      static_cast<double*>(work_dev), s);
+                                      static_cast<double*>(work_dev), g_adjoint_variant[0].load() == 1, s);
   else
     e = gh::launch_mhm_adjoint_padded(static_cast<const float*>(U_pad_dev), static_cast<const float*>(gU_out_dev),
                                       static_cast<float*>(gU_pad_dev), n_groups, ghost,
                                       make_gas<float>(gamma, theta, dt, dx), first_order, ws,
-                                      static_cast<float*>(work_dev), s);
+                                      static_cast<float*>(work_dev), g_adjoint_variant[1].load() == 1, s);
   return device_status(e);
 }
 
@@ -486,13 +489,25 @@ int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_d
     e = gh::launch_mhm_adjoint_level(static_cast<const double*>(level_dev), static_cast<const double*>(g_level_out_dev),
                                      static_cast<double*>(g_level_in_dev), geo,
                                      make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws,
-                                     static_cast<double*>(work_dev), s);
+                                     static_cast<double*>(work_dev), g_adjoint_variant[0].load() == 1, s);
   else
     e = gh::launch_mhm_adjoint_level(static_cast<const float*>(level_dev), static_cast<const float*>(g_level_out_dev),
                                      static_cast<float*>(g_level_in_dev), geo,
                                      make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws,
-                                     static_cast<float*>(work_dev), s);
+                                     static_cast<float*>(work_dev), g_adjoint_variant[1].load() == 1, s);
   return device_status(e);
+}
+
+int hydro_set_adjoint_variant(int32_t dtype, int32_t variant) {
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  if (variant != 0 && variant != 1) return HYDRO_EINVAL;
+  g_adjoint_variant[dtype].store(variant);
+  return HYDRO_OK;
+}
+
+int hydro_get_adjoint_variant(int32_t dtype) {
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  return g_adjoint_variant[dtype].load();
 }
 
 int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dtype, double dx, double gamma,

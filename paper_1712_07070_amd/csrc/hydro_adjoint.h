@@ -91,6 +91,9 @@ __device__ __forceinline__ void hancock_states_vjp_stream(const T Wc[5], const G
     gdU[q] = g.half_dtdx * gdU[q];
     gWc[q] = T(0);
   }
+  // the face cotangents are fetched again per direction below: keep the
+  // compiler from holding all six vectors live across the loop
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     T Wl[5], Wr[5];

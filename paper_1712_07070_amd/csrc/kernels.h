@@ -63,13 +63,14 @@ hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int f
 // adjoint_workspace_elems(G, level).
 size_t adjoint_workspace_elems(int64_t n_groups, bool level);
 
+// split: the two-kernel form (face workspace) instead of the fused one.
 template <typename T>
 hipError_t launch_mhm_adjoint_padded(const T* U_pad, const T* g_out, T* g_pad, int64_t G, int ghost, const Gas<T>& gas,
-                                     int first_order, int ws, T* work, hipStream_t stream);
+                                     int first_order, int ws, T* work, bool split, hipStream_t stream);
 
 template <typename T>
 hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, const LevelGeom& geo, const Gas<T>& gas,
-                                    const double* dt_dev, double dx, int first_order, int ws, T* work,
+                                    const double* dt_dev, double dx, int first_order, int ws, T* work, bool split,
                                     hipStream_t stream);
 
 // Adjoint of the ghost fill: g_level[cell] = sum of g_pad over every padded

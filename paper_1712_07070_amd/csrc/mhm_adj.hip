@@ -460,6 +460,387 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
   }
 }
 
+// ------------------------------------------------------- split kernels ----
+// The same adjoint as two z-marches per group with a face workspace between
+// them, each small enough in LDS (and registers) for two workgroups per CU:
+//   faces: recompute the half-step states of plane k, take the HLLC VJP of
+//      every face and store the cotangents of its two face states;
+//   cells: reverse the Hancock predictor of every state cell from its six
+//      face cotangents, gather in-plane (LDS) and along z (register ring),
+//      and finish as the fused kernel does.
+// Workspace per group: for each direction d, side s (0: the low cell's high
+// face state, 1: the high cell's low face state), field q and face f,
+// element ((d * 2 + s) * 5 + q) * kFaces + f.
+constexpr int kFaces = 17 * 16 * 16;  // faces per direction per group
+constexpr int64_t kFaceWs = 3 * 2 * 5 * int64_t(kFaces);
+__device__ __forceinline__ int xface_id(int i, int y, int k) { return (k * 16 + y) * 17 + i; }    // i in [0, 16]
+__device__ __forceinline__ int yface_id(int x, int j, int k) { return (k * 17 + j) * 16 + x; }    // j in [0, 16]
+__device__ __forceinline__ int zface_id(int x, int y, int kz) { return (kz * 16 + y) * 16 + x; }  // kz in [0, 16]
+__device__ __forceinline__ int64_t ws_at(int d, int side, int q, int f) {
+  return (int64_t(d * 2 + side) * 5 + q) * kFaces + f;
+}
+
+template <typename T>
+struct SmemFaces {
+  T P[5][kPW * kPW];     // primitive plane k
+  T S[2][5][kSW * kSW];  // x+ and y+ half-step states of plane k
+};
+template <typename T>
+struct SmemCells {
+  T P[5][kPW * kPW];     // primitive plane k
+  T O[4][5][kSW * kSW];  // in-plane neighbour contributions of plane k (x-, x+, y-, y+)
+};
+
+template <typename T, bool kInterior>
+struct SplitCol {
+  static constexpr int zlo = kInterior ? -2 : -1, zhi = kInterior ? 17 : 16;
+  int cx, cy;
+  bool xface16, yface16;
+  int64_t col;
+  T Wm[5], Wc[5], Wp[5];  // primitive states at planes k-1, k, k+1
+  T Ux[5], Uy[5], Uz[5];  // faces: own x-, y- face states of plane k; z+ state of plane k-1
+  T A0[5], A1[5], A2[5];  // cells: input cotangents of the column at planes k-1, k, k+1
+};
+
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ void split_col_init(SplitCol<T, kI>& c, const Src& src, int cx, int cy, const Gas<T>& gas) {
+  c.cx = cx;
+  c.cy = cy;
+  c.xface16 = !kI && cx == 16;
+  c.yface16 = !kI && cy == 16;
+  c.col = src.col(cx, cy);
+  if (kI) load_prim(src, c.col, -2, gas, c.Wm);
+  load_prim(src, c.col, -1, gas, c.Wc);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) c.A0[q] = c.A1[q] = c.A2[q] = T(0);
+}
+
+template <typename T, bool kI, class Src>
+__device__ __forceinline__ void split_col_publish(SplitCol<T, kI>& c, const Src& src, int k, const Gas<T>& gas,
+                                                  T (*P)[kPW * kPW]) {
+  if (k + 1 <= c.zhi) load_prim(src, c.col, k + 1, gas, c.Wp);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) P[q][pidx(c.cx, c.cy)] = c.Wc[q];
+}
+
+template <typename T, bool kI>
+__device__ __forceinline__ void split_col_shift(SplitCol<T, kI>& c) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    c.Wm[q] = c.Wc[q];
+    c.Wc[q] = c.Wp[q];
+  }
+}
+
+// The 2-deep and edge columns of the halo role: publish plane k (0..15).
+template <typename T, class Src>
+__device__ __forceinline__ void publish_outer(const Src& src, int k, int64_t col_out, int ox, int oy, bool has_edge,
+                                              int64_t col_edge, int ex, int ey, const Gas<T>& gas,
+                                              T (*P)[kPW * kPW]) {
+  T Wo[5];
+  load_prim(src, col_out, k, gas, Wo);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) P[q][pidx(ox, oy)] = Wo[q];
+  if (has_edge) {
+    load_prim(src, col_edge, k, gas, Wo);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) P[q][pidx(ex, ey)] = Wo[q];
+  }
+}
+
+// faces kernel, states phase: half-step states of plane k; z-face (k-1 | k).
+template <typename T, bool kI>
+__device__ __forceinline__ void faces_col_states(SplitCol<T, kI>& c, int k, const T* __restrict__ go,
+                                                 T* __restrict__ ws, const Gas<T>& gas, bool fo, int wsp,
+                                                 SmemFaces<T>& sm) {
+  const int cx = c.cx, cy = c.cy;
+  if (k > 16 || !in_state_plane(cx, cy, k)) return;
+  T Wn[3][2][5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
+    Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
+    Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
+    Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
+    Wn[2][0][q] = c.Wm[q];
+    Wn[2][1][q] = c.Wp[q];
+  }
+  T Ut[3][2][5];
+  hancock_states(c.Wc, Wn, gas, fo, Ut);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
+    sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
+    if (kI) {
+      c.Ux[q] = Ut[0][0][q];
+      c.Uy[q] = Ut[1][0][q];
+    } else {
+      c.Ux[q] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
+    }
+  }
+  if (kI) {
+    if (k >= 0) {
+      T gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)}, gR[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy, k - 1));
+      hllc_flux_vjp<2>(c.Uz, Ut[2][0], gas, wsp, gF, gL, gR);
+      const int f = zface_id(cx, cy, k);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        ws[ws_at(2, 0, q, f)] = gL[q];
+        ws[ws_at(2, 1, q, f)] = gR[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c.Uz[q] = Ut[2][1][q];
+  }
+}
+
+// faces kernel, faces phase: the x / y faces the column solves at plane k.
+template <typename T, bool kI>
+__device__ __forceinline__ void faces_col_faces(SplitCol<T, kI>& c, int k, const T* __restrict__ go,
+                                                T* __restrict__ ws, const Gas<T>& gas, int wsp, SmemFaces<T>& sm) {
+  if (k < 0 || k > 15) return;
+  const int cx = c.cx, cy = c.cy;
+  if (kI) {
+    {
+      T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)}, gR[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+        gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx - 1, cy, k));
+      }
+      hllc_flux_vjp<0>(L, c.Ux, gas, wsp, gF, gL, gR);
+      const int f = xface_id(cx, cy, k);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        ws[ws_at(0, 0, q, f)] = gL[q];
+        ws[ws_at(0, 1, q, f)] = gR[q];
+      }
+    }
+    {
+      T L[5], gF[5], gL[5] = {T(0), T(0), T(0), T(0), T(0)}, gR[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+        gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, cx, cy - 1, k));
+      }
+      hllc_flux_vjp<1>(L, c.Uy, gas, wsp, gF, gL, gR);
+      const int f = yface_id(cx, cy, k);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        ws[ws_at(1, 0, q, f)] = gL[q];
+        ws[ws_at(1, 1, q, f)] = gR[q];
+      }
+    }
+  } else if (c.xface16 || c.yface16) {
+    // one pass for both halo faces: a y face in the x-normal frame with
+    // rotated states and cotangents (the y-normal solver's arithmetic)
+    const bool yf = c.yface16;
+    const int lx = yf ? cx : cx - 1, ly = yf ? cy - 1 : cy;
+    const T* Sb = yf ? &sm.S[1][0][sidx(lx, ly)] : &sm.S[0][0][sidx(lx, ly)];
+    T L[5], gF[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      L[q] = Sb[q * kSW * kSW];
+      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, lx, ly, k));
+    }
+    auto rot = [&](const T a[5], T r[5]) {
+      r[0] = a[0];
+      r[1] = yf ? a[2] : a[1];
+      r[2] = yf ? a[3] : a[2];
+      r[3] = yf ? a[1] : a[3];
+      r[4] = a[4];
+    };
+    auto unrot = [&](const T r[5], T a[5]) {
+      a[0] = r[0];
+      a[1] = yf ? r[3] : r[1];
+      a[2] = yf ? r[1] : r[2];
+      a[3] = yf ? r[2] : r[3];
+      a[4] = r[4];
+    };
+    T Lr[5], Rr[5], gFr[5];
+    rot(L, Lr);
+    rot(c.Ux, Rr);
+    rot(gF, gFr);
+    T gLr[5] = {T(0), T(0), T(0), T(0), T(0)}, gRr[5] = {T(0), T(0), T(0), T(0), T(0)};
+    hllc_flux_vjp<0>(Lr, Rr, gas, wsp, gFr, gLr, gRr);
+    T gL[5], gR[5];
+    unrot(gLr, gL);
+    unrot(gRr, gR);
+    const int d = yf ? 1 : 0;
+    const int f = yf ? yface_id(cx, cy, k) : xface_id(cx, cy, k);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      ws[ws_at(d, 0, q, f)] = gL[q];
+      ws[ws_at(d, 1, q, f)] = gR[q];
+    }
+  }
+}
+
+template <typename T, class Src>
+__device__ __forceinline__ void adjoint_faces_pass(const Src& src, const T* __restrict__ go, T* __restrict__ ws,
+                                                   const Gas<T>& gas, int first_order, int wsp, SmemFaces<T>& sm) {
+  const int tid = threadIdx.x;
+  const bool halo = tid < 64;
+  const bool fo = first_order != 0;
+  const int side = tid >> 4, kk = tid & 15;
+  const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
+  const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
+  const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
+  const bool has_edge = halo && tid < 4;
+  const int64_t col_out = halo ? src.col(ox, oy) : 0;
+  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
+  SplitCol<T, true> ci;
+  SplitCol<T, false> ch;
+  split_col_init(ci, src, tid & 15, tid >> 4, gas);
+  if (halo) split_col_init(ch, src, hx, hy, gas);
+  for (int k = -1; k <= 16; ++k) {
+    split_col_publish(ci, src, k, gas, sm.P);
+    if (halo) {
+      split_col_publish(ch, src, k, gas, sm.P);
+      if (k >= 0 && k <= 15) publish_outer(src, k, col_out, ox, oy, has_edge, col_edge, ex, ey, gas, sm.P);
+    }
+    __syncthreads();
+    faces_col_states(ci, k, go, ws, gas, fo, wsp, sm);
+    if (halo) faces_col_states(ch, k, go, ws, gas, fo, wsp, sm);
+    __syncthreads();
+    faces_col_faces(ci, k, go, ws, gas, wsp, sm);
+    if (halo) faces_col_faces(ch, k, go, ws, gas, wsp, sm);
+    split_col_shift(ci);
+    if (halo) split_col_shift(ch);
+  }
+}
+
+// cells kernel, states phase: reverse the Hancock predictor of the column's
+// state cell at plane k from its six face cotangents.
+template <typename T, bool kI>
+__device__ __forceinline__ void cells_col_vjp(SplitCol<T, kI>& c, int k, const T* __restrict__ ws,
+                                              const Gas<T>& gas, bool fo, SmemCells<T>& sm) {
+  const int cx = c.cx, cy = c.cy;
+  if (k > 16 || !in_state_plane(cx, cy, k)) return;
+  const bool u0 = face_used(cx, cy, k, 0), u1 = face_used(cx, cy, k, 1), u2 = face_used(cx, cy, k, 2);
+  const bool u3 = face_used(cx, cy, k, 3), u4 = face_used(cx, cy, k, 4), u5 = face_used(cx, cy, k, 5);
+  T gWc[5];
+  hancock_states_vjp_stream(
+      c.Wc, gas, fo,
+      [&](int d, int s, T W[5]) {
+        if (d == 2) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) W[q] = s == 0 ? c.Wm[q] : c.Wp[q];
+        } else {
+          const int x = d == 0 ? cx + (s ? 1 : -1) : cx, y = d == 1 ? cy + (s ? 1 : -1) : cy;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) W[q] = sm.P[q][pidx(x, y)];
+        }
+      },
+      [&](int d, int s, T G[5]) {
+        const int f = 2 * d + s;
+        const bool used = f == 0 ? u0 : f == 1 ? u1 : f == 2 ? u2 : f == 3 ? u3 : f == 4 ? u4 : u5;
+        // the low face of the cell holds the cell's state as the high side (1);
+        // the high face as the low side (0)
+        const int id = !used ? 0 : d == 0 ? xface_id(cx + s, cy, k) : d == 1 ? yface_id(cx, cy + s, k)
+                                                          : zface_id(cx, cy, k + s);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) G[q] = used ? ws[ws_at(d, 1 - s, q, id)] : T(0);
+      },
+      [&](int d, int s, const T G[5]) {
+        if (d == 2) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            if (s == 0) c.A0[q] = c.A0[q] + G[q];
+            else c.A2[q] = c.A2[q] + G[q];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) sm.O[2 * d + s][q][sidx(cx, cy)] = G[q];
+        }
+      },
+      gWc);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) c.A1[q] = c.A1[q] + gWc[q];
+}
+
+template <typename T>
+__device__ __forceinline__ void cells_gather_plane(int x, int y, int j, const SmemCells<T>& sm, T g[5]) {
+  const bool l = in_state_plane(x - 1, y, j), r = in_state_plane(x + 1, y, j);
+  const bool d = in_state_plane(x, y - 1, j), u = in_state_plane(x, y + 1, j);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    T s = g[q];
+    if (l) s = s + sm.O[1][q][sidx(x - 1, y)];
+    if (r) s = s + sm.O[0][q][sidx(x + 1, y)];
+    if (d) s = s + sm.O[3][q][sidx(x, y - 1)];
+    if (u) s = s + sm.O[2][q][sidx(x, y + 1)];
+    g[q] = s;
+  }
+}
+
+// cells kernel, finish phase: in-plane gather of plane k; plane k-1 is complete.
+template <typename T, bool kI, class Src, class Sink>
+__device__ __forceinline__ void cells_col_finish(SplitCol<T, kI>& c, const Src& src, int k, const T* __restrict__ go,
+                                                 const Gas<T>& gas, const SmemCells<T>& sm, const Sink& sink) {
+  if (k <= 16 && k >= c.zlo && k <= c.zhi) cells_gather_plane(c.cx, c.cy, k, sm, c.A1);
+  if (k - 1 >= c.zlo && k - 1 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, k - 1, c.A0, go, gas, sink);
+  if (k == 17 && 17 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, 17, c.A1, go, gas, sink);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    c.A0[q] = c.A1[q];
+    c.A1[q] = c.A2[q];
+    c.A2[q] = T(0);
+  }
+}
+
+template <typename T, class Src, class Sink>
+__device__ __forceinline__ void adjoint_cells_pass(const Src& src, const T* __restrict__ go, const T* __restrict__ ws,
+                                                   const Gas<T>& gas, int first_order, SmemCells<T>& sm,
+                                                   const Sink& sink) {
+  const int tid = threadIdx.x;
+  const bool halo = tid < 64;
+  const bool fo = first_order != 0;
+  const int side = tid >> 4, kk = tid & 15;
+  const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
+  const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
+  const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
+  const bool has_edge = halo && tid < 4;
+  const int64_t col_out = halo ? src.col(ox, oy) : 0;
+  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
+  SplitCol<T, true> ci;
+  SplitCol<T, false> ch;
+  split_col_init(ci, src, tid & 15, tid >> 4, gas);
+  if (halo) split_col_init(ch, src, hx, hy, gas);
+  for (int k = -1; k <= 17; ++k) {
+    if (k <= 16) {
+      split_col_publish(ci, src, k, gas, sm.P);
+      if (halo) {
+        split_col_publish(ch, src, k, gas, sm.P);
+        if (k >= 0 && k <= 15) publish_outer(src, k, col_out, ox, oy, has_edge, col_edge, ex, ey, gas, sm.P);
+      }
+    }
+    __syncthreads();
+    cells_col_vjp(ci, k, ws, gas, fo, sm);
+    if (halo) cells_col_vjp(ch, k, ws, gas, fo, sm);
+    __syncthreads();
+    cells_col_finish(ci, src, k, go, gas, sm, sink);
+    if (halo) {
+      cells_col_finish(ch, src, k, go, gas, sm, sink);
+      if (k >= 0 && k <= 15) {
+        // the 2-deep and edge columns get only in-plane contributions
+        T g[5] = {T(0), T(0), T(0), T(0), T(0)};
+        cells_gather_plane(ox, oy, k, sm, g);
+        finalize_cell(src, col_out, ox, oy, k, g, go, gas, sink);
+        if (has_edge) {
+          T e[5] = {T(0), T(0), T(0), T(0), T(0)};
+          cells_gather_plane(ex, ey, k, sm, e);
+          finalize_cell(src, col_edge, ex, ey, k, e, go, gas, sink);
+        }
+      }
+    }
+    split_col_shift(ci);
+    if (halo) split_col_shift(ch);
+  }
+}
+
 // ------------------------------------------------------------- kernels ----
 
 template <typename T>
@@ -495,6 +876,53 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(Adj
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
   adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void adj_faces_padded(
+    const T* __restrict__ Upad, const T* __restrict__ gout_, T* __restrict__ ws, int gh, Gas<T> gas,
+    int first_order, int wsp) {
+  __shared__ SmemFaces<T> sm;
+  const int P = 16 + 2 * gh;
+  const int64_t g = blockIdx.x;
+  PaddedSource<T> src{Upad + g * 5 * int64_t(P) * P * P, P, gh};
+  adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, wsp, sm);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void adj_cells_padded(
+    const T* __restrict__ Upad, const T* __restrict__ gout_, const T* __restrict__ ws, T* __restrict__ gpad, int gh,
+    Gas<T> gas, int first_order) {
+  __shared__ SmemCells<T> sm;
+  const int P = 16 + 2 * gh;
+  const int64_t g = blockIdx.x;
+  const int64_t P3 = int64_t(P) * P * P;
+  PaddedSource<T> src{Upad + g * 5 * P3, P, gh};
+  PadSink<T> sink{gpad + g * 5 * P3, P, gh};
+  adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, sm, sink);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void adj_faces_level(
+    const T* __restrict__ level, const T* __restrict__ gout_, T* __restrict__ ws, LevelGeom geo, Gas<T> gas,
+    const double* __restrict__ dt_dev, double dx, int first_order, int wsp) {
+  __shared__ SmemFaces<T> sm;
+  set_dt_adj(gas, dt_dev, dx);
+  const int64_t g = blockIdx.x;
+  LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
+  adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, wsp, sm);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void adj_cells_level(
+    const T* __restrict__ level, const T* __restrict__ gout_, const T* __restrict__ ws, T* __restrict__ gbox,
+    LevelGeom geo, Gas<T> gas, const double* __restrict__ dt_dev, double dx, int first_order) {
+  __shared__ SmemCells<T> sm;
+  set_dt_adj(gas, dt_dev, dx);
+  const int64_t g = blockIdx.x;
+  LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
+  BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
+  adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, sm, sink);
 }
 
 // ------------------------------------------------------------ kernel C ----
@@ -669,12 +1097,13 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ p, int64_t n)
 }  // namespace
 
 size_t adjoint_workspace_elems(int64_t n_groups, bool level) {
-  return level ? size_t(n_groups) * 5 * size_t(kBox * kBox * kBox) : 0;
+  // the face workspace of the split form, plus the reachable-cell box of the level path
+  return size_t(n_groups) * (size_t(kFaceWs) + (level ? 5 * size_t(kBox * kBox * kBox) : 0));
 }
 
 template <typename T>
 hipError_t launch_mhm_adjoint_padded(const T* U_pad, const T* g_out, T* g_pad, int64_t G, int ghost, const Gas<T>& gas,
-                                     int first_order, int ws, T* /*work*/, hipStream_t stream) {
+                                     int first_order, int ws, T* work, bool split, hipStream_t stream) {
   if (G == 0) return hipSuccess;
   if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int P = 16 + 2 * ghost;
@@ -683,22 +1112,37 @@ hipError_t launch_mhm_adjoint_padded(const T* U_pad, const T* g_out, T* g_pad, i
   if (zb > 65536) zb = 65536;
   // positions the step does not read receive zero
   hipLaunchKernelGGL(zero_kernel<T>, dim3(unsigned(zb)), dim3(256), 0, stream, g_pad, n);
-  hipLaunchKernelGGL(adj_fused_padded<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, U_pad, g_out, g_pad, ghost,
-                     gas, first_order, ws);
+  if (split) {
+    hipLaunchKernelGGL(adj_faces_padded<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, U_pad, g_out, work,
+                       ghost, gas, first_order, ws);
+    hipLaunchKernelGGL(adj_cells_padded<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, U_pad, g_out, work,
+                       g_pad, ghost, gas, first_order);
+  } else {
+    hipLaunchKernelGGL(adj_fused_padded<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, U_pad, g_out, g_pad,
+                       ghost, gas, first_order, ws);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, const LevelGeom& geo, const Gas<T>& gas,
-                                    const double* dt_dev, double dx, int first_order, int ws, T* work,
+                                    const double* dt_dev, double dx, int first_order, int ws, T* work, bool split,
                                     hipStream_t stream) {
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   if (G == 0) return hipSuccess;
   if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
   if (geo.ngx >= (1 << 19) || geo.ngy >= (1 << 19) || geo.ngz >= (1 << 19)) return hipErrorInvalidValue;
   T* gbox = work;  // [G][5][20^3]; only reachable positions are written, and only those are read
-  hipLaunchKernelGGL(adj_fused_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, gbox, geo, gas,
-                     dt_dev, dx, first_order, ws);
+  T* fws = work + G * 5 * int64_t(kBox * kBox * kBox);
+  if (split) {
+    hipLaunchKernelGGL(adj_faces_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, fws, geo,
+                       gas, dt_dev, dx, first_order, ws);
+    hipLaunchKernelGGL(adj_cells_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, fws, gbox,
+                       geo, gas, dt_dev, dx, first_order);
+  } else {
+    hipLaunchKernelGGL(adj_fused_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, gbox, geo,
+                       gas, dt_dev, dx, first_order, ws);
+  }
   const int64_t ncells = G * 4096;
   hipLaunchKernelGGL((adj_gather<T, true>), dim3(unsigned((ncells + 255) / 256)), dim3(256), 0, stream, gbox, g_in,
                      geo, 2, ncells);
@@ -719,14 +1163,14 @@ hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGe
 }
 
 template hipError_t launch_mhm_adjoint_padded<double>(const double*, const double*, double*, int64_t, int,
-                                                      const Gas<double>&, int, int, double*, hipStream_t);
+                                                      const Gas<double>&, int, int, double*, bool, hipStream_t);
 template hipError_t launch_mhm_adjoint_padded<float>(const float*, const float*, float*, int64_t, int,
-                                                     const Gas<float>&, int, int, float*, hipStream_t);
+                                                     const Gas<float>&, int, int, float*, bool, hipStream_t);
 template hipError_t launch_mhm_adjoint_level<double>(const double*, const double*, double*, const LevelGeom&,
                                                      const Gas<double>&, const double*, double, int, int, double*,
-                                                     hipStream_t);
+                                                     bool, hipStream_t);
 template hipError_t launch_mhm_adjoint_level<float>(const float*, const float*, float*, const LevelGeom&,
-                                                    const Gas<float>&, const double*, double, int, int, float*,
+                                                    const Gas<float>&, const double*, double, int, int, float*, bool,
                                                     hipStream_t);
 template hipError_t launch_gather_ghost_adjoint<double>(const double*, double*, const LevelGeom&, int, hipStream_t);
 template hipError_t launch_gather_ghost_adjoint<float>(const float*, float*, const LevelGeom&, int, hipStream_t);

@@ -67,6 +67,8 @@ def load():
         "hydro_gather_ghost_adjoint": (i32, [P, P, i32, i32, i32, i32, i32, P, P]),
         "hydro_num_variants": (i32, []),
         "hydro_set_variant": (i32, [i32, i32]),
+        "hydro_set_adjoint_variant": (i32, [i32, i32]),
+        "hydro_get_adjoint_variant": (i32, [i32]),
         "hydro_get_variant": (i32, [i32]),
         "hydro_variant_name": (i32, [i32, ctypes.c_char_p, i32]),
         "hydro_autotune": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, i32, P, P]),
@@ -460,6 +462,19 @@ def variant_name(v: int) -> str:
     buf = ctypes.create_string_buffer(128)
     _check(load().hydro_variant_name(int(v), buf, 128), "hydro_variant_name")
     return buf.value.decode()
+
+
+def set_adjoint_variant(dtype, v: int) -> None:
+    """Form of the step adjoint for a dtype: 0 fused sweep, 1 two kernels with a face workspace."""
+    _check(load().hydro_set_adjoint_variant(F64 if dtype == torch.float64 else F32, int(v)),
+           "hydro_set_adjoint_variant")
+
+
+def get_adjoint_variant(dtype) -> int:
+    v = load().hydro_get_adjoint_variant(F64 if dtype == torch.float64 else F32)
+    if v < 0:
+        raise HydroError("hydro_get_adjoint_variant", v)
+    return int(v)
 
 
 def set_variant(dtype, v: int) -> None:
