@@ -103,7 +103,10 @@ def run_workload(hydro, torch, lv, dtype, steps, warmup, fused=True, autotune=Tr
     if fused and autotune:
         # choose the launch shape (all shapes give bit-identical results) before timing
         best, times = hydro.autotune(U0, lv.ng, lv.bc, lv.dx, lv.gamma, reps=5)
-        tune = {"variant": best, "name": hydro.variant_name(best), "ms": [round(t, 4) for t in times]}
+        n = hydro.num_variants()
+        tune = {"variant": best, "name": hydro.variant_name(best),
+                "ms": [round(t, 4) for t in times[n:]], "ms_without_cfl": [round(t, 4) for t in times[:n]],
+                "variant_without_cfl": hydro.get_level_variant(tdt, False)}
     solver.load_state(U0)
     for _ in range(warmup):
         solver.step()

@@ -285,13 +285,19 @@ int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t
  * differ in the register budget the compiler was given (occupancy) and in the
  * order groups are dealt to workgroups (plain, or blocked so that each of the
  * 8 XCDs sweeps a contiguous range of groups and finds neighbour-group halos
- * in its own L2).  The choice is process-wide, per dtype.
- *   hydro_num_variants   number of shapes (>= 1)
- *   hydro_set_variant    select one (0 .. n-1); HYDRO_EINVAL otherwise
- *   hydro_get_variant    current selection for a dtype
- *   hydro_variant_name   short description into buf[len] (host memory)
+ * in its own L2).  The choice is process-wide, per dtype and per kernel
+ * form (with_cfl: the form that reduces the next CFL time-step, which needs
+ * more registers).
+ *   hydro_num_variants       number of shapes (>= 1)
+ *   hydro_set_level_variant  select one (0 .. n-1) for one form; HYDRO_EINVAL otherwise
+ *   hydro_get_level_variant  current selection for a dtype and form
+ *   hydro_set_variant        select one for both forms
+ *   hydro_get_variant        current selection of the CFL form
+ *   hydro_variant_name       short description into buf[len] (host memory)
  */
 int hydro_num_variants(void);
+int hydro_set_level_variant(int32_t dtype, int32_t with_cfl, int32_t variant);
+int hydro_get_level_variant(int32_t dtype, int32_t with_cfl);
 int hydro_set_variant(int32_t dtype, int32_t variant);
 int hydro_get_variant(int32_t dtype);
 int hydro_variant_name(int32_t variant, char* buf, int32_t len);
@@ -300,9 +306,12 @@ int hydro_variant_name(int32_t variant, char* buf, int32_t len);
  * caller's level (1 untimed + `reps` timed launches each, HIP events on
  * `stream`, 1 <= reps <= 1000), select the fastest for `dtype` and return its
  * index (>= 0), or a negative status (the previous selection is then kept).
- * SYNCHRONOUS: waits on `stream`.  level_dev is read, scratch_out_dev
- * ([G][5][16^3], not overlapping) is overwritten.  times_ms_host, if not
- * NULL, receives hydro_num_variants() mean times in milliseconds.
+ * Both kernel forms are timed and tuned separately (without and with the CFL
+ * epilogue; the returned index is the CFL form's).  SYNCHRONOUS: waits on
+ * `stream`; allocates (and frees) a small device buffer for the CFL outputs.
+ * level_dev is read, scratch_out_dev ([G][5][16^3], not overlapping) is
+ * overwritten.  times_ms_host, if not NULL, receives 2 * hydro_num_variants()
+ * mean times in milliseconds (the form without CFL first).
  */
 int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                    const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps,

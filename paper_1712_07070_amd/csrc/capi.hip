@@ -22,7 +22,9 @@ thread_local int g_last_hip_error = 0;
 
 // Launch shape of the level step per dtype (index into the variants of
 // mhm_fwd.hip); set by hydro_set_variant or hydro_autotune, process-wide.
-std::atomic<int> g_level_variant[2] = {{1}, {1}};  // measured defaults: plain order, high occupancy
+// [dtype][with CFL epilogue]: the two kernels differ in register needs, so
+// each gets its own shape.
+std::atomic<int> g_level_variant[2][2] = {{{1}, {1}}, {{1}, {1}}};  // measured defaults: plain order, high occupancy
 // Form of the step adjoint per dtype: 0 fused single sweep, 1 two kernels
 // with a face workspace.
 std::atomic<int> g_adjoint_variant[2] = {{0}, {0}};  // measured: fused faster in both dtypes
@@ -220,31 +222,40 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
   const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
   const int ws = (scheme >> 8) & 3;
   const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  const bool with_cfl = cfl.dt_min != nullptr || cfl.dt_patch != nullptr || cfl.reset != nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (dtype == HYDRO_F64)
     e = gh::launch_mhm_level(static_cast<const double*>(level_dev), static_cast<double*>(level_out_dev), geo,
                              make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
-                             g_level_variant[0].load(), s);
+                             g_level_variant[0][with_cfl ? 1 : 0].load(), s);
   else
     e = gh::launch_mhm_level(static_cast<const float*>(level_dev), static_cast<float*>(level_out_dev), geo,
                              make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
-                             g_level_variant[1].load(), s);
+                             g_level_variant[1][with_cfl ? 1 : 0].load(), s);
   return device_status(e);
 }
 
 int hydro_num_variants(void) { return gh::kLevelVariants; }
 
-int hydro_get_variant(int32_t dtype) {
+int hydro_get_level_variant(int32_t dtype, int32_t with_cfl) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
-  return g_level_variant[dtype].load();
+  return g_level_variant[dtype][with_cfl ? 1 : 0].load();
 }
 
-int hydro_set_variant(int32_t dtype, int32_t variant) {
+int hydro_set_level_variant(int32_t dtype, int32_t with_cfl, int32_t variant) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
   if (variant < 0 || variant >= gh::kLevelVariants) return HYDRO_EINVAL;
-  g_level_variant[dtype].store(variant);
+  g_level_variant[dtype][with_cfl ? 1 : 0].store(variant);
   return HYDRO_OK;
+}
+
+int hydro_get_variant(int32_t dtype) { return hydro_get_level_variant(dtype, 1); }
+
+int hydro_set_variant(int32_t dtype, int32_t variant) {
+  int st = hydro_set_level_variant(dtype, 0, variant);
+  if (st == HYDRO_OK) st = hydro_set_level_variant(dtype, 1, variant);
+  return st;
 }
 
 int hydro_variant_name(int32_t variant, char* buf, int32_t len) {
@@ -258,53 +269,71 @@ int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, in
                    const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps, float* times_ms_host,
                    void* stream) {
   if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  if (ngx < 1 || ngy < 1 || ngz < 1) return HYDRO_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int saved = g_level_variant[dtype].load();
+  const int saved[2] = {g_level_variant[dtype][0].load(), g_level_variant[dtype][1].load()};
+  // CFL outputs of the timed CFL-epilogue launches: 3 scalars + 8 per group
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  double* cfl_buf = nullptr;
+  if (hipMalloc(&cfl_buf, sizeof(double) * size_t(3 + 8 * G)) != hipSuccess) return device_status(hipGetLastError());
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return device_status(hipGetLastError());
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
+  if (hipEventCreate(&e0) != hipSuccess) {
+    (void)hipFree(cfl_buf);
     return device_status(hipGetLastError());
   }
-  int best = -1, status = HYDRO_OK;
-  float best_ms = 0.0f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    (void)hipFree(cfl_buf);
+    return device_status(hipGetLastError());
+  }
+  int best[2] = {-1, -1}, status = HYDRO_OK;
+  float best_ms[2] = {0.0f, 0.0f};
   const double dt = 1e-3 * dx;  // any positive step does the same work
-  for (int v = 0; v < gh::kLevelVariants && status == HYDRO_OK; ++v) {
-    g_level_variant[dtype].store(v);
-    // one untimed launch, then `reps` timed ones
-    status = hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
-                                 HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, nullptr, nullptr, nullptr,
-                                 stream);
-    if (status != HYDRO_OK) break;
-    hipError_t he = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r)
-      status = hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
-                                   HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, nullptr, nullptr, nullptr,
+  for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
+    double* dt_next = form ? cfl_buf : nullptr;
+    double* dt_reset = form ? cfl_buf + 1 : nullptr;
+    double* dt_patch = form ? cfl_buf + 3 : nullptr;
+    for (int v = 0; v < gh::kLevelVariants && status == HYDRO_OK; ++v) {
+      g_level_variant[dtype][form].store(v);
+      auto launch = [&]() {
+        return hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
+                                   HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, dt_next, dt_patch, dt_reset,
                                    stream);
-    if (status != HYDRO_OK) break;
-    if (he == hipSuccess) he = hipEventRecord(e1, s);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-    if (he != hipSuccess) {
-      status = device_status(he);
-      break;
-    }
-    ms /= float(reps);
-    if (times_ms_host != nullptr) times_ms_host[v] = ms;
-    if (best < 0 || ms < best_ms) {
-      best = v;
-      best_ms = ms;
+      };
+      // one untimed launch, then `reps` timed ones
+      status = launch();
+      if (status != HYDRO_OK) break;
+      hipError_t he = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch();
+      if (status != HYDRO_OK) break;
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        status = device_status(he);
+        break;
+      }
+      ms /= float(reps);
+      if (times_ms_host != nullptr) times_ms_host[form * gh::kLevelVariants + v] = ms;
+      if (best[form] < 0 || ms < best_ms[form]) {
+        best[form] = v;
+        best_ms[form] = ms;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(cfl_buf);
   if (status != HYDRO_OK) {
-    g_level_variant[dtype].store(saved);
+    g_level_variant[dtype][0].store(saved[0]);
+    g_level_variant[dtype][1].store(saved[1]);
     return status;
   }
-  g_level_variant[dtype].store(best);
-  return best;
+  g_level_variant[dtype][0].store(best[0]);
+  g_level_variant[dtype][1].store(best[1]);
+  return best[1];
 }
 
 int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,

@@ -115,10 +115,14 @@ __device__ __forceinline__ void fwd_col_init(FwdCol<T, kI>& c, const Src& src, i
 template <typename T, bool kI, class Src>
 __device__ __forceinline__ void fwd_col_publish(FwdCol<T, kI>& c, const Src& src, int k, const Gas<T>& gas,
                                                 Smem<T>& sm) {
-  if (k + 1 <= c.zhi) {
-    cons_to_prim(c.Un, gas, c.Wp);
-    if (k + 2 <= c.zhi) load_cons(src, c.col, k + 2, c.Un);
-  }
+  // Convert the plane that arrived, then issue the next one.  The load is
+  // unconditional (plane index clamped to the column's last plane, re-read
+  // harmlessly near the top) and issued after the conversion, so the loaded
+  // registers are never merged with old values: a merge would need the data
+  // and wait for the load that is meant to stay in flight.
+  cons_to_prim(c.Un, gas, c.Wp);
+  asm volatile("" ::: "memory");
+  load_cons(src, c.col, k + 2 <= c.zhi ? k + 2 : c.zhi, c.Un);
 #pragma unroll
   for (int q = 0; q < 5; ++q) sm.P[q][pidx(c.cx, c.cy)] = c.Wc[q];
 }
@@ -261,54 +265,53 @@ __device__ __forceinline__ void fwd_col_shift(FwdCol<T, kI>& c) {
   }
 }
 
-// Advance one group: read through `src`, write the 16^3 x 5 interior to `out`
-// (field stride 4096).  Returns this thread's unphysical count.  If smax is
-// non-null, also returns the maximum CFL signal speed of the thread's interior
-// cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's index in the
-// workgroup (a loop over groups passes it opaque, so that the compiler keeps
-// thread-derived addresses out of the loop's live set).
-template <typename T, class Src>
-__device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
-                                             int first_order, int ws, Smem<T>& sm, double* smax,
-                                             double gamma_d, int tid = threadIdx.x) {
-  const bool halo = tid < 64;  // wave 0
+// The z-march of one wave: interior role, plus the halo roles when kHalo
+// (wave 0).  Both instantiations pass the same barriers in the same order.
+template <typename T, class Src, bool kHalo>
+__device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, const Gas<T>& gas, int first_order,
+                                           int ws, Smem<T>& sm, double* smax, double gamma_d, int tid) {
   // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
   // 0..3 also one of the 4 edge columns
-  const int side = tid >> 4, kk = tid & 15;
+  const int side = (tid >> 4) & 3, kk = tid & 15;
   const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
   const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
   const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
-  const bool has_edge = halo && tid < 4;
-  const int64_t col_out = halo ? src.col(ox, oy) : 0;
-  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
+  const bool has_edge = kHalo && tid < 4;
 
   FwdCol<T, true> ci;
   FwdCol<T, false> ch;
   fwd_col_init(ci, src, tid & 15, tid >> 4, gas);
+  int64_t col_out = 0, col_edge = 0;
   T Uo[5], Ue[5];  // halo role: 2-deep and edge column, plane k (in flight)
-  if (halo) {
+  if (kHalo) {
+    col_out = src.col(ox, oy);
+    col_edge = src.col(has_edge ? ex : ox, has_edge ? ey : oy);  // lanes without an edge re-read their 2-deep column
     fwd_col_init(ch, src, hx, hy, gas);
     load_cons(src, col_out, 0, Uo);
-    if (has_edge) load_cons(src, col_edge, 0, Ue);
+    load_cons(src, col_edge, 0, Ue);
   }
   int bad = 0;
 
   for (int k = -1; k <= 16; ++k) {
     // ---- next planes (prefetched); publish plane k to LDS
     fwd_col_publish(ci, src, k, gas, sm);
-    if (halo) {
+    if (kHalo) {
       fwd_col_publish(ch, src, k, gas, sm);
+      // 2-deep and edge columns (planes 0..15; loads clamped, no merge of
+      // loaded registers with old values)
+      T Wo[5], We[5];
+      cons_to_prim(Uo, gas, Wo);
+      cons_to_prim(Ue, gas, We);
+      asm volatile("" ::: "memory");
+      const int kn = k + 1 < 0 ? 0 : (k + 1 > 15 ? 15 : k + 1);
+      load_cons(src, col_out, kn, Uo);
+      load_cons(src, col_edge, kn, Ue);
       if (k >= 0 && k <= 15) {
-        T Wo[5];
-        cons_to_prim(Uo, gas, Wo);
-        if (k + 1 <= 15) load_cons(src, col_out, k + 1, Uo);
 #pragma unroll
         for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
         if (has_edge) {
-          cons_to_prim(Ue, gas, Wo);
-          if (k + 1 <= 15) load_cons(src, col_edge, k + 1, Ue);
 #pragma unroll
-          for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = Wo[q];
+          for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = We[q];
         }
       }
     }
@@ -316,17 +319,33 @@ __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out
 
     // ---- half-step face states of plane k; z-face and update of plane k-1
     bad += fwd_col_states(ci, src, out, k, gas, first_order, ws, sm, smax, gamma_d);
-    if (halo) bad += fwd_col_states(ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d);
+    if (kHalo) bad += fwd_col_states(ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d);
     __syncthreads();
 
     // ---- x and y faces of plane k
     bad += fwd_col_faces(ci, k, gas, ws, sm);
-    if (halo) bad += fwd_col_faces(ch, k, gas, ws, sm);
+    if (kHalo) bad += fwd_col_faces(ch, k, gas, ws, sm);
 
     fwd_col_shift(ci);
-    if (halo) fwd_col_shift(ch);
+    if (kHalo) fwd_col_shift(ch);
   }
   return bad;
+}
+
+// Advance one group: read through `src`, write the 16^3 x 5 interior to `out`
+// (field stride 4096).  Returns this thread's unphysical count.  If smax is
+// non-null, also returns the maximum CFL signal speed of the thread's interior
+// cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's index in the
+// workgroup (a loop over groups passes it opaque, so that the compiler keeps
+// thread-derived addresses out of the loop's live set).  Wave 0 runs the
+// march with the halo roles, waves 1-3 without them (a wave-uniform branch).
+template <typename T, class Src>
+__device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
+                                             int first_order, int ws, Smem<T>& sm, double* smax,
+                                             double gamma_d, int tid = threadIdx.x) {
+  if (__builtin_amdgcn_readfirstlane(tid >> 6) == 0)
+    return march_group<T, Src, true>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+  return march_group<T, Src, false>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
 }
 
 // Reduce the per-thread signal-speed maxima of one group to its 8 patch

@@ -67,6 +67,8 @@ def load():
         "hydro_gather_ghost_adjoint": (i32, [P, P, i32, i32, i32, i32, i32, P, P]),
         "hydro_num_variants": (i32, []),
         "hydro_set_variant": (i32, [i32, i32]),
+        "hydro_set_level_variant": (i32, [i32, i32, i32]),
+        "hydro_get_level_variant": (i32, [i32, i32]),
         "hydro_set_adjoint_variant": (i32, [i32, i32]),
         "hydro_get_adjoint_variant": (i32, [i32]),
         "hydro_get_variant": (i32, [i32]),
@@ -485,15 +487,26 @@ def get_variant(dtype) -> int:
     return int(load().hydro_get_variant(F64 if dtype == torch.float64 else F32))
 
 
+def set_level_variant(dtype, with_cfl: bool, v: int) -> None:
+    _check(load().hydro_set_level_variant(F64 if dtype == torch.float64 else F32, int(bool(with_cfl)), int(v)),
+           "hydro_set_level_variant")
+
+
+def get_level_variant(dtype, with_cfl: bool) -> int:
+    return int(load().hydro_get_level_variant(F64 if dtype == torch.float64 else F32, int(bool(with_cfl))))
+
+
 def autotune(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dx: float, gamma: float,
              reps: int = 5) -> Tuple[int, list]:
-    """Time every launch shape on this level, select the fastest (hydro_autotune).
+    """Time every launch shape on this level in both kernel forms (without and
+    with the CFL epilogue), select the fastest of each (hydro_autotune).
 
-    Returns (chosen variant, mean ms per variant)."""
+    Returns (chosen variant of the CFL form, mean ms per variant: the form
+    without CFL first, then the CFL form)."""
     ngx, ngy, ngz = (int(v) for v in ng)
     scratch = torch.empty_like(level)
     n = num_variants()
-    times = (ctypes.c_float * n)()
+    times = (ctypes.c_float * (2 * n))()
     b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
     st = load().hydro_autotune(_dev(level, "level"), _dev(scratch, "scratch"), ngx, ngy, ngz, b, _dtype_code(level),
                                float(dx), float(gamma), int(reps), times, _stream())

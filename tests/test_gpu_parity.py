@@ -377,9 +377,12 @@ def test_autotune_selects_a_shape(hydro):
     saved = hydro.get_variant(torch.float64)
     try:
         best, times = hydro.autotune(t, lv.ng, lv.bc, lv.dx, lv.gamma, reps=2)
-        assert 0 <= best < hydro.num_variants()
-        assert hydro.get_variant(torch.float64) == best
-        assert all(x > 0 for x in times) and times[best] == min(times)
+        n = hydro.num_variants()
+        assert 0 <= best < n and len(times) == 2 * n
+        assert hydro.get_variant(torch.float64) == best == hydro.get_level_variant(torch.float64, True)
+        assert all(x > 0 for x in times) and times[n + best] == min(times[n:])
+        b0 = hydro.get_level_variant(torch.float64, False)
+        assert times[b0] == min(times[:n])
     finally:
         hydro.set_variant(torch.float64, saved)
 
