@@ -14,6 +14,17 @@ namespace gh {
 
 namespace {
 
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const long long r = (long long)(unsigned int)__builtin_amdgcn_readfirstlane((int)(b & 0xffffffff)) |
+                      ((long long)__builtin_amdgcn_readfirstlane((int)(b >> 32)) << 32);
+  return __longlong_as_double(r);
+}
+
 // Work counters: kQueues ticket counters, then the departure counter.
 // Queue modes: 0, one queue, items in ticket order; 1, queue c serves the
 // items c, c + kQueues, c + 2 kQueues, ... and workgroup b starts at queue
@@ -63,6 +74,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     // order 1 deals items from the last (finest, largest) level first
     return i < 0 ? -1 : (order ? args.total - 1 - i : i);
   };
+  // dt / dx of every level, once per workgroup (the same expression as the
+  // level kernel's, kept out of the item loop's registers)
+  __shared__ T lv_dtdx[kMaxLevels], lv_half_dtdx[kMaxLevels];
+  if (threadIdx.x < unsigned(args.n_levels)) {
+    const BatchLevel<T>& L = args.lv[threadIdx.x];
+    Gas<T> gl = gas;
+    gl.dtdx = L.dtdx;
+    gl.half_dtdx = L.half_dtdx;
+    set_dt(gl, L.dt_dev, L.dx);
+    lv_dtdx[threadIdx.x] = gl.dtdx;
+    lv_half_dtdx[threadIdx.x] = gl.half_dtdx;
+  }
   if (threadIdx.x == 0) {
     tried = 0;
     item_slot = resolve(take());
@@ -82,13 +105,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     const BatchLevel<T>& L = args.lv[l];
     const int64_t g = item - L.g_begin;
     Gas<T> gl = gas;
-    gl.dtdx = L.dtdx;
-    gl.half_dtdx = L.half_dtdx;
-    if (L.dt_dev != nullptr) {
-      const double dt = *L.dt_dev;
-      gl.dtdx = T(dt / L.dx);
-      gl.half_dtdx = T(0.5 * (dt / L.dx));
-    }
+    gl.dtdx = uniform(lv_dtdx[l]);
+    gl.half_dtdx = uniform(lv_half_dtdx[l]);
     const LevelGeom& geo = L.geo;
     LevelSource<T> src{L.in, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
     // an opaque thread index per item keeps thread-derived addresses from
