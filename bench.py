@@ -61,16 +61,18 @@ def kernel_source_sha() -> str:
 
 
 def measured_traffic(kernel_key: str, variant):
-    """HBM bytes per launch from the committed counter profile, or None when
-    the kernel sources or the launch shape differ from what was measured."""
+    """HBM bytes per launch from the committed counter profile of this launch
+    shape, or None when the kernel sources differ from what was measured or
+    the shape was not measured."""
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
             rec = json.load(fh).get(kernel_key)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_sha256") != kernel_source_sha() or rec.get("variant") != variant:
+    if not rec or rec.get("source_sha256") != kernel_source_sha():
         return None
-    return rec["bytes_per_launch"]
+    shape = rec.get("by_variant", {}).get(str(variant))
+    return shape["bytes_per_launch"] if shape else None
 
 
 def parse():
@@ -85,6 +87,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--unfused", action="store_true", help="time fill + dt + padded advance per step")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="launch shape of the level step (implies --no-autotune), e.g. for counter runs")
     ap.add_argument("--no-amr", action="store_true", help="skip the batched multi-level measurement")
     ap.add_argument("--amr-coarse-steps", type=int, default=4)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fwd+adjoint rollout measurements")
@@ -347,6 +351,9 @@ def main():
     cells = lv.n_cells
     print("bench: timing %s" % args.dtype, file=sys.stderr, flush=True)
     fused = not args.unfused
+    if args.variant is not None:
+        args.no_autotune = True
+        hydro.set_variant(torch.float64 if args.dtype == "f64" else torch.float32, args.variant)
     el, kms, solver, dts, n_bad, tune = run_workload(hydro, torch, lv, args.dtype, args.steps, args.warmup, fused,
                                                      not args.no_autotune)
     value = cells * args.steps / el
