@@ -22,27 +22,25 @@ struct BC6 {
 
 template <typename T>
 __global__ __launch_bounds__(256) void fill_ghosts_kernel(const T* __restrict__ level, T* __restrict__ U_pad,
-                                                          int ngx, int ngy, int ngz, int gh, BC6 bc,
-                                                          int64_t total) {
+                                                          int ngx, int ngy, int ngz, int gh, BC6 bc) {
+  // one workgroup per padded plane: (group g, field f, padded z); the plane's
+  // P x P cells are written contiguously
   const int P = 16 + 2 * gh;
+  const unsigned int blk = blockIdx.x;
+  const int z = int(blk % unsigned(P));
+  const int f = int((blk / unsigned(P)) % 5u);
+  const unsigned int g = blk / unsigned(5 * P);
+  const int gx = int(g % unsigned(ngx)), gy = int((g / unsigned(ngx)) % unsigned(ngy));
+  const int gz = int(g / (unsigned(ngx) * unsigned(ngy)));
   const int Nx = ngx * 16, Ny = ngy * 16, Nz = ngz * 16;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    int64_t r = i;
-    const int x = int(r % P);
-    r /= P;
-    const int y = int(r % P);
-    r /= P;
-    const int z = int(r % P);
-    r /= P;
-    const int f = int(r % 5);
-    const int64_t g = r / 5;
-    const int gx = int(g % ngx), gy = int((g / ngx) % ngy), gz = int(g / (int64_t(ngx) * ngy));
+  const int Z = bc_map(gz * 16 + z - gh, Nz, bc.b[4], bc.b[5]);
+  T* dst = U_pad + (int64_t(blk / unsigned(P)) * P + z) * P * P;  // ((g*5 + f)*P + z)*P*P
+  for (int i = threadIdx.x; i < P * P; i += blockDim.x) {
+    const int x = i % P, y = i / P;
     const int X = bc_map(gx * 16 + x - gh, Nx, bc.b[0], bc.b[1]);
     const int Y = bc_map(gy * 16 + y - gh, Ny, bc.b[2], bc.b[3]);
-    const int Z = bc_map(gz * 16 + z - gh, Nz, bc.b[4], bc.b[5]);
     const int64_t sg = (int64_t(Z >> 4) * ngy + (Y >> 4)) * ngx + (X >> 4);
-    U_pad[i] = level[((sg * 5 + f) * 16 + (Z & 15)) * 256 + (Y & 15) * 16 + (X & 15)];
+    dst[i] = level[((sg * 5 + f) * 16 + (Z & 15)) * 256 + (Y & 15) * 16 + (X & 15)];
   }
 }
 
@@ -98,14 +96,13 @@ template <typename T>
 hipError_t launch_fill_ghosts(const T* level, T* U_pad, int ngx, int ngy, int ngz, int ghost, const int bc[6],
                               hipStream_t stream) {
   const int P = 16 + 2 * ghost;
-  const int64_t total = int64_t(ngx) * ngy * ngz * 5 * P * P * P;
-  if (total == 0) return hipSuccess;
+  const int64_t planes = int64_t(ngx) * ngy * ngz * 5 * P;  // one workgroup per padded plane
+  if (planes == 0) return hipSuccess;
+  if (planes > (int64_t(1) << 31)) return hipErrorInvalidValue;
   BC6 b;
   for (int i = 0; i < 6; ++i) b.b[i] = bc[i];
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 1048576) blocks = 1048576;
-  hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, stream, level, U_pad, ngx, ngy,
-                     ngz, ghost, b, total);
+  hipLaunchKernelGGL(fill_ghosts_kernel<T>, dim3(unsigned(planes)), dim3(256), 0, stream, level, U_pad, ngx, ngy,
+                     ngz, ghost, b);
   return hipGetLastError();
 }
 
