@@ -95,7 +95,9 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
  * a group (2 layers) is read from the neighbouring group with the index map
  * of hydro_fill_ghosts, so the result equals hydro_fill_ghosts followed by
  * hydro_advance, without the padded copy.
- *   level_dev       [G][5][16^3] input level, G = ngx*ngy*ngz (not modified)
+ *   level_dev       [G][5][16^3] input level, G = ngx*ngy*ngz (not modified);
+ *                   every level entry point takes 1 <= ngx, ngy, ngz <= 2^26
+ *                   and G < 2^31 - 8 (else HYDRO_EINVAL)
  *   level_out_dev   [G][5][16^3] output level; must not overlap level_dev
  *   bc_host         6 ints on the host (x-, x+, y-, y+, z-, z+), 0 periodic,
  *                   1 outflow
@@ -181,7 +183,7 @@ int hydro_get_adjoint_variant(int32_t dtype);
 typedef struct {
   const void* level_dev;  /* [G_l][5][16^3] input level storage */
   void* level_out_dev;    /* [G_l][5][16^3] output level storage */
-  int32_t ngx, ngy, ngz;  /* group lattice of the level */
+  int32_t ngx, ngy, ngz;  /* group lattice of the level (limits as hydro_advance_level) */
   int32_t bc[6];
   double dt;
   double dx;
@@ -208,9 +210,11 @@ typedef struct {
  * per XCD, each serving one residue class of items mod 8, with stealing when
  * it runs dry; 2: static round-robin, workgroup b takes items b, b + grid, ...);
  * hydro_set_batched_variant / hydro_get_batched_variant select and read it,
- * hydro_autotune_batched times all of them on the given levels (SYNCHRONOUS;
- * the outputs are overwritten; times_ms_host receives HYDRO_BATCHED_VARIANTS
- * floats) and keeps the fastest.
+ * hydro_autotune_batched times all of them on the given levels (two passes
+ * of 1 untimed + `reps` timed launches per shape, a shape's time is the
+ * smaller of its two means; SYNCHRONOUS; the outputs are overwritten;
+ * times_ms_host receives HYDRO_BATCHED_VARIANTS floats) and keeps the
+ * fastest.
  */
 #define HYDRO_BATCH_WORK_WORDS 16
 #define HYDRO_BATCHED_VARIANTS 12
@@ -303,15 +307,16 @@ int hydro_get_variant(int32_t dtype);
 int hydro_variant_name(int32_t variant, char* buf, int32_t len);
 
 /* hydro_autotune -- time every launch shape of hydro_advance_level on the
- * caller's level (1 untimed + `reps` timed launches each, HIP events on
- * `stream`, 1 <= reps <= 1000), select the fastest for `dtype` and return its
+ * caller's level (two passes of 1 untimed + `reps` timed launches per shape,
+ * HIP events on `stream`, 1 <= reps <= 1000; a shape's time is the smaller of
+ * its two means), select the fastest for `dtype` and return its
  * index (>= 0), or a negative status (the previous selection is then kept).
  * Both kernel forms are timed and tuned separately (without and with the CFL
  * epilogue; the returned index is the CFL form's).  SYNCHRONOUS: waits on
  * `stream`; allocates (and frees) a small device buffer for the CFL outputs.
  * level_dev is read, scratch_out_dev ([G][5][16^3], not overlapping) is
  * overwritten.  times_ms_host, if not NULL, receives 2 * hydro_num_variants()
- * mean times in milliseconds (the form without CFL first).
+ * times in milliseconds (the form without CFL first).
  */
 int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                    const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps,

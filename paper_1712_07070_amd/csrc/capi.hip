@@ -114,13 +114,21 @@ int batched_impl(const hydro_level_t* lv, int32_t n_levels, double gamma, int32_
                                                  n_bad_dev, work_dev, variant, int(g), s));
 }
 
+// A level of ngx x ngy x ngz groups: cell indices along each axis (plus
+// ghosts) fit in 32-bit ints and group indices in 31 bits.
+bool level_geom_ok(long long ngx, long long ngy, long long ngz) {
+  if (ngx < 1 || ngy < 1 || ngz < 1) return false;
+  if (ngx > (1ll << 26) || ngy > (1ll << 26) || ngz > (1ll << 26)) return false;
+  return ngx * ngy * ngz < (1ll << 31) - 8;
+}
+
 int validate_levels(const hydro_level_t* lv, int32_t n_levels, int32_t dtype) {
   if (lv == nullptr || n_levels < 1 || n_levels > gh::kMaxLevels) return HYDRO_EINVAL;
   const size_t es = dtype_size(dtype);
   long long total = 0;
   for (int l = 0; l < n_levels; ++l) {
     const hydro_level_t& L = lv[l];
-    if (L.ngx < 1 || L.ngy < 1 || L.ngz < 1 || !finite_pos(L.dx)) return HYDRO_EINVAL;
+    if (!level_geom_ok(L.ngx, L.ngy, L.ngz) || !finite_pos(L.dx)) return HYDRO_EINVAL;
     if (L.dt_dev == nullptr && !finite_pos(L.dt)) return HYDRO_EINVAL;
     for (int i = 0; i < 6; ++i)
       if (L.bc[i] != HYDRO_BC_PERIODIC && L.bc[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
@@ -192,7 +200,7 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
                         const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
                         double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl, double* dt_next_dev,
                         double* dt_patch_next_dev, double* dt_reset_dev, void* stream) {
-  if (ngx < 1 || ngy < 1 || ngz < 1 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (!level_geom_ok(ngx, ngy, ngz) || bc_host == nullptr) return HYDRO_EINVAL;
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
   if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
     return HYDRO_EINVAL;
@@ -269,7 +277,7 @@ int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, in
                    const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps, float* times_ms_host,
                    void* stream) {
   if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
-  if (ngx < 1 || ngy < 1 || ngz < 1) return HYDRO_EINVAL;
+  if (!level_geom_ok(ngx, ngy, ngz)) return HYDRO_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int saved[2] = {g_level_variant[dtype][0].load(), g_level_variant[dtype][1].load()};
   // CFL outputs of the timed CFL-epilogue launches: 3 scalars + 8 per group
@@ -288,37 +296,47 @@ int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, in
   }
   int best[2] = {-1, -1}, status = HYDRO_OK;
   float best_ms[2] = {0.0f, 0.0f};
+  float ms_min[2][gh::kLevelVariants] = {};
   const double dt = 1e-3 * dx;  // any positive step does the same work
-  for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
-    double* dt_next = form ? cfl_buf : nullptr;
-    double* dt_reset = form ? cfl_buf + 1 : nullptr;
-    double* dt_patch = form ? cfl_buf + 3 : nullptr;
-    for (int v = 0; v < gh::kLevelVariants && status == HYDRO_OK; ++v) {
-      g_level_variant[dtype][form].store(v);
-      auto launch = [&]() {
-        return hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
-                                   HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, dt_next, dt_patch, dt_reset,
-                                   stream);
-      };
-      // one untimed launch, then `reps` timed ones
-      status = launch();
-      if (status != HYDRO_OK) break;
-      hipError_t he = hipEventRecord(e0, s);
-      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch();
-      if (status != HYDRO_OK) break;
-      if (he == hipSuccess) he = hipEventRecord(e1, s);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (he != hipSuccess) {
-        status = device_status(he);
-        break;
+  // two passes over every (form, shape); a shape's time is the smaller of its
+  // two, so clock ramp-up or drift during the first pass does not decide
+  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
+    for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
+      double* dt_next = form ? cfl_buf : nullptr;
+      double* dt_reset = form ? cfl_buf + 1 : nullptr;
+      double* dt_patch = form ? cfl_buf + 3 : nullptr;
+      for (int v = 0; v < gh::kLevelVariants && status == HYDRO_OK; ++v) {
+        g_level_variant[dtype][form].store(v);
+        auto launch = [&]() {
+          return hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
+                                     HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, dt_next, dt_patch,
+                                     dt_reset, stream);
+        };
+        // one untimed launch, then `reps` timed ones
+        status = launch();
+        if (status != HYDRO_OK) break;
+        hipError_t he = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch();
+        if (status != HYDRO_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+          status = device_status(he);
+          break;
+        }
+        ms /= float(reps);
+        if (pass == 0 || ms < ms_min[form][v]) ms_min[form][v] = ms;
       }
-      ms /= float(reps);
-      if (times_ms_host != nullptr) times_ms_host[form * gh::kLevelVariants + v] = ms;
-      if (best[form] < 0 || ms < best_ms[form]) {
+    }
+  }
+  for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
+    for (int v = 0; v < gh::kLevelVariants; ++v) {
+      if (times_ms_host != nullptr) times_ms_host[form * gh::kLevelVariants + v] = ms_min[form][v];
+      if (best[form] < 0 || ms_min[form][v] < best_ms[form]) {
         best[form] = v;
-        best_ms[form] = ms;
+        best_ms[form] = ms_min[form][v];
       }
     }
   }
@@ -379,29 +397,36 @@ int hydro_autotune_batched(const hydro_level_t* levels_host, int32_t n_levels, i
   }
   int best = -1, status = HYDRO_OK;
   float best_ms = 0.0f;
-  for (int var = 0; var < gh::kBatchedVariants && status == HYDRO_OK; ++var) {
-    g_batched_variant[dtype].store(var);
-    status = hydro_advance_batched(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr,
-                                   work_dev, 0, stream);
-    if (status != HYDRO_OK) break;
-    hipError_t he = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r)
+  float ms_min[gh::kBatchedVariants] = {};
+  // two passes, a shape's time is the smaller of its two (as hydro_autotune)
+  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
+    for (int var = 0; var < gh::kBatchedVariants && status == HYDRO_OK; ++var) {
+      g_batched_variant[dtype].store(var);
       status = hydro_advance_batched(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr,
                                      work_dev, 0, stream);
-    if (status != HYDRO_OK) break;
-    if (he == hipSuccess) he = hipEventRecord(e1, s);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-    if (he != hipSuccess) {
-      status = device_status(he);
-      break;
+      if (status != HYDRO_OK) break;
+      hipError_t he = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r)
+        status = hydro_advance_batched(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr,
+                                       work_dev, 0, stream);
+      if (status != HYDRO_OK) break;
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        status = device_status(he);
+        break;
+      }
+      ms /= float(reps);
+      if (pass == 0 || ms < ms_min[var]) ms_min[var] = ms;
     }
-    ms /= float(reps);
-    if (times_ms_host != nullptr) times_ms_host[var] = ms;
-    if (best < 0 || ms < best_ms) {
+  }
+  for (int var = 0; var < gh::kBatchedVariants && status == HYDRO_OK; ++var) {
+    if (times_ms_host != nullptr) times_ms_host[var] = ms_min[var];
+    if (best < 0 || ms_min[var] < best_ms) {
       best = var;
-      best_ms = ms;
+      best_ms = ms_min[var];
     }
   }
   (void)hipEventDestroy(e0);
@@ -486,7 +511,7 @@ int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_d
                                 int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx,
                                 double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
                                 int64_t work_bytes, void* stream) {
-  if (ngx < 1 || ngy < 1 || ngz < 1 || bc_host == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+  if (!level_geom_ok(ngx, ngy, ngz) || bc_host == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
     return HYDRO_EINVAL;
   if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta)) return HYDRO_EINVAL;
   if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
@@ -557,7 +582,7 @@ int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dty
 
 int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32_t ngy, int32_t ngz, int32_t ghost,
                       int32_t dtype, const int32_t* bc_host, void* stream) {
-  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (!level_geom_ok(ngx, ngy, ngz) || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
   int bc[6];
   for (int i = 0; i < 6; ++i) {
@@ -581,7 +606,7 @@ int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32
 
 int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                                int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream) {
-  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (!level_geom_ok(ngx, ngy, ngz) || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
   gh::LevelGeom geo;
   geo.ngx = ngx;

@@ -29,7 +29,7 @@ template <typename T> struct Fp;
 // FP64: hardware reciprocal / reciprocal square root refined by Newton steps
 // (error about 1 ulp, far inside the 1e-12 parity bound) instead of the
 // correctly rounded IEEE sequences, which cost two to three times as many
-// instructions.  sqrt(0) is returned as 0 (the refinement would give NaN).
+// instructions.
 template <> struct Fp<double> {
   // the hardware reciprocal is good to about 2^-24; one Newton step gives
   // about 2^-48 relative (div corrects its quotient once more)
@@ -43,15 +43,19 @@ template <> struct Fp<double> {
     const double q = a * r;
     return __builtin_fma(__builtin_fma(-b, q, a), r, q);
   }
+  // Goldschmidt iteration from the hardware reciprocal square root.  The
+  // estimate is taken at x + 2^-1074, which equals x for every x >= 2^-1020
+  // and keeps it finite at x = 0, where every step then yields 0 (x itself
+  // enters the iteration, so sqrt(+-0) = +-0; negative or NaN x give NaN).
+  // Subnormal x (never a density or pressure here) get a coarser estimate.
   static __device__ __forceinline__ double sqrt(double x) {
-    const double y = __builtin_amdgcn_rsq(x);
+    const double y = __builtin_amdgcn_rsq(x + 0x1p-1074);
     double g = x * y, h = 0.5 * y;
     const double r = __builtin_fma(-g, h, 0.5);
     g = __builtin_fma(g, r, g);
     h = __builtin_fma(h, r, h);
     const double d = __builtin_fma(-g, g, x);
-    g = __builtin_fma(d, h, g);
-    return x == 0.0 ? 0.0 : g;
+    return __builtin_fma(d, h, g);
   }
 };
 

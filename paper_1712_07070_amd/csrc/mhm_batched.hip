@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     unsigned int* __restrict__ work, int order, int queues) {
   __shared__ Smem<T> sm;
   __shared__ long long item_slot;
-  __shared__ int tried;  // queues found empty / static items taken (thread 0 only)
+  __shared__ int tried;  // queues found empty / static items taken (ticket thread only)
   const int home = int(blockIdx.x % unsigned(kQueues));
   auto queue_size = [&](int c) -> long long {
     return c < args.total ? (args.total - c + kQueues - 1) / kQueues : 0;
@@ -86,7 +86,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     lv_dtdx[threadIdx.x] = gl.dtdx;
     lv_half_dtdx[threadIdx.x] = gl.half_dtdx;
   }
-  if (threadIdx.x == 0) {
+  // tickets are taken and resolved by the first lane of the last wave: the
+  // atomic's return then holds up a wave without halo roles (the halo wave
+  // sets the pace of every plane)
+  const bool taker = threadIdx.x == kThreads - 64;
+  if (taker) {
     tried = 0;
     item_slot = resolve(take());
   }
@@ -99,25 +103,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
                            (unsigned int)__builtin_amdgcn_readfirstlane((int)(it & 0xffffffff));
     if (item < 0) break;
     unsigned int ticket = 0;
-    if (threadIdx.x == 0) ticket = take();
+    if (taker) ticket = take();
     int l = 0;
     while (l + 1 < args.n_levels && item >= args.lv[l + 1].g_begin) ++l;
     const BatchLevel<T>& L = args.lv[l];
-    const int64_t g = item - L.g_begin;
+    const int g = int(item - L.g_begin);  // < 2^31 groups per level
     Gas<T> gl = gas;
     gl.dtdx = uniform(lv_dtdx[l]);
     gl.half_dtdx = uniform(lv_half_dtdx[l]);
     const LevelGeom& geo = L.geo;
-    LevelSource<T> src{L.in, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
+    const unsigned int gu = unsigned(g), nx = unsigned(geo.ngx), ny = unsigned(geo.ngy);
+    LevelSource<T> src{L.in, geo, int(gu % nx), int((gu / nx) % ny), int(gu / nx / ny)};
     // an opaque thread index per item keeps thread-derived addresses from
     // being hoisted out of the item loop (they would stay live across the
     // whole group step and cost registers / occupancy)
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int bad = process_group<T>(src, L.out + g * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
+    const int bad = process_group<T>(src, L.out + int64_t(g) * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
     if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
     // every thread has read item_slot (first barrier of the group step)
-    if (threadIdx.x == 0) item_slot = resolve(ticket);
+    if (taker) item_slot = resolve(ticket);
     __syncthreads();
   }
   // the last workgroup to leave re-arms the queues for the next launch

@@ -272,11 +272,12 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
                                            int ws, Smem<T>& sm, double* smax, double gamma_d, int tid) {
   // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
   // 0..3 also one of the 4 edge columns
-  const int side = (tid >> 4) & 3, kk = tid & 15;
+  const int lane = tid & 63;
+  const int side = lane >> 4, kk = lane & 15;
   const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
   const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
-  const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
-  const bool has_edge = kHalo && tid < 4;
+  const int ex = (lane & 1) ? 16 : -1, ey = (lane & 2) ? 16 : -1;
+  const bool has_edge = kHalo && lane < 4;
 
   FwdCol<T, true> ci;
   FwdCol<T, false> ch;
@@ -339,12 +340,18 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 // workgroup (a loop over groups passes it opaque, so that the compiler keeps
 // thread-derived addresses out of the loop's live set).  Wave 0 runs the
 // march with the halo roles, waves 1-3 without them (a wave-uniform branch).
+// The second-order scheme (first_order == 0) gets its own inlined copy with
+// the limiter unconditional; the first-order one keeps the runtime flag.
 template <typename T, class Src>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
                                              int first_order, int ws, Smem<T>& sm, double* smax,
                                              double gamma_d, int tid = threadIdx.x) {
-  if (__builtin_amdgcn_readfirstlane(tid >> 6) == 0)
-    return march_group<T, Src, true>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+  const bool halo = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
+  if (first_order == 0) {
+    if (halo) return march_group<T, Src, true>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
+    return march_group<T, Src, false>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
+  }
+  if (halo) return march_group<T, Src, true>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
   return march_group<T, Src, false>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
 }
 

@@ -407,6 +407,7 @@ class MultiLevel:
         self.bufs = [[torch.empty((ng[0] * ng[1] * ng[2], 5, 16, 16, 16), dtype=dtype, device=dev) for _ in range(2)]
                      for ng, _, _ in self.geo]
         self.cur = [0] * self.L
+        self.dtype = dtype
         self.work = torch.zeros(BATCH_WORK_WORDS, dtype=torch.int32, device=dev)
         self.n_bad = torch.zeros(1, dtype=torch.int32, device=dev)
 
@@ -443,6 +444,23 @@ class MultiLevel:
     def coarse_step(self) -> None:
         for s in range(2 ** (self.L - 1)):
             self.stage(s)
+
+    def autotune(self, reps: int = 3) -> Tuple[int, list]:
+        """Choose the batched launch shape by the time of a whole coarse step:
+        hydro_autotune_batched times every shape on each distinct stage (its
+        outputs go to the scratch halves, the state is kept) and the stage
+        times are summed with the number of times the stage occurs."""
+        counts = {}
+        for s in range(2 ** (self.L - 1)):
+            key = tuple(self.stage_levels(s))
+            counts[key] = counts.get(key, 0) + 1
+        total = [0.0] * BATCHED_VARIANTS
+        for lvls, c in counts.items():
+            _, times = autotune_batched(self._entries(lvls), self.gamma, self.work, reps)
+            total = [a + c * t for a, t in zip(total, times)]
+        best = min(range(len(total)), key=total.__getitem__)
+        set_batched_variant(self.dtype, best)
+        return best, total
 
     def capture(self, n_coarse: int = 2) -> Graph:
         """Graph of n_coarse coarse steps (an even count returns every level's

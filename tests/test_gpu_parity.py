@@ -482,6 +482,36 @@ def test_wcycle_graph_replays_match_eager(hydro):
             assert all(torch.equal(x, y) for x, y in zip(a, b)), name
 
 
+def test_multilevel_autotune_keeps_state(hydro):
+    """Tuning on whole coarse steps leaves the levels untouched, selects the
+    shape with the smallest weighted stage time, and the tuned W-cycle equals
+    the per-level one bit for bit."""
+    say("multilevel autotune")
+    lvs = _amr_levels()
+    geo = [(lv.ng, lv.dx, lv.bc) for lv in lvs]
+    dt0 = 0.3 * min(float(oracle.dt_patch(lv.U, lv.dx, lv.gamma).min()) * 2 ** l for l, lv in enumerate(lvs))
+    mls = []
+    for batched in (True, False):
+        ml = hydro.MultiLevel(geo, 5 / 3, dt0, batched=batched)
+        for l, lv in enumerate(lvs):
+            ml.load_state(l, dev(lv.U))
+        mls.append(ml)
+    saved = hydro.get_batched_variant(torch.float64)
+    try:
+        best, total = mls[0].autotune(reps=1)
+        assert len(total) == hydro.BATCHED_VARIANTS and all(t > 0 for t in total)
+        assert best == min(range(len(total)), key=total.__getitem__)
+        assert hydro.get_batched_variant(torch.float64) == best
+        for l, lv in enumerate(lvs):
+            assert np.array_equal(host(mls[0].state(l)), lv.U)
+        for ml in mls:
+            ml.coarse_step()
+        for l in range(len(lvs)):
+            assert torch.equal(mls[0].state(l), mls[1].state(l))
+    finally:
+        hydro.set_batched_variant(torch.float64, saved)
+
+
 def test_sedov_levels_mirror_symmetric(hydro):
     say("sedov symmetry")
     lvs = _amr_levels()
