@@ -263,6 +263,16 @@ def step_ratio(hydro, torch, lv, dtype, dt, reps=10):
     return {"fwd_step_ms": fwd, "adjoint_step_ms": adj, "adjoint_over_fwd": adj / fwd}
 
 
+def tune_adjoint(hydro, torch, lv, dtype):
+    """Choose the adjoint form (fused / two kernels) on this workload's state."""
+    U = torch.from_numpy(np.ascontiguousarray(lv.U.astype(dtype))).cuda()
+    g = torch.ones_like(U)
+    form, times = hydro.autotune_adjoint(U, g, lv.ng, lv.bc, lv.dx, lv.gamma, reps=3)
+    del U, g
+    torch.cuda.empty_cache()
+    return {"form": form, "ms": [round(t, 4) for t in times]}
+
+
 def time_events(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -283,7 +293,9 @@ def differentiation_workloads(hydro, torch, W, fd_samples):
     # checkpointed (k = 1, no replay: 8 x 84 MB), and k = 4 with segment replay
     lv, target = W.smooth_wave(128)
     dt = 0.2 * lv.dx
+    form = tune_adjoint(hydro, torch, lv, np.float64)
     r, grad = adjoint_rollout(hydro, torch, lv, np.float64, 8, 1, dt, target)
+    r["adjoint_form"] = form
     r4, _ = adjoint_rollout(hydro, torch, lv, np.float64, 8, 4, dt, target)
     r["workload"] = "smooth wave 128^3 (512 groups), FP64, 8 steps at dt = 0.2 dx, every state checkpointed, " \
                     "loss sum (rho_8 - rho_target)^2"
@@ -306,7 +318,9 @@ def differentiation_workloads(hydro, torch, W, fd_samples):
     U = torch.from_numpy(lv.U).cuda()
     dt = float(hydro.cfl_dt(U, lv.dx, lv.gamma, 0.5).min())
     del U
+    form = tune_adjoint(hydro, torch, lv, np.float32)
     r, grad = adjoint_rollout(hydro, torch, lv, np.float32, 4, 1, dt, None, reps=2)
+    r["adjoint_form"] = form
     r["workload"] = "turbulence 384^3 (13824 groups), FP32 state, 4 steps at the initial CFL time-step " \
                     "(FP64 reduction), every state checkpointed, cotangent of ones"
     r["dt"] = dt

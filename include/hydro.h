@@ -175,6 +175,19 @@ int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_d
 int hydro_set_adjoint_variant(int32_t dtype, int32_t variant);
 int hydro_get_adjoint_variant(int32_t dtype);
 
+/* hydro_autotune_adjoint -- time both adjoint forms of
+ * hydro_advance_level_adjoint on the caller's level (same arguments as that
+ * call, dt fixed internally; two passes of 1 untimed + `reps` timed launches
+ * per form, 1 <= reps <= 1000, a form's time is the smaller of its two means),
+ * select the faster for `dtype` and return it (0 fused, 1 two kernels), or a
+ * negative status (the previous selection is then kept).  SYNCHRONOUS;
+ * g_level_in_dev and the workspace are overwritten; times_ms_host, if not
+ * NULL, receives the 2 times in milliseconds.  Results do not depend on the
+ * form (within rounding of the 1e-12 parity bound; both are deterministic). */
+int hydro_autotune_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
+                           int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx, double gamma,
+                           void* work_dev, int64_t work_bytes, int32_t reps, float* times_ms_host, void* stream);
+
 /* One level of a batched launch (hydro_advance_batched).  Pointers are
  * device memory; bc holds the x-, x+, y-, y+, z-, z+ boundary conditions;
  * dt is this level's time-step (dt_l = dt_0 / 2^l in the W-cycle of Sec. 2.1)

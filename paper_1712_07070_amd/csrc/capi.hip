@@ -552,6 +552,64 @@ int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_d
   return device_status(e);
 }
 
+int hydro_autotune_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
+                           int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx, double gamma,
+                           void* work_dev, int64_t work_bytes, int32_t reps, float* times_ms_host, void* stream) {
+  if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int saved = g_adjoint_variant[dtype].load();
+  const double dt = 1e-3 * dx;  // any positive step does the same work
+  auto launch = [&]() {
+    return hydro_advance_level_adjoint(level_dev, g_level_out_dev, g_level_in_dev, ngx, ngy, ngz, bc_host, dtype, dt,
+                                       dx, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, work_dev, work_bytes,
+                                       stream);
+  };
+  // argument errors surface here, before any event is created
+  int status = launch();
+  if (status != HYDRO_OK) return status;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return device_status(hipGetLastError());
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return device_status(hipGetLastError());
+  }
+  float ms_min[2] = {0.0f, 0.0f};
+  // two passes over both forms, each form's time the smaller of its two
+  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
+    for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
+      g_adjoint_variant[dtype].store(form);
+      status = launch();
+      if (status != HYDRO_OK) break;
+      hipError_t he = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch();
+      if (status != HYDRO_OK) break;
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        status = device_status(he);
+        break;
+      }
+      ms /= float(reps);
+      if (pass == 0 || ms < ms_min[form]) ms_min[form] = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != HYDRO_OK) {
+    g_adjoint_variant[dtype].store(saved);
+    return status;
+  }
+  if (times_ms_host != nullptr) {
+    times_ms_host[0] = ms_min[0];
+    times_ms_host[1] = ms_min[1];
+  }
+  const int best = ms_min[1] < ms_min[0] ? 1 : 0;
+  g_adjoint_variant[dtype].store(best);
+  return best;
+}
+
 int hydro_set_adjoint_variant(int32_t dtype, int32_t variant) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
   if (variant != 0 && variant != 1) return HYDRO_EINVAL;

@@ -862,7 +862,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(Adj
   const int64_t P3 = int64_t(P) * P * P;
   PaddedSource<T> src{Upad + g * 5 * P3, P, gh};
   PadSink<T> sink{gpad + g * 5 * P3, P, gh};
-  adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
+  // the second-order scheme gets its own inlined copy (limiter unconditional)
+  if (first_order == 0)
+    adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, 0, ws, sm, sink);
+  else
+    adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
 }
 
 template <typename T>
@@ -875,7 +879,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(Adj
   const int64_t g = blockIdx.x;
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
-  adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
+  // the second-order scheme gets its own inlined copy (limiter unconditional)
+  if (first_order == 0)
+    adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, 0, ws, sm, sink);
+  else
+    adjoint_fused<T>(src, gout_ + g * 5 * 4096, gas, first_order, ws, sm, sink);
 }
 
 template <typename T>
@@ -886,7 +894,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 
   const int P = 16 + 2 * gh;
   const int64_t g = blockIdx.x;
   PaddedSource<T> src{Upad + g * 5 * int64_t(P) * P * P, P, gh};
-  adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, wsp, sm);
+  // the second-order scheme gets its own inlined copy (limiter unconditional)
+  if (first_order == 0)
+    adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, 0, wsp, sm);
+  else
+    adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, wsp, sm);
 }
 
 template <typename T>
@@ -899,7 +911,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 
   const int64_t P3 = int64_t(P) * P * P;
   PaddedSource<T> src{Upad + g * 5 * P3, P, gh};
   PadSink<T> sink{gpad + g * 5 * P3, P, gh};
-  adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, sm, sink);
+  // the second-order scheme gets its own inlined copy (limiter unconditional)
+  if (first_order == 0)
+    adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, 0, sm, sink);
+  else
+    adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, sm, sink);
 }
 
 template <typename T>
@@ -910,7 +926,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 
   set_dt_adj(gas, dt_dev, dx);
   const int64_t g = blockIdx.x;
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
-  adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, wsp, sm);
+  // the second-order scheme gets its own inlined copy (limiter unconditional)
+  if (first_order == 0)
+    adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, 0, wsp, sm);
+  else
+    adjoint_faces_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, wsp, sm);
 }
 
 template <typename T>
@@ -922,7 +942,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 
   const int64_t g = blockIdx.x;
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
-  adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, sm, sink);
+  // the second-order scheme gets its own inlined copy (limiter unconditional)
+  if (first_order == 0)
+    adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, 0, sm, sink);
+  else
+    adjoint_cells_pass<T>(src, gout_ + g * 5 * 4096, ws + g * kFaceWs, gas, first_order, sm, sink);
 }
 
 // ------------------------------------------------------------ kernel C ----

@@ -78,6 +78,7 @@ def load():
         "hydro_set_batched_variant": (i32, [i32, i32]),
         "hydro_get_batched_variant": (i32, [i32]),
         "hydro_autotune_batched": (i32, [P, i32, i32, f64, P, i32, P, P]),
+        "hydro_autotune_adjoint": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, P, i64, i32, P, P]),
         "hydro_graph_begin": (i32, [P]),
         "hydro_graph_end": (i32, [P, ctypes.POINTER(ctypes.c_void_p)]),
         "hydro_graph_launch": (i32, [P, P]),
@@ -230,6 +231,29 @@ def advance_level_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence
                                             _dev(work, "work"), work.numel(), _stream())
     _check(st, "hydro_advance_level_adjoint")
     return out
+
+
+def autotune_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dx: float,
+                     gamma: float, reps: int = 3, work: Optional[torch.Tensor] = None,
+                     out: Optional[torch.Tensor] = None) -> Tuple[int, list]:
+    """Time both adjoint forms on this level and keep the faster for its dtype
+    (hydro_autotune_adjoint); returns (form, [ms fused, ms two kernels])."""
+    ngx, ngy, ngz = (int(v) for v in ng)
+    G = ngx * ngy * ngz
+    if tuple(level.shape) != (G, 5, 16, 16, 16) or g_out.shape != level.shape or g_out.dtype != level.dtype:
+        raise ValueError("level and g_out must be [G,5,16,16,16] of one dtype")
+    if out is None:
+        out = torch.empty_like(level)
+    if work is None:
+        work = adjoint_workspace(G, level.dtype, True, level.device)
+    b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
+    times = (ctypes.c_float * 2)()
+    st = load().hydro_autotune_adjoint(_dev(level, "level"), _dev(g_out, "g_out"), _dev(out, "out"), ngx, ngy, ngz, b,
+                                       _dtype_code(level), float(dx), float(gamma), _dev(work, "work"), work.numel(),
+                                       int(reps), times, _stream())
+    if st < 0:
+        raise HydroError("hydro_autotune_adjoint", st)
+    return int(st), list(times)
 
 
 def cfl_dt(U_pad: torch.Tensor, dx: float, gamma: float, c_cfl: float = 0.5, out: Optional[torch.Tensor] = None,

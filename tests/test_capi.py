@@ -91,3 +91,32 @@ def test_gather_ghost_adjoint_rejects_bad_arguments(lib):
     assert f(P(4096), P(1 << 40), 1, 1, 1, 3, 0, None, None) == -1
     assert f(None, P(1 << 40), 1, 1, 1, 3, 0, bc, None) == -1
     assert f(P(4096), P(4096 + 8), 1, 1, 1, 3, 0, bc, None) == -1   # output overlaps the input
+
+
+@pytest.mark.parametrize("ng", [(0, 1, 1), (1, -3, 1), ((1 << 26) + 1, 1, 1), (1 << 11, 1 << 10, 1 << 10)])
+def test_level_entry_points_reject_bad_geometry(lib, ng):
+    """Every level entry point takes 1 <= ng <= 2^26 per axis and fewer than
+    2^31 - 8 groups; larger lattices are refused before any HIP call."""
+    P = ctypes.c_void_p
+    bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    a, b = P(4096), P(1 << 46)
+    assert lib.hydro_advance_level(a, b, *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, None, 0.5, None, None, None,
+                                   None) == -1
+    assert lib.hydro_advance_level_adjoint(a, b, P(1 << 47), *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, P(1 << 45),
+                                           1 << 40, None) == -1
+    assert lib.hydro_fill_ghosts(a, b, *ng, 3, 0, bc, None) == -1
+    assert lib.hydro_gather_ghost_adjoint(a, b, *ng, 3, 0, bc, None) == -1
+    assert lib.hydro_autotune_adjoint(a, b, P(1 << 47), *ng, bc, 0, 0.01, 1.4, P(1 << 45), 1 << 40, 1, None,
+                                      None) == -1
+
+
+def test_autotune_adjoint_rejects_bad_arguments(lib):
+    P = ctypes.c_void_p
+    bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    f = lib.hydro_autotune_adjoint
+    a, b, c, w = P(4096), P(1 << 44), P(1 << 45), P(1 << 46)
+    assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 1 << 30, 0, None, None) == -1      # reps < 1
+    assert f(a, b, c, 1, 1, 1, bc, 2, 0.01, 1.4, w, 1 << 30, 1, None, None) == -1      # dtype
+    assert f(a, b, c, 1, 1, 1, bc, 0, -0.01, 1.4, w, 1 << 30, 1, None, None) == -1     # dx
+    assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 16, 1, None, None) == -1           # workspace too small
+    assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, None, 1 << 30, 1, None, None) == -1   # no workspace

@@ -68,3 +68,28 @@ def test_padded_adjoint_forms_agree(hydro):
     t32, tw32 = t.float(), tw.float()
     o32 = _forms(hydro, torch.float32, lambda: hydro.advance_adjoint(t32, tw32, 0.3 * dx, dx, G53).cpu().numpy())
     assert np.max(np.abs(o32[0] - o32[1])) <= 1e-5 * np.max(np.abs(o32[0]))
+
+
+def test_autotune_adjoint_selects_a_form(hydro):
+    print("adjoint autotune", file=sys.stderr, flush=True)
+    U, ng, dx = smooth_all_fields(32)
+    t = torch.from_numpy(U).cuda()
+    g = torch.ones_like(t)
+    saved = hydro.get_adjoint_variant(torch.float64)
+    try:
+        form, times = hydro.autotune_adjoint(t, g, ng, (0,) * 6, dx, G53, reps=1)
+        assert form in (0, 1) and len(times) == 2 and all(x > 0 for x in times)
+        assert form == (1 if times[1] < times[0] else 0)
+        assert hydro.get_adjoint_variant(torch.float64) == form
+        # the tuned form gives the cotangents of either form
+        a = hydro.advance_level_adjoint(t, g, ng, (0,) * 6, 0.3 * dx, dx, G53)
+        hydro.set_adjoint_variant(torch.float64, 1 - form)
+        b = hydro.advance_level_adjoint(t, g, ng, (0,) * 6, 0.3 * dx, dx, G53)
+        assert float((a - b).abs().max()) <= 1e-12 * float(a.abs().max())
+        # argument errors come back as status codes, the selection is kept
+        hydro.set_adjoint_variant(torch.float64, 0)
+        with pytest.raises(hydro.HydroError):
+            hydro.autotune_adjoint(t, g, ng, (0,) * 6, -dx, G53)
+        assert hydro.get_adjoint_variant(torch.float64) == 0
+    finally:
+        hydro.set_adjoint_variant(torch.float64, saved)
