@@ -43,6 +43,12 @@ template <> struct Fp<double> {
     const double q = a * r;
     return __builtin_fma(__builtin_fma(-b, q, a), r, q);
   }
+  // a / b as div, and the refined reciprocal of b it used
+  static __device__ __forceinline__ double div(double a, double b, double& rb) {
+    rb = rcp(b);
+    const double q = a * rb;
+    return __builtin_fma(__builtin_fma(-b, q, a), rb, q);
+  }
   // Goldschmidt iteration from the hardware reciprocal square root.  The
   // estimate is taken at x + 2^-1074, which equals x for every x >= 2^-1020
   // and keeps it finite at x = 0, where every step then yields 0 (x itself
@@ -64,6 +70,10 @@ template <> struct Fp<double> {
 template <> struct Fp<float> {
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ float div(float a, float b, float& rb) {
+    rb = __builtin_amdgcn_rcpf(b);
+    return a * rb;
+  }
   static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 };
 
@@ -230,12 +240,15 @@ __device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<
     const T mn = left ? L[n] : R[n], m1 = left ? L[t1] : R[t1], m2 = left ? L[t2] : R[t2];
     const T E = left ? L[4] : R[4];
     const T S = left ? SL : SR, a = left ? aL : aR;
-    const T rr = Fp<T>::div(a, S - Ss);
+    // r_K p_K / (S_K - u_K) = p_K / (S_K - S*): the energy term takes the
+    // reciprocal of S_K - S* that r_K's division already formed
+    T t;
+    const T rr = Fp<T>::div(a, S - Ss, t);
     const T Us0 = rr * r;
     const T Us1 = rr * (r * Ss);
     const T Us2 = rr * m1;
     const T Us3 = rr * m2;
-    const T Us4 = rr * (E + (Ss - u) * (r * Ss + Fp<T>::div(p, a)));
+    const T Us4 = rr * E + (Ss - u) * (Us1 + p * t);
     Fn[0] = mn + S * (Us0 - r);
     Fn[1] = (mn * u + p) + S * (Us1 - mn);
     Fn[2] = m1 * u + S * (Us2 - m1);

@@ -75,6 +75,7 @@ struct Smem {
   T P[5][kPW * kPW];     // primitive plane k
   T S[2][5][kSW * kSW];  // x+ and y+ half-step states of plane k
   T F[2][5][17 * 16];    // x and y fluxes of plane k
+  T H[5][32];            // high-side states of the last faces: x = 16 (slot y), y = 16 (slot 16 + x)
 };
 
 // ---------------------------------------------------- one patch group ----
@@ -84,18 +85,20 @@ struct Smem {
 // interior (x = -1, x = 16, y = -1, y = 16), whose half-step states feed the
 // faces on the group boundary, together with the column two cells out and,
 // for 4 of them, an edge column (both only read as neighbours).  Wave 0 runs
-// its halo role after its interior role in every phase.
+// its halo role after its interior role in every phase; wave 2 solves the 32
+// faces on the high x and y boundary of the group (their high-side states
+// come from the halo role through LDS) after its own faces.
 
 // Per-column state of one role across the z-march.
 template <typename T, bool kInterior>
 struct FwdCol {
   static constexpr int zhi = kInterior ? 17 : 16;  // last plane of the column that is read
   int cx, cy;
-  bool xface16, yface16;  // halo columns at x = 16 / y = 16 solve the last x / y face
+  bool xface16, yface16;  // halo columns at x = 16 / y = 16 (high side of the last x / y face)
   int64_t col;
   T Wm[5], Wc[5], Wp[5];  // primitive states at planes k-1, k, k+1
   T Un[5];                // conserved values of the next plane to convert (in flight)
-  T Ux[5], Uy[5];         // own x- and y- face states of plane k (halo: Ux holds the one it uses)
+  T Ux[5], Uy[5];         // own x- and y- face states of plane k (interior)
   T Uz[5], Fz0[5];        // interior: z+ face state of plane k-1; z flux at the low face of plane k-1
 };
 
@@ -164,9 +167,14 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI>& c, const Src& src, 
     if (kI) {
       c.Ux[q] = Ut[0][0][q];
       c.Uy[q] = Ut[1][0][q];
-    } else {
-      c.Ux[q] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
     }
+  }
+  // halo columns at x = 16 / y = 16: their low x / y state is the high side
+  // of the last face, solved by another wave after the next barrier
+  if (!kI && (c.xface16 || c.yface16)) {
+    const int slot = c.xface16 ? cy : 16 + cx;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.H[q][slot] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
   }
   if (kI) {
     if (k >= 0) {
@@ -200,59 +208,67 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI>& c, const Src& src, 
   return bad;
 }
 
-// x and y faces of plane k that the column solves: interior columns their
-// low x and low y face; halo columns at x = 16 / y = 16 the last face.  The
-// halo lanes solve their x and y faces in one pass: a y face is solved in the
-// x-normal frame with its states rotated (m_y, m_z, m_x) -> (m_x, m_y, m_z),
-// the same arithmetic on the same values as the y-normal solver, and the flux
-// rotated back.
+// x and y faces of plane k that an interior column solves: its low x and low
+// y face.
 template <typename T, bool kI>
 __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI>& c, int k, const Gas<T>& gas, int ws, Smem<T>& sm) {
-  if (k < 0 || k > 15) return 0;
+  if (!kI || k < 0 || k > 15) return 0;
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
-  if (kI) {
-    {
-      T L[5], F[5];
+  {
+    T L[5], F[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
-      bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
+    for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+    bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
-    }
-    {
-      T L[5], F[5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
-      bad += hllc_flux<1>(L, c.Uy, gas, ws, F);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
-    }
-  } else if (c.xface16 || c.yface16) {
-    const bool yf = c.yface16;
-    const T* Sb = yf ? &sm.S[1][0][sidx(cx, cy - 1)] : &sm.S[0][0][sidx(cx - 1, cy)];
-    T L[5], Lr[5], Rr[5], F[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = Sb[q * kSW * kSW];
-    // rotation of a y-face problem into the x-normal frame (identity for x faces)
-    Lr[0] = L[0];
-    Lr[1] = yf ? L[2] : L[1];
-    Lr[2] = yf ? L[3] : L[2];
-    Lr[3] = yf ? L[1] : L[3];
-    Lr[4] = L[4];
-    Rr[0] = c.Ux[0];
-    Rr[1] = yf ? c.Ux[2] : c.Ux[1];
-    Rr[2] = yf ? c.Ux[3] : c.Ux[2];
-    Rr[3] = yf ? c.Ux[1] : c.Ux[3];
-    Rr[4] = c.Ux[4];
-    bad += hllc_flux<0>(Lr, Rr, gas, ws, F);
-    T* Fb = yf ? &sm.F[1][0][fyidx(cx, cy)] : &sm.F[0][0][fxidx(cx, cy)];
-    Fb[0] = F[0];
-    Fb[1 * 17 * 16] = yf ? F[3] : F[1];
-    Fb[2 * 17 * 16] = yf ? F[1] : F[2];
-    Fb[3 * 17 * 16] = yf ? F[2] : F[3];
-    Fb[4 * 17 * 16] = F[4];
+    for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
   }
+  {
+    T L[5], F[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+    bad += hllc_flux<1>(L, c.Uy, gas, ws, F);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
+  }
+  return bad;
+}
+
+// The 32 last faces of plane k (x = 16 for lanes 0..15 at y = lane, y = 16
+// for lanes 16..31 at x = lane - 16), in one solver pass: a y face is solved
+// in the x-normal frame with its states rotated (m_y, m_z, m_x) -> (m_x,
+// m_y, m_z), the same arithmetic on the same values as the y-normal solver,
+// and the flux rotated back.  The halo wave wrote the high-side states to
+// H; this pass runs on another wave, which has no halo work.
+template <typename T>
+__device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, int ws, Smem<T>& sm) {
+  if (k < 0 || k > 15 || lane >= 32) return 0;
+  const bool yf = lane >= 16;
+  const int i = lane & 15;
+  const T* Sb = yf ? &sm.S[1][0][sidx(i, 15)] : &sm.S[0][0][sidx(15, i)];
+  T L[5], R[5], Lr[5], Rr[5], F[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    L[q] = Sb[q * kSW * kSW];
+    R[q] = sm.H[q][lane];
+  }
+  Lr[0] = L[0];
+  Lr[1] = yf ? L[2] : L[1];
+  Lr[2] = yf ? L[3] : L[2];
+  Lr[3] = yf ? L[1] : L[3];
+  Lr[4] = L[4];
+  Rr[0] = R[0];
+  Rr[1] = yf ? R[2] : R[1];
+  Rr[2] = yf ? R[3] : R[2];
+  Rr[3] = yf ? R[1] : R[3];
+  Rr[4] = R[4];
+  const int bad = hllc_flux<0>(Lr, Rr, gas, ws, F);
+  T* Fb = yf ? &sm.F[1][0][fyidx(i, 16)] : &sm.F[0][0][fxidx(16, i)];
+  Fb[0] = F[0];
+  Fb[1 * 17 * 16] = yf ? F[3] : F[1];
+  Fb[2 * 17 * 16] = yf ? F[1] : F[2];
+  Fb[3 * 17 * 16] = yf ? F[2] : F[3];
+  Fb[4 * 17 * 16] = F[4];
   return bad;
 }
 
@@ -265,9 +281,13 @@ __device__ __forceinline__ void fwd_col_shift(FwdCol<T, kI>& c) {
   }
 }
 
-// The z-march of one wave: interior role, plus the halo roles when kHalo
-// (wave 0).  Both instantiations pass the same barriers in the same order.
-template <typename T, class Src, bool kHalo>
+// Roles of the waves of a workgroup beyond their interior columns.
+enum WaveRole { kRoleHalo = 0, kRoleLastFaces = 1, kRolePlain = 2 };
+
+// The z-march of one wave: interior role, plus the halo roles (kRoleHalo,
+// wave 0) or the solve of the 32 last faces (kRoleLastFaces, wave 2).  Every
+// instantiation passes the same barriers in the same order.
+template <typename T, class Src, int kRole>
 __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, const Gas<T>& gas, int first_order,
                                            int ws, Smem<T>& sm, double* smax, double gamma_d, int tid) {
   // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
@@ -277,6 +297,7 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
   const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
   const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
   const int ex = (lane & 1) ? 16 : -1, ey = (lane & 2) ? 16 : -1;
+  constexpr bool kHalo = kRole == kRoleHalo;
   const bool has_edge = kHalo && lane < 4;
 
   FwdCol<T, true> ci;
@@ -325,7 +346,7 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 
     // ---- x and y faces of plane k
     bad += fwd_col_faces(ci, k, gas, ws, sm);
-    if (kHalo) bad += fwd_col_faces(ch, k, gas, ws, sm);
+    if (kRole == kRoleLastFaces) bad += last_faces(lane, k, gas, ws, sm);
 
     fwd_col_shift(ci);
     if (kHalo) fwd_col_shift(ch);
@@ -339,20 +360,26 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 // cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's index in the
 // workgroup (a loop over groups passes it opaque, so that the compiler keeps
 // thread-derived addresses out of the loop's live set).  Wave 0 runs the
-// march with the halo roles, waves 1-3 without them (a wave-uniform branch).
-// The second-order scheme (first_order == 0) gets its own inlined copy with
-// the limiter unconditional; the first-order one keeps the runtime flag.
+// march with the halo roles, wave 2 with the last faces, waves 1 and 3 with
+// their interior columns only (wave-uniform branches).  Two co-resident
+// workgroups get their waves on SIMDs (0, 2, 1, 3) and (2, 1, 3, 0), so the
+// halo waves sit on SIMDs 0 and 2 and the last-face waves on SIMDs 1 and 3.
+// The second-order scheme (first_order == 0) gets its own inlined copies
+// with the limiter unconditional; the first-order one keeps the runtime flag.
 template <typename T, class Src>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
                                              int first_order, int ws, Smem<T>& sm, double* smax,
                                              double gamma_d, int tid = threadIdx.x) {
-  const bool halo = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (first_order == 0) {
-    if (halo) return march_group<T, Src, true>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
-    return march_group<T, Src, false>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
+    if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
+    if (wave == 2) return march_group<T, Src, kRoleLastFaces>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
+    return march_group<T, Src, kRolePlain>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
   }
-  if (halo) return march_group<T, Src, true>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
-  return march_group<T, Src, false>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+  if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+  if (wave == 2)
+    return march_group<T, Src, kRoleLastFaces>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+  return march_group<T, Src, kRolePlain>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
 }
 
 // Reduce the per-thread signal-speed maxima of one group to its 8 patch
