@@ -100,7 +100,9 @@ __device__ __forceinline__ void finalize_cell(const Src& src, int64_t col, int x
 // interior column; the 64 threads of wave 0 also own one halo column each (the
 // 4 x 16 columns just outside the faces, whose state cells feed the boundary
 // faces) with its 2-deep neighbour and, for 4 of them, an edge column, and run
-// that role after the interior one in every phase.  One wave per SIMD leaves
+// that role after the interior one in every phase; wave 2 takes the VJPs of
+// the 32 faces the halo columns at x = 16 and y = 16 share with the interior
+// (states and cotangents through LDS), which evens out the waves' work.  One wave per SIMD leaves
 // the whole register file (VGPRs and AGPRs) to each wave.
 constexpr int kAdjThreads = 256;
 // Waves per SIMD the register allocation targets: FP64 takes the whole
@@ -115,7 +117,13 @@ struct SmemF {
   T S[2][5][kSW * kSW];   // x+ and y+ half-step states of plane k
   T GL[2][5][kSW * kSW];  // cotangents of the x+ / y+ face states of plane k-1 cells
   T O[4][5][kSW * kSW];   // in-plane neighbour contributions of plane k-1 cells (x-, x+, y-, y+)
+  T H[5][32];             // high-side states of the last faces of plane k: x = 16 (slot y), y = 16 (slot 16 + x)
+  T GR[5][32];            // their cotangents (same slots), read by the halo columns one plane later
 };
+
+// Slot of a halo column at x = 16 or y = 16 in SmemF::H / GR (in range for
+// every halo column; only those two sides use it).
+__device__ __forceinline__ int last_slot(bool xface16, int cx, int cy) { return (xface16 ? cy : 16 + cx) & 31; }
 
 __device__ __forceinline__ int pslot(int k) { return (k + 3) % 3; }
 
@@ -130,8 +138,9 @@ __device__ __forceinline__ bool in_state_plane(int x, int y, int z) {
 // Per-column state of one role (interior or halo column) across the march.
 // The column's primitive states of planes k-2, k-1, k are read back from the
 // LDS planes (the column publishes its own values there); only W(k+1) lives
-// in registers.  A halo column solves at most one face (x = 16 or y = 16), so
-// its face state and face cotangent share the x slots.
+// in registers.  The face a halo column at x = 16 or y = 16 shares with the
+// interior is solved by another wave: its state and cotangent go through LDS
+// (SmemF::H, GR).
 template <typename T, bool kInterior>
 struct AdjCol {
   static constexpr bool interior = kInterior;
@@ -208,9 +217,12 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
       if (kI) {
         c.Ux[q] = Ut[0][0][q];
         c.Uy[q] = Ut[1][0][q];
-      } else {
-        c.Ux[q] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
       }
+    }
+    if (!kI && (c.xface16 || c.yface16)) {
+      const int slot = last_slot(c.xface16, cx, cy);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sm.H[q][slot] = c.xface16 ? Ut[0][0][q] : Ut[1][0][q];
     }
     if (kI) {
       if (k >= 0) {
@@ -229,6 +241,7 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
     const bool u0 = face_used(cx, cy, j, 0), u1 = face_used(cx, cy, j, 1), u2 = face_used(cx, cy, j, 2);
     const bool u3 = face_used(cx, cy, j, 3), u4 = face_used(cx, cy, j, 4), u5 = face_used(cx, cy, j, 5);
     T Wj[5], gWc[5];
+    const int slot = last_slot(c.xface16, cx, cy);
 #pragma unroll
     for (int q = 0; q < 5; ++q) Wj[q] = sm.P[sj][q][pidx(cx, cy)];
     hancock_states_vjp_stream(
@@ -249,9 +262,9 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
             T v;
-            if (f == 0) v = c.gRx[q];
+            if (f == 0) v = kI ? c.gRx[q] : sm.GR[q][slot];
             else if (f == 1) v = sm.GL[0][q][sidx(cx, cy)];
-            else if (f == 2) v = kI ? c.gRy[q] : c.gRx[q];
+            else if (f == 2) v = kI ? c.gRy[q] : sm.GR[q][slot];
             else if (f == 3) v = sm.GL[1][q][sidx(cx, cy)];
             else if (f == 4) v = c.gRz[q];
             else v = gLz[q];
@@ -280,11 +293,8 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
   }
 }
 
-// F3a: the x and y face VJPs this column solves at plane k (its x- face and
-// y- face; halo columns only the face at x = 16 or y = 16, in one pass: a
-// y face is solved in the x-normal frame with its states and cotangents
-// rotated (m_y, m_z, m_x) -> (m_x, m_y, m_z), the same arithmetic on the same
-// values as the y-normal solver, and the results rotated back).
+// F3a: the x and y face VJPs an interior column solves at plane k (its x-
+// face and y- face).
 template <typename T, bool kI>
 __device__ __forceinline__ void adj_col_faces(AdjCol<T, kI>& c, int k, const T* __restrict__ go, const Gas<T>& gas,
                                               int ws, SmemF<T>& sm) {
@@ -315,42 +325,60 @@ __device__ __forceinline__ void adj_col_faces(AdjCol<T, kI>& c, int k, const T* 
 #pragma unroll
       for (int q = 0; q < 5; ++q) sm.GL[1][q][sidx(cx, cy - 1)] = gL[q];
     }
-  } else if (c.xface16 || c.yface16) {
-    const bool yf = c.yface16;
-    const int lx = yf ? cx : cx - 1, ly = yf ? cy - 1 : cy;  // the cell on the low side of the face
-    const T* Sb = yf ? &sm.S[1][0][sidx(lx, ly)] : &sm.S[0][0][sidx(lx, ly)];
-    T L[5], gF[5];
+  }
+}
+
+// The 32 last faces of plane k (x = 16 for lanes 0..15 at y = lane, y = 16
+// for lanes 16..31 at x = lane - 16), solved by a wave without halo columns
+// in one pass: a y face is solved in the x-normal frame with its states and
+// cotangents rotated (m_y, m_z, m_x) -> (m_x, m_y, m_z), the same arithmetic
+// on the same values as the y-normal solver, and the results rotated back.
+// The high-side states come from the halo columns (H); the cotangent of the
+// low-side state goes to GL, that of the high-side state to GR.
+template <typename T>
+__device__ __forceinline__ void adj_last_faces(int lane, int k, const T* __restrict__ go, const Gas<T>& gas, int ws,
+                                               SmemF<T>& sm) {
+  if (k < 0 || k > 15 || lane >= 32) return;
+  const bool yf = lane >= 16;
+  const int i = lane & 15;
+  const int hx = yf ? i : 16, hy = yf ? 16 : i;    // the halo cell on the high side
+  const int lx = yf ? i : 15, ly = yf ? 15 : i;    // the interior cell on the low side
+  const T* Sb = yf ? &sm.S[1][0][sidx(lx, ly)] : &sm.S[0][0][sidx(lx, ly)];
+  T L[5], R[5], gF[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      L[q] = Sb[q * kSW * kSW];
-      gF[q] = gas.dtdx * (gout(go, q, cx, cy, k) - gout(go, q, lx, ly, k));
-    }
-    auto rot = [&](const T a[5], T r[5]) {  // axis frame -> x-normal frame of this face
-      r[0] = a[0];
-      r[1] = yf ? a[2] : a[1];
-      r[2] = yf ? a[3] : a[2];
-      r[3] = yf ? a[1] : a[3];
-      r[4] = a[4];
-    };
-    auto unrot = [&](const T r[5], T a[5]) {
-      a[0] = r[0];
-      a[1] = yf ? r[3] : r[1];
-      a[2] = yf ? r[1] : r[2];
-      a[3] = yf ? r[2] : r[3];
-      a[4] = r[4];
-    };
-    T Lr[5], Rr[5], gFr[5];
-    rot(L, Lr);
-    rot(c.Ux, Rr);
-    rot(gF, gFr);
-    T gLr[5] = {T(0), T(0), T(0), T(0), T(0)}, gRr[5] = {T(0), T(0), T(0), T(0), T(0)};
-    hllc_flux_vjp<0>(Lr, Rr, gas, ws, gFr, gLr, gRr);
-    T gL[5];
-    unrot(gLr, gL);
-    unrot(gRr, c.gRx);
-    T* Gb = yf ? &sm.GL[1][0][sidx(lx, ly)] : &sm.GL[0][0][sidx(lx, ly)];
+  for (int q = 0; q < 5; ++q) {
+    L[q] = Sb[q * kSW * kSW];
+    R[q] = sm.H[q][lane];
+    gF[q] = gas.dtdx * (gout(go, q, hx, hy, k) - gout(go, q, lx, ly, k));
+  }
+  auto rot = [&](const T a[5], T r[5]) {  // axis frame -> x-normal frame of this face
+    r[0] = a[0];
+    r[1] = yf ? a[2] : a[1];
+    r[2] = yf ? a[3] : a[2];
+    r[3] = yf ? a[1] : a[3];
+    r[4] = a[4];
+  };
+  auto unrot = [&](const T r[5], T a[5]) {
+    a[0] = r[0];
+    a[1] = yf ? r[3] : r[1];
+    a[2] = yf ? r[1] : r[2];
+    a[3] = yf ? r[2] : r[3];
+    a[4] = r[4];
+  };
+  T Lr[5], Rr[5], gFr[5];
+  rot(L, Lr);
+  rot(R, Rr);
+  rot(gF, gFr);
+  T gLr[5] = {T(0), T(0), T(0), T(0), T(0)}, gRr[5] = {T(0), T(0), T(0), T(0), T(0)};
+  hllc_flux_vjp<0>(Lr, Rr, gas, ws, gFr, gLr, gRr);
+  T gL[5], gR[5];
+  unrot(gLr, gL);
+  unrot(gRr, gR);
+  T* Gb = yf ? &sm.GL[1][0][sidx(lx, ly)] : &sm.GL[0][0][sidx(lx, ly)];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) Gb[q * kSW * kSW] = gL[q];
+  for (int q = 0; q < 5; ++q) {
+    Gb[q * kSW * kSW] = gL[q];
+    sm.GR[q][lane] = gR[q];
   }
 }
 
@@ -395,7 +423,8 @@ template <typename T, class Src, class Sink>
 __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restrict__ go, const Gas<T>& gas,
                                               int first_order, int ws, SmemF<T>& sm, const Sink& sink) {
   const int tid = threadIdx.x;
-  const bool halo = tid < 64;  // wave 0
+  const bool halo = tid < 64;                  // wave 0
+  const bool last = (tid >> 6) == 2;           // wave 2: the 32 last faces
   const bool fo = first_order != 0;
   // halo role of wave 0: side 0..3 = x-, x+, y-, y+; the column two cells out;
   // lanes 0..3 also one of the 4 edge columns
@@ -436,7 +465,7 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
     if (halo) adj_col_states(ch, k, go, gas, fo, ws, sm);
     __syncthreads();
     adj_col_faces(ci, k, go, gas, ws, sm);
-    if (halo) adj_col_faces(ch, k, go, gas, ws, sm);
+    if (last) adj_last_faces(tid & 63, k, go, gas, ws, sm);
     adj_col_finish(ci, src, k, go, gas, sm, sink);
     if (halo) {
       adj_col_finish(ch, src, k, go, gas, sm, sink);
