@@ -127,6 +127,30 @@ __device__ __forceinline__ int last_slot(bool xface16, int cx, int cy) { return 
 
 __device__ __forceinline__ int pslot(int k) { return (k + 3) % 3; }
 
+// finalize_cell with the cell's primitive state taken from its LDS plane
+// (published by the march; the same values cons_to_prim gives, so the same
+// Jacobian as from the conserved state) instead of a load from memory.
+template <typename T, class Sink>
+__device__ __forceinline__ void finalize_cell_lds(const SmemF<T>& sm, int x, int y, int z, const T gW[5],
+                                                  const T* __restrict__ go, const Gas<T>& gas, const Sink& sink) {
+  const int s = pslot(z), i = pidx(x, y);
+  const T W0 = sm.P[s][0][i];
+  const T inv = Fp<T>::rcp(W0);
+  const T u = sm.P[s][1][i], v = sm.P[s][2][i], w = sm.P[s][3][i];
+  const T gp = gW[4] * gas.gm1;
+  T gU[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) gU[q] = gout(go, q, x, y, z);  // identity term of the update (interior cells)
+  // the arithmetic of cons_to_prim_vjp with u = m_x / rho, ... read back
+  gU[0] = gU[0] + gW[0] - (gW[1] * u + gW[2] * v + gW[3] * w) * inv + T(0.5) * gp * (u * u + v * v + w * w);
+  gU[1] = gU[1] + gW[1] * inv - gp * u;
+  gU[2] = gU[2] + gW[2] * inv - gp * v;
+  gU[3] = gU[3] + gW[3] * inv - gp * w;
+  gU[4] = gU[4] + gp;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sink.put(q, x, y, z, gU[q]);
+}
+
 // Is (x, y, z) a state cell (one whose half-step states the step computes)?
 __device__ __forceinline__ bool in_state_plane(int x, int y, int z) {
   const bool in_x = x >= 0 && x <= 15, in_y = y >= 0 && y <= 15;
@@ -149,6 +173,7 @@ struct AdjCol {
   bool xface16, yface16;
   int64_t col;
   T Wp[5];                    // W(k+1) (becomes W(k) at the next publish)
+  T Un[5];                    // conserved values of plane k+2 (in flight)
   T Uz[5];                    // z+ face state of plane k-1 (interior columns)
   T Ux[5], Uy[5];             // own x- and y- face states of plane k
   T gRx[5], gRy[5], gRz[5];   // cotangents of the own x-, y-, z- face states of plane k-1
@@ -170,6 +195,7 @@ __device__ __forceinline__ void adj_col_init(AdjCol<T, kI>& c, const Src& src, i
     for (int q = 0; q < 5; ++q) sm.P[pslot(-2)][q][pidx(cx, cy)] = W[q];
   }
   load_prim(src, c.col, -1, gas, c.Wp);  // published as plane -1 by the first iteration
+  load_cons(src, c.col, 0, c.Un);
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     c.gRx[q] = c.gRy[q] = c.gRz[q] = T(0);
@@ -177,14 +203,19 @@ __device__ __forceinline__ void adj_col_init(AdjCol<T, kI>& c, const Src& src, i
   }
 }
 
-// F1: publish plane k (loaded last iteration); load plane k+1.  Interior
-// columns publish up to plane 17 (read back by the last reverse predictor).
+// F1: publish plane k; convert plane k+1 (loaded one iteration ago) and
+// issue the load of plane k+2 (clamped to the column's last plane, so it is
+// unconditional and its registers are never merged with old values: a merge
+// would wait for the load that is meant to stay in flight).  Interior columns
+// publish up to plane 17 (read back by the last reverse predictor).
 template <typename T, bool kI, class Src>
 __device__ __forceinline__ void adj_col_publish(AdjCol<T, kI>& c, const Src& src, int k, const Gas<T>& gas,
                                                 SmemF<T>& sm) {
 #pragma unroll
   for (int q = 0; q < 5; ++q) sm.P[pslot(k)][q][pidx(c.cx, c.cy)] = c.Wp[q];
-  if (k + 1 <= c.zhi) load_prim(src, c.col, k + 1, gas, c.Wp);
+  cons_to_prim(c.Un, gas, c.Wp);
+  asm volatile("" ::: "memory");
+  load_cons(src, c.col, k + 2 <= c.zhi ? k + 2 : c.zhi, c.Un);
 }
 
 // F2: half-step states of plane k and the z-face (k-1 | k) VJP; then the
@@ -406,10 +437,10 @@ __device__ __forceinline__ void adj_col_finish(AdjCol<T, kI>& c, const Src& src,
                                                const Gas<T>& gas, const SmemF<T>& sm, const Sink& sink) {
   const int j = k - 1;
   if (j >= c.zlo && j <= c.zhi) adj_gather_plane(c.cx, c.cy, j, sm, c.A1);
-  if (k - 2 >= c.zlo && k - 2 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, k - 2, c.A0, go, gas, sink);
+  if (k - 2 >= c.zlo && k - 2 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, k - 2, c.A0, go, gas, sink);
   if (k == 17) {
-    if (16 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, 16, c.A1, go, gas, sink);
-    if (17 <= c.zhi) finalize_cell(src, c.col, c.cx, c.cy, 17, c.A2, go, gas, sink);
+    if (16 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, 16, c.A1, go, gas, sink);
+    if (17 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, 17, c.A2, go, gas, sink);
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
@@ -434,12 +465,18 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
   const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
   const bool has_edge = halo && tid < 4;
   const int64_t col_out = halo ? src.col(ox, oy) : 0;
-  const int64_t col_edge = has_edge ? src.col(ex, ey) : 0;
+  // lanes without an edge column re-read their 2-deep column (unconditional loads)
+  const int64_t col_edge = halo ? src.col(has_edge ? ex : ox, has_edge ? ey : oy) : 0;
 
   AdjCol<T, true> ci;
   AdjCol<T, false> ch;
   adj_col_init(ci, src, tid & 15, tid >> 4, gas, sm);
-  if (halo) adj_col_init(ch, src, hx, hy, gas, sm);
+  T Uo[5], Ue[5];  // halo role: 2-deep and edge column, plane k (in flight)
+  if (halo) {
+    adj_col_init(ch, src, hx, hy, gas, sm);
+    load_cons(src, col_out, 0, Uo);
+    load_cons(src, col_edge, 0, Ue);
+  }
 
   for (int k = -1; k <= 17; ++k) {
     const int sk = pslot(k);
@@ -448,14 +485,18 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
       if (halo) {
         adj_col_publish(ch, src, k, gas, sm);
         if (k >= 0 && k <= 15) {
-          T Wo[5];
-          load_prim(src, col_out, k, gas, Wo);
+          T Wo[5], We[5];
+          cons_to_prim(Uo, gas, Wo);
+          cons_to_prim(Ue, gas, We);
+          asm volatile("" ::: "memory");
+          const int kn = k + 1 > 15 ? 15 : k + 1;
+          load_cons(src, col_out, kn, Uo);
+          load_cons(src, col_edge, kn, Ue);
 #pragma unroll
           for (int q = 0; q < 5; ++q) sm.P[sk][q][pidx(ox, oy)] = Wo[q];
           if (has_edge) {
-            load_prim(src, col_edge, k, gas, Wo);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) sm.P[sk][q][pidx(ex, ey)] = Wo[q];
+            for (int q = 0; q < 5; ++q) sm.P[sk][q][pidx(ex, ey)] = We[q];
           }
         }
       }
@@ -474,11 +515,11 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
         // the 2-deep and edge columns get only in-plane contributions
         T g[5] = {T(0), T(0), T(0), T(0), T(0)};
         adj_gather_plane(ox, oy, j, sm, g);
-        finalize_cell(src, col_out, ox, oy, j, g, go, gas, sink);
+        finalize_cell_lds(sm, ox, oy, j, g, go, gas, sink);
         if (has_edge) {
           T e[5] = {T(0), T(0), T(0), T(0), T(0)};
           adj_gather_plane(ex, ey, j, sm, e);
-          finalize_cell(src, col_edge, ex, ey, j, e, go, gas, sink);
+          finalize_cell_lds(sm, ex, ey, j, e, go, gas, sink);
         }
       }
     }
