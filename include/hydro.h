@@ -155,6 +155,9 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
  *   g_level_in_dev   [G][5][16^3] receives the cotangent of the input level
  *   work_dev, work_bytes  at least hydro_adjoint_workspace_bytes(G, dtype, 1)
  *   dt_dev           optional device double read instead of dt
+ *   Lattice limits: those of hydro_advance_level, and also every axis below
+ *   2^19 groups and G < 2^28 - 1 (else HYDRO_EINVAL); the same for
+ *   hydro_gather_ghost_adjoint.
  */
 int64_t hydro_adjoint_workspace_bytes(int64_t n_groups, int32_t dtype, int32_t level);
 int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* gU_pad_dev, int64_t n_groups,

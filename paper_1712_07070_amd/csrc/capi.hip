@@ -122,6 +122,14 @@ bool level_geom_ok(long long ngx, long long ngy, long long ngz) {
   return ngx * ngy * ngz < (1ll << 31) - 8;
 }
 
+// The level adjoint and the ghost gather also pack group indices per axis in
+// 19 bits and launch 16 workgroups per group.
+bool adjoint_geom_ok(long long ngx, long long ngy, long long ngz) {
+  if (!level_geom_ok(ngx, ngy, ngz)) return false;
+  if (ngx >= (1ll << 19) || ngy >= (1ll << 19) || ngz >= (1ll << 19)) return false;
+  return ngx * ngy * ngz < (1ll << 28) - 1;
+}
+
 int validate_levels(const hydro_level_t* lv, int32_t n_levels, int32_t dtype) {
   if (lv == nullptr || n_levels < 1 || n_levels > gh::kMaxLevels) return HYDRO_EINVAL;
   const size_t es = dtype_size(dtype);
@@ -511,7 +519,7 @@ int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_d
                                 int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx,
                                 double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
                                 int64_t work_bytes, void* stream) {
-  if (!level_geom_ok(ngx, ngy, ngz) || bc_host == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+  if (!adjoint_geom_ok(ngx, ngy, ngz) || bc_host == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
     return HYDRO_EINVAL;
   if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta)) return HYDRO_EINVAL;
   if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
@@ -664,7 +672,7 @@ int hydro_fill_ghosts(const void* level_dev, void* U_pad_dev, int32_t ngx, int32
 
 int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                                int32_t ghost, int32_t dtype, const int32_t* bc_host, void* stream) {
-  if (!level_geom_ok(ngx, ngy, ngz) || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
+  if (!adjoint_geom_ok(ngx, ngy, ngz) || ghost < 0 || ghost > 16 || bc_host == nullptr) return HYDRO_EINVAL;
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
   gh::LevelGeom geo;
   geo.ngx = ngx;

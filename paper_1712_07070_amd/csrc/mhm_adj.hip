@@ -1115,14 +1115,19 @@ __device__ __forceinline__ Copies4 axis_copies2(const Runs& r) {
 // [-2, 17], only stencil-reachable ones hold values); the x copies of each
 // (z, y) pair are loaded together.  Otherwise a padded [5][P^3] block per
 // group with ghost width gh (runs of up to gh positions per face).
+// One workgroup of 256 threads per (group, z) plane of the level, so the
+// group, its lattice position and the z runs are uniform (scalar) per
+// workgroup and each thread maps only its (x, y).
 template <typename T, bool kBoxSrc>
 __global__ __launch_bounds__(256) void adj_gather(const T* __restrict__ src, T* __restrict__ glevel, LevelGeom geo,
                                                   int gh, int64_t ncells) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= ncells) return;
+  const unsigned int blk = blockIdx.x;
+  const int z = int(blk & 15u);
+  const int64_t g = int64_t(blk >> 4);
+  const int x = int(threadIdx.x & 15u), y = int(threadIdx.x >> 4);
   // level cell (g, z, y, x) in group-major order
-  const int x = int(i & 15), y = int((i >> 4) & 15), z = int((i >> 8) & 15);
-  const int64_t g = i >> 12;
+  const int64_t i = (g << 12) + (int64_t(z) << 8) + threadIdx.x;
+  if (i >= ncells) return;
   const int gx = int(g % geo.ngx), gy = int((g / geo.ngx) % geo.ngy), gz = int(g / (int64_t(geo.ngx) * geo.ngy));
   const int w = kBoxSrc ? 2 : gh;        // position offset of the source block
   const int P = kBoxSrc ? kBox : 16 + 2 * gh;
@@ -1224,7 +1229,7 @@ hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, con
                                     hipStream_t stream) {
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   if (G == 0) return hipSuccess;
-  if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
+  if (G > (int64_t(1) << 28) - 1) return hipErrorInvalidValue;  // the gather takes G * 16 workgroups
   if (geo.ngx >= (1 << 19) || geo.ngy >= (1 << 19) || geo.ngz >= (1 << 19)) return hipErrorInvalidValue;
   T* gbox = work;  // [G][5][20^3]; only reachable positions are written, and only those are read
   T* fws = work + G * 5 * int64_t(kBox * kBox * kBox);
@@ -1238,8 +1243,7 @@ hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, con
                        gas, dt_dev, dx, first_order, ws);
   }
   const int64_t ncells = G * 4096;
-  hipLaunchKernelGGL((adj_gather<T, true>), dim3(unsigned((ncells + 255) / 256)), dim3(256), 0, stream, gbox, g_in,
-                     geo, 2, ncells);
+  hipLaunchKernelGGL((adj_gather<T, true>), dim3(unsigned(G * 16)), dim3(256), 0, stream, gbox, g_in, geo, 2, ncells);
   return hipGetLastError();
 }
 
@@ -1248,11 +1252,11 @@ hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGe
                                        hipStream_t stream) {
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   if (G == 0) return hipSuccess;
-  if (G > (int64_t(1) << 30)) return hipErrorInvalidValue;
+  if (G > (int64_t(1) << 28) - 1) return hipErrorInvalidValue;  // one workgroup per (group, z) plane
   if (geo.ngx >= (1 << 19) || geo.ngy >= (1 << 19) || geo.ngz >= (1 << 19)) return hipErrorInvalidValue;
   const int64_t ncells = G * 4096;
-  hipLaunchKernelGGL((adj_gather<T, false>), dim3(unsigned((ncells + 255) / 256)), dim3(256), 0, stream, g_pad,
-                     g_level, geo, ghost, ncells);
+  hipLaunchKernelGGL((adj_gather<T, false>), dim3(unsigned(G * 16)), dim3(256), 0, stream, g_pad, g_level, geo, ghost,
+                     ncells);
   return hipGetLastError();
 }
 

@@ -120,3 +120,15 @@ def test_autotune_adjoint_rejects_bad_arguments(lib):
     assert f(a, b, c, 1, 1, 1, bc, 0, -0.01, 1.4, w, 1 << 30, 1, None, None) == -1     # dx
     assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 16, 1, None, None) == -1           # workspace too small
     assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, None, 1 << 30, 1, None, None) == -1   # no workspace
+
+
+@pytest.mark.parametrize("ng", [(1 << 19, 1, 1), (1, 1, 1 << 19), (1 << 14, 1 << 14, 1)])
+def test_adjoint_entry_points_reject_their_extra_limits(lib, ng):
+    """The level adjoint and the ghost gather also need every axis below 2^19
+    groups and fewer than 2^28 - 1 groups."""
+    P = ctypes.c_void_p
+    bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    a, b = P(4096), P(1 << 46)
+    assert lib.hydro_advance_level_adjoint(a, b, P(1 << 47), *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, P(1 << 45),
+                                           1 << 62, None) == -1
+    assert lib.hydro_gather_ghost_adjoint(a, b, *ng, 3, 0, bc, None) == -1
