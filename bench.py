@@ -60,10 +60,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel_key: str, variant):
-    """HBM bytes per launch from the committed counter profile of this launch
-    shape, or None when the kernel sources differ from what was measured or
-    the shape was not measured."""
+def measured_profile(kernel_key: str, variant, field: str):
+    """A per-launch figure (HBM bytes, VALU wave-instructions) from the
+    committed counter profile of this launch shape, or None when the kernel
+    sources differ from what was measured or the shape was not measured."""
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
             rec = json.load(fh).get(kernel_key)
@@ -72,7 +72,17 @@ def measured_traffic(kernel_key: str, variant):
     if not rec or rec.get("source_sha256") != kernel_source_sha():
         return None
     shape = rec.get("by_variant", {}).get(str(variant))
-    return shape["bytes_per_launch"] if shape else None
+    return shape.get(field) if shape else None
+
+
+def measured_traffic(kernel_key: str, variant):
+    return measured_profile(kernel_key, variant, "bytes_per_launch")
+
+
+# VALU issue capacity: one wave-instruction (64 lanes) occupies a SIMD for 4
+# cycles (16 lanes per cycle, FP64 and unpacked FP32 alike); 256 CUs x 4
+# SIMDs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def parse():
@@ -400,8 +410,17 @@ def main():
             "kernel_ms": round(kms, 4), "cells_per_launch": cells, "other_roof": other}
     roof["alg_per_cell"] = main.get("alg_flops_per_cell", main.get("alg_bytes_per_cell"))
     if fused:
-        roof["traffic"] = measured_traffic("mhm_level_kernel<%s, true>" % tname,
-                                           tune["variant"] if tune else hydro.get_variant(solver.state.dtype))
+        shape = tune["variant"] if tune else hydro.get_variant(solver.state.dtype)
+        roof["traffic"] = measured_traffic("mhm_level_kernel<%s, true>" % tname, shape)
+        # how much of the VALU issue capacity the kernel's measured instruction
+        # count uses at this duration (context for the flop roofline: divisions
+        # and square roots cost several instructions, selects and moves none)
+        valu = measured_profile("mhm_level_kernel<%s, true>" % tname, shape, "valu_insts_per_launch")
+        if valu:
+            rate = valu / (kms * 1e-3)
+            roof["valu_issue"] = {"achieved": round(rate / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+                                  "unit": "G wave-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4),
+                                  "per_cell": round(valu / cells, 2)}
     extra = {"kernel_cell_updates_per_s": k_rate, "n_bad": n_bad, "dt_last_step": float(dts[0]),
              "path": "fused level step" if fused else "fill + dt + padded advance", "launch_shape": tune}
     if not args.no_f32 and args.dtype == "f64":
