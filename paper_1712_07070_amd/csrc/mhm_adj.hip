@@ -102,7 +102,9 @@ __device__ __forceinline__ void finalize_cell(const Src& src, int64_t col, int x
 // faces) with its 2-deep neighbour and, for 4 of them, an edge column, and run
 // that role after the interior one in every phase; wave 2 takes the VJPs of
 // the 32 faces the halo columns at x = 16 and y = 16 share with the interior
-// (states and cotangents through LDS), which evens out the waves' work.  One wave per SIMD leaves
+// (states and cotangents through LDS) and wave 3 finishes the 2-deep and
+// edge columns (their contributions are in LDS), which evens out the waves'
+// work.  One wave per SIMD leaves
 // the whole register file (VGPRs and AGPRs) to each wave.
 constexpr int kAdjThreads = 256;
 // Waves per SIMD the register allocation targets: FP64 takes the whole
@@ -456,6 +458,7 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
   const int tid = threadIdx.x;
   const bool halo = tid < 64;                  // wave 0
   const bool last = (tid >> 6) == 2;           // wave 2: the 32 last faces
+  const bool outer = (tid >> 6) == 3;          // wave 3: finishes the 2-deep and edge columns
   const bool fo = first_order != 0;
   // halo role of wave 0: side 0..3 = x-, x+, y-, y+; the column two cells out;
   // lanes 0..3 also one of the 4 edge columns
@@ -464,6 +467,11 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
   const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
   const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
   const bool has_edge = halo && tid < 4;
+  // lane l of wave 3 finishes the 2-deep (and edge) column of halo lane l
+  const int ol = tid & 63, oside = ol >> 4, okk = ol & 15;
+  const int fox = oside == 0 ? -2 : oside == 1 ? 17 : okk, foy = oside == 2 ? -2 : oside == 3 ? 17 : okk;
+  const int fex = (ol & 1) ? 16 : -1, fey = (ol & 2) ? 16 : -1;
+  const bool fedge = outer && ol < 4;
   const int64_t col_out = halo ? src.col(ox, oy) : 0;
   // lanes without an edge column re-read their 2-deep column (unconditional loads)
   const int64_t col_edge = halo ? src.col(has_edge ? ex : ox, has_edge ? ey : oy) : 0;
@@ -508,18 +516,18 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
     adj_col_faces(ci, k, go, gas, ws, sm);
     if (last) adj_last_faces(tid & 63, k, go, gas, ws, sm);
     adj_col_finish(ci, src, k, go, gas, sm, sink);
-    if (halo) {
-      adj_col_finish(ch, src, k, go, gas, sm, sink);
+    if (halo) adj_col_finish(ch, src, k, go, gas, sm, sink);
+    if (outer) {
       const int j = k - 1;
       if (j >= 0 && j <= 15) {
         // the 2-deep and edge columns get only in-plane contributions
         T g[5] = {T(0), T(0), T(0), T(0), T(0)};
-        adj_gather_plane(ox, oy, j, sm, g);
-        finalize_cell_lds(sm, ox, oy, j, g, go, gas, sink);
-        if (has_edge) {
+        adj_gather_plane(fox, foy, j, sm, g);
+        finalize_cell_lds(sm, fox, foy, j, g, go, gas, sink);
+        if (fedge) {
           T e[5] = {T(0), T(0), T(0), T(0), T(0)};
-          adj_gather_plane(ex, ey, j, sm, e);
-          finalize_cell_lds(sm, ex, ey, j, e, go, gas, sink);
+          adj_gather_plane(fex, fey, j, sm, e);
+          finalize_cell_lds(sm, fex, fey, j, e, go, gas, sink);
         }
       }
     }
