@@ -100,7 +100,8 @@ __device__ __forceinline__ void finalize_cell(const Src& src, int64_t col, int x
 // interior column; the 64 threads of wave 0 also own one halo column each (the
 // 4 x 16 columns just outside the faces, whose state cells feed the boundary
 // faces) with its 2-deep neighbour and, for 4 of them, an edge column, and run
-// that role after the interior one in every phase; wave 2 takes the VJPs of
+// that role after the interior one in every phase (the reverse predictor and
+// finish of the halo columns run on wave 1, from LDS); wave 2 takes the VJPs of
 // the 32 faces the halo columns at x = 16 and y = 16 share with the interior
 // (states and cotangents through LDS) and wave 3 finishes the 2-deep and
 // edge columns (their contributions are in LDS), which evens out the waves'
@@ -220,16 +221,19 @@ __device__ __forceinline__ void adj_col_publish(AdjCol<T, kI>& c, const Src& src
   load_cons(src, c.col, k + 2 <= c.zhi ? k + 2 : c.zhi, c.Un);
 }
 
-// F2: half-step states of plane k and the z-face (k-1 | k) VJP; then the
-// reverse Hancock predictor of the state cell at plane k-1.
-template <typename T, bool kI>
+// F2: half-step states of plane k and the z-face (k-1 | k) VJP (kFwd); then
+// the reverse Hancock predictor of the state cell at plane k-1 (kRev).  A
+// halo column's two parts run on different waves, each with its own AdjCol
+// of the column (the reverse part needs nothing the forward part keeps in
+// registers: its face cotangent comes through LDS).
+template <typename T, bool kI, bool kFwd = true, bool kRev = true>
 __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T* __restrict__ go, const Gas<T>& gas,
                                                bool fo, int ws, SmemF<T>& sm) {
   const int cx = c.cx, cy = c.cy;
   const int sk = pslot(k), sj = pslot(k - 1), si = pslot(k - 2);
   T gLz[5] = {T(0), T(0), T(0), T(0), T(0)};   // cotangent of the z+ face state of plane k-1
   T gRzn[5] = {T(0), T(0), T(0), T(0), T(0)};  // cotangent of the z- face state of plane k
-  if (k <= 16 && in_state_plane(cx, cy, k)) {
+  if (kFwd && k <= 16 && in_state_plane(cx, cy, k)) {
     T Wc[5], Wn[3][2][5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -270,7 +274,7 @@ __device__ __forceinline__ void adj_col_states(AdjCol<T, kI>& c, int k, const T*
   }
 
   const int j = k - 1;
-  if (j >= -1 && in_state_plane(cx, cy, j)) {
+  if (kRev && j >= -1 && in_state_plane(cx, cy, j)) {
     const bool u0 = face_used(cx, cy, j, 0), u1 = face_used(cx, cy, j, 1), u2 = face_used(cx, cy, j, 2);
     const bool u3 = face_used(cx, cy, j, 3), u4 = face_used(cx, cy, j, 4), u5 = face_used(cx, cy, j, 5);
     T Wj[5], gWc[5];
@@ -432,14 +436,25 @@ __device__ __forceinline__ void adj_gather_plane(int x, int y, int j, const Smem
   }
 }
 
+// Finalize plane k-2 of the column (complete once the reverse predictor of
+// plane k-1 has run).  A column whose planes another wave publishes calls this
+// right after its reverse part, before the barrier that lets the publisher
+// overwrite that plane's LDS slot with plane k+1.
+template <typename T, bool kI, class Sink>
+__device__ __forceinline__ void adj_col_finalize_prev(const AdjCol<T, kI>& c, int k, const T* __restrict__ go,
+                                                      const Gas<T>& gas, const SmemF<T>& sm, const Sink& sink) {
+  if (k - 2 >= c.zlo && k - 2 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, k - 2, c.A0, go, gas, sink);
+}
+
 // F3b: in-plane gather of plane k-1 into the column; finalize the planes that
-// are complete (k-2; after the last plane also k-1 and k); advance the rings.
-template <typename T, bool kI, class Src, class Sink>
+// are complete (k-2 unless kPrevDone; after the last plane also k-1 and k);
+// advance the rings.
+template <typename T, bool kI, class Src, class Sink, bool kPrevDone = false>
 __device__ __forceinline__ void adj_col_finish(AdjCol<T, kI>& c, const Src& src, int k, const T* __restrict__ go,
                                                const Gas<T>& gas, const SmemF<T>& sm, const Sink& sink) {
   const int j = k - 1;
   if (j >= c.zlo && j <= c.zhi) adj_gather_plane(c.cx, c.cy, j, sm, c.A1);
-  if (k - 2 >= c.zlo && k - 2 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, k - 2, c.A0, go, gas, sink);
+  if (!kPrevDone) adj_col_finalize_prev(c, k, go, gas, sm, sink);
   if (k == 17) {
     if (16 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, 16, c.A1, go, gas, sink);
     if (17 <= c.zhi) finalize_cell_lds(sm, c.cx, c.cy, 17, c.A2, go, gas, sink);
@@ -456,13 +471,15 @@ template <typename T, class Src, class Sink>
 __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restrict__ go, const Gas<T>& gas,
                                               int first_order, int ws, SmemF<T>& sm, const Sink& sink) {
   const int tid = threadIdx.x;
-  const bool halo = tid < 64;                  // wave 0
+  const bool halo = tid < 64;                  // wave 0: halo columns, forward part
+  const bool hrev = (tid >> 6) == 1;           // wave 1: halo columns, reverse part and finish
   const bool last = (tid >> 6) == 2;           // wave 2: the 32 last faces
   const bool outer = (tid >> 6) == 3;          // wave 3: finishes the 2-deep and edge columns
   const bool fo = first_order != 0;
   // halo role of wave 0: side 0..3 = x-, x+, y-, y+; the column two cells out;
-  // lanes 0..3 also one of the 4 edge columns
-  const int side = tid >> 4, kk = tid & 15;
+  // lanes 0..3 also one of the 4 edge columns; lane l of wave 1 takes the
+  // reverse part of the halo column of lane l
+  const int side = (tid & 63) >> 4, kk = tid & 15;
   const int hx = side == 0 ? -1 : side == 1 ? 16 : kk, hy = side == 2 ? -1 : side == 3 ? 16 : kk;
   const int ox = side == 0 ? -2 : side == 1 ? 17 : kk, oy = side == 2 ? -2 : side == 3 ? 17 : kk;
   const int ex = (tid & 1) ? 16 : -1, ey = (tid & 2) ? 16 : -1;
@@ -477,11 +494,11 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
   const int64_t col_edge = halo ? src.col(has_edge ? ex : ox, has_edge ? ey : oy) : 0;
 
   AdjCol<T, true> ci;
-  AdjCol<T, false> ch;
+  AdjCol<T, false> ch;  // wave 0: forward part; wave 1: reverse part of the same halo column
   adj_col_init(ci, src, tid & 15, tid >> 4, gas, sm);
   T Uo[5], Ue[5];  // halo role: 2-deep and edge column, plane k (in flight)
+  if (halo || hrev) adj_col_init(ch, src, hx, hy, gas, sm);
   if (halo) {
-    adj_col_init(ch, src, hx, hy, gas, sm);
     load_cons(src, col_out, 0, Uo);
     load_cons(src, col_edge, 0, Ue);
   }
@@ -511,12 +528,17 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
     }
     __syncthreads();
     adj_col_states(ci, k, go, gas, fo, ws, sm);
-    if (halo) adj_col_states(ch, k, go, gas, fo, ws, sm);
+    if (halo) adj_col_states<T, false, true, false>(ch, k, go, gas, fo, ws, sm);
+    if (hrev) {
+      adj_col_states<T, false, false, true>(ch, k, go, gas, fo, ws, sm);
+      // wave 0 publishes this column: plane k-2's slot is rewritten after the barrier
+      adj_col_finalize_prev(ch, k, go, gas, sm, sink);
+    }
     __syncthreads();
     adj_col_faces(ci, k, go, gas, ws, sm);
     if (last) adj_last_faces(tid & 63, k, go, gas, ws, sm);
     adj_col_finish(ci, src, k, go, gas, sm, sink);
-    if (halo) adj_col_finish(ch, src, k, go, gas, sm, sink);
+    if (hrev) adj_col_finish<T, false, Src, Sink, true>(ch, src, k, go, gas, sm, sink);
     if (outer) {
       const int j = k - 1;
       if (j >= 0 && j <= 15) {
