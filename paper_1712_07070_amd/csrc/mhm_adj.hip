@@ -553,10 +553,13 @@ __device__ __forceinline__ void adjoint_fused(const Src& src, const T* __restric
         }
       }
     }
-    // next writes: P slot k+1 held plane k-2 (last read in this iteration's
-    // states phase), S / O in the next states phase (after its first
-    // barrier), GL in the next faces phase (after the barrier that follows
-    // its reads)
+    // next writes: P slot k+1 held plane k-2, read in this iteration's
+    // states phase by every wave and in its finish phase only by the thread
+    // that publishes the column (program order orders the two; the halo
+    // columns, published by wave 0, are finalized by wave 1 in the states
+    // phase); S / O / H in the next states phase (after its first barrier);
+    // GL / GR in the next faces phase (after the barrier that follows their
+    // reads)
   }
 }
 

@@ -288,6 +288,37 @@ def test_level_step_equals_fill_then_advance(hydro, dtype, case):
     assert int(host(nb)[0]) == nb_ref == 0
 
 
+@pytest.mark.parametrize("scheme", [1 | (1 << 10), 1 | (1 << 8), 1 | (1 << 8) | (1 << 10)])
+def test_level_and_batched_scheme_options(hydro, scheme):
+    """The first-order and Davis options take the run-time-flag path of the
+    march (the default scheme has its own inlined copy): the level step and
+    the batched launch equal ghost fill + padded step bit for bit, and the
+    oracle within tolerance."""
+    say("scheme options", scheme)
+    ng, bc = (2, 3, 2), (1, 0, 0, 1, 1, 1)
+    rng = np.random.default_rng(8)
+    n = [16 * v for v in ng]
+    shape = (n[2], n[1], n[0])
+    grid = W.conserved(rng.uniform(0.5, 2, shape), *(rng.normal(0, 0.3, shape) for _ in range(3)),
+                       rng.uniform(0.5, 2, shape), 5 / 3)
+    U = W.grid_to_groups(grid)
+    t = dev(U)
+    dx = 1.0 / n[0]
+    pad = hydro.fill_ghosts(t, ng, 3, bc)
+    a = hydro.advance(pad, 1e-3, dx, 5 / 3, 1.5, scheme)
+    b = hydro.advance_level(t, ng, bc, 1e-3, dx, 5 / 3, 1.5, scheme)
+    assert torch.equal(a, b)
+    c = torch.empty_like(t)
+    work = torch.zeros(hydro.BATCH_WORK_WORDS, dtype=torch.int32, device="cuda")
+    hydro.advance_batched([(t, c, ng, bc, 1e-3, dx)], 5 / 3, work, 1.5, scheme)
+    assert torch.equal(a, c)
+    ref, _ = oracle.mhm_step(oracle.fill_ghosts(U, ng, 3, bc), 1e-3, dx, 5 / 3, 1.5, scheme)
+    assert field_scale_error(host(b), ref) <= TOL[np.float64]
+    # the options change the result
+    d = hydro.advance_level(t, ng, bc, 1e-3, dx, 5 / 3)
+    assert not torch.equal(b, d)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_level_cfl_epilogue_bitwise(hydro, dtype):
     say("level cfl epilogue", dtype.__name__)
