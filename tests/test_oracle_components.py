@@ -119,20 +119,24 @@ def test_hllc_stationary_contact_exact():
         assert np.array_equal(F, expect)
 
 
-def test_hllc_rotation_and_mirror():
+@pytest.mark.parametrize("ws", [0, 1])
+def test_hllc_rotation_and_mirror(ws):
+    # both wave-speed estimates map to their mirror image (S_L <-> -S_R), so
+    # the mirrored problem's flux is the mirrored flux; a wrong term in either
+    # speed breaks it
     g = G53
     rng = np.random.default_rng(3)
     for _ in range(40):
         UL = prim2cons(rng.uniform(0.2, 3), *rng.normal(0, 1, 3), rng.uniform(0.2, 3), g)
         UR = prim2cons(rng.uniform(0.2, 3), *rng.normal(0, 1, 3), rng.uniform(0.2, 3), g)
-        Fx, _ = oracle.hllc(UL, UR, 0, g, 0)
+        Fx, _ = oracle.hllc(UL, UR, 0, g, ws)
         # rotate (x, y, z) -> (y, z, x): the y-face flux of the rotated states
         rot = [0, 3, 1, 2, 4]
-        Fy, _ = oracle.hllc(UL[rot], UR[rot], 1, g, 0)
+        Fy, _ = oracle.hllc(UL[rot], UR[rot], 1, g, ws)
         assert np.array_equal(Fy, Fx[rot])
         # mirror x -> -x swaps the sides and flips normal momentum
         M = np.array([1, -1, 1, 1, 1.0])
-        Fm, _ = oracle.hllc(UR * M, UL * M, 0, g, 0)
+        Fm, _ = oracle.hllc(UR * M, UL * M, 0, g, ws)
         np.testing.assert_allclose(Fm, -Fx * M, rtol=1e-12, atol=1e-13)
 
 
