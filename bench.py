@@ -353,18 +353,37 @@ def cpu_baseline(lv_factory, seconds):
     U = np.ascontiguousarray(lv.U[:nsub])
     ng = (ngx, ngy, 2)
     cells = nsub * 4096
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        U, _, _ = oracle.rollout(U, ng, 3, lv.bc, 1, lv.dx, lv.gamma)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+
+    def timed(budget):
+        V, steps, t0 = U, 0, time.perf_counter()
+        while True:
+            V, _, _ = oracle.rollout(V, ng, 3, lv.bc, 1, lv.dx, lv.gamma)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return steps, el
+
+    threads = oracle.num_threads()
+    steps, el = timed(seconds)
+    # the same sample on one thread (shorter budget, at least one step)
+    oracle.set_num_threads(1)
+    try:
+        steps1, el1 = timed(seconds / 3)
+    finally:
+        oracle.set_num_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d steps (ghost fill + CFL + MHM) of %d groups (%dx%dx%d cells, a %dx%dx2-group slab of "
                       "the workload as its own periodic brick), FP64, OpenMP over groups" %
-                      (steps, nsub, ngx * 16, ngy * 16, 32, ngx, ngy)}
+                      (steps, nsub, ngx * 16, ngy * 16, 32, ngx, ngy),
+            "single_thread": {"value": cells * steps1 / el1, "steps": steps1},
+            "host": {"cpu_count": os.cpu_count(), "model": model}}
 
 
 def main():

@@ -75,6 +75,7 @@ def _load():
         "oracle_exact_residual": (f64, [f64] * 8),
         "oracle_count_ops": (None, [P, P, P, P, P, P, f64, f64, f64, P]),
         "oracle_num_threads": (i32, []),
+        "oracle_set_num_threads": (None, [i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -246,6 +247,11 @@ def exact_residual(left, right, gamma, p):
 def num_threads() -> int:
     """OpenMP threads used by the oracle's loops over groups."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Set the OpenMP threads of the oracle's loops over groups (n >= 1)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def count_ops(U, Wc, Wm, Wp, UL, UR, gamma, theta, half_dtdx):

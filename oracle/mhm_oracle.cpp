@@ -689,8 +689,12 @@ int64_t oracle_mhm_step_jvp(const double* Upad, const double* Tpad, double* Uout
   return n_bad;
 }
 
-// Number of OpenMP threads the oracle's parallel loops use.
+// Number of OpenMP threads the oracle's parallel loops use, and a way to set
+// it (n >= 1) for timing the oracle on fewer threads.
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+}
 
 // Single HLLC flux (tests): UL, UR conserved, d = normal axis.  Returns 1 if an
 // input state is unphysical.
