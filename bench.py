@@ -51,12 +51,19 @@ ALG_FLOPS_PER_CELL = 880.2
 
 
 def kernel_source_sha() -> str:
-    """sha256 of the sources of the MHM kernels (changes whenever they do)."""
+    """sha256 of the code of the MHM kernels' sources: comments and blank
+    lines are dropped, so it changes whenever the code does and not when
+    only a comment does."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("hydro_device.h", "mhm_group.h", "mhm_fwd.hip"):
-        with open(os.path.join(ROOT, "paper_1712_07070_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1712_07070_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()
 
 

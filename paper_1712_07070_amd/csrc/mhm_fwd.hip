@@ -1,20 +1,23 @@
 // MHM step of 16^3 patch groups, one group per workgroup (GAMER-2, Sec. 2.2).
 //
 // Mapping on gfx950 (wave64, 160 KB LDS per CU):
-//   * 320 threads = 5 waves.  Waves 0-3 own the 256 interior (x, y) columns
-//     of the group; wave 4 owns the 64 "halo" columns one cell outside the
-//     interior (x = -1, x = 16, y = -1, y = 16), whose face states feed the
-//     x/y faces on the group boundary.  Wave 4 also loads the 64 columns two
-//     cells out and the 4 edge columns, which are only read as neighbours.
+//   * 256 threads = 4 waves, one per SIMD; every thread owns one interior
+//     (x, y) column.  Wave 0 also owns the 64 "halo" columns one cell outside
+//     the interior (x = -1, x = 16, y = -1, y = 16), whose face states feed
+//     the x/y faces on the group boundary, and loads the 64 columns two cells
+//     out and the 4 edge columns, which are only read as neighbours.  Wave 2
+//     solves the 32 faces on the high x / y boundary from states the halo
+//     columns leave in LDS.  Two workgroups share a CU (FP64).
 //   * The workgroup marches in z over the state planes k = -1 .. 16.  Each
 //     thread keeps the primitive states of its own column at planes k-1, k,
-//     k+1 in registers (the z stencil); plane k of all columns goes through
-//     LDS for the x/y stencil.
+//     k+1 in registers (the z stencil) and the conserved values of the next
+//     plane in flight; plane k of all columns goes through LDS for the x/y
+//     stencil.
 //   * Per plane: every state cell computes its six half-step face states
 //     (a2-a4) in registers; the x+ and y+ states go to LDS, the z+ state stays
 //     in a register for the z-face of the next plane.  Then each interior
-//     thread solves the HLLC problems of its low x and low y faces (the halo
-//     threads at x = 16 / y = 16 solve the last face) and its z-face k-1/2.
+//     thread solves the HLLC problems of its low x and low y faces (wave 2
+//     also the last faces) and its z-face k-1/2.
 //   * x/y fluxes go through LDS once; the z flux stays in registers, so the
 //     update of plane k-1 is completed in the iteration of plane k, summing
 //     the flux differences in the order x, y, z.

@@ -1,8 +1,8 @@
 // Per-group device code of the MHM step shared by the level kernels
 // (mhm_fwd.hip) and the batched persistent kernel (mhm_batched.hip): input
 // sources, the LDS layout, and the z-marching routine that advances one
-// 16^3 patch group with one 256-thread workgroup.  See mhm_fwd.hip for the
-// mapping of threads to columns.
+// 16^3 patch group with one 256-thread workgroup (the mapping of threads to
+// columns and roles is described at "one patch group" below).
 #pragma once
 
 #include "hydro_device.h"
