@@ -371,6 +371,14 @@ __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out
                                              int first_order, int ws, Smem<T>& sm, double* smax,
                                              double gamma_d, int tid = threadIdx.x) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // FP32: the halo wave (the most work per plane) and the last-faces wave
+  // take issue priority over the plain waves they share a SIMD with, so the
+  // plane's barrier is reached sooner (measured: FP32 step -8%; FP64 +5%, so
+  // FP64 keeps equal priorities)
+  if constexpr (sizeof(T) == 4) {
+    if (wave == 0) __builtin_amdgcn_s_setprio(2);
+    if (wave == 2) __builtin_amdgcn_s_setprio(1);
+  }
   if (first_order == 0) {
     if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
     if (wave == 2) return march_group<T, Src, kRoleLastFaces>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
