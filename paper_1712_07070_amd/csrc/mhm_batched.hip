@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     // whole group step and cost registers / occupancy)
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int bad = process_group<T>(src, L.out + int64_t(g) * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
+    const int bad = process_group<T, (kWaves >= 4)>(src, L.out + int64_t(g) * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
     if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
     // every thread has read item_slot (first barrier of the group step)
     if (taker) item_slot = resolve(ticket);

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const int P = 16 + 2 * gh;
   const int64_t P3 = int64_t(P) * P * P;
   PaddedSource<T> src{Upad + int64_t(blockIdx.x) * 5 * P3, P, gh};
-  const int bad = process_group<T>(src, Uout + int64_t(blockIdx.x) * 5 * 4096, gas, first_order, ws, sm, nullptr,
+  const int bad = process_group<T, (kWaves >= 4)>(src, Uout + int64_t(blockIdx.x) * 5 * 4096, gas, first_order, ws, sm, nullptr,
                                    0.0);
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
 }
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   if (g >= G) return;  // whole workgroup leaves together (g is uniform)
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   double smax[2] = {0.0, 0.0};
-  const int bad = process_group<T>(src, level_out + g * 5 * 4096, gas, first_order, ws, sm,
+  const int bad = process_group<T, (kWaves >= 4)>(src, level_out + g * 5 * 4096, gas, first_order, ws, sm,
                                    kCfl ? smax : nullptr, cfl.gamma);
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
   if (kCfl)

@@ -366,16 +366,18 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 // halo waves sit on SIMDs 0 and 2 and the last-face waves on SIMDs 1 and 3.
 // The second-order scheme (first_order == 0) gets its own inlined copies
 // with the limiter unconditional; the first-order one keeps the runtime flag.
-template <typename T, class Src>
+// kPrio: the halo wave (the most work per plane) and the last-faces wave take
+// issue priority over the plain waves they share a SIMD with, so the plane's
+// barrier is reached sooner.  Measured on the 256^3 shear layer: with four
+// waves per SIMD (FP32, high occupancy) the step is 6-8% faster; with two
+// (FP64, FP32 low occupancy) 2-5% slower, so those kernels keep equal
+// priorities.
+template <typename T, bool kPrio, class Src>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
                                              int first_order, int ws, Smem<T>& sm, double* smax,
                                              double gamma_d, int tid = threadIdx.x) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // FP32: the halo wave (the most work per plane) and the last-faces wave
-  // take issue priority over the plain waves they share a SIMD with, so the
-  // plane's barrier is reached sooner (measured: FP32 step -8%; FP64 +5%, so
-  // FP64 keeps equal priorities)
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (kPrio) {
     if (wave == 0) __builtin_amdgcn_s_setprio(2);
     if (wave == 2) __builtin_amdgcn_s_setprio(1);
   }
