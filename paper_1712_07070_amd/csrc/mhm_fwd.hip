@@ -80,13 +80,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const int64_t g = xcd_order ? xcd_group(blockIdx.x, G) : int64_t(blockIdx.x);
   if (g >= G) return;  // whole workgroup leaves together (g is uniform)
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
-  double smax[2] = {0.0, 0.0};
-  const int bad = process_group<T, (kWaves >= 4)>(src, level_out + g * 5 * 4096, gas, first_order, ws, sm,
-                                   kCfl ? smax : nullptr, cfl.gamma);
+  __shared__ double cfl_slots[kCfl ? 2 * kCflHalfStride : 1];
+  double* smax = nullptr;
+  if (kCfl) {
+    smax = cfl_slots + cfl_slot(threadIdx.x);
+    smax[0] = 0.0;
+    smax[kCflHalfStride] = 0.0;
+  }
+  const int bad = process_group<T, (kWaves >= 4)>(src, level_out + g * 5 * 4096, gas, first_order, ws, sm, smax,
+                                                  cfl.gamma);
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
   if (kCfl)
-    cfl_epilogue(smax, reinterpret_cast<double*>(&sm), cfl.c_cfl_dx,
-                 cfl.dt_patch != nullptr ? cfl.dt_patch + g * 8 : nullptr, cfl.dt_min);
+    cfl_epilogue(cfl_slots, cfl.c_cfl_dx, cfl.dt_patch != nullptr ? cfl.dt_patch + g * 8 : nullptr, cfl.dt_min);
 }
 
 template <typename T, bool kCfl>

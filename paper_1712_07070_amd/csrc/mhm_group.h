@@ -130,6 +130,17 @@ __device__ __forceinline__ void fwd_col_publish(FwdCol<T, kI>& c, const Src& src
   for (int q = 0; q < 5; ++q) sm.P[q][pidx(c.cx, c.cy)] = c.Wc[q];
 }
 
+// CFL signal-speed maxima of a group live in LDS as [z half][patch xy][64
+// columns of the patch] (the order the epilogue reduces in): a thread's slot
+// for z half 0 is cfl_slot(tid), its slot for z half 1 lies kCflHalfStride
+// doubles further.  Kept in LDS rather than registers (4 VGPRs fewer through
+// the march).
+constexpr int kCflHalfStride = 256;
+__device__ __forceinline__ int cfl_slot(int tid) {
+  const int x = tid & 15, y = tid >> 4;
+  return ((y >> 3) * 2 + (x >> 3)) * 64 + (y & 7) * 8 + (x & 7);
+}
+
 // Half-step face states of the column's state cell at plane k.  Interior
 // columns also solve the z-face k-1/2 and complete plane k-1.
 template <typename T, bool kI, class Src>
@@ -195,7 +206,7 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI>& c, const Src& src, 
         if (smax != nullptr) {
           const double s = cfl_signal_speed(double(Un[0]), double(Un[1]), double(Un[2]), double(Un[3]),
                                             double(Un[4]), gamma_d);
-          double& m = smax[(k - 1) >> 3];
+          double& m = smax[((k - 1) >> 3) * kCflHalfStride];
           if (s > m) m = s;
         }
       }
@@ -356,7 +367,8 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 
 // Advance one group: read through `src`, write the 16^3 x 5 interior to `out`
 // (field stride 4096).  Returns this thread's unphysical count.  If smax is
-// non-null, also returns the maximum CFL signal speed of the thread's interior
+// non-null (the thread's cfl_slot in an LDS array, both halves set to 0),
+// also leaves there the maximum CFL signal speed of the thread's interior
 // cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's index in the
 // workgroup (a loop over groups passes it opaque, so that the compiler keeps
 // thread-derived addresses out of the loop's live set).  Wave 0 runs the
@@ -392,25 +404,19 @@ __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out
   return march_group<T, Src, kRolePlain>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
 }
 
-// Reduce the per-thread signal-speed maxima of one group to its 8 patch
-// time-steps (patch p = (pz*2 + py)*2 + px); LDS scratch `red` >= 512 doubles.
-// Optionally stores dt_patch[8] and folds the minimum into *dt_min (integer
-// minimum of non-negative doubles: exact and order-independent).
-__device__ __forceinline__ void cfl_epilogue(const double smax[2], double* red, double c_cfl_dx,
+// Reduce the per-thread signal-speed maxima of one group (the LDS array
+// `slots` of cfl_slot's layout, 512 doubles) to its 8 patch time-steps (patch
+// p = (pz*2 + py)*2 + px).  Optionally stores dt_patch[8] and folds the
+// minimum into *dt_min (integer minimum of non-negative doubles: exact and
+// order-independent).
+__device__ __forceinline__ void cfl_epilogue(const double* slots, double c_cfl_dx,
                                              double* __restrict__ dt_patch, unsigned long long* __restrict__ dt_min) {
   const int tid = threadIdx.x;
-  __syncthreads();
-  if (tid < 256) {
-    const int x = tid & 15, y = tid >> 4;
-    const int pxy = (y >> 3) * 2 + (x >> 3), col = (y & 7) * 8 + (x & 7);
-    red[(0 * 4 + pxy) * 64 + col] = smax[0];
-    red[(1 * 4 + pxy) * 64 + col] = smax[1];
-  }
   __syncthreads();
   if (tid < 8) {
     double m = 0.0;
     for (int i = 0; i < 64; ++i) {
-      const double s = red[((tid >> 2) * 4 + (tid & 3)) * 64 + i];
+      const double s = slots[tid * 64 + i];
       if (s > m) m = s;
     }
     const double dt = c_cfl_dx / m;
