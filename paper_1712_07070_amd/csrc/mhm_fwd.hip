@@ -7,7 +7,8 @@
 //     the x/y faces on the group boundary, and loads the 64 columns two cells
 //     out and the 4 edge columns, which are only read as neighbours.  Wave 2
 //     solves the 32 faces on the high x / y boundary from states the halo
-//     columns leave in LDS.  Two workgroups share a CU (FP64).
+//     columns leave in LDS.  Two workgroups share a CU in FP64, up to four
+//     in FP32.
 //   * The workgroup marches in z over the state planes k = -1 .. 16.  Each
 //     thread keeps the primitive states of its own column at planes k-1, k,
 //     k+1 in registers (the z stencil) and the conserved values of the next
