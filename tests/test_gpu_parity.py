@@ -338,6 +338,43 @@ def test_level_cfl_epilogue_bitwise(hydro, dtype):
     assert torch.equal(hydro.cfl_dt(out, lv.dx, lv.gamma, 0.5), dt_patch)
 
 
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", ["periodic", "outflow-x", "single-group"])
+def test_every_shape_with_cfl_on_ragged_group_counts(hydro, dtype, case):
+    """Group counts that are not a multiple of the 8 XCDs (12, 4, 1 groups):
+    in every launch shape, with the CFL epilogue on, the fused step equals
+    ghost fill + padded step bit for bit, and its per-patch time-steps equal
+    the standalone CFL kernel's on the output and the oracle's."""
+    say("every shape, cfl, ragged", dtype.__name__, case)
+    ng, bc = LEVEL_CASES[case]
+    rng = np.random.default_rng(11)
+    n = [16 * v for v in ng]
+    shape = (n[2], n[1], n[0])
+    grid = W.conserved(rng.uniform(0.5, 2, shape), *(rng.normal(0, 0.3, shape) for _ in range(3)),
+                       rng.uniform(0.5, 2, shape), 5 / 3)
+    U = W.grid_to_groups(grid).astype(dtype)
+    G = U.shape[0]
+    t = dev(U)
+    dx = 1.0 / n[0]
+    ref = hydro.advance(hydro.fill_ghosts(t, ng, 3, bc), 1e-3, dx, 5 / 3)
+    tdt = t.dtype
+    saved = hydro.get_level_variant(tdt, True)
+    try:
+        for v in range(hydro.num_variants()):
+            hydro.set_level_variant(tdt, True, v)
+            dt_next = torch.full((1,), float("inf"), dtype=torch.float64, device="cuda")
+            dt_patch = torch.full((G, 8), -1.0, dtype=torch.float64, device="cuda")
+            out = hydro.advance_level(t, ng, bc, 1e-3, dx, 5 / 3, c_cfl=0.5, dt_next=dt_next,
+                                      dt_patch_next=dt_patch)
+            assert torch.equal(out, ref), v
+            assert torch.equal(hydro.cfl_dt(out, dx, 5 / 3, 0.5), dt_patch), v
+            want = oracle.dt_patch(host(out).astype(np.float64), dx, 5 / 3, 0.5)
+            assert np.array_equal(host(dt_patch), want), v
+            assert host(dt_next)[0] == want.min(), v
+    finally:
+        hydro.set_level_variant(tdt, True, saved)
+
 def test_level_sod_rollout_outflow(hydro):
     say("level sod rollout")
     lv = W.sod_tube(128)
