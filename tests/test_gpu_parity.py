@@ -462,10 +462,19 @@ def _amr_levels(scale_ng=((2, 2, 2), (2, 2, 6), (2, 4, 6)), dtype=np.float64):
     return [lv.astype(dtype) for lv in lvs]
 
 
+# level lattices: the default (8 + 24 + 48 groups) and counts with no common
+# factor with the 8 XCDs or the queue count (3 + 5 + 7 groups)
+BATCH_LATTICES = {
+    "even": ((2, 2, 2), (2, 2, 6), (2, 4, 6)),
+    "ragged": ((3, 1, 1), (1, 5, 1), (1, 1, 7)),
+}
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_batched_equals_per_level(hydro, dtype):
-    say("batched vs per-level", dtype.__name__)
-    lvs = _amr_levels(dtype=dtype)
+@pytest.mark.parametrize("lattice", list(BATCH_LATTICES))
+def test_batched_equals_per_level(hydro, dtype, lattice):
+    say("batched vs per-level", dtype.__name__, lattice)
+    lvs = _amr_levels(BATCH_LATTICES[lattice], dtype=dtype)
     tdt = torch.float64 if dtype == np.float64 else torch.float32
     ins = [dev(lv.U) for lv in lvs]
     dt0 = 0.3 * min(float(oracle.dt_patch(lv.U.astype(np.float64), lv.dx, lv.gamma).min()) * 2 ** l
