@@ -307,7 +307,7 @@ int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t
  * 8 XCDs sweeps a contiguous range of groups and finds neighbour-group halos
  * in its own L2).  The choice is process-wide, per dtype and per kernel
  * form (with_cfl: the form that reduces the next CFL time-step, which needs
- * more registers).
+ * more registers and 4 KB more LDS per workgroup).
  *   hydro_num_variants       number of shapes (>= 1)
  *   hydro_set_level_variant  select one (0 .. n-1) for one form; HYDRO_EINVAL otherwise
  *   hydro_get_level_variant  current selection for a dtype and form
