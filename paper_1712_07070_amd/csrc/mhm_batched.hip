@@ -37,7 +37,7 @@ __device__ __forceinline__ double uniform(double v) {
 //
 // The ticket for the next item is taken when an item starts and decoded when
 // it ends, so the atomic's round trip overlaps the whole group step.
-template <typename T, int kWaves>
+template <typename T, int kWaves, typename Off>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_batched_kernel(
     BatchArgs<T> args, Gas<T> gas, int first_order, int ws, int* __restrict__ n_bad,
     unsigned int* __restrict__ work, int order, int queues) {
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     gl.half_dtdx = uniform(lv_half_dtdx[l]);
     const LevelGeom& geo = L.geo;
     const unsigned int gu = unsigned(g), nx = unsigned(geo.ngx), ny = unsigned(geo.ngy);
-    LevelSource<T> src{L.in, geo, int(gu % nx), int((gu / nx) % ny), int(gu / nx / ny)};
+    LevelSource<T, Off> src{L.in, geo, int(gu % nx), int((gu / nx) % ny), int(gu / nx / ny)};
     // an opaque thread index per item keeps thread-derived addresses from
     // being hoisted out of the item loop (they would stay live across the
     // whole group step and cost registers / occupancy)
@@ -141,12 +141,27 @@ hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int f
                               unsigned int* work, int variant, int grid, hipStream_t stream) {
   if (args.total == 0) return hipSuccess;
   const int order = variant & 1, queues = (variant >> 2) & 3;
-  if (variant & 2)
-    hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo>), dim3(unsigned(grid)), dim3(kThreads), 0, stream,
-                       args, gas, first_order, ws, n_bad, work, order, queues);
-  else
-    hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi>), dim3(unsigned(grid)), dim3(kThreads), 0, stream,
-                       args, gas, first_order, ws, n_bad, work, order, queues);
+  // 32-bit element offsets when every level's elements have one
+  bool small = true;
+  for (int l = 0; l < args.n_levels; ++l) {
+    const LevelGeom& g = args.lv[l].geo;
+    small = small && int64_t(g.ngx) * g.ngy * g.ngz * 5 * 4096 <= int64_t(0xffffffffu);
+  }
+  if (small) {
+    if (variant & 2)
+      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo, unsigned int>), dim3(unsigned(grid)), dim3(kThreads),
+                         0, stream, args, gas, first_order, ws, n_bad, work, order, queues);
+    else
+      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi, unsigned int>), dim3(unsigned(grid)), dim3(kThreads),
+                         0, stream, args, gas, first_order, ws, n_bad, work, order, queues);
+  } else {
+    if (variant & 2)
+      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo, int64_t>), dim3(unsigned(grid)), dim3(kThreads), 0,
+                         stream, args, gas, first_order, ws, n_bad, work, order, queues);
+    else
+      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi, int64_t>), dim3(unsigned(grid)), dim3(kThreads), 0,
+                         stream, args, gas, first_order, ws, n_bad, work, order, queues);
+  }
   return hipGetLastError();
 }
 

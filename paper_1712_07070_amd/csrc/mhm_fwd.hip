@@ -68,7 +68,7 @@ __device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t G) {
   return g;
 }
 
-template <typename T, bool kCfl, int kWaves>
+template <typename T, bool kCfl, int kWaves, typename Off>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_level_kernel(const T* __restrict__ level, T* __restrict__ level_out,
                                                              LevelGeom geo, Gas<T> gas,
                                                              const double* __restrict__ dt_dev, double dx,
@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   const int64_t g = xcd_order ? xcd_group(blockIdx.x, G) : int64_t(blockIdx.x);
   if (g >= G) return;  // whole workgroup leaves together (g is uniform)
-  LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
+  LevelSource<T, Off> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy),
+                          int(g / (int64_t(geo.ngx) * geo.ngy))};
   __shared__ double cfl_slots[kCfl ? 2 * kCflHalfStride : 1];
   double* smax = nullptr;
   if (kCfl) {
@@ -95,6 +96,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     cfl_epilogue(cfl_slots, cfl.c_cfl_dx, cfl.dt_patch != nullptr ? cfl.dt_patch + g * 8 : nullptr, cfl.dt_min);
 }
 
+template <typename T, bool kCfl, typename Off>
+void launch_level_shape(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
+                        const double* dt_dev, double dx, int first_order, int ws, int* n_bad, const CflOut& cfl,
+                        int variant, int64_t blocks, int xcd, hipStream_t stream) {
+  if (variant & 2)
+    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::lo, Off>), dim3(unsigned(blocks)), dim3(kThreads), 0,
+                       stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, xcd);
+  else
+    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::hi, Off>), dim3(unsigned(blocks)), dim3(kThreads), 0,
+                       stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, xcd);
+}
+
 template <typename T, bool kCfl>
 hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
                                 const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
@@ -102,12 +115,13 @@ hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& g
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   const int xcd = (variant & 1) ? 0 : 1;
   const int64_t blocks = xcd ? ((G + 7) / 8) * 8 : G;
-  if (variant & 2)
-    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::lo>), dim3(unsigned(blocks)), dim3(kThreads), 0,
-                       stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, xcd);
+  // 32-bit element offsets when every element of the level has one
+  if (G * 5 * 4096 <= int64_t(0xffffffffu))
+    launch_level_shape<T, kCfl, unsigned int>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl,
+                                              variant, blocks, xcd, stream);
   else
-    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::hi>), dim3(unsigned(blocks)), dim3(kThreads), 0,
-                       stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, xcd);
+    launch_level_shape<T, kCfl, int64_t>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl,
+                                         variant, blocks, xcd, stream);
   return hipGetLastError();
 }
 

@@ -114,6 +114,34 @@ def white_noise(n: int = 64, config_id: int = 1, gamma: float = 5.0 / 3.0) -> Le
     return Level(U, (n // N,) * 3, 1.0 / n, gamma, meta={"name": "white-noise", "n": n})
 
 
+def white_noise_device(ng: Tuple[int, int, int], dtype, device, config_id: int = 1, gamma: float = 5.0 / 3.0,
+                       chunk: int = 4096):
+    """Workload 1's white-noise recipe on an (NGx, NGy, NGz) lattice of any
+    size, generated directly in device memory in level storage (a torch
+    tensor [G, 5, 16, 16, 16] of `dtype`): for levels too large to build on
+    the host.  Seeded with torch's device generator (SEED_BASE + config_id);
+    the groups are drawn chunk by chunk, so the values depend on `chunk`."""
+    import torch
+
+    G = int(ng[0]) * int(ng[1]) * int(ng[2])
+    U = torch.empty((G, 5, N, N, N), dtype=dtype, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + config_id)
+    for g0 in range(0, G, chunk):
+        n = min(chunk, G - g0)
+        shape = (n, N, N, N)
+        rho = torch.rand(shape, generator=gen, device=device, dtype=torch.float32) * 1.5 + 0.5
+        v = [torch.randn(shape, generator=gen, device=device, dtype=torch.float32) * 0.3 for _ in range(3)]
+        p = torch.rand(shape, generator=gen, device=device, dtype=torch.float32) * 1.5 + 0.5
+        E = p / (gamma - 1.0) + 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2])
+        blk = U[g0:g0 + n]
+        blk[:, 0] = rho
+        for i in range(3):
+            blk[:, 1 + i] = rho * v[i]
+        blk[:, 4] = E
+    return U
+
+
 def sod_tube(n: int = 128, gamma: float = 5.0 / 3.0, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1),
              axis: int = 0) -> Level:
     """Sod tube along `axis` (n cells, x in [0, 1], interface at 0.5), 16 cells across.

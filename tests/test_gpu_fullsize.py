@@ -122,3 +122,43 @@ def test_smooth_wave_128_adjoint_full_size(hydro):
                                            dt, lv.dx, lv.gamma))
     lhs, rhs = float(np.sum(Jv * w)), float(np.sum(v * JTw))
     assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+
+
+def _neighbourhood(U, ng, g):
+    """The 3x3x3 groups around group g of a device level (periodic wrap),
+    copied to the host as a 3x3x3 level whose centre is group g."""
+    ngx, ngy, ngz = ng
+    gx, gy, gz = g % ngx, (g // ngx) % ngy, g // (ngx * ngy)
+    idx = [(((gz + dz) % ngz) * ngy + (gy + dy) % ngy) * ngx + (gx + dxx) % ngx
+           for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dxx in (-1, 0, 1)]
+    return host(U[torch.tensor(idx, device=U.device)]).astype(np.float64)
+
+
+def test_level_beyond_32bit_offsets_fp32(hydro):
+    """A level of more than 2^32 elements (64 x 64 x 52 groups, FP32, 17.4 GB
+    per copy) runs the kernels with 64-bit element offsets: sampled groups,
+    the last ones of the level included, against the oracle on their 3x3x3
+    neighbourhoods (the centre group's ghost cells all lie inside it), their
+    patch time-steps bit for bit, and the batched kernel bit for bit against
+    the level step."""
+    ng, bc = (64, 64, 52), (0, 0, 0, 0, 0, 0)
+    G = ng[0] * ng[1] * ng[2]
+    assert G * 5 * 4096 > 2 ** 32
+    say("level beyond 32-bit offsets", G)
+    U = W.white_noise_device(ng, torch.float32, "cuda")
+    dx, gamma, dt = 1.0 / 1024, 5.0 / 3.0, 1e-5
+    dt_next = torch.full((1,), float("inf"), dtype=torch.float64, device="cuda")
+    dt_patch = torch.empty(8 * G, dtype=torch.float64, device="cuda")
+    out = hydro.advance_level(U, ng, bc, dt, dx, gamma, c_cfl=0.5, dt_next=dt_next, dt_patch_next=dt_patch)
+    for g in (0, G // 2 + 17, G - ng[0] * ng[1] - 1, G - 2, G - 1):
+        pad = oracle.fill_ghosts(_neighbourhood(U, ng, g), (3, 3, 3), 3, bc)[13:14]
+        ref, _ = oracle.mhm_step(pad, dt, dx, gamma)
+        assert field_scale_error(host(out[g:g + 1]), ref) <= TOL[np.float32], g
+        opad = oracle.fill_ghosts(_neighbourhood(out, ng, g), (3, 3, 3), 3, bc)[13:14]
+        np.testing.assert_array_equal(host(dt_patch[8 * g:8 * g + 8]), oracle.dt_patch(opad, dx, gamma)[0])
+    del dt_patch
+    work = torch.zeros(hydro.BATCH_WORK_WORDS, dtype=torch.int32, device="cuda")
+    out2 = torch.empty_like(U)
+    hydro.advance_batched([(U, out2, ng, bc, dt, dx)], gamma, work)
+    assert torch.equal(out2, out)
+    assert not host(work).any()
