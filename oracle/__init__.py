@@ -74,6 +74,7 @@ def _load():
         "oracle_exact_sample": (i32, [f64] * 7 + [P, i64, P, P, P]),
         "oracle_exact_residual": (f64, [f64] * 8),
         "oracle_count_ops": (None, [P, P, P, P, P, P, f64, f64, f64, P]),
+        "oracle_rollout_box": (i64, [P, P, P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32, P]),
         "oracle_num_threads": (i32, []),
         "oracle_set_num_threads": (None, [i32]),
     }
@@ -189,6 +190,32 @@ def rollout_jvp(level, tangent, ng, ghost, bc, n_steps, dt, dx, gamma, theta=1.5
     return out, tout, int(n_bad)
 
 
+def rollout_box(box, n_steps, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC, tangent=None,
+                signature=False):
+    """n_steps MHM steps of one box [5, nz, ny, nx] without ghost refills: each
+    step drops a 2-cell margin, so the result is [5, nz-4n, ny-4n, nx-4n], the
+    cells the box alone determines.  tangent: optional dual-number tangent of
+    the box.  Returns (out, tangent_out or None, n_bad, signature or None),
+    signature being the hash of every branch decision taken (limiter one-sign
+    tests, |.| signs, min/max arguments, HLLC branches) in evaluation order."""
+    b = _f64(box)
+    assert b.ndim == 4 and b.shape[0] == 5
+    nz, ny, nx = b.shape[1:]
+    m = [s - 4 * n_steps for s in (nz, ny, nx)]
+    if min(m) < 1:
+        raise ValueError("box too small for %d steps" % n_steps)
+    out = np.empty([5] + m, np.float64)
+    t = None if tangent is None else _f64(tangent)
+    tout = None if t is None else np.empty_like(out)
+    sig = np.zeros(1, np.uint64)
+    nb = _load().oracle_rollout_box(_p(b), None if t is None else _p(t), _p(out), None if t is None else _p(tout),
+                                    nx, ny, nz, n_steps, dt, dx, gamma, theta, scheme,
+                                    _p(sig) if signature else None)
+    if nb < 0:
+        raise ValueError("oracle_rollout_box: bad arguments")
+    return out, tout, int(nb), (int(sig[0]) if signature else None)
+
+
 # ------------------------------------------------------------ component API --
 
 def hllc(UL, UR, d, gamma, wavespeed=0):
@@ -259,5 +286,5 @@ def count_ops(U, Wc, Wm, Wp, UL, UR, gamma, theta, half_dtdx):
     args = [_f64(a) for a in (U, Wc, Wm, Wp, UL, UR)]
     ops = np.zeros(16, np.int64)
     _load().oracle_count_ops(*[_p(a) for a in args], gamma, theta, half_dtdx, _p(ops))
-    names = ("cons_to_prim", "hancock_cell", "hllc_flux", "update")
+    names = ("cons_to_prim", "hancock_cell", "hllc_flux", "update")  # hllc_flux: the branch UL, UR select
     return {n: dict(zip(("add", "mul", "div", "sqrt"), ops[4 * i:4 * i + 4].tolist())) for i, n in enumerate(names)}

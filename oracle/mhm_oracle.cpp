@@ -87,13 +87,40 @@ inline double val(Cnt a) { return a.v; }
 inline double tsqrt(double a) { return std::sqrt(a); }
 inline double val(double a) { return a; }
 
+// ------------------------------------------------------ branch record ----
+// When switched on for the calling thread, every branch decision of the step
+// (the limiter's one-sign test, the sign of each |.|, which argument a
+// min / max keeps, the HLLC branch) is folded, in evaluation order, into a
+// 64-bit FNV-1a hash.  Two evaluations of the same cells take the same
+// branches everywhere iff (up to hash collisions) their hashes agree; this is
+// what a central difference needs to know (both sides on one smooth piece).
+// Recording reads the decision only: the arithmetic is the same on or off.
+thread_local bool g_sig_on = false;
+thread_local uint64_t g_sig = 0;
+inline void sig_mix(uint64_t code) {
+  if (!g_sig_on) return;
+  g_sig = (g_sig ^ code) * 0x100000001b3ull;
+}
+
 // |x| with derivative sign(x) * dx (never evaluated at x == 0 on a path whose
 // derivative matters: the limiter only takes |.| of strictly signed values).
-template <class T> inline T tabs(T x) { return val(x) < 0.0 ? -x : x; }
+template <class T> inline T tabs(T x) {
+  const bool neg = val(x) < 0.0;
+  sig_mix(neg ? 3 : 4);
+  return neg ? -x : x;
+}
 
 // min / max that keep the FIRST argument on ties (value and derivative).
-template <class T> inline T tmin(T a, T b) { return val(b) < val(a) ? b : a; }
-template <class T> inline T tmax(T a, T b) { return val(b) > val(a) ? b : a; }
+template <class T> inline T tmin(T a, T b) {
+  const bool second = val(b) < val(a);
+  sig_mix(second ? 5 : 6);
+  return second ? b : a;
+}
+template <class T> inline T tmax(T a, T b) {
+  const bool second = val(b) > val(a);
+  sig_mix(second ? 7 : 8);
+  return second ? b : a;
+}
 
 // ------------------------------------------------------------ scheme word --
 constexpr int SCHEME_ID_MASK = 0xff;
@@ -168,11 +195,13 @@ template <class T>
 T limited_slope(T qm, T q0, T qp, double theta) {
   const T dm = q0 - qm, dp = qp - q0;
   const bool same_sign = (val(dm) > 0.0 && val(dp) > 0.0) || (val(dm) < 0.0 && val(dp) < 0.0);
+  sig_mix(same_sign ? 1 : 2);
   if (!same_sign) return T(0.0);
   const T dc = T(0.5) * (qp - qm);
   T m = T(theta) * tabs(dm);
   m = tmin(m, tabs(dc));
   m = tmin(m, T(theta) * tabs(dp));
+  sig_mix(val(dc) > 0.0 ? 9 : 10);
   return val(dc) > 0.0 ? m : -m;
 }
 
@@ -272,6 +301,7 @@ bool hllc_flux(const T UL[5], const T UR[5], int d, double gamma, int wavespeed,
   const T FR[5] = {R[1], R[1] * uR + pR, R[2] * uR, R[3] * uR, (R[4] + pR) * uR};
 
   T Fn[5];
+  sig_mix(val(SL) >= 0.0 ? 11 : val(Sst) >= 0.0 ? 12 : val(SR) > 0.0 ? 13 : 14);
   if (val(SL) >= 0.0) {
     for (int q = 0; q < 5; ++q) Fn[q] = FL[q];
   } else if (val(Sst) >= 0.0) {
@@ -570,6 +600,31 @@ void sample(const RP& s, double ps, double us, double xi, double* r, double* u, 
   }
 }
 
+// n_steps MHM steps of one block without ghost refills: a step advances the
+// box's interior and drops its 2-cell margin, so the box shrinks by 4 cells
+// per axis and step, and after n steps it holds exactly the cells whose
+// values the n steps determine from the box alone.  This gives a rollout's
+// result on a sub-box of a level (a periodic level's box taken with wrapped
+// indices), with the branch record of every decision made on the way.
+// box [5][nz][ny][nx] (double), tbox (optional) its tangent (dual numbers);
+// out / tout [5][nz-4n][ny-4n][nx-4n]; *sig_out (optional) the branch hash.
+template <class T>
+int64_t rollout_box(std::vector<T> cur, int nx, int ny, int nz, int n_steps, double dt, double dx, double gamma,
+                    double theta, int scheme, std::vector<T>& result) {
+  int64_t n_bad = 0;
+  for (int s = 0; s < n_steps; ++s) {
+    const Block b(nx - 4, ny - 4, nz - 4, 2);
+    std::vector<T> nxt(size_t(5) * b.nx * b.ny * b.nz);
+    n_bad += mhm_step_block(cur.data(), nxt.data(), b, dt, dx, gamma, theta, scheme);
+    cur.swap(nxt);
+    nx -= 4;
+    ny -= 4;
+    nz -= 4;
+  }
+  result.swap(cur);
+  return n_bad;
+}
+
 }  // namespace
 
 // =================================================================== C ABI ==
@@ -753,6 +808,36 @@ double oracle_exact_residual(double rL, double uL, double pL, double rR, double 
   pressure_fn(p, rL, pL, gamma, &fL, &dfL);
   pressure_fn(p, rR, pR, gamma, &fR, &dfR);
   return fL + fR + (uR - uL);
+}
+
+// Box rollout (see rollout_box above); returns the unphysical count or -1.
+int64_t oracle_rollout_box(const double* box, const double* tbox, double* out, double* tout, int nx, int ny, int nz,
+                           int n_steps, double dt, double dx, double gamma, double theta, int scheme,
+                           uint64_t* sig_out) {
+  if (n_steps < 0 || nx - 4 * n_steps < 1 || ny - 4 * n_steps < 1 || nz - 4 * n_steps < 1 ||
+      (scheme & SCHEME_ID_MASK) != SCHEME_MHM_PLM_HLLC)
+    return -1;
+  const size_t n = size_t(5) * nx * ny * nz;
+  const size_t m = size_t(5) * (nx - 4 * n_steps) * (ny - 4 * n_steps) * (nz - 4 * n_steps);
+  g_sig_on = sig_out != nullptr;
+  g_sig = 0xcbf29ce484222325ull;
+  int64_t n_bad;
+  if (tbox == nullptr) {
+    std::vector<double> res;
+    n_bad = rollout_box(std::vector<double>(box, box + n), nx, ny, nz, n_steps, dt, dx, gamma, theta, scheme, res);
+    std::memcpy(out, res.data(), sizeof(double) * m);
+  } else {
+    std::vector<Dual> in(n), res;
+    for (size_t i = 0; i < n; ++i) in[i] = Dual(box[i], tbox[i]);
+    n_bad = rollout_box(std::move(in), nx, ny, nz, n_steps, dt, dx, gamma, theta, scheme, res);
+    for (size_t i = 0; i < m; ++i) {
+      out[i] = res[i].v;
+      if (tout != nullptr) tout[i] = res[i].d;
+    }
+  }
+  if (sig_out != nullptr) *sig_out = g_sig;
+  g_sig_on = false;
+  return n_bad;
 }
 
 // Algorithmic operation counts of the four per-item stages, each evaluated on

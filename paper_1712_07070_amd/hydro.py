@@ -192,6 +192,12 @@ def adjoint_workspace(n_groups: int, dtype, level: bool, device=None) -> torch.T
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
 
+def _check_work(work: Optional[torch.Tensor]) -> None:
+    # the byte size is checked by the library against hydro_adjoint_workspace_bytes
+    if work is not None and (work.dtype != torch.uint8 or work.dim() != 1):
+        raise ValueError("work must be a 1-D uint8 tensor (adjoint_workspace)")
+
+
 def advance_adjoint(U_pad: torch.Tensor, gU_out: torch.Tensor, dt: float, dx: float, gamma: float,
                     theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, out: Optional[torch.Tensor] = None,
                     work: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -200,6 +206,9 @@ def advance_adjoint(U_pad: torch.Tensor, gU_out: torch.Tensor, dt: float, dx: fl
     G = U_pad.shape[0]
     if gU_out.dtype != U_pad.dtype or tuple(gU_out.shape) != (G, 5, 16, 16, 16):
         raise ValueError("gU_out must be [G,5,16,16,16] of the state dtype")
+    if out is not None and (out.dtype != U_pad.dtype or out.shape != U_pad.shape):
+        raise ValueError("out must be [G,5,P,P,P] of the state dtype")
+    _check_work(work)
     if out is None:
         out = torch.empty_like(U_pad)
     if work is None:
@@ -220,6 +229,9 @@ def advance_level_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence
     G = ngx * ngy * ngz
     if tuple(level.shape) != (G, 5, 16, 16, 16) or g_out.shape != level.shape or g_out.dtype != level.dtype:
         raise ValueError("level and g_out must be [G,5,16,16,16] of one dtype")
+    if out is not None and (out.dtype != level.dtype or out.shape != level.shape):
+        raise ValueError("out must be [G,5,16,16,16] of the level dtype")
+    _check_work(work)
     if out is None:
         out = torch.empty_like(level)
     if work is None:
@@ -242,6 +254,9 @@ def autotune_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence[int]
     G = ngx * ngy * ngz
     if tuple(level.shape) != (G, 5, 16, 16, 16) or g_out.shape != level.shape or g_out.dtype != level.dtype:
         raise ValueError("level and g_out must be [G,5,16,16,16] of one dtype")
+    if out is not None and (out.dtype != level.dtype or out.shape != level.shape):
+        raise ValueError("out must be [G,5,16,16,16] of the level dtype")
+    _check_work(work)
     if out is None:
         out = torch.empty_like(level)
     if work is None:
@@ -664,7 +679,8 @@ class Rollout(torch.autograd.Function):
         ng, bc = tuple(int(v) for v in ng), tuple(int(v) for v in bc)
         k = max(1, int(k_ckpt))
         ckpts = []
-        cur = U0.detach().contiguous()
+        # private ping-pong buffers: the caller's U0 is never written
+        cur = U0.detach().contiguous().clone()
         nxt = torch.empty_like(cur)
         for n in range(int(n_steps)):
             if n % k == 0:

@@ -265,3 +265,144 @@ def test_rollout_gradient_central_differences(hydro):
         errs.append(abs(f2 - grad[idx]) / max(abs(f2), 1e-8))
     assert accepted >= 24, accepted
     assert max(errs) <= 1e-6, max(errs)
+
+
+def test_rollout_leaves_its_input_unchanged(hydro):
+    """The rollout steps through private buffers: the caller's initial state is
+    bitwise unchanged after forward and backward, for any checkpoint interval."""
+    say("rollout input untouched")
+    U0, ng, dx = smooth_all_fields(32)
+    for k in (1, 3):
+        x = dev(U0).requires_grad_(True)
+        keep = x.detach().clone()
+        out = hydro.Rollout.apply(x, ng, (0,) * 6, 4, 0.2 * dx, dx, G53, k)
+        out.sum().backward()
+        assert torch.equal(x.detach(), keep), k
+
+
+def _box_around(grid, c, R):
+    x, y, z = c
+    nz, ny, nx = grid.shape[1:]
+    iz = np.arange(z - R, z + R + 1) % nz
+    iy = np.arange(y - R, y + R + 1) % ny
+    ix = np.arange(x - R, x + R + 1) % nx
+    return grid[:, iz][:, :, iy][:, :, :, ix]
+
+
+def _fd_branch_protocol(hydro, lv, target, n_steps, draws, eps=1e-7, seed=20171223):
+    """Central differences of L = sum (rho_N - rho_target)^2 at sampled
+    (cell, field) entries against the adjoint gradient, eps = 1e-7.  A draw is
+    rejected when the oracle's +eps and -eps rollouts of the perturbation's
+    cone (a periodic box of radius 4 n around the cell, which determines every
+    value the perturbation can reach) take different branches anywhere;
+    returns (rejected, list of relative errors of the accepted draws)."""
+    from concurrent.futures import ThreadPoolExecutor
+    U0 = lv.U
+    dt = 0.2 * lv.dx
+    tgt = dev(target)
+    x = dev(U0).requires_grad_(True)
+    out = hydro.Rollout.apply(x, lv.ng, lv.bc, n_steps, dt, lv.dx, lv.gamma, 4)
+    ((out[:, 0] - tgt) ** 2).sum().backward()
+    grad = host(x.grad)
+    grid = W.groups_to_grid(U0, lv.ng)
+    R = 4 * n_steps
+    rng = np.random.default_rng(seed)
+    picks = [(int(rng.integers(0, 5)), tuple(int(v) for v in rng.integers(0, grid.shape[1], 3)))
+             for _ in range(draws)]
+
+    def signatures(pick):
+        f, c = pick
+        box = _box_around(grid, c, R)
+        sig = []
+        for s in (1.0, -1.0):
+            b = box.copy()
+            b[f, R, R, R] += s * eps
+            sig.append(oracle.rollout_box(b, n_steps, dt, lv.dx, lv.gamma, signature=True)[3])
+        return sig[0] != sig[1]
+
+    with ThreadPoolExecutor(8) as ex:
+        differ = list(ex.map(signatures, picks))
+
+    def resid(U):
+        o = hydro.Rollout.apply(dev(U), lv.ng, lv.bc, n_steps, dt, lv.dx, lv.gamma, n_steps)
+        return o[:, 0] - tgt
+
+    errs, rejected = [], 0
+    for (f, c), d in zip(picks, differ):
+        if d:
+            rejected += 1
+            continue
+        gx, gy, gz = c[0] // 16, c[1] // 16, c[2] // 16
+        g = (gz * lv.ng[1] + gy) * lv.ng[0] + gx
+        idx = (g, f, c[2] % 16, c[1] % 16, c[0] % 16)
+        up, um = U0.copy(), U0.copy()
+        up[idx] += eps
+        um[idx] -= eps
+        rp, rm = resid(up), resid(um)
+        fd = float(((rp - rm) * (rp + rm)).sum()) / (2 * eps)
+        errs.append(abs(fd - grad[idx]) / max(abs(fd), abs(grad[idx]), 1e-300))
+    return rejected, errs
+
+
+def test_rollout_fd_branch_protocol_workload_as_stated(hydro):
+    """The differentiation workload's recipe (uniform v and p) on a 64^3 grid,
+    8 steps: draws whose +-eps runs branch differently are rejected (on this
+    state nearly all: its velocity and pressure slopes are round-off on the
+    limiter's kink), and every accepted draw agrees to 1e-6."""
+    say("rollout fd branch protocol, as stated")
+    lv, target = W.smooth_wave(64)
+    rejected, errs = _fd_branch_protocol(hydro, lv, target, 8, 24)
+    say("  rejected %d of 24, accepted errors %s" % (rejected, ["%.1e" % e for e in errs]))
+    assert rejected >= 1
+    assert all(e <= 1e-6 for e in errs), errs
+
+
+def test_rollout_fd_branch_protocol_smooth_v_and_p(hydro):
+    say("rollout fd branch protocol, smooth v and p")
+    lv, target = W.smooth_wave(64, smooth_vp=0.01)
+    rejected, errs = _fd_branch_protocol(hydro, lv, target, 8, 24)
+    say("  rejected %d of 24, max error %.2e" % (rejected, max(errs) if errs else float("nan")))
+    assert len(errs) >= 16
+    assert max(errs) <= 1e-6, errs
+
+
+def test_fp32_level_adjoint_turbulence_384_sampled(hydro):
+    """The FP32 level adjoint at the turbulence workload's full size (384^3,
+    13,824 groups): sampled entries of J^T w against <J e, w> from the
+    oracle's dual-number JVP of a unit tangent e on the FP32-rounded state
+    (one step, on the radius-4 box that determines the radius-2 cone of e).
+    Tolerance 1e-4 of the field's scale (the largest |entry| of that field
+    among the samples; momentum on one scale): each entry sums ~600 terms whose
+    FP32 rounding (6e-8 each) compounds through the predictor, HLLC and update
+    chains.  An entry whose evaluation passes within FP32 rounding of a branch
+    switch (which the FP64 oracle may resolve the other way) would differ at
+    O(1); none may occur among the samples for the test to pass."""
+    say("fullsize fp32 adjoint 384^3")
+    lv = W.turbulence(384).astype(np.float32)
+    U = dev(lv.U)
+    dt = float(hydro.cfl_dt(U, lv.dx, lv.gamma, 0.5).min())
+    rng = np.random.default_rng(8)
+    w = rng.normal(size=lv.U.shape).astype(np.float32)
+    JTw = host(hydro.advance_level_adjoint(U, dev(w), lv.ng, lv.bc, dt, lv.dx, lv.gamma))
+    del U
+    torch.cuda.empty_cache()
+    grid = W.groups_to_grid(lv.U.astype(np.float64), lv.ng)
+    wgrid = W.groups_to_grid(w.astype(np.float64), lv.ng)
+    gT = W.groups_to_grid(JTw.astype(np.float64), lv.ng)
+    N = grid.shape[1]
+    picks = [(int(rng.integers(0, 5)), tuple(int(v) for v in rng.integers(0, N, 3))) for _ in range(60)]
+    got, ref = [], []
+    for f, c in picks:
+        box = _box_around(grid, c, 4)
+        t = np.zeros_like(box)
+        t[f, 4, 4, 4] = 1.0
+        _, tout, _, _ = oracle.rollout_box(box, 1, dt, lv.dx, lv.gamma, tangent=t)
+        ref.append(float(np.sum(tout * _box_around(wgrid, c, 2))))
+        got.append(float(gT[(f, c[2], c[1], c[0])]))
+    got, ref = np.array(got), np.array(ref)
+    fields = np.array([f for f, _ in picks])
+    scale = np.array([np.abs(ref[fields == f]).max() if np.any(fields == f) else 1.0 for f in range(5)])
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - ref) / (np.abs(ref) + scale[fields])
+    say("  max scaled error %.2e, median %.2e" % (err.max(), np.median(err)))
+    assert err.max() <= 1e-4, err.max()

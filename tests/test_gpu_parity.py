@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_1712_07070_amd import workloads as W
-from tests.oracle_runs import field_scale_error
+from tests.oracle_runs import assert_parity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -110,7 +110,7 @@ def test_advance_white_noise(hydro, dtype, case):
     dt = cfl_dt_of(lv)
     got, ref, nb, nb_ref = run_step(hydro, lv, dtype, dt, **CASES[case])
     assert nb == nb_ref == 0
-    assert field_scale_error(got, ref) <= TOL[dtype]
+    assert_parity(got, ref, TOL[dtype])
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -120,7 +120,7 @@ def test_advance_sod_tube(hydro, dtype, axis):
     lv = W.sod_tube(128, axis=axis)
     got, ref, nb, nb_ref = run_step(hydro, lv, dtype, cfl_dt_of(lv))
     assert nb == nb_ref == 0
-    assert field_scale_error(got, ref) <= TOL[dtype]
+    assert_parity(got, ref, TOL[dtype])
 
 
 def test_advance_hllc_branches(hydro):
@@ -139,7 +139,7 @@ def test_advance_hllc_branches(hydro):
     lv = W.Level(W.grid_to_groups(W.conserved(rho, vx, vy, vz, p, 5 / 3)), (2, 2, 2), 1 / n, 5 / 3)
     got, ref, nb, nb_ref = run_step(hydro, lv, np.float64, 0.3 * cfl_dt_of(lv))
     assert nb == nb_ref
-    assert field_scale_error(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -160,7 +160,7 @@ def test_zero_and_single_group(hydro):
     assert hydro.advance(empty, 1e-3, 0.1, 1.4).shape == (0, 5, 16, 16, 16)
     lv = W.white_noise(16)
     got, ref, nb, nb_ref = run_step(hydro, lv, np.float64, cfl_dt_of(lv))
-    assert field_scale_error(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12)
 
 
 def test_dt_from_device_memory(hydro):
@@ -250,7 +250,7 @@ def test_rollout_matches_oracle(hydro, dtype, fused):
         solver.step()
         got_dts.append(float(host(solver.dt_min)[0]))
     np.testing.assert_allclose(got_dts, dts, rtol=1e-13 if dtype == np.float64 else 1e-5)
-    assert field_scale_error(host(solver.state), ref) <= (1e-12 if dtype == np.float64 else 2e-5)
+    assert_parity(host(solver.state), ref, (1e-12 if dtype == np.float64 else 2e-5))
 
 
 # ------------------------------------------------------ fused level step ---
@@ -284,7 +284,7 @@ def test_level_step_equals_fill_then_advance(hydro, dtype, case):
     b = hydro.advance_level(t, ng, bc, 1e-3, dx, 5 / 3, n_bad=nb)
     assert torch.equal(a, b)
     ref, nb_ref = oracle.mhm_step(oracle.fill_ghosts(U.astype(np.float64), ng, 3, bc), 1e-3, dx, 5 / 3)
-    assert field_scale_error(host(b), ref) <= TOL[dtype]
+    assert_parity(host(b), ref, TOL[dtype])
     assert int(host(nb)[0]) == nb_ref == 0
 
 
@@ -313,7 +313,7 @@ def test_level_and_batched_scheme_options(hydro, scheme):
     hydro.advance_batched([(t, c, ng, bc, 1e-3, dx)], 5 / 3, work, 1.5, scheme)
     assert torch.equal(a, c)
     ref, _ = oracle.mhm_step(oracle.fill_ghosts(U, ng, 3, bc), 1e-3, dx, 5 / 3, 1.5, scheme)
-    assert field_scale_error(host(b), ref) <= TOL[np.float64]
+    assert_parity(host(b), ref, TOL[np.float64])
     # the options change the result
     d = hydro.advance_level(t, ng, bc, 1e-3, dx, 5 / 3)
     assert not torch.equal(b, d)
@@ -386,7 +386,7 @@ def test_level_sod_rollout_outflow(hydro):
         solver.step()
         got_dts.append(float(host(solver.dt_min)[0]))
     np.testing.assert_allclose(got_dts, dts, rtol=1e-13)
-    assert field_scale_error(host(solver.state), ref) <= 1e-12
+    assert_parity(host(solver.state), ref, 1e-12)
     assert int(host(solver.n_bad)[0]) == nb == 0
 
 
@@ -413,7 +413,7 @@ def test_shear_layer_256_sampled(hydro, dtype):
                                        lv.gamma).min())
     ref, _ = oracle.mhm_step(opad, dt, lv.dx, lv.gamma)
     got = host(out)[sample]
-    assert field_scale_error(got, ref) <= TOL[dtype]
+    assert_parity(got, ref, TOL[dtype])
 
 
 # ------------------------------------------------------- launch shapes -----
@@ -499,7 +499,7 @@ def test_batched_equals_per_level(hydro, dtype, lattice):
     for l, (lv, r) in enumerate(zip(lvs, ref)):
         o, _ = oracle.mhm_step(oracle.fill_ghosts(lv.U.astype(np.float64), lv.ng, 3, lv.bc), dt0 / 2 ** l, lv.dx,
                                lv.gamma)
-        assert field_scale_error(host(r), o) <= TOL[dtype]
+        assert_parity(host(r), o, TOL[dtype])
 
 
 def test_batched_small_grid_and_uneven_items(hydro):
@@ -602,4 +602,4 @@ def test_sedov_levels_mirror_symmetric(hydro):
     for ax in (1, 2, 3):          # z, y, x axes of the grid
         m = np.flip(grid, axis=ax).copy()
         m[4 - ax] *= -1           # the momentum along that axis changes sign
-        assert field_scale_error(m, grid) <= 1e-12
+        assert_parity(m, grid, 1e-12)
