@@ -39,8 +39,18 @@
  * Every call is asynchronous on it; argument errors are reported
  * synchronously by the return value and nothing is launched.
  *
- * Status: HYDRO_OK (0) or a negative error code; hydro_strerror() names it.
- * HYDRO_EDEVICE means a HIP call failed; hydro_last_hip_error() returns it.
+ * Status: HYDRO_OK (0), HYDRO_UNPHYSICAL (1, only from hydro_check_unphysical),
+ * or a negative error code; hydro_strerror() names it.  HYDRO_EDEVICE means a
+ * HIP call failed; hydro_last_hip_error() returns it.
+ *
+ * Context: the entry points whose kernels come in several launch shapes
+ * (level step, batched step, adjoint) take a hydro_ctx* first.  The context
+ * holds the caller's shape selections (set explicitly or autotuned, the
+ * latter keyed by dtype and level lattice), optionally loaded from and saved
+ * to a tuning-cache JSON file, and the graphs captured through it; two
+ * contexts in one process never see each other's selections.  NULL selects
+ * the measured defaults.  A context is used by one thread at a time for
+ * tuning; launches through one context from several threads are safe.
  *
  * Determinism: for the same inputs, arguments and device the outputs are
  * bitwise identical from run to run (no floating-point atomics).
@@ -55,8 +65,14 @@ extern "C" {
 #endif
 
 #define HYDRO_OK 0
-#define HYDRO_EINVAL (-1)   /* bad shape, ghost, dtype, null pointer, aliasing, dt/dx/gamma/theta */
-#define HYDRO_EDEVICE (-2)  /* a HIP runtime call failed */
+#define HYDRO_UNPHYSICAL 1   /* hydro_check_unphysical: >= 1 unphysical item was counted */
+#define HYDRO_EINVAL (-1)    /* bad shape, ghost, dtype, null pointer, aliasing, dt/dx/gamma/theta */
+#define HYDRO_EDEVICE (-2)   /* a HIP runtime call failed */
+#define HYDRO_ENOTUNED (-3)  /* the context requires a tuned shape and has none for this call */
+#define HYDRO_EIO (-4)       /* tuning cache unreadable, malformed or not writable */
+
+/* Opaque solver context (launch-shape selections, tuning cache, graphs). */
+typedef struct hydro_ctx hydro_ctx;
 
 #define HYDRO_F64 0
 #define HYDRO_F32 1
@@ -68,6 +84,36 @@ extern "C" {
 
 #define HYDRO_BC_PERIODIC 0
 #define HYDRO_BC_OUTFLOW 1
+
+/* Context (the solver's launch configuration, Sec. 3.1: the GPU solver is
+ * configured once and then advances patch groups call after call).
+ *   hydro_ctx_create    *ctx receives a new context.  tune_cache_json_path
+ *                       (host string, may be NULL): a file of tuned shapes,
+ *                       {"version": 1, "entries": {"<key>": <shape>, ...}},
+ *                       read now if it exists (HYDRO_EIO if malformed) and
+ *                       rewritten after every autotune call.  Keys name the
+ *                       kernel, dtype and lattice, e.g. "level/f64/cfl/16x16x16",
+ *                       "adjoint/f32/24x24x24", "batched/f64/8x8x8+8x8x24".
+ *   hydro_ctx_destroy   destroys the graphs still owned by ctx, frees ctx.
+ *   hydro_ctx_save      writes the cache file now (HYDRO_OK if no path).
+ *   hydro_ctx_set_require_tuned  on != 0: a launch with no tuned (or cached)
+ *                       shape for its key and no explicit selection returns
+ *                       HYDRO_ENOTUNED instead of using the default.
+ *   hydro_ctx_num_tuned number of tuned entries held (>= 0).
+ * Shape lookup of a launch: the tuned entry for its key, else the explicit
+ * selection (hydro_set_*_variant), else the default. */
+int hydro_ctx_create(hydro_ctx** ctx, const char* tune_cache_json_path);
+int hydro_ctx_destroy(hydro_ctx* ctx);
+int hydro_ctx_save(hydro_ctx* ctx);
+int hydro_ctx_set_require_tuned(hydro_ctx* ctx, int32_t on);
+int hydro_ctx_num_tuned(hydro_ctx* ctx);
+
+/* hydro_check_unphysical -- waits for `stream`, reads the device int32
+ * n_bad_dev that the steps add their unphysical counts to (Sec. 2.2: results
+ * with rho <= 0 or p <= 0 are detected) and returns HYDRO_UNPHYSICAL if it is
+ * positive, HYDRO_OK if not; *n_bad_host (optional) receives the count.
+ * SYNCHRONOUS.  The counter is not reset. */
+int hydro_check_unphysical(const int32_t* n_bad_dev, void* stream, int32_t* n_bad_host);
 
 /* hydro_advance -- one MHM step of G padded patch groups (Sec. 2.2: MHM with
  * PLM on primitive variables, generalized minmod limiter, HLLC solver, and the
@@ -115,7 +161,7 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
  *                   rollout (read dt from A, reduce into B, reset C); must
  *                   differ from dt_dev and dt_next_dev
  */
-int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+int hydro_advance_level(hydro_ctx* ctx, const void* level_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
                         const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
                         double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl, double* dt_next_dev,
                         double* dt_patch_next_dev, double* dt_reset_dev, void* stream);
@@ -160,34 +206,34 @@ int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx,
  *   hydro_gather_ghost_adjoint.
  */
 int64_t hydro_adjoint_workspace_bytes(int64_t n_groups, int32_t dtype, int32_t level);
-int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* gU_pad_dev, int64_t n_groups,
+int hydro_advance_adjoint(hydro_ctx* ctx, const void* U_pad_dev, const void* gU_out_dev, void* gU_pad_dev, int64_t n_groups,
                           int32_t ghost, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
                           double theta, void* work_dev, int64_t work_bytes, void* stream);
-int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
+int hydro_advance_level_adjoint(hydro_ctx* ctx, const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
                                 int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx,
                                 double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
                                 int64_t work_bytes, void* stream);
 
-/* Form of the two adjoint calls (process-wide, per dtype); both give the same
+/* Form of the two adjoint calls (per context and dtype); both give the same
  * cotangents up to the summation order of the limiter / flux terms:
  *   0  one fused z-march per group (face cotangents stay on chip);
  *   1  two z-marches per group with the face cotangents in the workspace
  *      (smaller LDS and register footprint: two workgroups per CU).
  * hydro_set_adjoint_variant returns HYDRO_EINVAL for other values;
  * hydro_get_adjoint_variant returns the current form. */
-int hydro_set_adjoint_variant(int32_t dtype, int32_t variant);
-int hydro_get_adjoint_variant(int32_t dtype);
+int hydro_set_adjoint_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant);
+int hydro_get_adjoint_variant(hydro_ctx* ctx, int32_t dtype);
 
 /* hydro_autotune_adjoint -- time both adjoint forms of
  * hydro_advance_level_adjoint on the caller's level (same arguments as that
  * call, dt fixed internally; two passes of 1 untimed + `reps` timed launches
  * per form, 1 <= reps <= 1000, a form's time is the smaller of its two means),
- * select the faster for `dtype` and return it (0 fused, 1 two kernels), or a
- * negative status (the previous selection is then kept).  SYNCHRONOUS;
+ * record the faster in ctx (non-NULL) for `dtype` and this lattice and return
+ * it (0 fused, 1 two kernels), or a negative status (nothing is recorded).  SYNCHRONOUS;
  * g_level_in_dev and the workspace are overwritten; times_ms_host, if not
  * NULL, receives the 2 times in milliseconds.  Results do not depend on the
  * form (within rounding of the 1e-12 parity bound; both are deterministic). */
-int hydro_autotune_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
+int hydro_autotune_adjoint(hydro_ctx* ctx, const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
                            int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx, double gamma,
                            void* work_dev, int64_t work_bytes, int32_t reps, float* times_ms_host, void* stream);
 
@@ -220,7 +266,7 @@ typedef struct {
  *                concurrently.
  *   grid         persistent workgroups (0: two per compute unit in FP64,
  *                four in FP32, capped at the item count)
- * Launch shapes (process-wide per dtype, HYDRO_BATCHED_VARIANTS of them):
+ * Launch shapes (per context and dtype, HYDRO_BATCHED_VARIANTS of them):
  * bit 0 item order (0: level 0 first, 1: finest level first), bit 1
  * occupancy target, bits 2-3 work distribution (0: one queue; 1: one queue
  * per XCD, each serving one residue class of items mod 8, with stealing when
@@ -229,34 +275,36 @@ typedef struct {
  * hydro_autotune_batched times all of them on the given levels (two passes
  * of 1 untimed + `reps` timed launches per shape, a shape's time is the
  * smaller of its two means; SYNCHRONOUS; the outputs are overwritten;
- * times_ms_host receives HYDRO_BATCHED_VARIANTS floats) and keeps the
- * fastest.
+ * times_ms_host receives HYDRO_BATCHED_VARIANTS floats) and records the
+ * fastest in ctx (non-NULL) for these level lattices.
  */
 #define HYDRO_BATCH_WORK_WORDS 16
 #define HYDRO_BATCHED_VARIANTS 12
-int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
+int hydro_advance_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
                           int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
                           void* stream);
-int hydro_set_batched_variant(int32_t dtype, int32_t variant);
-int hydro_get_batched_variant(int32_t dtype);
-int hydro_autotune_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
+int hydro_set_batched_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant);
+int hydro_get_batched_variant(hydro_ctx* ctx, int32_t dtype);
+int hydro_autotune_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
                            uint32_t* work_dev, int32_t reps, float* times_ms_host, void* stream);
 
 /* Graph capture of a sequence of library calls (e.g. a level's substeps or
  * the stages of a coarse step), replayed without per-launch host overhead.
  *   hydro_graph_begin    start capturing `stream` (a non-NULL hipStream_t)
  *   hydro_graph_end      stop capturing, instantiate; *graph_exec receives an
- *                        opaque handle owned by the caller
+ *                        opaque handle, owned by ctx (freed at the latest by
+ *                        hydro_ctx_destroy) or, with ctx NULL, by the caller
  *   hydro_graph_launch   replay the captured work on `stream`
- *   hydro_graph_destroy  free a handle
+ *   hydro_graph_destroy  free a handle (with the ctx it was captured through;
+ *                        HYDRO_EINVAL if that ctx does not own it)
  * Calls made between begin and end are recorded, not executed; kernel
  * arguments (pointers, dt values) are frozen at capture time, so buffers
  * must stay allocated while the graph is used.  The library records no
  * memset nodes. */
 int hydro_graph_begin(void* stream);
-int hydro_graph_end(void* stream, void** graph_exec);
+int hydro_graph_end(hydro_ctx* ctx, void* stream, void** graph_exec);
 int hydro_graph_launch(void* graph_exec, void* stream);
-int hydro_graph_destroy(void* graph_exec);
+int hydro_graph_destroy(hydro_ctx* ctx, void* graph_exec);
 
 /* hydro_dt -- per-patch CFL time-step, Sec. 2.6 Eq. 2 (the form for MHM):
  * dt_patch = (c_cfl * dx) / max over the patch's 8^3 cells of
@@ -305,9 +353,10 @@ int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t
  * differ in the register budget the compiler was given (occupancy) and in the
  * order groups are dealt to workgroups (plain, or blocked so that each of the
  * 8 XCDs sweeps a contiguous range of groups and finds neighbour-group halos
- * in its own L2).  The choice is process-wide, per dtype and per kernel
- * form (with_cfl: the form that reduces the next CFL time-step, which needs
- * more registers and 4 KB more LDS per workgroup).
+ * in its own L2).  The choice is per context, per dtype and per kernel form
+ * (with_cfl: the form that reduces the next CFL time-step, which needs more
+ * registers and 4 KB more LDS per workgroup).  Setters need a context;
+ * getters with ctx NULL return the default (XCD-blocked, high occupancy).
  *   hydro_num_variants       number of shapes (>= 1)
  *   hydro_set_level_variant  select one (0 .. n-1) for one form; HYDRO_EINVAL otherwise
  *   hydro_get_level_variant  current selection for a dtype and form
@@ -316,27 +365,29 @@ int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t
  *   hydro_variant_name       short description into buf[len] (host memory)
  */
 int hydro_num_variants(void);
-int hydro_set_level_variant(int32_t dtype, int32_t with_cfl, int32_t variant);
-int hydro_get_level_variant(int32_t dtype, int32_t with_cfl);
-int hydro_set_variant(int32_t dtype, int32_t variant);
-int hydro_get_variant(int32_t dtype);
+int hydro_set_level_variant(hydro_ctx* ctx, int32_t dtype, int32_t with_cfl, int32_t variant);
+int hydro_get_level_variant(hydro_ctx* ctx, int32_t dtype, int32_t with_cfl);
+int hydro_set_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant);
+int hydro_get_variant(hydro_ctx* ctx, int32_t dtype);
 int hydro_variant_name(int32_t variant, char* buf, int32_t len);
 
 /* hydro_autotune -- time every launch shape of hydro_advance_level on the
  * caller's level (two passes of 1 untimed + `reps` timed launches per shape,
  * HIP events on `stream`, 1 <= reps <= 1000; a shape's time is the smaller of
- * its two means), select the fastest for `dtype` and return its
- * index (>= 0), or a negative status (the previous selection is then kept).
- * Both kernel forms are timed and tuned separately (without and with the CFL
- * epilogue; the returned index is the CFL form's).  SYNCHRONOUS: waits on
- * `stream`; allocates (and frees) a small device buffer for the CFL outputs.
- * level_dev is read, scratch_out_dev ([G][5][16^3], not overlapping) is
- * overwritten.  times_ms_host, if not NULL, receives 2 * hydro_num_variants()
- * times in milliseconds (the form without CFL first).
+ * its two means), record the fastest in ctx (non-NULL) for `dtype` and this
+ * lattice and return its index (>= 0), or a negative status (nothing is
+ * recorded).  Both kernel forms are timed and tuned separately (without and
+ * with the CFL epilogue; the returned index is the CFL form's).  SYNCHRONOUS:
+ * waits on `stream`; allocates nothing on the device.  level_dev is read,
+ * scratch_out_dev ([G][5][16^3]) is overwritten, cfl_scratch_dev receives the
+ * CFL form's outputs: at least (3 + 8 G) doubles (cfl_scratch_bytes); no two
+ * of the three may overlap.  times_ms_host, if not NULL, receives
+ * 2 * hydro_num_variants() times in milliseconds (the form without CFL first).
  */
-int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
-                   const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps,
-                   float* times_ms_host, void* stream);
+int hydro_autotune(hydro_ctx* ctx, const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy,
+                   int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx, double gamma,
+                   double* cfl_scratch_dev, int64_t cfl_scratch_bytes, int32_t reps, float* times_ms_host,
+                   void* stream);
 
 /* Name of a status code (static string). */
 const char* hydro_strerror(int status);

@@ -2,9 +2,15 @@
 // the kernels.  Declarations and documentation: include/hydro.h.
 
 #include <atomic>
+#include <cctype>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
 
 #include "hydro.h"
 #include "kernels.h"
@@ -20,17 +26,132 @@ namespace {
 
 thread_local int g_last_hip_error = 0;
 
-// Launch shape of the level step per dtype (index into the variants of
-// mhm_fwd.hip); set by hydro_set_variant or hydro_autotune, process-wide.
-// [dtype][with CFL epilogue]: the two kernels differ in register needs, so
-// each gets its own shape.
-std::atomic<int> g_level_variant[2][2] = {{{1}, {1}}, {{1}, {1}}};  // measured defaults: plain order, high occupancy
-// Form of the step adjoint per dtype: 0 fused single sweep, 1 two kernels
-// with a face workspace.
-std::atomic<int> g_adjoint_variant[2] = {{0}, {0}};  // measured: fused faster in both dtypes
-// Launch shape of the batched kernel per dtype (bit 0: item order, bit 1:
-// occupancy target, bit 2: per-XCD queues).
-std::atomic<int> g_batched_variant[2] = {{0}, {0}};  // one queue, high occupancy
+// Measured defaults of the launch shapes (used when a context has no
+// selection): level step XCD-blocked at the high occupancy target (variant
+// 0); fused adjoint (0); batched: one queue, high occupancy (0).
+constexpr int kDefaultLevelVariant = 0;
+constexpr int kDefaultAdjointVariant = 0;
+constexpr int kDefaultBatchedVariant = 0;
+
+}  // namespace
+
+// A solver context: the launch-shape selections of one user of the library
+// (explicitly set, or autotuned and keyed by dtype and level shape), the
+// optional tuning-cache file they are loaded from and saved to, and the
+// graphs captured through it.  Entry points take it as their first argument;
+// NULL selects the measured defaults.
+struct hydro_ctx {
+  std::mutex mu;
+  std::string cache_path;
+  bool require_tuned = false;
+  int level_sel[2][2] = {{-1, -1}, {-1, -1}};  // [dtype][with CFL epilogue], -1 = not set
+  int batched_sel[2] = {-1, -1};
+  int adjoint_sel[2] = {-1, -1};
+  std::map<std::string, int> tuned;          // autotuned or cached selections by key
+  std::set<void*> graphs;                    // hipGraphExec_t handles captured through this context
+};
+
+namespace {
+
+const char* dtype_name(int32_t dtype) { return dtype == HYDRO_F64 ? "f64" : "f32"; }
+
+std::string level_key(int32_t dtype, bool with_cfl, int ngx, int ngy, int ngz) {
+  char b[96];
+  std::snprintf(b, sizeof b, "level/%s/%s/%dx%dx%d", dtype_name(dtype), with_cfl ? "cfl" : "plain", ngx, ngy, ngz);
+  return b;
+}
+
+std::string adjoint_key(int32_t dtype, int ngx, int ngy, int ngz) {
+  char b[96];
+  std::snprintf(b, sizeof b, "adjoint/%s/%dx%dx%d", dtype_name(dtype), ngx, ngy, ngz);
+  return b;
+}
+
+std::string batched_key(int32_t dtype, const hydro_level_t* lv, int n) {
+  std::string k = std::string("batched/") + dtype_name(dtype) + "/";
+  for (int l = 0; l < n; ++l) {
+    char b[64];
+    std::snprintf(b, sizeof b, "%s%dx%dx%d", l ? "+" : "", lv[l].ngx, lv[l].ngy, lv[l].ngz);
+    k += b;
+  }
+  return k;
+}
+
+// The shape a launch uses: a tuned selection for this key, else the one set
+// explicitly, else (unless the context requires tuning) the default.
+// explicit_sel points into the context and is read under its lock.
+int select_shape(hydro_ctx* c, const std::string& key, const int* explicit_sel, int fallback, int* out) {
+  if (c == nullptr) {
+    *out = fallback;
+    return HYDRO_OK;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    *out = it->second;
+    return HYDRO_OK;
+  }
+  if (*explicit_sel >= 0) {
+    *out = *explicit_sel;
+    return HYDRO_OK;
+  }
+  if (c->require_tuned) return HYDRO_ENOTUNED;
+  *out = fallback;
+  return HYDRO_OK;
+}
+
+// Tuning cache: a JSON object {"version": 1, "entries": {"<key>": <shape>, ...}}.
+// The reader accepts exactly what the writer produces (string keys, integer
+// values), so a malformed file is reported rather than half-read.
+bool parse_cache(const std::string& text, std::map<std::string, int>& out) {
+  size_t i = text.find("\"entries\"");
+  if (i == std::string::npos) return false;
+  i = text.find('{', i);
+  if (i == std::string::npos) return false;
+  ++i;
+  for (;;) {
+    while (i < text.size() && std::isspace((unsigned char)text[i])) ++i;
+    if (i < text.size() && text[i] == '}') return true;
+    if (i >= text.size() || text[i] != '"') return false;
+    const size_t e = text.find('"', i + 1);
+    if (e == std::string::npos) return false;
+    std::string key = text.substr(i + 1, e - i - 1);
+    i = e + 1;
+    while (i < text.size() && std::isspace((unsigned char)text[i])) ++i;
+    if (i >= text.size() || text[i] != ':') return false;
+    ++i;
+    char* end = nullptr;
+    const long v = std::strtol(text.c_str() + i, &end, 10);
+    if (end == text.c_str() + i || v < 0 || v > 1000) return false;
+    out[key] = int(v);
+    i = size_t(end - text.c_str());
+    while (i < text.size() && std::isspace((unsigned char)text[i])) ++i;
+    if (i < text.size() && text[i] == ',') ++i;
+  }
+}
+
+int save_cache_locked(hydro_ctx* c) {
+  if (c->cache_path.empty()) return HYDRO_OK;
+  const std::string tmp = c->cache_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (f == nullptr) return HYDRO_EIO;
+  std::fprintf(f, "{\"version\": 1, \"entries\": {");
+  bool first = true;
+  for (const auto& kv : c->tuned) {
+    std::fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  std::fprintf(f, "\n}}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), c->cache_path.c_str()) != 0) return HYDRO_EIO;
+  return HYDRO_OK;
+}
+
+void record_tuned(hydro_ctx* c, const std::string& key, int v) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tuned[key] = v;
+  (void)save_cache_locked(c);  // best effort; hydro_ctx_save reports errors
+}
 
 // Compute units of the current device (persistent-grid size), cached per device.
 int device_cus() {
@@ -158,9 +279,164 @@ int validate_levels(const hydro_level_t* lv, int32_t n_levels, int32_t dtype) {
 
 }  // namespace
 
+namespace {
+
+int check_level_args(const void* level_dev, const void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                     const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                     double theta, const double* dt_dev, double c_cfl, double* dt_next_dev,
+                     double* dt_patch_next_dev, double* dt_reset_dev, gh::LevelGeom* geo) {
+  if (!level_geom_ok(ngx, ngy, ngz) || bc_host == nullptr) return HYDRO_EINVAL;
+  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
+    return HYDRO_EINVAL;
+  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
+  const bool want_cfl = dt_next_dev != nullptr || dt_patch_next_dev != nullptr || dt_reset_dev != nullptr;
+  if (want_cfl && !finite_pos(c_cfl)) return HYDRO_EINVAL;
+  if (dt_reset_dev != nullptr && (dt_reset_dev == dt_dev || dt_reset_dev == dt_next_dev)) return HYDRO_EINVAL;
+  if (dt_next_dev != nullptr && dt_next_dev == dt_dev) return HYDRO_EINVAL;
+  geo->ngx = ngx;
+  geo->ngy = ngy;
+  geo->ngz = ngz;
+  for (int i = 0; i < 6; ++i) {
+    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
+    geo->bc[i] = bc_host[i];
+  }
+  if (level_dev == nullptr || level_out_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  const size_t bytes = size_t(G) * 5 * 4096 * dtype_size(dtype);
+  if (overlap(level_dev, bytes, level_out_dev, bytes)) return HYDRO_EINVAL;
+  return HYDRO_OK;
+}
+
+// hydro_advance_level after argument checks, with the launch shape given.
+int level_launch(const void* level_dev, void* level_out_dev, const gh::LevelGeom& geo, int32_t dtype, double dt,
+                 double dx, double gamma, int32_t scheme, double theta, const double* dt_dev, int32_t* n_bad_dev,
+                 double c_cfl, double* dt_next_dev, double* dt_patch_next_dev, double* dt_reset_dev, int variant,
+                 hipStream_t s) {
+  gh::CflOut cfl;
+  cfl.dt_patch = dt_patch_next_dev;
+  cfl.dt_min = reinterpret_cast<unsigned long long*>(dt_next_dev);
+  cfl.reset = reinterpret_cast<unsigned long long*>(dt_reset_dev);
+  const bool with_cfl = cfl.dt_min != nullptr || cfl.dt_patch != nullptr || cfl.reset != nullptr;
+  cfl.c_cfl_dx = with_cfl ? c_cfl * dx : 0.0;
+  cfl.gamma = gamma;
+  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
+  const int ws = (scheme >> 8) & 3;
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_mhm_level(static_cast<const double*>(level_dev), static_cast<double*>(level_out_dev), geo,
+                             make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
+                             variant, s);
+  else
+    e = gh::launch_mhm_level(static_cast<const float*>(level_dev), static_cast<float*>(level_out_dev), geo,
+                             make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
+                             variant, s);
+  return device_status(e);
+}
+
+int check_level_adjoint_args(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
+                             int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx,
+                             double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
+                             int64_t work_bytes, gh::LevelGeom* geo) {
+  if (!adjoint_geom_ok(ngx, ngy, ngz) || bc_host == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+    return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta)) return HYDRO_EINVAL;
+  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
+  geo->ngx = ngx;
+  geo->ngy = ngy;
+  geo->ngz = ngz;
+  for (int i = 0; i < 6; ++i) {
+    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
+    geo->bc[i] = bc_host[i];
+  }
+  if (level_dev == nullptr || g_level_out_dev == nullptr || g_level_in_dev == nullptr || work_dev == nullptr)
+    return HYDRO_EINVAL;
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  const size_t es = dtype_size(dtype);
+  const size_t need = gh::adjoint_workspace_elems(G, true) * es;
+  if (work_bytes < 0 || size_t(work_bytes) < need) return HYDRO_EINVAL;
+  const size_t lb = size_t(G) * 5 * 4096 * es;
+  if (overlap(g_level_in_dev, lb, level_dev, lb) || overlap(g_level_in_dev, lb, g_level_out_dev, lb) ||
+      overlap(work_dev, need, level_dev, lb) || overlap(work_dev, need, g_level_out_dev, lb) ||
+      overlap(work_dev, need, g_level_in_dev, lb))
+    return HYDRO_EINVAL;
+  return HYDRO_OK;
+}
+
+int level_adjoint_launch(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev,
+                         const gh::LevelGeom& geo, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                         double theta, const double* dt_dev, void* work_dev, int form, hipStream_t s) {
+  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
+  const int ws = (scheme >> 8) & 3;
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_mhm_adjoint_level(static_cast<const double*>(level_dev), static_cast<const double*>(g_level_out_dev),
+                                     static_cast<double*>(g_level_in_dev), geo,
+                                     make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws,
+                                     static_cast<double*>(work_dev), form == 1, s);
+  else
+    e = gh::launch_mhm_adjoint_level(static_cast<const float*>(level_dev), static_cast<const float*>(g_level_out_dev),
+                                     static_cast<float*>(g_level_in_dev), geo,
+                                     make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws,
+                                     static_cast<float*>(work_dev), form == 1, s);
+  return device_status(e);
+}
+
+int batched_launch(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma, int32_t scheme,
+                   double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid, int variant, hipStream_t s) {
+  if (dtype == HYDRO_F64)
+    return batched_impl<double>(levels_host, n_levels, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant, s);
+  return batched_impl<float>(levels_host, n_levels, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant, s);
+}
+
+// Times `launch(v)` for v in [0, n): two passes of 1 untimed + reps timed
+// launches each, a shape's time the smaller of its two means (so clock
+// ramp-up during the first pass does not decide).  Returns the fastest v or a
+// negative status; ms[n] receives the times.
+template <typename F>
+int time_shapes(int n, int reps, hipStream_t s, float* ms, F launch) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return device_status(hipGetLastError());
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return device_status(hipGetLastError());
+  }
+  int status = HYDRO_OK;
+  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
+    for (int v = 0; v < n && status == HYDRO_OK; ++v) {
+      status = launch(v);
+      if (status != HYDRO_OK) break;
+      hipError_t he = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch(v);
+      if (status != HYDRO_OK) break;
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float t = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+      if (he != hipSuccess) {
+        status = device_status(he);
+        break;
+      }
+      t /= float(reps);
+      if (pass == 0 || t < ms[v]) ms[v] = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != HYDRO_OK) return status;
+  int best = 0;
+  for (int v = 1; v < n; ++v)
+    if (ms[v] < ms[best]) best = v;
+  return best;
+}
+
+}  // namespace
+
 extern "C" {
 
-int hydro_version(void) { return 4; }
+int hydro_version(void) { return 5; }
 
 int hydro_last_hip_error(void) { return g_last_hip_error; }
 
@@ -168,15 +444,87 @@ const char* hydro_strerror(int status) {
   switch (status) {
     case HYDRO_OK:
       return "ok";
+    case HYDRO_UNPHYSICAL:
+      return "unphysical cells (rho <= 0 or p <= 0) in the result";
     case HYDRO_EINVAL:
       return "invalid argument";
     case HYDRO_EDEVICE:
       return "HIP runtime error";
+    case HYDRO_ENOTUNED:
+      return "no tuned launch shape for this call and the context requires one";
+    case HYDRO_EIO:
+      return "tuning cache unreadable, malformed or not writable";
     default:
       return "unknown status";
   }
 }
 
+// ------------------------------------------------------------ context ----
+int hydro_ctx_create(hydro_ctx** ctx, const char* tune_cache_json_path) {
+  if (ctx == nullptr) return HYDRO_EINVAL;
+  *ctx = nullptr;
+  hydro_ctx* c = new (std::nothrow) hydro_ctx();
+  if (c == nullptr) return HYDRO_EINVAL;
+  if (tune_cache_json_path != nullptr && tune_cache_json_path[0] != '\0') {
+    c->cache_path = tune_cache_json_path;
+    FILE* f = std::fopen(tune_cache_json_path, "r");
+    if (f != nullptr) {  // a missing file is an empty cache
+      std::string text;
+      char buf[4096];
+      size_t n;
+      while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+      std::fclose(f);
+      if (!parse_cache(text, c->tuned)) {
+        delete c;
+        return HYDRO_EIO;
+      }
+    }
+  }
+  *ctx = c;
+  return HYDRO_OK;
+}
+
+int hydro_ctx_destroy(hydro_ctx* ctx) {
+  if (ctx == nullptr) return HYDRO_EINVAL;
+  int status = HYDRO_OK;
+  for (void* g : ctx->graphs) {
+    const hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(g));
+    if (e != hipSuccess && status == HYDRO_OK) status = device_status(e);
+  }
+  delete ctx;
+  return status;
+}
+
+int hydro_ctx_save(hydro_ctx* ctx) {
+  if (ctx == nullptr) return HYDRO_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return save_cache_locked(ctx);
+}
+
+int hydro_ctx_set_require_tuned(hydro_ctx* ctx, int32_t on) {
+  if (ctx == nullptr) return HYDRO_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->require_tuned = on != 0;
+  return HYDRO_OK;
+}
+
+int hydro_ctx_num_tuned(hydro_ctx* ctx) {
+  if (ctx == nullptr) return HYDRO_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return int(ctx->tuned.size());
+}
+
+int hydro_check_unphysical(const int32_t* n_bad_dev, void* stream, int32_t* n_bad_host) {
+  if (n_bad_dev == nullptr) return HYDRO_EINVAL;
+  int32_t v = 0;
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = hipMemcpy(&v, n_bad_dev, sizeof v, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_status(e);
+  if (n_bad_host != nullptr) *n_bad_host = v;
+  return v > 0 ? HYDRO_UNPHYSICAL : HYDRO_OK;
+}
+
+// -------------------------------------------------------- padded step ----
 int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
                   double dt, double dx, double gamma, int32_t scheme, double theta, const double* dt_dev,
                   int32_t* n_bad_dev, void* stream) {
@@ -204,73 +552,51 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
   return device_status(e);
 }
 
-int hydro_advance_level(const void* level_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
-                        const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
-                        double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl, double* dt_next_dev,
-                        double* dt_patch_next_dev, double* dt_reset_dev, void* stream) {
-  if (!level_geom_ok(ngx, ngy, ngz) || bc_host == nullptr) return HYDRO_EINVAL;
-  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
-  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
-    return HYDRO_EINVAL;
-  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
-  const bool want_cfl = dt_next_dev != nullptr || dt_patch_next_dev != nullptr || dt_reset_dev != nullptr;
-  if (want_cfl && !finite_pos(c_cfl)) return HYDRO_EINVAL;
-  if (dt_reset_dev != nullptr && (dt_reset_dev == dt_dev || dt_reset_dev == dt_next_dev)) return HYDRO_EINVAL;
-  if (dt_next_dev != nullptr && dt_next_dev == dt_dev) return HYDRO_EINVAL;
+// --------------------------------------------------------- level step ----
+int hydro_advance_level(hydro_ctx* ctx, const void* level_dev, void* level_out_dev, int32_t ngx, int32_t ngy,
+                        int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma,
+                        int32_t scheme, double theta, const double* dt_dev, int32_t* n_bad_dev, double c_cfl,
+                        double* dt_next_dev, double* dt_patch_next_dev, double* dt_reset_dev, void* stream) {
   gh::LevelGeom geo;
-  geo.ngx = ngx;
-  geo.ngy = ngy;
-  geo.ngz = ngz;
-  for (int i = 0; i < 6; ++i) {
-    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
-    geo.bc[i] = bc_host[i];
-  }
-  if (level_dev == nullptr || level_out_dev == nullptr) return HYDRO_EINVAL;
-  const int64_t G = int64_t(ngx) * ngy * ngz;
-  const size_t bytes = size_t(G) * 5 * 4096 * dtype_size(dtype);
-  if (overlap(level_dev, bytes, level_out_dev, bytes)) return HYDRO_EINVAL;
-  gh::CflOut cfl;
-  cfl.dt_patch = dt_patch_next_dev;
-  cfl.dt_min = reinterpret_cast<unsigned long long*>(dt_next_dev);
-  cfl.reset = reinterpret_cast<unsigned long long*>(dt_reset_dev);
-  cfl.c_cfl_dx = want_cfl ? c_cfl * dx : 0.0;
-  cfl.gamma = gamma;
-  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
-  const int ws = (scheme >> 8) & 3;
-  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
-  const bool with_cfl = cfl.dt_min != nullptr || cfl.dt_patch != nullptr || cfl.reset != nullptr;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  if (dtype == HYDRO_F64)
-    e = gh::launch_mhm_level(static_cast<const double*>(level_dev), static_cast<double*>(level_out_dev), geo,
-                             make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
-                             g_level_variant[0][with_cfl ? 1 : 0].load(), s);
-  else
-    e = gh::launch_mhm_level(static_cast<const float*>(level_dev), static_cast<float*>(level_out_dev), geo,
-                             make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, cfl,
-                             g_level_variant[1][with_cfl ? 1 : 0].load(), s);
-  return device_status(e);
+  int st = check_level_args(level_dev, level_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma, scheme, theta,
+                            dt_dev, c_cfl, dt_next_dev, dt_patch_next_dev, dt_reset_dev, &geo);
+  if (st != HYDRO_OK) return st;
+  const bool with_cfl = dt_next_dev != nullptr || dt_patch_next_dev != nullptr || dt_reset_dev != nullptr;
+  int variant = 0;
+  st = select_shape(ctx, level_key(dtype, with_cfl, ngx, ngy, ngz),
+                    ctx ? &ctx->level_sel[dtype][with_cfl ? 1 : 0] : nullptr, kDefaultLevelVariant, &variant);
+  if (st != HYDRO_OK) return st;
+  return level_launch(level_dev, level_out_dev, geo, dtype, dt, dx, gamma, scheme, theta, dt_dev, n_bad_dev, c_cfl,
+                      dt_next_dev, dt_patch_next_dev, dt_reset_dev, variant, static_cast<hipStream_t>(stream));
 }
 
 int hydro_num_variants(void) { return gh::kLevelVariants; }
 
-int hydro_get_level_variant(int32_t dtype, int32_t with_cfl) {
+int hydro_get_level_variant(hydro_ctx* ctx, int32_t dtype, int32_t with_cfl) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
-  return g_level_variant[dtype][with_cfl ? 1 : 0].load();
+  if (ctx == nullptr) return kDefaultLevelVariant;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const int v = ctx->level_sel[dtype][with_cfl ? 1 : 0];
+  return v >= 0 ? v : kDefaultLevelVariant;
 }
 
-int hydro_set_level_variant(int32_t dtype, int32_t with_cfl, int32_t variant) {
-  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+int hydro_set_level_variant(hydro_ctx* ctx, int32_t dtype, int32_t with_cfl, int32_t variant) {
+  if (ctx == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
   if (variant < 0 || variant >= gh::kLevelVariants) return HYDRO_EINVAL;
-  g_level_variant[dtype][with_cfl ? 1 : 0].store(variant);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->level_sel[dtype][with_cfl ? 1 : 0] = variant;
+  // an explicit choice overrides earlier tuned choices of this dtype and form
+  const std::string prefix = std::string("level/") + dtype_name(dtype) + (with_cfl ? "/cfl/" : "/plain/");
+  for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
+    it = it->first.compare(0, prefix.size(), prefix) == 0 ? ctx->tuned.erase(it) : std::next(it);
   return HYDRO_OK;
 }
 
-int hydro_get_variant(int32_t dtype) { return hydro_get_level_variant(dtype, 1); }
+int hydro_get_variant(hydro_ctx* ctx, int32_t dtype) { return hydro_get_level_variant(ctx, dtype, 1); }
 
-int hydro_set_variant(int32_t dtype, int32_t variant) {
-  int st = hydro_set_level_variant(dtype, 0, variant);
-  if (st == HYDRO_OK) st = hydro_set_level_variant(dtype, 1, variant);
+int hydro_set_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant) {
+  int st = hydro_set_level_variant(ctx, dtype, 0, variant);
+  if (st == HYDRO_OK) st = hydro_set_level_variant(ctx, dtype, 1, variant);
   return st;
 }
 
@@ -281,169 +607,102 @@ int hydro_variant_name(int32_t variant, char* buf, int32_t len) {
   return HYDRO_OK;
 }
 
-int hydro_autotune(const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
-                   const int32_t* bc_host, int32_t dtype, double dx, double gamma, int32_t reps, float* times_ms_host,
-                   void* stream) {
-  if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
-  if (!level_geom_ok(ngx, ngy, ngz)) return HYDRO_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int saved[2] = {g_level_variant[dtype][0].load(), g_level_variant[dtype][1].load()};
-  // CFL outputs of the timed CFL-epilogue launches: 3 scalars + 8 per group
-  const int64_t G = int64_t(ngx) * ngy * ngz;
-  double* cfl_buf = nullptr;
-  if (hipMalloc(&cfl_buf, sizeof(double) * size_t(3 + 8 * G)) != hipSuccess) return device_status(hipGetLastError());
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) {
-    (void)hipFree(cfl_buf);
-    return device_status(hipGetLastError());
-  }
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    (void)hipFree(cfl_buf);
-    return device_status(hipGetLastError());
-  }
-  int best[2] = {-1, -1}, status = HYDRO_OK;
-  float best_ms[2] = {0.0f, 0.0f};
-  float ms_min[2][gh::kLevelVariants] = {};
+int hydro_autotune(hydro_ctx* ctx, const void* level_dev, void* scratch_out_dev, int32_t ngx, int32_t ngy,
+                   int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx, double gamma, double* cfl_scratch_dev,
+                   int64_t cfl_scratch_bytes, int32_t reps, float* times_ms_host, void* stream) {
+  if (ctx == nullptr || reps < 1 || reps > 1000) return HYDRO_EINVAL;
   const double dt = 1e-3 * dx;  // any positive step does the same work
-  // two passes over every (form, shape); a shape's time is the smaller of its
-  // two, so clock ramp-up or drift during the first pass does not decide
-  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
-    for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
-      double* dt_next = form ? cfl_buf : nullptr;
-      double* dt_reset = form ? cfl_buf + 1 : nullptr;
-      double* dt_patch = form ? cfl_buf + 3 : nullptr;
-      for (int v = 0; v < gh::kLevelVariants && status == HYDRO_OK; ++v) {
-        g_level_variant[dtype][form].store(v);
-        auto launch = [&]() {
-          return hydro_advance_level(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
-                                     HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, nullptr, 0.5, dt_next, dt_patch,
-                                     dt_reset, stream);
-        };
-        // one untimed launch, then `reps` timed ones
-        status = launch();
-        if (status != HYDRO_OK) break;
-        hipError_t he = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch();
-        if (status != HYDRO_OK) break;
-        if (he == hipSuccess) he = hipEventRecord(e1, s);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) {
-          status = device_status(he);
-          break;
-        }
-        ms /= float(reps);
-        if (pass == 0 || ms < ms_min[form][v]) ms_min[form][v] = ms;
-      }
-    }
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  // the CFL form's outputs: next dt, reset scalar, 8 patch time-steps per group
+  if (cfl_scratch_dev == nullptr || G < 0 || cfl_scratch_bytes < int64_t(sizeof(double)) * (3 + 8 * G))
+    return HYDRO_EINVAL;
+  gh::LevelGeom geo;
+  int st = check_level_args(level_dev, scratch_out_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx, gamma,
+                            HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, 0.5, cfl_scratch_dev, cfl_scratch_dev + 3,
+                            cfl_scratch_dev + 1, &geo);
+  if (st != HYDRO_OK) return st;
+  const size_t lb = size_t(G) * 5 * 4096 * dtype_size(dtype), cb = sizeof(double) * size_t(3 + 8 * G);
+  if (overlap(cfl_scratch_dev, cb, level_dev, lb) || overlap(cfl_scratch_dev, cb, scratch_out_dev, lb))
+    return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float ms[2][gh::kLevelVariants] = {};
+  int best[2];
+  for (int form = 0; form < 2; ++form) {
+    double* dt_next = form ? cfl_scratch_dev : nullptr;
+    double* dt_reset = form ? cfl_scratch_dev + 1 : nullptr;
+    double* dt_patch = form ? cfl_scratch_dev + 3 : nullptr;
+    best[form] = time_shapes(gh::kLevelVariants, reps, s, ms[form], [&](int v) {
+      return level_launch(level_dev, scratch_out_dev, geo, dtype, dt, dx, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5,
+                          nullptr, nullptr, 0.5, dt_next, dt_patch, dt_reset, v, s);
+    });
+    if (best[form] < 0) return best[form];
   }
-  for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
-    for (int v = 0; v < gh::kLevelVariants; ++v) {
-      if (times_ms_host != nullptr) times_ms_host[form * gh::kLevelVariants + v] = ms_min[form][v];
-      if (best[form] < 0 || ms_min[form][v] < best_ms[form]) {
-        best[form] = v;
-        best_ms[form] = ms_min[form][v];
-      }
-    }
+  if (times_ms_host != nullptr)
+    for (int form = 0; form < 2; ++form)
+      for (int v = 0; v < gh::kLevelVariants; ++v) times_ms_host[form * gh::kLevelVariants + v] = ms[form][v];
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuned[level_key(dtype, false, ngx, ngy, ngz)] = best[0];
+    ctx->tuned[level_key(dtype, true, ngx, ngy, ngz)] = best[1];
+    ctx->level_sel[dtype][0] = best[0];
+    ctx->level_sel[dtype][1] = best[1];
+    (void)save_cache_locked(ctx);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipStreamSynchronize(s);
-  (void)hipFree(cfl_buf);
-  if (status != HYDRO_OK) {
-    g_level_variant[dtype][0].store(saved[0]);
-    g_level_variant[dtype][1].store(saved[1]);
-    return status;
-  }
-  g_level_variant[dtype][0].store(best[0]);
-  g_level_variant[dtype][1].store(best[1]);
   return best[1];
 }
 
-int hydro_advance_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
-                          int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
-                          void* stream) {
+// ------------------------------------------------------------ batched ----
+int hydro_advance_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype,
+                          double gamma, int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev,
+                          int32_t grid, void* stream) {
   if ((dtype != HYDRO_F64 && dtype != HYDRO_F32) || !(std::isfinite(gamma) && gamma > 1.0) ||
       !valid_scheme(scheme, theta) || work_dev == nullptr || grid < 0)
     return HYDRO_EINVAL;
-  const int v = validate_levels(levels_host, n_levels, dtype);
-  if (v != HYDRO_OK) return v;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int variant = g_batched_variant[dtype].load();
-  if (dtype == HYDRO_F64)
-    return batched_impl<double>(levels_host, n_levels, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant, s);
-  return batched_impl<float>(levels_host, n_levels, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant, s);
+  int st = validate_levels(levels_host, n_levels, dtype);
+  if (st != HYDRO_OK) return st;
+  int variant = 0;
+  st = select_shape(ctx, batched_key(dtype, levels_host, n_levels), ctx ? &ctx->batched_sel[dtype] : nullptr,
+                    kDefaultBatchedVariant, &variant);
+  if (st != HYDRO_OK) return st;
+  return batched_launch(levels_host, n_levels, dtype, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant,
+                        static_cast<hipStream_t>(stream));
 }
 
-int hydro_set_batched_variant(int32_t dtype, int32_t variant) {
-  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+int hydro_set_batched_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant) {
+  if (ctx == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
   if (variant < 0 || variant >= gh::kBatchedVariants) return HYDRO_EINVAL;
-  g_batched_variant[dtype].store(variant);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->batched_sel[dtype] = variant;
+  const std::string prefix = std::string("batched/") + dtype_name(dtype) + "/";
+  for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
+    it = it->first.compare(0, prefix.size(), prefix) == 0 ? ctx->tuned.erase(it) : std::next(it);
   return HYDRO_OK;
 }
 
-int hydro_get_batched_variant(int32_t dtype) {
+int hydro_get_batched_variant(hydro_ctx* ctx, int32_t dtype) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
-  return g_batched_variant[dtype].load();
+  if (ctx == nullptr) return kDefaultBatchedVariant;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return ctx->batched_sel[dtype] >= 0 ? ctx->batched_sel[dtype] : kDefaultBatchedVariant;
 }
 
-int hydro_autotune_batched(const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
-                           uint32_t* work_dev, int32_t reps, float* times_ms_host, void* stream) {
-  if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32) || work_dev == nullptr)
+int hydro_autotune_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype,
+                           double gamma, uint32_t* work_dev, int32_t reps, float* times_ms_host, void* stream) {
+  if (ctx == nullptr || reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32) ||
+      work_dev == nullptr || !(std::isfinite(gamma) && gamma > 1.0))
     return HYDRO_EINVAL;
   const int v = validate_levels(levels_host, n_levels, dtype);
   if (v != HYDRO_OK) return v;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int saved = g_batched_variant[dtype].load();
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return device_status(hipGetLastError());
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return device_status(hipGetLastError());
-  }
-  int best = -1, status = HYDRO_OK;
-  float best_ms = 0.0f;
-  float ms_min[gh::kBatchedVariants] = {};
-  // two passes, a shape's time is the smaller of its two (as hydro_autotune)
-  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
-    for (int var = 0; var < gh::kBatchedVariants && status == HYDRO_OK; ++var) {
-      g_batched_variant[dtype].store(var);
-      status = hydro_advance_batched(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr,
-                                     work_dev, 0, stream);
-      if (status != HYDRO_OK) break;
-      hipError_t he = hipEventRecord(e0, s);
-      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r)
-        status = hydro_advance_batched(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr,
-                                       work_dev, 0, stream);
-      if (status != HYDRO_OK) break;
-      if (he == hipSuccess) he = hipEventRecord(e1, s);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (he != hipSuccess) {
-        status = device_status(he);
-        break;
-      }
-      ms /= float(reps);
-      if (pass == 0 || ms < ms_min[var]) ms_min[var] = ms;
-    }
-  }
-  for (int var = 0; var < gh::kBatchedVariants && status == HYDRO_OK; ++var) {
-    if (times_ms_host != nullptr) times_ms_host[var] = ms_min[var];
-    if (best < 0 || ms_min[var] < best_ms) {
-      best = var;
-      best_ms = ms_min[var];
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (status != HYDRO_OK) {
-    g_batched_variant[dtype].store(saved);
-    return status;
-  }
-  g_batched_variant[dtype].store(best);
+  float ms[gh::kBatchedVariants] = {};
+  const int best = time_shapes(gh::kBatchedVariants, reps, s, ms, [&](int var) {
+    return batched_launch(levels_host, n_levels, dtype, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, work_dev, 0,
+                          var, s);
+  });
+  if (best < 0) return best;
+  if (times_ms_host != nullptr)
+    for (int var = 0; var < gh::kBatchedVariants; ++var) times_ms_host[var] = ms[var];
+  record_tuned(ctx, batched_key(dtype, levels_host, n_levels), best);
   return best;
 }
 
@@ -453,7 +712,7 @@ int hydro_graph_begin(void* stream) {
   return device_status(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
 }
 
-int hydro_graph_end(void* stream, void** graph_exec) {
+int hydro_graph_end(hydro_ctx* ctx, void* stream, void** graph_exec) {
   if (stream == nullptr || graph_exec == nullptr) return HYDRO_EINVAL;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(static_cast<hipStream_t>(stream), &g);
@@ -462,6 +721,10 @@ int hydro_graph_end(void* stream, void** graph_exec) {
   e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return device_status(e);
+  if (ctx != nullptr) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->graphs.insert(x);
+  }
   *graph_exec = x;
   return HYDRO_OK;
 }
@@ -471,19 +734,24 @@ int hydro_graph_launch(void* graph_exec, void* stream) {
   return device_status(hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), static_cast<hipStream_t>(stream)));
 }
 
-int hydro_graph_destroy(void* graph_exec) {
+int hydro_graph_destroy(hydro_ctx* ctx, void* graph_exec) {
   if (graph_exec == nullptr) return HYDRO_EINVAL;
+  if (ctx != nullptr) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->graphs.erase(graph_exec) == 0) return HYDRO_EINVAL;  // not captured through this context
+  }
   return device_status(hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec)));
 }
 
+// ------------------------------------------------------------ adjoint ----
 int64_t hydro_adjoint_workspace_bytes(int64_t n_groups, int32_t dtype, int32_t level) {
   if (n_groups < 0 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
   return int64_t(gh::adjoint_workspace_elems(n_groups, level != 0) * dtype_size(dtype));
 }
 
-int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* gU_pad_dev, int64_t n_groups,
-                          int32_t ghost, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
-                          double theta, void* work_dev, int64_t work_bytes, void* stream) {
+int hydro_advance_adjoint(hydro_ctx* ctx, const void* U_pad_dev, const void* gU_out_dev, void* gU_pad_dev,
+                          int64_t n_groups, int32_t ghost, int32_t dtype, double dt, double dx, double gamma,
+                          int32_t scheme, double theta, void* work_dev, int64_t work_bytes, void* stream) {
   if (n_groups < 0 || ghost < 2 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
   if (!finite_pos(dt) || !finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta))
     return HYDRO_EINVAL;
@@ -498,6 +766,10 @@ int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* g
       overlap(work_dev, need, U_pad_dev, pad) || overlap(work_dev, need, gU_out_dev, out) ||
       overlap(work_dev, need, gU_pad_dev, pad))
     return HYDRO_EINVAL;
+  int form = 0;
+  // the padded form has no tuned entry: it follows the explicit selection
+  int st = select_shape(ctx, "adjoint/padded", ctx ? &ctx->adjoint_sel[dtype] : nullptr, kDefaultAdjointVariant, &form);
+  if (st != HYDRO_OK) return st;
   const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
   const int ws = (scheme >> 8) & 3;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -506,128 +778,78 @@ int hydro_advance_adjoint(const void* U_pad_dev, const void* gU_out_dev, void* g
     e = gh::launch_mhm_adjoint_padded(static_cast<const double*>(U_pad_dev), static_cast<const double*>(gU_out_dev),
                                       static_cast<double*>(gU_pad_dev), n_groups, ghost,
                                       make_gas<double>(gamma, theta, dt, dx), first_order, ws,
-                                      static_cast<double*>(work_dev), g_adjoint_variant[0].load() == 1, s);
+                                      static_cast<double*>(work_dev), form == 1, s);
   else
     e = gh::launch_mhm_adjoint_padded(static_cast<const float*>(U_pad_dev), static_cast<const float*>(gU_out_dev),
                                       static_cast<float*>(gU_pad_dev), n_groups, ghost,
                                       make_gas<float>(gamma, theta, dt, dx), first_order, ws,
-                                      static_cast<float*>(work_dev), g_adjoint_variant[1].load() == 1, s);
+                                      static_cast<float*>(work_dev), form == 1, s);
   return device_status(e);
 }
 
-int hydro_advance_level_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
-                                int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt, double dx,
-                                double gamma, int32_t scheme, double theta, const double* dt_dev, void* work_dev,
-                                int64_t work_bytes, void* stream) {
-  if (!adjoint_geom_ok(ngx, ngy, ngz) || bc_host == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
-    return HYDRO_EINVAL;
-  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta)) return HYDRO_EINVAL;
-  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
+int hydro_advance_level_adjoint(hydro_ctx* ctx, const void* level_dev, const void* g_level_out_dev,
+                                void* g_level_in_dev, int32_t ngx, int32_t ngy, int32_t ngz, const int32_t* bc_host,
+                                int32_t dtype, double dt, double dx, double gamma, int32_t scheme, double theta,
+                                const double* dt_dev, void* work_dev, int64_t work_bytes, void* stream) {
   gh::LevelGeom geo;
-  geo.ngx = ngx;
-  geo.ngy = ngy;
-  geo.ngz = ngz;
-  for (int i = 0; i < 6; ++i) {
-    if (bc_host[i] != HYDRO_BC_PERIODIC && bc_host[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
-    geo.bc[i] = bc_host[i];
-  }
-  if (level_dev == nullptr || g_level_out_dev == nullptr || g_level_in_dev == nullptr || work_dev == nullptr)
-    return HYDRO_EINVAL;
-  const int64_t G = int64_t(ngx) * ngy * ngz;
-  const size_t es = dtype_size(dtype);
-  const size_t need = gh::adjoint_workspace_elems(G, true) * es;
-  if (work_bytes < 0 || size_t(work_bytes) < need) return HYDRO_EINVAL;
-  const size_t lb = size_t(G) * 5 * 4096 * es;
-  if (overlap(g_level_in_dev, lb, level_dev, lb) || overlap(g_level_in_dev, lb, g_level_out_dev, lb) ||
-      overlap(work_dev, need, level_dev, lb) || overlap(work_dev, need, g_level_out_dev, lb) ||
-      overlap(work_dev, need, g_level_in_dev, lb))
-    return HYDRO_EINVAL;
-  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
-  const int ws = (scheme >> 8) & 3;
-  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  if (dtype == HYDRO_F64)
-    e = gh::launch_mhm_adjoint_level(static_cast<const double*>(level_dev), static_cast<const double*>(g_level_out_dev),
-                                     static_cast<double*>(g_level_in_dev), geo,
-                                     make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws,
-                                     static_cast<double*>(work_dev), g_adjoint_variant[0].load() == 1, s);
-  else
-    e = gh::launch_mhm_adjoint_level(static_cast<const float*>(level_dev), static_cast<const float*>(g_level_out_dev),
-                                     static_cast<float*>(g_level_in_dev), geo,
-                                     make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws,
-                                     static_cast<float*>(work_dev), g_adjoint_variant[1].load() == 1, s);
-  return device_status(e);
+  int st = check_level_adjoint_args(level_dev, g_level_out_dev, g_level_in_dev, ngx, ngy, ngz, bc_host, dtype, dt, dx,
+                                    gamma, scheme, theta, dt_dev, work_dev, work_bytes, &geo);
+  if (st != HYDRO_OK) return st;
+  int form = 0;
+  st = select_shape(ctx, adjoint_key(dtype, ngx, ngy, ngz), ctx ? &ctx->adjoint_sel[dtype] : nullptr,
+                    kDefaultAdjointVariant, &form);
+  if (st != HYDRO_OK) return st;
+  return level_adjoint_launch(level_dev, g_level_out_dev, g_level_in_dev, geo, dtype, dt, dx, gamma, scheme, theta,
+                              dt_dev, work_dev, form, static_cast<hipStream_t>(stream));
 }
 
-int hydro_autotune_adjoint(const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev, int32_t ngx,
-                           int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx, double gamma,
-                           void* work_dev, int64_t work_bytes, int32_t reps, float* times_ms_host, void* stream) {
-  if (reps < 1 || reps > 1000 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int saved = g_adjoint_variant[dtype].load();
+int hydro_autotune_adjoint(hydro_ctx* ctx, const void* level_dev, const void* g_level_out_dev, void* g_level_in_dev,
+                           int32_t ngx, int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dx,
+                           double gamma, void* work_dev, int64_t work_bytes, int32_t reps, float* times_ms_host,
+                           void* stream) {
+  if (ctx == nullptr || reps < 1 || reps > 1000) return HYDRO_EINVAL;
   const double dt = 1e-3 * dx;  // any positive step does the same work
-  auto launch = [&]() {
-    return hydro_advance_level_adjoint(level_dev, g_level_out_dev, g_level_in_dev, ngx, ngy, ngz, bc_host, dtype, dt,
-                                       dx, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, work_dev, work_bytes,
-                                       stream);
-  };
-  // argument errors surface here, before any event is created
-  int status = launch();
-  if (status != HYDRO_OK) return status;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return device_status(hipGetLastError());
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return device_status(hipGetLastError());
-  }
-  float ms_min[2] = {0.0f, 0.0f};
-  // two passes over both forms, each form's time the smaller of its two
-  for (int pass = 0; pass < 2 && status == HYDRO_OK; ++pass) {
-    for (int form = 0; form < 2 && status == HYDRO_OK; ++form) {
-      g_adjoint_variant[dtype].store(form);
-      status = launch();
-      if (status != HYDRO_OK) break;
-      hipError_t he = hipEventRecord(e0, s);
-      for (int r = 0; r < reps && status == HYDRO_OK && he == hipSuccess; ++r) status = launch();
-      if (status != HYDRO_OK) break;
-      if (he == hipSuccess) he = hipEventRecord(e1, s);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (he != hipSuccess) {
-        status = device_status(he);
-        break;
-      }
-      ms /= float(reps);
-      if (pass == 0 || ms < ms_min[form]) ms_min[form] = ms;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (status != HYDRO_OK) {
-    g_adjoint_variant[dtype].store(saved);
-    return status;
-  }
+  gh::LevelGeom geo;
+  const int st = check_level_adjoint_args(level_dev, g_level_out_dev, g_level_in_dev, ngx, ngy, ngz, bc_host, dtype,
+                                          dt, dx, gamma, HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, work_dev,
+                                          work_bytes, &geo);
+  if (st != HYDRO_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float ms[2] = {};
+  const int best = time_shapes(2, reps, s, ms, [&](int form) {
+    return level_adjoint_launch(level_dev, g_level_out_dev, g_level_in_dev, geo, dtype, dt, dx, gamma,
+                                HYDRO_SCHEME_MHM_PLM_HLLC, 1.5, nullptr, work_dev, form, s);
+  });
+  if (best < 0) return best;
   if (times_ms_host != nullptr) {
-    times_ms_host[0] = ms_min[0];
-    times_ms_host[1] = ms_min[1];
+    times_ms_host[0] = ms[0];
+    times_ms_host[1] = ms[1];
   }
-  const int best = ms_min[1] < ms_min[0] ? 1 : 0;
-  g_adjoint_variant[dtype].store(best);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuned[adjoint_key(dtype, ngx, ngy, ngz)] = best;
+    ctx->adjoint_sel[dtype] = best;
+    (void)save_cache_locked(ctx);
+  }
   return best;
 }
 
-int hydro_set_adjoint_variant(int32_t dtype, int32_t variant) {
-  if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
+int hydro_set_adjoint_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant) {
+  if (ctx == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
   if (variant != 0 && variant != 1) return HYDRO_EINVAL;
-  g_adjoint_variant[dtype].store(variant);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->adjoint_sel[dtype] = variant;
+  const std::string prefix = std::string("adjoint/") + dtype_name(dtype) + "/";
+  for (auto it = ctx->tuned.begin(); it != ctx->tuned.end();)
+    it = it->first.compare(0, prefix.size(), prefix) == 0 ? ctx->tuned.erase(it) : std::next(it);
   return HYDRO_OK;
 }
 
-int hydro_get_adjoint_variant(int32_t dtype) {
+int hydro_get_adjoint_variant(hydro_ctx* ctx, int32_t dtype) {
   if (dtype != HYDRO_F64 && dtype != HYDRO_F32) return HYDRO_EINVAL;
-  return g_adjoint_variant[dtype].load();
+  if (ctx == nullptr) return kDefaultAdjointVariant;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return ctx->adjoint_sel[dtype] >= 0 ? ctx->adjoint_sel[dtype] : kDefaultAdjointVariant;
 }
 
 int hydro_dt(const void* U_pad_dev, int64_t n_groups, int32_t ghost, int32_t dtype, double dx, double gamma,

@@ -53,8 +53,9 @@ struct BatchArgs {
   long long total;  // number of work items (groups over all levels)
 };
 
-// work: 2 device uint32, zero before the first launch; every launch leaves
-// them zero.  grid: number of persistent workgroups.
+// work: kBatchWorkWords device uint32 (kQueues ticket counters and one
+// departure counter), zero before the first launch; every launch leaves them
+// zero.  grid: number of persistent workgroups.
 template <typename T>
 hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
                               unsigned int* work, int variant, int grid, hipStream_t stream);

@@ -18,8 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhydro.so")
 
 HYDRO_OK = 0
+HYDRO_UNPHYSICAL = 1
 HYDRO_EINVAL = -1
 HYDRO_EDEVICE = -2
+HYDRO_ENOTUNED = -3
+HYDRO_EIO = -4
 F64, F32 = 0, 1
 SCHEME_MHM_PLM_HLLC = 1
 WAVESPEED_ROE = 0 << 8
@@ -59,33 +62,40 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     sig = {
+        "hydro_ctx_create": (i32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_char_p]),
+        "hydro_ctx_destroy": (i32, [P]),
+        "hydro_ctx_save": (i32, [P]),
+        "hydro_ctx_set_require_tuned": (i32, [P, i32]),
+        "hydro_ctx_num_tuned": (i32, [P]),
+        "hydro_check_unphysical": (i32, [P, P, P]),
         "hydro_advance": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P, P]),
-        "hydro_advance_level": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, f64, P, P, P,
+        "hydro_advance_level": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, f64, P, P, P,
                                       P]),
         "hydro_dt": (i32, [P, i64, i32, i32, f64, f64, f64, P, P, P]),
         "hydro_fill_ghosts": (i32, [P, P, i32, i32, i32, i32, i32, P, P]),
         "hydro_gather_ghost_adjoint": (i32, [P, P, i32, i32, i32, i32, i32, P, P]),
         "hydro_num_variants": (i32, []),
-        "hydro_set_variant": (i32, [i32, i32]),
-        "hydro_set_level_variant": (i32, [i32, i32, i32]),
-        "hydro_get_level_variant": (i32, [i32, i32]),
-        "hydro_set_adjoint_variant": (i32, [i32, i32]),
-        "hydro_get_adjoint_variant": (i32, [i32]),
-        "hydro_get_variant": (i32, [i32]),
+        "hydro_set_variant": (i32, [P, i32, i32]),
+        "hydro_set_level_variant": (i32, [P, i32, i32, i32]),
+        "hydro_get_level_variant": (i32, [P, i32, i32]),
+        "hydro_set_adjoint_variant": (i32, [P, i32, i32]),
+        "hydro_get_adjoint_variant": (i32, [P, i32]),
+        "hydro_get_variant": (i32, [P, i32]),
         "hydro_variant_name": (i32, [i32, ctypes.c_char_p, i32]),
-        "hydro_autotune": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, i32, P, P]),
-        "hydro_advance_batched": (i32, [P, i32, i32, f64, i32, f64, P, P, i32, P]),
-        "hydro_set_batched_variant": (i32, [i32, i32]),
-        "hydro_get_batched_variant": (i32, [i32]),
-        "hydro_autotune_batched": (i32, [P, i32, i32, f64, P, i32, P, P]),
-        "hydro_autotune_adjoint": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, P, i64, i32, P, P]),
+        "hydro_autotune": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, P, i64, i32, P, P]),
+        "hydro_advance_batched": (i32, [P, P, i32, i32, f64, i32, f64, P, P, i32, P]),
+        "hydro_set_batched_variant": (i32, [P, i32, i32]),
+        "hydro_get_batched_variant": (i32, [P, i32]),
+        "hydro_autotune_batched": (i32, [P, P, i32, i32, f64, P, i32, P, P]),
+        "hydro_autotune_adjoint": (i32, [P, P, P, P, i32, i32, i32, P, i32, f64, f64, P, i64, i32, P, P]),
         "hydro_graph_begin": (i32, [P]),
-        "hydro_graph_end": (i32, [P, ctypes.POINTER(ctypes.c_void_p)]),
+        "hydro_graph_end": (i32, [P, P, ctypes.POINTER(ctypes.c_void_p)]),
         "hydro_graph_launch": (i32, [P, P]),
-        "hydro_graph_destroy": (i32, [P]),
+        "hydro_graph_destroy": (i32, [P, P]),
         "hydro_adjoint_workspace_bytes": (i64, [i64, i32, i32]),
-        "hydro_advance_adjoint": (i32, [P, P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, i64, P]),
-        "hydro_advance_level_adjoint": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, i64, P]),
+        "hydro_advance_adjoint": (i32, [P, P, P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, i64, P]),
+        "hydro_advance_level_adjoint": (i32, [P, P, P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, i64,
+                                              P]),
         "hydro_strerror": (ctypes.c_char_p, [i32]),
         "hydro_last_hip_error": (i32, []),
         "hydro_version": (i32, []),
@@ -131,6 +141,68 @@ def _check(status: int, fn: str):
         raise HydroError(fn, status)
 
 
+class Context:
+    """A solver context (hydro_ctx): launch-shape selections, explicit or
+    autotuned per dtype and lattice, optionally persisted in a tuning-cache
+    JSON file, and the graphs captured through it."""
+
+    def __init__(self, tune_cache: Optional[str] = None, require_tuned: bool = False):
+        lib = load()
+        h = ctypes.c_void_p()
+        st = lib.hydro_ctx_create(ctypes.byref(h), None if tune_cache is None else os.fsencode(tune_cache))
+        _check(st, "hydro_ctx_create")
+        self.handle = h
+        if require_tuned:
+            _check(lib.hydro_ctx_set_require_tuned(h, 1), "hydro_ctx_set_require_tuned")
+
+    def save(self) -> None:
+        _check(load().hydro_ctx_save(self.handle), "hydro_ctx_save")
+
+    def num_tuned(self) -> int:
+        n = load().hydro_ctx_num_tuned(self.handle)
+        if n < 0:
+            raise HydroError("hydro_ctx_num_tuned", n)
+        return int(n)
+
+    def close(self) -> None:
+        if self.handle is not None:
+            load().hydro_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    """The module's context, used by every call given ctx=None."""
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def _ctx(ctx: Optional[Context]):
+    return (ctx if ctx is not None else default_context()).handle
+
+
+def check_unphysical(n_bad: torch.Tensor) -> int:
+    """Wait for the current stream and return the unphysical count held in the
+    device int32 n_bad (hydro_check_unphysical)."""
+    if n_bad.dtype != torch.int32 or n_bad.numel() < 1:
+        raise ValueError("n_bad must be an int32 tensor")
+    v = ctypes.c_int32()
+    st = load().hydro_check_unphysical(_dev(n_bad, "n_bad"), _stream(), ctypes.byref(v))
+    if st not in (HYDRO_OK, HYDRO_UNPHYSICAL):
+        raise HydroError("hydro_check_unphysical", st)
+    return int(v.value)
+
+
 def ghost_of(U_pad: torch.Tensor) -> int:
     P = U_pad.shape[-1]
     if U_pad.dim() != 5 or U_pad.shape[1] != 5 or tuple(U_pad.shape[2:]) != (P, P, P) or (P - 16) % 2:
@@ -161,7 +233,7 @@ def advance_level(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt:
                   theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, out: Optional[torch.Tensor] = None,
                   n_bad: Optional[torch.Tensor] = None, dt_dev: Optional[torch.Tensor] = None, c_cfl: float = 0.5,
                   dt_next: Optional[torch.Tensor] = None, dt_patch_next: Optional[torch.Tensor] = None,
-                  dt_reset: Optional[torch.Tensor] = None) -> torch.Tensor:
+                  dt_reset: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """One MHM step of a whole level read from level storage (hydro_advance_level)."""
     ngx, ngy, ngz = (int(v) for v in ng)
     G = ngx * ngy * ngz
@@ -174,7 +246,7 @@ def advance_level(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt:
     if dt_patch_next is not None and (dt_patch_next.dtype != torch.float64 or dt_patch_next.numel() != 8 * G):
         raise ValueError("dt_patch_next must hold G*8 float64")
     b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
-    st = load().hydro_advance_level(_dev(level, "level"), _dev(out, "out"), ngx, ngy, ngz, b, _dtype_code(level),
+    st = load().hydro_advance_level(_ctx(ctx), _dev(level, "level"), _dev(out, "out"), ngx, ngy, ngz, b, _dtype_code(level),
                                     float(dt), float(dx), float(gamma), int(scheme), float(theta),
                                     _opt(dt_dev, "dt_dev", torch.float64), _opt(n_bad, "n_bad", torch.int32),
                                     float(c_cfl), _opt(dt_next, "dt_next", torch.float64),
@@ -200,7 +272,7 @@ def _check_work(work: Optional[torch.Tensor]) -> None:
 
 def advance_adjoint(U_pad: torch.Tensor, gU_out: torch.Tensor, dt: float, dx: float, gamma: float,
                     theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, out: Optional[torch.Tensor] = None,
-                    work: Optional[torch.Tensor] = None) -> torch.Tensor:
+                    work: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """Cotangent of U_pad given that of the step's output (hydro_advance_adjoint)."""
     gh = ghost_of(U_pad)
     G = U_pad.shape[0]
@@ -213,7 +285,7 @@ def advance_adjoint(U_pad: torch.Tensor, gU_out: torch.Tensor, dt: float, dx: fl
         out = torch.empty_like(U_pad)
     if work is None:
         work = adjoint_workspace(G, U_pad.dtype, False, U_pad.device)
-    st = load().hydro_advance_adjoint(_dev(U_pad, "U_pad"), _dev(gU_out, "gU_out"), _dev(out, "out"), G, gh,
+    st = load().hydro_advance_adjoint(_ctx(ctx), _dev(U_pad, "U_pad"), _dev(gU_out, "gU_out"), _dev(out, "out"), G, gh,
                                       _dtype_code(U_pad), float(dt), float(dx), float(gamma), int(scheme), float(theta),
                                       _dev(work, "work"), work.numel(), _stream())
     _check(st, "hydro_advance_adjoint")
@@ -223,7 +295,7 @@ def advance_adjoint(U_pad: torch.Tensor, gU_out: torch.Tensor, dt: float, dx: fl
 def advance_level_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt: float,
                           dx: float, gamma: float, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC,
                           out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None,
-                          dt_dev: Optional[torch.Tensor] = None) -> torch.Tensor:
+                          dt_dev: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
     """Cotangent of a level's input state given that of its stepped state (hydro_advance_level_adjoint)."""
     ngx, ngy, ngz = (int(v) for v in ng)
     G = ngx * ngy * ngz
@@ -237,7 +309,7 @@ def advance_level_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence
     if work is None:
         work = adjoint_workspace(G, level.dtype, True, level.device)
     b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
-    st = load().hydro_advance_level_adjoint(_dev(level, "level"), _dev(g_out, "g_out"), _dev(out, "out"), ngx, ngy,
+    st = load().hydro_advance_level_adjoint(_ctx(ctx), _dev(level, "level"), _dev(g_out, "g_out"), _dev(out, "out"), ngx, ngy,
                                             ngz, b, _dtype_code(level), float(dt), float(dx), float(gamma),
                                             int(scheme), float(theta), _opt(dt_dev, "dt_dev", torch.float64),
                                             _dev(work, "work"), work.numel(), _stream())
@@ -247,9 +319,10 @@ def advance_level_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence
 
 def autotune_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dx: float,
                      gamma: float, reps: int = 3, work: Optional[torch.Tensor] = None,
-                     out: Optional[torch.Tensor] = None) -> Tuple[int, list]:
-    """Time both adjoint forms on this level and keep the faster for its dtype
-    (hydro_autotune_adjoint); returns (form, [ms fused, ms two kernels])."""
+                     out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> Tuple[int, list]:
+    """Time both adjoint forms on this level and record the faster in the
+    context for its dtype and lattice (hydro_autotune_adjoint); returns
+    (form, [ms fused, ms two kernels])."""
     ngx, ngy, ngz = (int(v) for v in ng)
     G = ngx * ngy * ngz
     if tuple(level.shape) != (G, 5, 16, 16, 16) or g_out.shape != level.shape or g_out.dtype != level.dtype:
@@ -263,7 +336,7 @@ def autotune_adjoint(level: torch.Tensor, g_out: torch.Tensor, ng: Sequence[int]
         work = adjoint_workspace(G, level.dtype, True, level.device)
     b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
     times = (ctypes.c_float * 2)()
-    st = load().hydro_autotune_adjoint(_dev(level, "level"), _dev(g_out, "g_out"), _dev(out, "out"), ngx, ngy, ngz, b,
+    st = load().hydro_autotune_adjoint(_ctx(ctx), _dev(level, "level"), _dev(g_out, "g_out"), _dev(out, "out"), ngx, ngy, ngz, b,
                                        _dtype_code(level), float(dx), float(gamma), _dev(work, "work"), work.numel(),
                                        int(reps), times, _stream())
     if st < 0:
@@ -349,7 +422,7 @@ def _levels_array(levels):
 
 
 def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC,
-                    n_bad: Optional[torch.Tensor] = None, grid: int = 0) -> None:
+                    n_bad: Optional[torch.Tensor] = None, grid: int = 0, ctx: Optional[Context] = None) -> None:
     """One step of several levels in one persistent launch (hydro_advance_batched).
 
     levels: sequence of (level_in, level_out, ng, bc, dt, dx[, dt_dev]);
@@ -357,38 +430,41 @@ def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5
     if work.dtype != torch.int32 or work.numel() < BATCH_WORK_WORDS:
         raise ValueError("work must hold %d int32" % BATCH_WORK_WORDS)
     arr, dtype = _levels_array(levels)
-    st = load().hydro_advance_batched(ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
+    st = load().hydro_advance_batched(_ctx(ctx), ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
                                       float(gamma), int(scheme), float(theta), _opt(n_bad, "n_bad", torch.int32),
                                       _dev(work, "work"), int(grid), _stream())
     _check(st, "hydro_advance_batched")
 
 
-def autotune_batched(levels, gamma: float, work: torch.Tensor, reps: int = 5) -> Tuple[int, list]:
+def autotune_batched(levels, gamma: float, work: torch.Tensor, reps: int = 5,
+                     ctx: Optional[Context] = None) -> Tuple[int, list]:
     if work.dtype != torch.int32 or work.numel() < BATCH_WORK_WORDS:
         raise ValueError("work must hold %d int32" % BATCH_WORK_WORDS)
     arr, dtype = _levels_array(levels)
     times = (ctypes.c_float * BATCHED_VARIANTS)()
-    st = load().hydro_autotune_batched(ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
+    st = load().hydro_autotune_batched(_ctx(ctx), ctypes.cast(arr, ctypes.c_void_p), len(levels), _dtype_code(levels[0][0]),
                                        float(gamma), _dev(work, "work"), int(reps), times, _stream())
     if st < 0:
         raise HydroError("hydro_autotune_batched", st)
     return int(st), list(times)
 
 
-def set_batched_variant(dtype, v: int) -> None:
-    _check(load().hydro_set_batched_variant(F64 if dtype == torch.float64 else F32, int(v)), "hydro_set_batched_variant")
+def set_batched_variant(dtype, v: int, ctx: Optional[Context] = None) -> None:
+    _check(load().hydro_set_batched_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32, int(v)),
+           "hydro_set_batched_variant")
 
 
-def get_batched_variant(dtype) -> int:
-    return int(load().hydro_get_batched_variant(F64 if dtype == torch.float64 else F32))
+def get_batched_variant(dtype, ctx: Optional[Context] = None) -> int:
+    return int(load().hydro_get_batched_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32))
 
 
 class Graph:
     """A captured sequence of library calls (hydro_graph_*), replayed on the
     current stream.  Capture happens on a private non-default stream."""
 
-    def __init__(self):
+    def __init__(self, ctx: Optional[Context] = None):
         self.handle = None
+        self.ctx = ctx if ctx is not None else default_context()
         self.stream = torch.cuda.Stream()
 
     def capture(self, fn) -> "Graph":
@@ -402,10 +478,10 @@ class Graph:
             except BaseException as e:  # always end the capture
                 err = e
             h = ctypes.c_void_p()
-            st = lib.hydro_graph_end(self.stream.cuda_stream, ctypes.byref(h))
+            st = lib.hydro_graph_end(self.ctx.handle, self.stream.cuda_stream, ctypes.byref(h))
             if err is not None:
                 if st == HYDRO_OK:
-                    lib.hydro_graph_destroy(h)
+                    lib.hydro_graph_destroy(self.ctx.handle, h)
                 raise err
             _check(st, "hydro_graph_end")
         self.handle = h
@@ -416,9 +492,9 @@ class Graph:
         _check(load().hydro_graph_launch(self.handle, _stream()), "hydro_graph_launch")
 
     def close(self) -> None:
-        if self.handle is not None:
-            load().hydro_graph_destroy(self.handle)
-            self.handle = None
+        if self.handle is not None and self.ctx.handle is not None:
+            load().hydro_graph_destroy(self.ctx.handle, self.handle)
+        self.handle = None
 
     def __del__(self):
         try:
@@ -437,8 +513,9 @@ class MultiLevel:
     periodic bricks (no coarse-fine coupling)."""
 
     def __init__(self, levels, gamma: float, dt0: float, dtype=torch.float64, batched: bool = True,
-                 theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, device=None):
+                 theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, device=None, ctx: Optional[Context] = None):
         dev = torch.device("cuda") if device is None else torch.device(device)
+        self.ctx = ctx
         self.geo = [(tuple(int(v) for v in lv[0]), float(lv[1]), tuple(int(v) for v in lv[2])) for lv in levels]
         self.L = len(self.geo)
         self.gamma, self.dt0, self.batched = float(gamma), float(dt0), bool(batched)
@@ -473,10 +550,11 @@ class MultiLevel:
         lvls = self.stage_levels(s)
         ent = self._entries(lvls)
         if self.batched:
-            advance_batched(ent, self.gamma, self.work, self.theta, self.scheme, n_bad=self.n_bad)
+            advance_batched(ent, self.gamma, self.work, self.theta, self.scheme, n_bad=self.n_bad, ctx=self.ctx)
         else:
             for lin, lout, ng, bc, dt, dx in ent:
-                advance_level(lin, ng, bc, dt, dx, self.gamma, self.theta, self.scheme, out=lout, n_bad=self.n_bad)
+                advance_level(lin, ng, bc, dt, dx, self.gamma, self.theta, self.scheme, out=lout, n_bad=self.n_bad,
+                              ctx=self.ctx)
         for l in lvls:
             self.cur[l] = 1 - self.cur[l]
 
@@ -495,17 +573,17 @@ class MultiLevel:
             counts[key] = counts.get(key, 0) + 1
         total = [0.0] * BATCHED_VARIANTS
         for lvls, c in counts.items():
-            _, times = autotune_batched(self._entries(lvls), self.gamma, self.work, reps)
+            _, times = autotune_batched(self._entries(lvls), self.gamma, self.work, reps, ctx=self.ctx)
             total = [a + c * t for a, t in zip(total, times)]
         best = min(range(len(total)), key=total.__getitem__)
-        set_batched_variant(self.dtype, best)
+        set_batched_variant(self.dtype, best, ctx=self.ctx)
         return best, total
 
     def capture(self, n_coarse: int = 2) -> Graph:
         """Graph of n_coarse coarse steps (an even count returns every level's
         state to the buffer it started in, so the graph can be replayed)."""
         start = list(self.cur)
-        g = Graph().capture(lambda: [self.coarse_step() for _ in range(n_coarse)])
+        g = Graph(self.ctx).capture(lambda: [self.coarse_step() for _ in range(n_coarse)])
         if self.cur != start:
             raise ValueError("captured steps must return every level to its starting buffer")
         return g
@@ -523,50 +601,55 @@ def variant_name(v: int) -> str:
     return buf.value.decode()
 
 
-def set_adjoint_variant(dtype, v: int) -> None:
+def set_adjoint_variant(dtype, v: int, ctx: Optional[Context] = None) -> None:
     """Form of the step adjoint for a dtype: 0 fused sweep, 1 two kernels with a face workspace."""
-    _check(load().hydro_set_adjoint_variant(F64 if dtype == torch.float64 else F32, int(v)),
+    _check(load().hydro_set_adjoint_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32, int(v)),
            "hydro_set_adjoint_variant")
 
 
-def get_adjoint_variant(dtype) -> int:
-    v = load().hydro_get_adjoint_variant(F64 if dtype == torch.float64 else F32)
+def get_adjoint_variant(dtype, ctx: Optional[Context] = None) -> int:
+    v = load().hydro_get_adjoint_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32)
     if v < 0:
         raise HydroError("hydro_get_adjoint_variant", v)
     return int(v)
 
 
-def set_variant(dtype, v: int) -> None:
-    _check(load().hydro_set_variant(F64 if dtype == torch.float64 else F32, int(v)), "hydro_set_variant")
+def set_variant(dtype, v: int, ctx: Optional[Context] = None) -> None:
+    _check(load().hydro_set_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32, int(v)), "hydro_set_variant")
 
 
-def get_variant(dtype) -> int:
-    return int(load().hydro_get_variant(F64 if dtype == torch.float64 else F32))
+def get_variant(dtype, ctx: Optional[Context] = None) -> int:
+    return int(load().hydro_get_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32))
 
 
-def set_level_variant(dtype, with_cfl: bool, v: int) -> None:
-    _check(load().hydro_set_level_variant(F64 if dtype == torch.float64 else F32, int(bool(with_cfl)), int(v)),
-           "hydro_set_level_variant")
+def set_level_variant(dtype, with_cfl: bool, v: int, ctx: Optional[Context] = None) -> None:
+    _check(load().hydro_set_level_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32, int(bool(with_cfl)),
+                                          int(v)), "hydro_set_level_variant")
 
 
-def get_level_variant(dtype, with_cfl: bool) -> int:
-    return int(load().hydro_get_level_variant(F64 if dtype == torch.float64 else F32, int(bool(with_cfl))))
+def get_level_variant(dtype, with_cfl: bool, ctx: Optional[Context] = None) -> int:
+    return int(load().hydro_get_level_variant(_ctx(ctx), F64 if dtype == torch.float64 else F32,
+                                              int(bool(with_cfl))))
 
 
 def autotune(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dx: float, gamma: float,
-             reps: int = 5) -> Tuple[int, list]:
+             reps: int = 5, ctx: Optional[Context] = None) -> Tuple[int, list]:
     """Time every launch shape on this level in both kernel forms (without and
-    with the CFL epilogue), select the fastest of each (hydro_autotune).
+    with the CFL epilogue), record the fastest of each in the context for this
+    dtype and lattice (hydro_autotune).
 
     Returns (chosen variant of the CFL form, mean ms per variant: the form
     without CFL first, then the CFL form)."""
     ngx, ngy, ngz = (int(v) for v in ng)
+    G = ngx * ngy * ngz
     scratch = torch.empty_like(level)
+    cfl = torch.empty(3 + 8 * G, dtype=torch.float64, device=level.device)
     n = num_variants()
     times = (ctypes.c_float * (2 * n))()
     b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
-    st = load().hydro_autotune(_dev(level, "level"), _dev(scratch, "scratch"), ngx, ngy, ngz, b, _dtype_code(level),
-                               float(dx), float(gamma), int(reps), times, _stream())
+    st = load().hydro_autotune(_ctx(ctx), _dev(level, "level"), _dev(scratch, "scratch"), ngx, ngy, ngz, b,
+                               _dtype_code(level), float(dx), float(gamma), _dev(cfl, "cfl"), cfl.numel() * 8,
+                               int(reps), times, _stream())
     if st < 0:
         raise HydroError("hydro_autotune", st)
     return int(st), list(times)
@@ -586,7 +669,8 @@ class LevelSolver:
 
     def __init__(self, ng: Sequence[int], dx: float, gamma: float, bc: Sequence[int] = (0,) * 6,
                  ghost: int = 3, dtype=torch.float64, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC,
-                 c_cfl: float = 0.5, device=None, fused: bool = True):
+                 c_cfl: float = 0.5, device=None, fused: bool = True, ctx: Optional[Context] = None):
+        self.ctx = ctx
         self.ng = tuple(int(v) for v in ng)
         self.G = self.ng[0] * self.ng[1] * self.ng[2]
         self.dx, self.gamma, self.bc, self.ghost = float(dx), float(gamma), tuple(bc), int(ghost)
@@ -639,12 +723,12 @@ class LevelSolver:
             if dt is None:
                 advance_level(self.bufs[self.cur], self.ng, self.bc, 1.0, self.dx, self.gamma, self.theta,
                               self.scheme, out=nxt, n_bad=self.n_bad, dt_dev=a, c_cfl=self.c_cfl, dt_next=b,
-                              dt_reset=c)
+                              dt_reset=c, ctx=self.ctx)
                 self.dt_min = a
                 self.turn = (self.turn + 1) % 3
             else:
                 advance_level(self.bufs[self.cur], self.ng, self.bc, dt, self.dx, self.gamma, self.theta,
-                              self.scheme, out=nxt, n_bad=self.n_bad)
+                              self.scheme, out=nxt, n_bad=self.n_bad, ctx=self.ctx)
                 self.primed = False
             if events is not None:
                 events[1].record(stream)

@@ -42,6 +42,22 @@ def test_status_strings(lib):
     assert lib.hydro_version() >= 1
 
 
+class Ctx:
+    """A hydro_ctx for the duration of a with-block."""
+
+    def __init__(self, lib, path=None):
+        self.lib, self.path = lib, path
+
+    def __enter__(self):
+        h = ctypes.c_void_p()
+        assert self.lib.hydro_ctx_create(ctypes.byref(h), None if self.path is None else os.fsencode(self.path)) == 0
+        self.h = h
+        return h
+
+    def __exit__(self, *a):
+        assert self.lib.hydro_ctx_destroy(self.h) == 0
+
+
 def _adv(lib, **kw):
     a = dict(U=ctypes.c_void_p(4096), O=ctypes.c_void_p(1 << 40), G=1, gh=3, dtype=0, dt=1e-3, dx=1.0 / 64,
              gamma=5.0 / 3.0, scheme=1, theta=1.5, dt_dev=None, nbad=None, stream=None)
@@ -100,14 +116,15 @@ def test_level_entry_points_reject_bad_geometry(lib, ng):
     P = ctypes.c_void_p
     bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
     a, b = P(4096), P(1 << 46)
-    assert lib.hydro_advance_level(a, b, *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, None, 0.5, None, None, None,
-                                   None) == -1
-    assert lib.hydro_advance_level_adjoint(a, b, P(1 << 47), *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, P(1 << 45),
-                                           1 << 40, None) == -1
+    assert lib.hydro_advance_level(None, a, b, *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, None, 0.5, None, None,
+                                   None, None) == -1
+    assert lib.hydro_advance_level_adjoint(None, a, b, P(1 << 47), *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None,
+                                           P(1 << 45), 1 << 40, None) == -1
     assert lib.hydro_fill_ghosts(a, b, *ng, 3, 0, bc, None) == -1
     assert lib.hydro_gather_ghost_adjoint(a, b, *ng, 3, 0, bc, None) == -1
-    assert lib.hydro_autotune_adjoint(a, b, P(1 << 47), *ng, bc, 0, 0.01, 1.4, P(1 << 45), 1 << 40, 1, None,
-                                      None) == -1
+    with Ctx(lib) as c:
+        assert lib.hydro_autotune_adjoint(c, a, b, P(1 << 47), *ng, bc, 0, 0.01, 1.4, P(1 << 45), 1 << 40, 1, None,
+                                          None) == -1
 
 
 def test_autotune_adjoint_rejects_bad_arguments(lib):
@@ -115,11 +132,13 @@ def test_autotune_adjoint_rejects_bad_arguments(lib):
     bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
     f = lib.hydro_autotune_adjoint
     a, b, c, w = P(4096), P(1 << 44), P(1 << 45), P(1 << 46)
-    assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 1 << 30, 0, None, None) == -1      # reps < 1
-    assert f(a, b, c, 1, 1, 1, bc, 2, 0.01, 1.4, w, 1 << 30, 1, None, None) == -1      # dtype
-    assert f(a, b, c, 1, 1, 1, bc, 0, -0.01, 1.4, w, 1 << 30, 1, None, None) == -1     # dx
-    assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 16, 1, None, None) == -1           # workspace too small
-    assert f(a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, None, 1 << 30, 1, None, None) == -1   # no workspace
+    with Ctx(lib) as x:
+        assert f(x, a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 1 << 30, 0, None, None) == -1      # reps < 1
+        assert f(x, a, b, c, 1, 1, 1, bc, 2, 0.01, 1.4, w, 1 << 30, 1, None, None) == -1      # dtype
+        assert f(x, a, b, c, 1, 1, 1, bc, 0, -0.01, 1.4, w, 1 << 30, 1, None, None) == -1     # dx
+        assert f(x, a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 16, 1, None, None) == -1           # workspace too small
+        assert f(x, a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, None, 1 << 30, 1, None, None) == -1   # no workspace
+    assert f(None, a, b, c, 1, 1, 1, bc, 0, 0.01, 1.4, w, 1 << 30, 1, None, None) == -1      # tuning needs a ctx
 
 
 @pytest.mark.parametrize("ng", [(1 << 19, 1, 1), (1, 1, 1 << 19), (1 << 14, 1 << 14, 1)])
@@ -129,6 +148,99 @@ def test_adjoint_entry_points_reject_their_extra_limits(lib, ng):
     P = ctypes.c_void_p
     bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
     a, b = P(4096), P(1 << 46)
-    assert lib.hydro_advance_level_adjoint(a, b, P(1 << 47), *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None, P(1 << 45),
-                                           1 << 62, None) == -1
+    assert lib.hydro_advance_level_adjoint(None, a, b, P(1 << 47), *ng, bc, 0, 1e-3, 0.01, 1.4, 1, 1.5, None,
+                                           P(1 << 45), 1 << 62, None) == -1
     assert lib.hydro_gather_ghost_adjoint(a, b, *ng, 3, 0, bc, None) == -1
+
+
+# ------------------------------------------------------------- contexts ----
+
+def _level(lib, ctx, ng=(2, 2, 2), dtype=0, cfl=False):
+    """hydro_advance_level with valid arguments and fake device pointers: it
+    returns before any HIP call only if the shape lookup refuses."""
+    P = ctypes.c_void_p
+    bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    return lib.hydro_advance_level(ctx, P(4096), P(1 << 44), *ng, bc, dtype, 1e-3, 0.01, 1.4, 1, 1.5, None, None,
+                                   0.5, P(1 << 45) if cfl else None, None, None, None)
+
+
+def test_status_codes_of_the_context_api(lib):
+    assert lib.hydro_strerror(1).startswith(b"unphysical")
+    assert lib.hydro_strerror(-3).startswith(b"no tuned")
+    assert lib.hydro_strerror(-4).startswith(b"tuning cache")
+    assert lib.hydro_ctx_create(None, None) == -1
+    assert lib.hydro_ctx_destroy(None) == -1
+    assert lib.hydro_check_unphysical(None, None, None) == -1
+
+
+def test_two_contexts_keep_separate_selections(lib):
+    with Ctx(lib) as a, Ctx(lib) as b:
+        assert lib.hydro_set_level_variant(a, 0, 1, 3) == 0
+        assert lib.hydro_set_batched_variant(b, 1, 5) == 0
+        assert lib.hydro_set_adjoint_variant(a, 1, 1) == 0
+        assert lib.hydro_get_level_variant(a, 0, 1) == 3
+        assert lib.hydro_get_level_variant(b, 0, 1) == 0          # default
+        assert lib.hydro_get_batched_variant(b, 1) == 5
+        assert lib.hydro_get_batched_variant(a, 1) == 0
+        assert lib.hydro_get_adjoint_variant(a, 1) == 1
+        assert lib.hydro_get_adjoint_variant(b, 1) == 0
+    # setters need a context, getters without one report the defaults
+    assert lib.hydro_set_level_variant(None, 0, 1, 1) == -1
+    assert lib.hydro_get_level_variant(None, 0, 1) == 0
+    assert lib.hydro_set_variant(None, 0, 1) == -1
+
+
+def test_require_tuned_refuses_untuned_launches(lib, tmp_path):
+    path = tmp_path / "tune.json"
+    path.write_text('{"version": 1, "entries": {\n  "level/f64/plain/2x2x2": 1,\n  "adjoint/f32/4x4x4": 0\n}}\n')
+    with Ctx(lib, str(path)) as c:
+        assert lib.hydro_ctx_num_tuned(c) == 2
+        assert lib.hydro_ctx_set_require_tuned(c, 1) == 0
+        assert _level(lib, c, ng=(2, 2, 3)) == -3               # no entry for this lattice
+        assert _level(lib, c, ng=(2, 2, 2), cfl=True) == -3     # nor for the CFL form
+        assert _level(lib, c, ng=(2, 2, 2), dtype=1) == -3      # nor for FP32
+        # an explicit selection configures the form
+        assert lib.hydro_set_level_variant(c, 0, 1, 2) == 0
+        assert lib.hydro_get_level_variant(c, 0, 1) == 2
+    with Ctx(lib) as c:  # without the requirement the default is used (no refusal)
+        assert lib.hydro_ctx_num_tuned(c) == 0
+
+
+def test_tune_cache_round_trip_and_malformed_files(lib, tmp_path):
+    path = tmp_path / "tune.json"
+    path.write_text('{"version": 1, "entries": {"batched/f64/8x8x8+8x8x24": 4, "level/f32/cfl/16x16x16": 3}}')
+    with Ctx(lib, str(path)) as c:
+        assert lib.hydro_ctx_num_tuned(c) == 2
+        path.unlink()
+        assert lib.hydro_ctx_save(c) == 0
+    text = path.read_text()
+    assert '"batched/f64/8x8x8+8x8x24": 4' in text and '"level/f32/cfl/16x16x16": 3' in text
+    with Ctx(lib, str(path)) as c:
+        assert lib.hydro_ctx_num_tuned(c) == 2
+        # an explicit selection replaces the tuned entries of its dtype and form
+        assert lib.hydro_set_level_variant(c, 1, 1, 0) == 0
+        assert lib.hydro_ctx_num_tuned(c) == 1
+    for bad in ('{"entries": {"a": "x"}}', '{"entries": {"a" 1}}', "[1, 2]", '{"entries": {"a": -2}}'):
+        path.write_text(bad)
+        h = ctypes.c_void_p()
+        assert lib.hydro_ctx_create(ctypes.byref(h), os.fsencode(str(path))) == -4, bad
+    # a missing file is an empty cache
+    h = ctypes.c_void_p()
+    assert lib.hydro_ctx_create(ctypes.byref(h), os.fsencode(str(tmp_path / "none.json"))) == 0
+    assert lib.hydro_ctx_num_tuned(h) == 0
+    assert lib.hydro_ctx_destroy(h) == 0
+
+
+def test_autotune_needs_a_context_and_cfl_scratch(lib):
+    P = ctypes.c_void_p
+    bc = (ctypes.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    f = lib.hydro_autotune
+    a, b, s = P(4096), P(1 << 44), P(1 << 45)
+    need = 8 * (3 + 8 * 8)
+    assert f(None, a, b, 2, 2, 2, bc, 0, 0.01, 1.4, s, need, 1, None, None) == -1
+    with Ctx(lib) as c:
+        assert f(c, a, b, 2, 2, 2, bc, 0, 0.01, 1.4, s, need - 8, 1, None, None) == -1      # scratch too small
+        assert f(c, a, b, 2, 2, 2, bc, 0, 0.01, 1.4, None, need, 1, None, None) == -1       # no scratch
+        assert f(c, a, P(4096 + 64), 2, 2, 2, bc, 0, 0.01, 1.4, s, need, 1, None, None) == -1   # out overlaps in
+        assert f(c, a, b, 2, 2, 2, bc, 0, 0.01, 1.4, P(4096 + 64), need, 1, None, None) == -1   # scratch overlaps
+        assert lib.hydro_ctx_num_tuned(c) == 0
