@@ -14,6 +14,11 @@ periodic box, uniform-flow and stationary-contact invariance, x/y/z cyclic and
 mirror symmetry, block-decomposition invariance, limiter special cases
 (theta = 1 minmod, theta = 2 MC), HLLC limiting cases, brute-force CFL, and
 dual-number JVPs against central finite differences.
+
+The other options of Sec. 2.2 (limiters, characteristic PLM, PPM, Roe, HLLE,
+CTU, and the procedure for unphysical results) are reached through
+``step_any`` / ``level_step_any`` / ``level_step_fallback`` and pinned in
+``tests/test_oracle_ext_schemes.py`` and ``tests/test_oracle_fallback.py``.
 """
 
 from __future__ import annotations
@@ -34,6 +39,18 @@ SCHEME_MHM_PLM_HLLC = 1
 WAVESPEED_ROE = 0 << 8
 WAVESPEED_DAVIS = 1 << 8
 FIRST_ORDER = 1 << 10
+# other schemes of Sec. 2.2 (scheme word bits beyond the default)
+SCHEME_MHM = 1
+SCHEME_CTU = 2
+LIMITER_GMINMOD = 0 << 11
+LIMITER_VANLEER = 1 << 11
+LIMITER_VANALBADA = 2 << 11
+LIMITER_HYBRID = 3 << 11
+CHARACTERISTIC = 1 << 13
+PPM = 1 << 14
+RIEMANN_HLLC = 0 << 16
+RIEMANN_ROE = 1 << 16
+RIEMANN_HLLE = 2 << 16
 
 
 def build_library(force: bool = True) -> str:
@@ -75,6 +92,18 @@ def _load():
         "oracle_exact_residual": (f64, [f64] * 8),
         "oracle_count_ops": (None, [P, P, P, P, P, P, f64, f64, f64, P]),
         "oracle_rollout_box": (i64, [P, P, P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32, P]),
+        "oracle_step_any": (i64, [P, P, i64, i32, f64, f64, f64, f64, i32]),
+        "oracle_step_block_any": (i64, [P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32]),
+        "oracle_step_any_jvp": (i64, [P, P, P, P, i64, i32, f64, f64, f64, f64, i32]),
+        "oracle_riemann": (i32, [P, P, i32, f64, i32, P]),
+        "oracle_limit_diffs": (f64, [f64, f64, f64, f64, i32]),
+        "oracle_limited_slopes": (None, [P, P, P, i32, f64, f64, i32, P]),
+        "oracle_face_values": (None, [P, i32, f64, f64, i32, P]),
+        "oracle_to_characteristic": (None, [P, i32, f64, f64, P]),
+        "oracle_from_characteristic": (None, [P, i32, f64, f64, P]),
+        "oracle_level_step_any": (i64, [P, P, i32, i32, i32, i32, P, f64, f64, f64, f64, i32]),
+        "oracle_level_step_fallback": (i64, [P, P, i32, i32, i32, i32, P, f64, f64, f64, f64, f64, f64, i32, P]),
+        "oracle_first_order_cell": (None, [P, i32, i32, i32, P, i32, i32, i32, f64, f64, i32, i32, P]),
         "oracle_num_threads": (i32, []),
         "oracle_set_num_threads": (None, [i32]),
     }
@@ -288,3 +317,121 @@ def count_ops(U, Wc, Wm, Wp, UL, UR, gamma, theta, half_dtdx):
     _load().oracle_count_ops(*[_p(a) for a in args], gamma, theta, half_dtdx, _p(ops))
     names = ("cons_to_prim", "hancock_cell", "hllc_flux", "update")  # hllc_flux: the branch UL, UR select
     return {n: dict(zip(("add", "mul", "div", "sqrt"), ops[4 * i:4 * i + 4].tolist())) for i, n in enumerate(names)}
+
+
+# ----------------------------------------------- other schemes of Sec. 2.2 --
+
+def step_any(U_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """One step of padded 16^3 groups with any scheme word (MHM or CTU; PLM or
+    PPM; primitive or characteristic; any limiter; HLLC, Roe or HLLE):
+    returns (U_out[G,5,16,16,16], n_bad)."""
+    U = _f64(U_pad)
+    G, P = U.shape[0], U.shape[2]
+    out = np.empty((G, 5, 16, 16, 16), np.float64)
+    n_bad = _load().oracle_step_any(_p(U), _p(out), G, (P - 16) // 2, dt, dx, gamma, theta, scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_step_any: bad arguments")
+    return out, int(n_bad)
+
+
+def step_block_any(U_pad, ghost, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """step_any for one padded block [5, nz+2g, ny+2g, nx+2g]: returns (U_out[5,nz,ny,nx], n_bad)."""
+    U = _f64(U_pad)
+    nz, ny, nx = (s - 2 * ghost for s in U.shape[1:])
+    out = np.empty((5, nz, ny, nx), np.float64)
+    n_bad = _load().oracle_step_block_any(_p(U), _p(out), nx, ny, nz, ghost, dt, dx, gamma, theta, scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_step_block_any: bad arguments")
+    return out, int(n_bad)
+
+
+def step_any_jvp(U_pad, T_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """Dual-number JVP of step_any: returns (U_out, T_out, n_bad)."""
+    U, T = _f64(U_pad), _f64(T_pad)
+    G, P = U.shape[0], U.shape[2]
+    out = np.empty((G, 5, 16, 16, 16), np.float64)
+    tout = np.empty_like(out)
+    n_bad = _load().oracle_step_any_jvp(_p(U), _p(T), _p(out), _p(tout), G, (P - 16) // 2, dt, dx, gamma, theta,
+                                        scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_step_any_jvp: bad arguments")
+    return out, tout, int(n_bad)
+
+
+def riemann(UL, UR, d, gamma, scheme=SCHEME_MHM_PLM_HLLC):
+    """Flux of the scheme word's Riemann solver across a face normal to axis d: (F[5], bad)."""
+    l, r = _f64(UL), _f64(UR)
+    F = np.empty(5, np.float64)
+    bad = _load().oracle_riemann(_p(l), _p(r), d, gamma, scheme, _p(F))
+    if bad < 0:
+        raise ValueError("bad Riemann solver id")
+    return F, bool(bad)
+
+
+def limit_diffs(dm, dp, dc, theta, limiter):
+    """Limited slope from one-sided differences (limiter 0..3: generalized minmod, van Leer, van Albada, hybrid)."""
+    return _load().oracle_limit_diffs(float(dm), float(dp), float(dc), float(theta), int(limiter))
+
+
+def limited_slopes(Wm, Wc, Wp, d, gamma, theta, scheme):
+    out = np.empty(5, np.float64)
+    a, b, c = _f64(Wm), _f64(Wc), _f64(Wp)
+    _load().oracle_limited_slopes(_p(a), _p(b), _p(c), d, gamma, theta, scheme, _p(out))
+    return out
+
+
+def face_values(Ws, d, gamma, theta, scheme):
+    """Face values (low, high) of the centre cell of a 5-cell stencil Ws[5, 5] along axis d."""
+    w = _f64(Ws).reshape(5, 5)
+    out = np.empty((2, 5), np.float64)
+    _load().oracle_face_values(_p(w), d, gamma, theta, scheme, _p(out))
+    return out
+
+
+def to_characteristic(dW, d, rho, c):
+    a, out = _f64(dW), np.empty(5, np.float64)
+    _load().oracle_to_characteristic(_p(a), d, float(rho), float(c), _p(out))
+    return out
+
+
+def from_characteristic(a, d, rho, c):
+    x, out = _f64(a), np.empty(5, np.float64)
+    _load().oracle_from_characteristic(_p(x), d, float(rho), float(c), _p(out))
+    return out
+
+
+def level_step_any(level, ng, ghost, bc, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """Ghost fill + one step of any scheme over a level: returns (level_out, n_bad)."""
+    L = _f64(level)
+    ngx, ngy, ngz = ng
+    out = np.empty_like(L)
+    n_bad = _load().oracle_level_step_any(_p(L), _p(out), ngx, ngy, ngz, ghost, _p(_bc(bc)), dt, dx, gamma, theta,
+                                          scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_level_step_any: bad arguments")
+    return out, int(n_bad)
+
+
+def level_step_fallback(level, ng, ghost, bc, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC,
+                        dt_min=0.0, ratio=0.8):
+    """One level step with the procedure for unphysical results (Sec. 2.2):
+    returns (level_out, cells_still_unphysical, info) with info = dict(dt,
+    retries, unsplit, split) of the accepted (or last) attempt."""
+    L = _f64(level)
+    ngx, ngy, ngz = ng
+    out = np.empty_like(L)
+    info = np.zeros(4, np.float64)
+    left = _load().oracle_level_step_fallback(_p(L), _p(out), ngx, ngy, ngz, ghost, _p(_bc(bc)), dt, dt_min, ratio,
+                                              dx, gamma, theta, scheme, _p(info))
+    if left < 0:
+        raise ValueError("oracle_level_step_fallback: bad arguments")
+    return out, int(left), {"dt": float(info[0]), "retries": int(info[1]), "unsplit": int(info[2]),
+                            "split": int(info[3])}
+
+
+def first_order_cell(level, ng, bc, X, Y, Z, dtdx, gamma, scheme=SCHEME_MHM_PLM_HLLC, split=False):
+    """First-order recomputation of one level cell (global indices): unsplit or x, y, z split."""
+    L = _f64(level)
+    out = np.empty(5, np.float64)
+    _load().oracle_first_order_cell(_p(L), *ng, _p(_bc(bc)), X, Y, Z, dtdx, gamma, scheme, int(split), _p(out))
+    return out

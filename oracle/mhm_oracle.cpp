@@ -20,6 +20,17 @@
 //   a0  ghost-zone fill, periodic or outflow              (fill_ghosts)
 //   exact Riemann solver (Toro's pressure-function Newton method) for the
 //   Sod-tube pin.
+// The other options Sec. 2.2 lists, in the same plain style (step_block_any):
+//   van Leer, van Albada and hybrid limiters          (limit_diffs)
+//   PLM on characteristic variables                   (limited_slopes)
+//   PPM reconstruction                                (face_values)
+//   HLLE and Roe solvers, Roe switching to HLLC on an
+//   unphysical intermediate state                     (hlle_flux, roe_flux)
+//   CTU with 6 Riemann solves per cell                (step_block_any)
+//   the procedure for unphysical results: first-order
+//   unsplit, then split recompute of failed cells, then
+//   level retries at dt * 0.8                         (level_step_repaired,
+//                                                      oracle_level_step_fallback)
 //
 // Readings where the paper is silent (each stated in the function it governs):
 //   * MHM predictor is the conservative unsplit Hancock step, no Riemann solve
@@ -625,6 +636,602 @@ int64_t rollout_box(std::vector<T> cur, int nx, int ny, int nz, int n_steps, dou
   return n_bad;
 }
 
+// ================================================= other schemes (Sec. 2.2) ==
+// Sec. 2.2 lists, beside MHM + PLM + generalized minmod + HLLC: the CTU scheme
+// with 6 Riemann solves per cell, Roe's and the HLLE solver, PPM
+// reconstruction, reconstruction of primitive or characteristic variables,
+// van Leer-type, van Albada-type and hybrid (generalized minmod + van Leer)
+// limiters, and a procedure for cells with unphysical results.  The paper
+// defers the formulas to the literature; each function below states the
+// textbook form it takes.  Scheme word bits beyond the default:
+//   bits 0-7    scheme id: 1 MHM, 2 CTU
+//   bits 11-12  limiter: 0 generalized minmod, 1 van Leer, 2 van Albada, 3 hybrid
+//   bit 13      limit characteristic instead of primitive variables
+//   bit 14      PPM instead of PLM
+//   bits 16-17  Riemann solver: 0 HLLC, 1 Roe, 2 HLLE
+constexpr int SCHEME_CTU = 2;
+constexpr int LIMITER_SHIFT = 11;
+constexpr int CHARACTERISTIC_BIT = 1 << 13;
+constexpr int PPM_BIT = 1 << 14;
+constexpr int RIEMANN_SHIFT = 16;
+
+// Limited slope from the one-sided differences dm = q0 - q[-1], dp = q[+1] - q0
+// and the central difference dc (zero unless dm and dp have one strict sign):
+//   0 generalized minmod  sgn(dc) min(theta|dm|, |dc|, theta|dp|)
+//   1 van Leer            2 dm dp / (dm + dp)            (harmonic mean)
+//   2 van Albada          dm dp (dm + dp) / (dm^2 + dp^2)
+//   3 hybrid              sgn(dc) min(generalized minmod, |van Leer|)  (the
+//                         more restrictive of the two)
+template <class T>
+T limit_diffs(T dm, T dp, T dc, double theta, int limiter) {
+  const bool same_sign = (val(dm) > 0.0 && val(dp) > 0.0) || (val(dm) < 0.0 && val(dp) < 0.0);
+  sig_mix(same_sign ? 1 : 2);
+  if (!same_sign) return T(0.0);
+  if (limiter == 1) return T(2.0) * dm * dp / (dm + dp);
+  if (limiter == 2) return dm * dp * (dm + dp) / (dm * dm + dp * dp);
+  T m = T(theta) * tabs(dm);
+  m = tmin(m, tabs(dc));
+  m = tmin(m, T(theta) * tabs(dp));
+  if (limiter == 3) m = tmin(m, tabs(T(2.0) * dm * dp / (dm + dp)));
+  sig_mix(val(dc) > 0.0 ? 9 : 10);
+  return val(dc) > 0.0 ? m : -m;
+}
+
+// Characteristic variables of the primitive Euler system along axis d
+// (normal velocity n, transverse t1, t2; sound speed c of the cell):
+//   a0 = (dp/c^2 - (rho/c) du_n)/2   (wave u - c)
+//   a1 = drho - dp/c^2               (entropy wave, u)
+//   a2 = du_t1, a3 = du_t2           (shear waves, u)
+//   a4 = (dp/c^2 + (rho/c) du_n)/2   (wave u + c)
+// and back: drho = a0 + a1 + a4, du_n = (c/rho)(a4 - a0), du_t1 = a2,
+// du_t2 = a3, dp = c^2 (a0 + a4).
+template <class T>
+void to_characteristic(const T dW[5], int d, T rho, T c, T a[5]) {
+  const int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+  const T pc2 = dW[4] / (c * c);
+  const T run = (rho / c) * dW[n];
+  a[0] = T(0.5) * (pc2 - run);
+  a[1] = dW[0] - pc2;
+  a[2] = dW[t1];
+  a[3] = dW[t2];
+  a[4] = T(0.5) * (pc2 + run);
+}
+template <class T>
+void from_characteristic(const T a[5], int d, T rho, T c, T dW[5]) {
+  const int n = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+  dW[0] = (a[0] + a[1]) + a[4];
+  dW[n] = (c / rho) * (a[4] - a[0]);
+  dW[t1] = a[2];
+  dW[t2] = a[3];
+  dW[4] = (c * c) * (a[0] + a[4]);
+}
+
+// Limited slopes of the five primitive variables of cell Wc along axis d.
+// Primitive: each variable limited on its own (the generalized minmod with dc
+// = (q[+1] - q[-1])/2, exactly as limited_slope).  Characteristic: the one-
+// sided differences are projected with the cell's left eigenvectors, each
+// component is limited (dc = the mean of its two one-sided differences) and
+// the result is projected back with the right eigenvectors.
+template <class T>
+void limited_slopes(const T Wm[5], const T Wc[5], const T Wp[5], int d, double gamma, double theta, int scheme,
+                    T s[5]) {
+  const int lim = (scheme >> LIMITER_SHIFT) & 3;
+  if (!(scheme & CHARACTERISTIC_BIT)) {
+    for (int q = 0; q < 5; ++q)
+      s[q] = limit_diffs(Wc[q] - Wm[q], Wp[q] - Wc[q], T(0.5) * (Wp[q] - Wm[q]), theta, lim);
+    return;
+  }
+  const T c = tsqrt(T(gamma) * Wc[4] / Wc[0]);
+  T dm[5], dp[5], am[5], ap[5], as[5];
+  for (int q = 0; q < 5; ++q) {
+    dm[q] = Wc[q] - Wm[q];
+    dp[q] = Wp[q] - Wc[q];
+  }
+  to_characteristic(dm, d, Wc[0], c, am);
+  to_characteristic(dp, d, Wc[0], c, ap);
+  for (int k = 0; k < 5; ++k) as[k] = limit_diffs(am[k], ap[k], T(0.5) * (am[k] + ap[k]), theta, lim);
+  from_characteristic(as, d, Wc[0], c, s);
+}
+
+// Face values (primitive) of a cell along axis d from the stencil Ws[0..4] =
+// cells at -2..+2 (PLM reads -1..+1 only):
+//   PLM: W_{-,+} = W0 -+ s0/2
+//   PPM (Colella & Woodward 1984, with limited slopes s_j of cells j = -1, 0, +1):
+//     qL = (q[-1] + q0)/2 - (s0 - s[-1])/6,  qR = (q0 + q[+1])/2 - (s[+1] - s0)/6,
+//     then the monotonicity constraints: qL = qR = q0 if q0 is a local extremum
+//     ((qR - q0)(q0 - qL) <= 0); else with dq = qR - qL, q6 = 6(q0 - (qL+qR)/2):
+//     qL = 3 q0 - 2 qR if dq q6 > dq^2, qR = 3 q0 - 2 qL if -dq^2 > dq q6.
+// First order: both faces take the cell value.
+template <class T>
+void face_values(const T* const Ws[5], int d, double gamma, double theta, int scheme, T Wf[2][5]) {
+  const T* Wc = Ws[2];
+  if (scheme & FIRST_ORDER_BIT) {
+    for (int q = 0; q < 5; ++q) Wf[0][q] = Wf[1][q] = Wc[q];
+    return;
+  }
+  if (!(scheme & PPM_BIT)) {
+    T s[5];
+    limited_slopes(Ws[1], Wc, Ws[3], d, gamma, theta, scheme, s);
+    for (int q = 0; q < 5; ++q) {
+      Wf[0][q] = Wc[q] - T(0.5) * s[q];
+      Wf[1][q] = Wc[q] + T(0.5) * s[q];
+    }
+    return;
+  }
+  T sm[5], s0[5], sp[5];
+  limited_slopes(Ws[0], Ws[1], Ws[2], d, gamma, theta, scheme, sm);
+  limited_slopes(Ws[1], Ws[2], Ws[3], d, gamma, theta, scheme, s0);
+  limited_slopes(Ws[2], Ws[3], Ws[4], d, gamma, theta, scheme, sp);
+  for (int q = 0; q < 5; ++q) {
+    T qL = T(0.5) * (Ws[1][q] + Wc[q]) - (s0[q] - sm[q]) / T(6.0);
+    T qR = T(0.5) * (Wc[q] + Ws[3][q]) - (sp[q] - s0[q]) / T(6.0);
+    const bool extremum = !(val((qR - Wc[q]) * (Wc[q] - qL)) > 0.0);
+    sig_mix(extremum ? 15 : 16);
+    if (extremum) {
+      qL = Wc[q];
+      qR = Wc[q];
+    } else {
+      const T dq = qR - qL;
+      const T q6 = T(6.0) * (Wc[q] - T(0.5) * (qL + qR));
+      const bool over_l = val(dq * q6) > val(dq * dq);
+      const bool over_r = !over_l && val(-(dq * dq)) > val(dq * q6);
+      sig_mix(over_l ? 17 : over_r ? 18 : 19);
+      if (over_l) qL = T(3.0) * Wc[q] - T(2.0) * qR;
+      if (over_r) qR = T(3.0) * Wc[q] - T(2.0) * qL;
+    }
+    Wf[0][q] = qL;
+    Wf[1][q] = qR;
+  }
+}
+
+// Normal-frame quantities of a face's two conserved states (shared by the
+// HLLE and Roe solvers below; the HLLC solver above keeps its own copy).
+template <class T>
+struct FacePair {
+  int n, t1, t2;
+  T L[5], R[5];  // (rho, m_n, m_t1, m_t2, E)
+  T rL, rR, uL, vL, wL, uR, vR, wR, pL, pR, cL, cR;
+  bool bad;
+  FacePair(const T UL[5], const T UR[5], int d, double gamma)
+      : n(1 + d), t1(1 + (d + 1) % 3), t2(1 + (d + 2) % 3) {
+    const T gm1 = T(gamma - 1.0), g = T(gamma);
+    L[0] = UL[0]; L[1] = UL[n]; L[2] = UL[t1]; L[3] = UL[t2]; L[4] = UL[4];
+    R[0] = UR[0]; R[1] = UR[n]; R[2] = UR[t1]; R[3] = UR[t2]; R[4] = UR[4];
+    rL = L[0];
+    rR = R[0];
+    uL = L[1] / rL; vL = L[2] / rL; wL = L[3] / rL;
+    uR = R[1] / rR; vR = R[2] / rR; wR = R[3] / rR;
+    pL = gm1 * (L[4] - T(0.5) * rL * (uL * uL + vL * vL + wL * wL));
+    pR = gm1 * (R[4] - T(0.5) * rR * (uR * uR + vR * vR + wR * wR));
+    bad = !(val(rL) > 0.0 && val(pL) > 0.0 && val(rR) > 0.0 && val(pR) > 0.0);
+    cL = tsqrt(g * pL / rL);
+    cR = tsqrt(g * pR / rR);
+  }
+  void fluxes(T FL[5], T FR[5]) const {
+    FL[0] = L[1]; FL[1] = L[1] * uL + pL; FL[2] = L[2] * uL; FL[3] = L[3] * uL; FL[4] = (L[4] + pL) * uL;
+    FR[0] = R[1]; FR[1] = R[1] * uR + pR; FR[2] = R[2] * uR; FR[3] = R[3] * uR; FR[4] = (R[4] + pR) * uR;
+  }
+  void store(const T Fn[5], T F[5]) const {
+    F[0] = Fn[0];
+    F[n] = Fn[1];
+    F[t1] = Fn[2];
+    F[t2] = Fn[3];
+    F[4] = Fn[4];
+  }
+};
+
+// HLLE flux (Einfeldt 1988): wave speeds as in the HLLC solver (Einfeldt/Roe
+// by default, Davis as an option), then
+//   F = F_L if S_L >= 0;  F_R if S_R <= 0;
+//   else (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).
+template <class T>
+bool hlle_flux(const T UL[5], const T UR[5], int d, double gamma, int wavespeed, T F[5]) {
+  const FacePair<T> f(UL, UR, d, gamma);
+  const T gm1 = T(gamma - 1.0);
+  T SL, SR;
+  if (wavespeed == 1) {
+    SL = tmin(f.uL - f.cL, f.uR - f.cR);
+    SR = tmax(f.uL + f.cL, f.uR + f.cR);
+  } else {
+    const T sL = tsqrt(f.rL), sR = tsqrt(f.rR);
+    const T inv = T(1.0) / (sL + sR);
+    const T ut = (sL * f.uL + sR * f.uR) * inv;
+    const T vt = (sL * f.vL + sR * f.vR) * inv;
+    const T wt = (sL * f.wL + sR * f.wR) * inv;
+    const T HL = (f.L[4] + f.pL) / f.rL, HR = (f.R[4] + f.pR) / f.rR;
+    const T Ht = (sL * HL + sR * HR) * inv;
+    const T ct = tsqrt(gm1 * (Ht - T(0.5) * (ut * ut + vt * vt + wt * wt)));
+    SL = tmin(f.uL - f.cL, ut - ct);
+    SR = tmax(f.uR + f.cR, ut + ct);
+  }
+  T FL[5], FR[5], Fn[5];
+  f.fluxes(FL, FR);
+  sig_mix(val(SL) >= 0.0 ? 20 : val(SR) <= 0.0 ? 21 : 22);
+  if (val(SL) >= 0.0) {
+    for (int q = 0; q < 5; ++q) Fn[q] = FL[q];
+  } else if (val(SR) <= 0.0) {
+    for (int q = 0; q < 5; ++q) Fn[q] = FR[q];
+  } else {
+    const T inv = T(1.0) / (SR - SL);
+    for (int q = 0; q < 5; ++q) Fn[q] = (SR * FL[q] - SL * FR[q] + SL * SR * (f.R[q] - f.L[q])) * inv;
+  }
+  f.store(Fn, F);
+  return f.bad;
+}
+
+// Roe's flux (Roe 1981; wave strengths in the form of Toro 2009, Sec. 11.3):
+// Roe averages u~, v~, w~, H~ (weights sqrt(rho)), a~^2 = (gamma-1)(H~ - q~^2/2);
+// eigenvalues u~ - a~, u~ (x3), u~ + a~ with right eigenvectors
+//   K1 = (1, u~-a~, v~, w~, H~ - u~ a~),  K2 = (1, u~, v~, w~, q~^2/2),
+//   K3 = (0, 0, 1, 0, v~),  K4 = (0, 0, 0, 1, w~),  K5 = (1, u~+a~, v~, w~, H~ + u~ a~);
+// strengths from dU = U_R - U_L:
+//   al3 = dU2 - v~ dU0,  al4 = dU3 - w~ dU0,
+//   al2 = (gamma-1)/a~^2 [dU0 (H~ - u~^2) + u~ dU1 - (dU4 - al3 v~ - al4 w~)],
+//   al1 = [dU0 (u~ + a~) - dU1 - a~ al2] / (2 a~),  al5 = dU0 - (al1 + al2);
+//   F = (F_L + F_R)/2 - (|l1| al1 K1 + |u~| (al2 K2 + al3 K3 + al4 K4) + |l5| al5 K5)/2.
+// No entropy fix.  The states between the waves, U_L + al1 K1 and
+// U_L + al1 K1 + al2 K2 + al3 K3 + al4 K4, are checked: if a~^2 <= 0 or either
+// has rho <= 0 or p <= 0, the face's flux is recomputed with the HLLC solver
+// (the first step of the paper's procedure for unphysical results).
+template <class T>
+bool roe_flux(const T UL[5], const T UR[5], int d, double gamma, int wavespeed, T F[5]) {
+  const FacePair<T> f(UL, UR, d, gamma);
+  const T gm1 = T(gamma - 1.0);
+  const T sL = tsqrt(f.rL), sR = tsqrt(f.rR);
+  const T inv = T(1.0) / (sL + sR);
+  const T ut = (sL * f.uL + sR * f.uR) * inv;
+  const T vt = (sL * f.vL + sR * f.vR) * inv;
+  const T wt = (sL * f.wL + sR * f.wR) * inv;
+  const T HL = (f.L[4] + f.pL) / f.rL, HR = (f.R[4] + f.pR) / f.rR;
+  const T Ht = (sL * HL + sR * HR) * inv;
+  const T q2 = ut * ut + vt * vt + wt * wt;
+  const T a2 = gm1 * (Ht - T(0.5) * q2);
+  bool ok = val(a2) > 0.0;
+  T Fn[5];
+  if (ok) {
+    const T a = tsqrt(a2);
+    T dU[5];
+    for (int q = 0; q < 5; ++q) dU[q] = f.R[q] - f.L[q];
+    const T al3 = dU[2] - vt * dU[0];
+    const T al4 = dU[3] - wt * dU[0];
+    const T al2 = gm1 / a2 * (dU[0] * (Ht - ut * ut) + ut * dU[1] - (dU[4] - al3 * vt - al4 * wt));
+    const T al1 = (dU[0] * (ut + a) - dU[1] - a * al2) / (T(2.0) * a);
+    const T al5 = dU[0] - (al1 + al2);
+    const T K1[5] = {T(1.0), ut - a, vt, wt, Ht - ut * a};
+    const T K2[5] = {T(1.0), ut, vt, wt, T(0.5) * q2};
+    const T K3[5] = {T(0.0), T(0.0), T(1.0), T(0.0), vt};
+    const T K4[5] = {T(0.0), T(0.0), T(0.0), T(1.0), wt};
+    const T K5[5] = {T(1.0), ut + a, vt, wt, Ht + ut * a};
+    // states between the waves
+    T S1[5], S2[5];
+    for (int q = 0; q < 5; ++q) {
+      S1[q] = f.L[q] + al1 * K1[q];
+      S2[q] = S1[q] + ((al2 * K2[q] + al3 * K3[q]) + al4 * K4[q]);
+    }
+    for (const T* S : {S1, S2}) {
+      const T p = gm1 * (S[4] - T(0.5) * (S[1] * S[1] + S[2] * S[2] + S[3] * S[3]) / S[0]);
+      if (!(val(S[0]) > 0.0 && val(p) > 0.0)) ok = false;
+    }
+    if (ok) {
+      const T l1 = tabs(ut - a), l2 = tabs(ut), l5 = tabs(ut + a);
+      T FL[5], FR[5];
+      f.fluxes(FL, FR);
+      for (int q = 0; q < 5; ++q) {
+        const T diss = (l1 * al1 * K1[q] + l2 * ((al2 * K2[q] + al3 * K3[q]) + al4 * K4[q])) + l5 * al5 * K5[q];
+        Fn[q] = T(0.5) * (FL[q] + FR[q]) - T(0.5) * diss;
+      }
+    }
+  }
+  sig_mix(ok ? 23 : 24);
+  if (!ok) return hllc_flux(UL, UR, d, gamma, wavespeed, F);
+  f.store(Fn, F);
+  return f.bad;
+}
+
+template <class T>
+bool riemann_flux(const T UL[5], const T UR[5], int d, double gamma, int scheme, T F[5]) {
+  const int ws = (scheme >> WAVESPEED_SHIFT) & 3;
+  switch ((scheme >> RIEMANN_SHIFT) & 3) {
+    case 1: return roe_flux(UL, UR, d, gamma, ws, F);
+    case 2: return hlle_flux(UL, UR, d, gamma, ws, F);
+    default: return hllc_flux(UL, UR, d, gamma, ws, F);
+  }
+}
+
+// Cons and flux of a primitive face state.
+template <class T>
+void face_cons_flux(const T W[5], int d, double gamma, T U[5], T F[5]) {
+  prim_to_cons(W, gamma, U);
+  euler_flux(W, U, d, F);
+}
+
+inline int recon_radius(int scheme) {
+  if (scheme & FIRST_ORDER_BIT) return 0;
+  return (scheme & PPM_BIT) ? 2 : 1;
+}
+
+// One step of a padded block with any of the schemes above.
+//   MHM: face values (PLM/PPM, primitive/characteristic) -> conservative
+//        Hancock half step with the face values' fluxes summed over x, y, z
+//        (as hancock_cell) -> Riemann solve at every face -> update.
+//   CTU (Colella 1990, the variant with 6 Riemann solves per cell):
+//     1. along each axis d, face values and a half step with that axis' flux
+//        difference only: U1_{d,-+} = U_{d,-+} + dt/(2dx) (F_d(U_{d,-}) - F_d(U_{d,+}));
+//     2. first Riemann solves on every face between two such cells (3 per cell);
+//     3. transverse correction of each axis' states with the other axes'
+//        first-solve fluxes:
+//          U2_{d,-+} = U1_{d,-+} - dt/(2dx) sum_{e != d} (F1_e(+1/2) - F1_e(-1/2))
+//        (e ascending);
+//     4. second Riemann solves with the corrected states (3 per cell);
+//     5. conservative update with the second-solve fluxes.
+// Needs ghost >= 2 (PLM) or 3 (PPM); the update order and unphysical count
+// are those of mhm_step_block.
+template <class T>
+int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double dx, double gamma, double theta,
+                       int scheme) {
+  const bool ctu = (scheme & SCHEME_ID_MASK) == SCHEME_CTU;
+  const int R = recon_radius(scheme);
+  const T dtdx = T(dt) / T(dx);
+  const T half_dtdx = T(0.5) * dtdx;
+  int64_t n_bad = 0;
+  const int ex[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+
+  // primitive variables on [-1-R, n+R]^3
+  const int m = R + 1;
+  const int wx = b.nx + 2 * m, wy = b.ny + 2 * m, wz = b.nz + 2 * m;
+  auto wi = [&](int x, int y, int z) { return ((int64_t(z + m) * wy + (y + m)) * wx + (x + m)); };
+  std::vector<T> W(size_t(wx) * wy * wz * 5);
+  for (int z = -m; z < b.nz + m; ++z)
+    for (int y = -m; y < b.ny + m; ++y)
+      for (int x = -m; x < b.nx + m; ++x) {
+        T U[5];
+        for (int f = 0; f < 5; ++f) U[f] = Upad[b.at(f, x, y, z)];
+        cons_to_prim(U, gamma, &W[wi(x, y, z) * 5]);
+      }
+
+  // face states of every cell of [-1, n]^3: MHM's Hancock states, or CTU's
+  // one-axis predicted states
+  const int sx = b.nx + 2, sy = b.ny + 2, sz = b.nz + 2;
+  auto si = [&](int x, int y, int z) { return ((int64_t(z + 1) * sy + (y + 1)) * sx + (x + 1)); };
+  std::vector<T> S(size_t(sx) * sy * sz * 30);
+  for (int z = -1; z < b.nz + 1; ++z)
+    for (int y = -1; y < b.ny + 1; ++y)
+      for (int x = -1; x < b.nx + 1; ++x) {
+        T Wf[3][2][5];
+        for (int d = 0; d < 3; ++d) {
+          const T* Ws[5];
+          for (int j = -2; j <= 2; ++j) {
+            const int o = (j < -R || j > R) ? 0 : j;  // cells beyond the radius are not read
+            Ws[j + 2] = &W[wi(x + o * ex[d][0], y + o * ex[d][1], z + o * ex[d][2]) * 5];
+          }
+          face_values(Ws, d, gamma, theta, scheme, Wf[d]);
+        }
+        T Ut[3][2][5], Ff[3][2][5];
+        for (int d = 0; d < 3; ++d)
+          for (int s = 0; s < 2; ++s) face_cons_flux(Wf[d][s], d, gamma, Ut[d][s], Ff[d][s]);
+        if (ctu) {
+          for (int d = 0; d < 3; ++d)
+            for (int q = 0; q < 5; ++q) {
+              const T dU = half_dtdx * (Ff[d][0][q] - Ff[d][1][q]);
+              Ut[d][0][q] = Ut[d][0][q] + dU;
+              Ut[d][1][q] = Ut[d][1][q] + dU;
+            }
+        } else {
+          for (int q = 0; q < 5; ++q) {
+            T s = Ff[0][0][q] - Ff[0][1][q];
+            s = s + (Ff[1][0][q] - Ff[1][1][q]);
+            s = s + (Ff[2][0][q] - Ff[2][1][q]);
+            const T dU = half_dtdx * s;
+            for (int d = 0; d < 3; ++d) {
+              Ut[d][0][q] = Ut[d][0][q] + dU;
+              Ut[d][1][q] = Ut[d][1][q] + dU;
+            }
+          }
+        }
+        T* dst = &S[si(x, y, z) * 30];
+        for (int d = 0; d < 3; ++d)
+          for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < 5; ++q) dst[(d * 2 + s) * 5 + q] = Ut[d][s][q];
+      }
+  auto state = [&](int x, int y, int z, int d, int s) -> T* { return &S[si(x, y, z) * 30 + (d * 2 + s) * 5]; };
+
+  if (ctu) {
+    // first solves on faces between two cells of [-1, n]^3: face (d, x, y, z)
+    // lies between the cell at (x, y, z) - e_d and (x, y, z), for the normal
+    // coordinate 0..n and the transverse ones -1..n
+    auto f1i = [&](int d, int x, int y, int z) {
+      return (((int64_t(d) * (b.nz + 2) + (z + 1)) * (b.ny + 2) + (y + 1)) * (b.nx + 2) + (x + 1)) * 5;
+    };
+    std::vector<T> F1(size_t(3) * (b.nx + 2) * (b.ny + 2) * (b.nz + 2) * 5);
+    for (int d = 0; d < 3; ++d)
+      for (int z = -1; z <= b.nz; ++z)
+        for (int y = -1; y <= b.ny; ++y)
+          for (int x = -1; x <= b.nx; ++x) {
+            const int c[3] = {x, y, z};
+            if (c[d] < 0) continue;
+            const int lx = x - ex[d][0], ly = y - ex[d][1], lz = z - ex[d][2];
+            riemann_flux(state(lx, ly, lz, d, 1), state(x, y, z, d, 0), d, gamma, scheme, &F1[f1i(d, x, y, z)]);
+          }
+    // transverse corrections of the states the second solves need: axis d's
+    // states of cells with the normal coordinate in -1..n and the transverse
+    // ones in 0..n-1
+    for (int d = 0; d < 3; ++d)
+      for (int z = -1; z <= b.nz; ++z)
+        for (int y = -1; y <= b.ny; ++y)
+          for (int x = -1; x <= b.nx; ++x) {
+            const int c[3] = {x, y, z}, nn[3] = {b.nx, b.ny, b.nz};
+            bool inside = true;
+            for (int e = 0; e < 3; ++e)
+              if (e != d && (c[e] < 0 || c[e] >= nn[e])) inside = false;
+            if (!inside) continue;
+            T corr[5];
+            bool first = true;
+            for (int e = 0; e < 3; ++e) {
+              if (e == d) continue;
+              const T* Fp = &F1[f1i(e, x + ex[e][0], y + ex[e][1], z + ex[e][2])];
+              const T* Fm = &F1[f1i(e, x, y, z)];
+              for (int q = 0; q < 5; ++q) corr[q] = first ? (Fp[q] - Fm[q]) : corr[q] + (Fp[q] - Fm[q]);
+              first = false;
+            }
+            for (int s = 0; s < 2; ++s) {
+              T* st = state(x, y, z, d, s);
+              for (int q = 0; q < 5; ++q) st[q] = st[q] - half_dtdx * corr[q];
+            }
+          }
+  }
+
+  // (second) Riemann solves at the faces of the interior cells, update
+  auto fxi = [&](int x, int y, int z) { return ((int64_t(z) * b.ny + y) * (b.nx + 1) + x) * 5; };
+  auto fyi = [&](int x, int y, int z) { return ((int64_t(z) * (b.ny + 1) + y) * b.nx + x) * 5; };
+  auto fzi = [&](int x, int y, int z) { return ((int64_t(z) * b.ny + y) * b.nx + x) * 5; };
+  std::vector<T> Fx(size_t(b.nz) * b.ny * (b.nx + 1) * 5), Fy(size_t(b.nz) * (b.ny + 1) * b.nx * 5),
+      Fz(size_t(b.nz + 1) * b.ny * b.nx * 5);
+  for (int z = 0; z < b.nz; ++z)
+    for (int y = 0; y < b.ny; ++y)
+      for (int x = 0; x <= b.nx; ++x)
+        n_bad += riemann_flux(state(x - 1, y, z, 0, 1), state(x, y, z, 0, 0), 0, gamma, scheme, &Fx[fxi(x, y, z)]);
+  for (int z = 0; z < b.nz; ++z)
+    for (int y = 0; y <= b.ny; ++y)
+      for (int x = 0; x < b.nx; ++x)
+        n_bad += riemann_flux(state(x, y - 1, z, 1, 1), state(x, y, z, 1, 0), 1, gamma, scheme, &Fy[fyi(x, y, z)]);
+  for (int z = 0; z <= b.nz; ++z)
+    for (int y = 0; y < b.ny; ++y)
+      for (int x = 0; x < b.nx; ++x)
+        n_bad += riemann_flux(state(x, y, z - 1, 2, 1), state(x, y, z, 2, 0), 2, gamma, scheme, &Fz[fzi(x, y, z)]);
+  const T gm1 = T(gamma - 1.0);
+  for (int z = 0; z < b.nz; ++z)
+    for (int y = 0; y < b.ny; ++y)
+      for (int x = 0; x < b.nx; ++x) {
+        T Un[5];
+        for (int q = 0; q < 5; ++q) {
+          T acc = Fx[fxi(x + 1, y, z) + q] - Fx[fxi(x, y, z) + q];
+          acc = acc + (Fy[fyi(x, y + 1, z) + q] - Fy[fyi(x, y, z) + q]);
+          acc = acc + (Fz[fzi(x, y, z + 1) + q] - Fz[fzi(x, y, z) + q]);
+          Un[q] = Upad[b.at(q, x, y, z)] - dtdx * acc;
+          Uout[((int64_t(q) * b.nz + z) * b.ny + y) * b.nx + x] = Un[q];
+        }
+        const T p = gm1 * (Un[4] - T(0.5) * (Un[1] * Un[1] + Un[2] * Un[2] + Un[3] * Un[3]) / Un[0]);
+        if (!(val(Un[0]) > 0.0 && val(p) > 0.0)) ++n_bad;
+      }
+  return n_bad;
+}
+
+// ------------------------------------- procedure for unphysical results ---
+// Sec. 2.2: (ii) a cell whose update gives rho <= 0 or p <= 0 is recomputed
+// first-order in space and time, dimensionally unsplit; (iii) if that still
+// fails, first-order and dimensionally split; (iv)-(v) if that fails too, the
+// whole level is recomputed with the time-step reduced by a fixed ratio (0.8)
+// until nothing fails or the step falls below a minimum.  Steps (ii)-(iii)
+// touch only the failed cells.
+//   first-order unsplit: U = U^n - dt/dx sum_d (F_d(+1/2) - F_d(-1/2)), F the
+//     scheme's Riemann solver on the neighbouring cell averages of U^n;
+//   first-order split: x sweep of U^n, then y sweep of the result, then z
+//     sweep, each U' = U - dt/dx (F(+1/2) - F(-1/2)) of the sweep's axis; the
+//     split update of a cell reads the 3x3x3 block of U^n around it.
+template <class T>
+bool cons_unphysical(const T U[5], double gamma) {
+  const T p = T(gamma - 1.0) * (U[4] - T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0]);
+  return !(val(U[0]) > 0.0 && val(p) > 0.0);
+}
+
+// Level accessor: cell (X, Y, Z) of the level (global cell indices, mapped
+// through the boundary conditions) into U[5].
+struct LevelView {
+  const double* level;
+  int ngx, ngy, ngz;
+  const int* bc;
+  void get(int X, int Y, int Z, double U[5]) const {
+    X = bc_index(X, ngx * 16, bc[0], bc[1]);
+    Y = bc_index(Y, ngy * 16, bc[2], bc[3]);
+    Z = bc_index(Z, ngz * 16, bc[4], bc[5]);
+    const int64_t g = (int64_t(Z / 16) * ngy + Y / 16) * ngx + X / 16;
+    for (int f = 0; f < 5; ++f) U[f] = level[((g * 5 + f) * 16 + Z % 16) * 256 + (Y % 16) * 16 + X % 16];
+  }
+};
+
+void first_order_unsplit(const LevelView& lv, int X, int Y, int Z, double dtdx, double gamma, int scheme,
+                         double out[5]) {
+  const int ex[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double U0[5];
+  lv.get(X, Y, Z, U0);
+  double acc[5];
+  for (int d = 0; d < 3; ++d) {
+    double Um[5], Up[5], Fm[5], Fp[5];
+    lv.get(X - ex[d][0], Y - ex[d][1], Z - ex[d][2], Um);
+    lv.get(X + ex[d][0], Y + ex[d][1], Z + ex[d][2], Up);
+    riemann_flux(Um, U0, d, gamma, scheme, Fm);
+    riemann_flux(U0, Up, d, gamma, scheme, Fp);
+    for (int q = 0; q < 5; ++q) acc[q] = d == 0 ? (Fp[q] - Fm[q]) : acc[q] + (Fp[q] - Fm[q]);
+  }
+  for (int q = 0; q < 5; ++q) out[q] = U0[q] - dtdx * acc[q];
+}
+
+void first_order_split(const LevelView& lv, int X, int Y, int Z, double dtdx, double gamma, int scheme,
+                       double out[5]) {
+  // B[k][j][i][q]: the 3x3x3 block around the cell, offsets -1..1
+  double B[3][3][3][5], C[3][3][3][5];
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) lv.get(X + i - 1, Y + j - 1, Z + k - 1, B[k][j][i]);
+  auto sweep1 = [&](const double* Um, const double* U0, const double* Up, int d, double* res) {
+    double Fm[5], Fp[5];
+    riemann_flux(Um, U0, d, gamma, scheme, Fm);
+    riemann_flux(U0, Up, d, gamma, scheme, Fp);
+    for (int q = 0; q < 5; ++q) res[q] = U0[q] - dtdx * (Fp[q] - Fm[q]);
+  };
+  // x sweep on the 9 centre-x cells of every (y, z) line of the block (only
+  // the x = 0 column is needed: its y and z neighbours feed the next sweeps)
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) sweep1(B[k][j][0], B[k][j][1], B[k][j][2], 0, C[k][j][1]);
+  // y sweep at y = 0 for z = -1..1
+  double D[3][5];
+  for (int k = 0; k < 3; ++k) sweep1(C[k][0][1], C[k][1][1], C[k][2][1], 1, D[k]);
+  // z sweep at the cell
+  sweep1(D[0], D[1], D[2], 2, out);
+}
+
+// One step of a level with the procedure for unphysical results applied to
+// its output (steps ii-iii).  Returns the number of cells still unphysical;
+// *n_unsplit / *n_split receive how many cells each step repaired.
+int64_t level_step_repaired(const double* level, double* level_out, int ngx, int ngy, int ngz, int ghost,
+                            const int bc[6], double dt, double dx, double gamma, double theta, int scheme,
+                            int64_t* n_unsplit, int64_t* n_split) {
+  const int P = 16 + 2 * ghost;
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  std::vector<double> pad(size_t(G) * 5 * P * P * P);
+  fill_ghosts(level, pad.data(), ngx, ngy, ngz, ghost, bc);
+  const Block b(16, 16, 16, ghost);
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < G; ++g)
+    step_block_any(pad.data() + g * b.cells() * 5, level_out + g * 5 * 4096, b, dt, dx, gamma, theta, scheme);
+  const LevelView lv{level, ngx, ngy, ngz, bc};
+  const double dtdx = dt / dx;
+  int64_t left = 0, nu = 0, ns = 0;
+  // first-order procedure: Riemann solver of the scheme, zero slopes
+  const int fo = scheme | FIRST_ORDER_BIT;
+  for (int64_t g = 0; g < G; ++g)
+    for (int c = 0; c < 4096; ++c) {
+      double U[5];
+      for (int f = 0; f < 5; ++f) U[f] = level_out[(g * 5 + f) * 4096 + c];
+      if (!cons_unphysical(U, gamma)) continue;
+      const int gx = int(g % ngx), gy = int((g / ngx) % ngy), gz = int(g / (int64_t(ngx) * ngy));
+      const int X = gx * 16 + c % 16, Y = gy * 16 + (c / 16) % 16, Z = gz * 16 + c / 256;
+      double R[5];
+      first_order_unsplit(lv, X, Y, Z, dtdx, gamma, fo, R);
+      if (!cons_unphysical(R, gamma)) {
+        ++nu;
+      } else {
+        first_order_split(lv, X, Y, Z, dtdx, gamma, fo, R);
+        if (!cons_unphysical(R, gamma)) ++ns;
+        else ++left;
+      }
+      for (int f = 0; f < 5; ++f) level_out[(g * 5 + f) * 4096 + c] = R[f];
+    }
+  if (n_unsplit) *n_unsplit = nu;
+  if (n_split) *n_split = ns;
+  return left;
+}
+
 }  // namespace
 
 // =================================================================== C ABI ==
@@ -901,6 +1508,142 @@ void oracle_count_ops(const double* U, const double* Wc, const double* Wm, const
     (void)p;
   }
   take(3);
+}
+
+// ------------------------------------------------- other schemes (C ABI) ---
+static bool valid_any_scheme(int scheme, int ghost) {
+  const int id = scheme & SCHEME_ID_MASK;
+  if (id != SCHEME_MHM_PLM_HLLC && id != SCHEME_CTU) return false;
+  if (((scheme >> RIEMANN_SHIFT) & 3) == 3) return false;
+  return ghost >= recon_radius(scheme) + 1 && ghost >= 2;
+}
+
+// One step of G padded 16^3 groups with any scheme of the scheme word.
+int64_t oracle_step_any(const double* Upad, double* Uout, int64_t G, int ghost, double dt, double dx, double gamma,
+                        double theta, int scheme) {
+  if (G < 0 || !valid_any_scheme(scheme, ghost)) return -1;
+  const Block b(16, 16, 16, ghost);
+  int64_t n_bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
+  for (int64_t g = 0; g < G; ++g)
+    n_bad += step_block_any(Upad + g * b.cells() * 5, Uout + g * 5 * 4096, b, dt, dx, gamma, theta, scheme);
+  return n_bad;
+}
+
+int64_t oracle_step_block_any(const double* Upad, double* Uout, int nx, int ny, int nz, int ghost, double dt,
+                              double dx, double gamma, double theta, int scheme) {
+  if (nx < 1 || ny < 1 || nz < 1 || !valid_any_scheme(scheme, ghost)) return -1;
+  return step_block_any(Upad, Uout, Block(nx, ny, nz, ghost), dt, dx, gamma, theta, scheme);
+}
+
+// Dual-number JVP of oracle_step_any.
+int64_t oracle_step_any_jvp(const double* Upad, const double* Tpad, double* Uout, double* Tout, int64_t G, int ghost,
+                            double dt, double dx, double gamma, double theta, int scheme) {
+  if (G < 0 || !valid_any_scheme(scheme, ghost)) return -1;
+  const Block b(16, 16, 16, ghost);
+  const int64_t np = b.cells() * 5;
+  int64_t n_bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
+  for (int64_t g = 0; g < G; ++g) {
+    std::vector<Dual> in(np), out(5 * 4096);
+    for (int64_t i = 0; i < np; ++i) in[i] = Dual(Upad[g * np + i], Tpad[g * np + i]);
+    n_bad += step_block_any(in.data(), out.data(), b, dt, dx, gamma, theta, scheme);
+    for (int64_t i = 0; i < 5 * 4096; ++i) {
+      Uout[g * 5 * 4096 + i] = out[i].v;
+      Tout[g * 5 * 4096 + i] = out[i].d;
+    }
+  }
+  return n_bad;
+}
+
+// Riemann flux of the scheme word's solver (tests).  Returns 1 if an input
+// state is unphysical, -1 on a bad solver id.
+int oracle_riemann(const double* UL, const double* UR, int d, double gamma, int scheme, double* F) {
+  if (((scheme >> RIEMANN_SHIFT) & 3) == 3) return -1;
+  return riemann_flux(UL, UR, d, gamma, scheme, F) ? 1 : 0;
+}
+
+double oracle_limit_diffs(double dm, double dp, double dc, double theta, int limiter) {
+  return limit_diffs(dm, dp, dc, theta, limiter & 3);
+}
+
+void oracle_limited_slopes(const double* Wm, const double* Wc, const double* Wp, int d, double gamma, double theta,
+                           int scheme, double* s) {
+  limited_slopes(Wm, Wc, Wp, d, gamma, theta, scheme, s);
+}
+
+// Face values of one cell along axis d from the 5-cell stencil Ws[5*5]
+// (cells -2..2) -> Wf[2*5] (low face, high face).
+void oracle_face_values(const double* Ws, int d, double gamma, double theta, int scheme, double* Wf) {
+  const double* st[5] = {Ws, Ws + 5, Ws + 10, Ws + 15, Ws + 20};
+  double o[2][5];
+  face_values(st, d, gamma, theta, scheme, o);
+  std::memcpy(Wf, o, sizeof o);
+}
+
+void oracle_to_characteristic(const double* dW, int d, double rho, double c, double* a) {
+  to_characteristic(dW, d, rho, c, a);
+}
+void oracle_from_characteristic(const double* a, int d, double rho, double c, double* dW) {
+  from_characteristic(a, d, rho, c, dW);
+}
+
+// One step of a level (ghost fill + any scheme) without the procedure for
+// unphysical results.  Returns the unphysical count.
+int64_t oracle_level_step_any(const double* level, double* level_out, int ngx, int ngy, int ngz, int ghost,
+                              const int* bc, double dt, double dx, double gamma, double theta, int scheme) {
+  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost > 16 || !valid_any_scheme(scheme, ghost)) return -1;
+  const int P = 16 + 2 * ghost;
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  std::vector<double> pad(size_t(G) * 5 * P * P * P);
+  fill_ghosts(level, pad.data(), ngx, ngy, ngz, ghost, bc);
+  const Block b(16, 16, 16, ghost);
+  int64_t n_bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
+  for (int64_t g = 0; g < G; ++g)
+    n_bad += step_block_any(pad.data() + g * b.cells() * 5, level_out + g * 5 * 4096, b, dt, dx, gamma, theta,
+                            scheme);
+  return n_bad;
+}
+
+// One step of a level with the procedure for unphysical results: steps
+// (ii)-(iii) on the failed cells, then (iv)-(v): while cells still fail and
+// the reduced step dt*ratio is at least dt_min, recompute the level from its
+// input with dt *= ratio.  out_info[4] receives: the dt of the accepted (or
+// last) attempt, the number of retries, and the cells repaired unsplit and
+// split in that attempt.  Returns the number of cells still unphysical (0 on
+// success), or -1 on bad arguments.
+int64_t oracle_level_step_fallback(const double* level, double* level_out, int ngx, int ngy, int ngz, int ghost,
+                                   const int* bc, double dt, double dt_min, double ratio, double dx, double gamma,
+                                   double theta, int scheme, double* out_info) {
+  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost > 16 || !valid_any_scheme(scheme, ghost) || !(dt > 0.0) ||
+      !(ratio > 0.0 && ratio < 1.0) || !(dt_min >= 0.0))
+    return -1;
+  int retries = 0;
+  for (;;) {
+    int64_t nu = 0, ns = 0;
+    const int64_t left =
+        level_step_repaired(level, level_out, ngx, ngy, ngz, ghost, bc, dt, dx, gamma, theta, scheme, &nu, &ns);
+    const double next = dt * ratio;
+    if (left == 0 || next < dt_min) {
+      out_info[0] = dt;
+      out_info[1] = retries;
+      out_info[2] = double(nu);
+      out_info[3] = double(ns);
+      return left;
+    }
+    dt = next;
+    ++retries;
+  }
+}
+
+// First-order recomputations of one cell of a level (tests): mode 0 unsplit,
+// 1 split.  X, Y, Z are global cell indices.
+void oracle_first_order_cell(const double* level, int ngx, int ngy, int ngz, const int* bc, int X, int Y, int Z,
+                             double dtdx, double gamma, int scheme, int mode, double* out) {
+  const LevelView lv{level, ngx, ngy, ngz, bc};
+  if (mode == 0) first_order_unsplit(lv, X, Y, Z, dtdx, gamma, scheme | FIRST_ORDER_BIT, out);
+  else first_order_split(lv, X, Y, Z, dtdx, gamma, scheme | FIRST_ORDER_BIT, out);
 }
 
 }  // extern "C"
