@@ -283,6 +283,20 @@ typedef struct {
 int hydro_advance_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
                           int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
                           void* stream);
+/* hydro_advance_batched_noalloc -- hydro_advance_batched for callers that
+ * cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same launch and arguments
+ * except work_dev.  The work counters live in the library's own array of
+ * HYDRO_BATCH_WORK_WORDS uint32 (64 bytes) per device, held until the
+ * process ends, and are cleared by a small kernel on `stream` before every
+ * launch; nothing is allocated.  Limits: those of hydro_advance_batched (at
+ * most 8 levels, fewer than 2^32 - 2^20 groups in all; HYDRO_EINVAL beyond).
+ * Every call on one device shares that device's counters: calls that overlap
+ * in time on one device (different streams, or host threads) race and must
+ * not be issued. */
+int hydro_advance_batched_noalloc(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype,
+                                  double gamma, int32_t scheme, double theta, int32_t* n_bad_dev, int32_t grid,
+                                  void* stream);
 int hydro_set_batched_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant);
 int hydro_get_batched_variant(hydro_ctx* ctx, int32_t dtype);
 int hydro_autotune_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,

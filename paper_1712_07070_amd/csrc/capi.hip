@@ -231,8 +231,11 @@ int batched_impl(const hydro_level_t* lv, int32_t n_levels, double gamma, int32_
   long long g = grid > 0 ? grid : (long long)device_cus() * per_cu;
   if (g > total) g = total;
   gh::Gas<T> gas = make_gas<T>(gamma, theta, 1.0, 1.0);
-  return device_status(gh::launch_mhm_batched<T>(a, gas, (scheme & HYDRO_FIRST_ORDER) ? 1 : 0, (scheme >> 8) & 3,
-                                                 n_bad_dev, work_dev, variant, int(g), s));
+  const int fo = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0, ws = (scheme >> 8) & 3;
+  // work_dev NULL: the allocation-free entry point (the library's own counters)
+  if (work_dev == nullptr)
+    return device_status(gh::launch_mhm_batched_noalloc<T>(a, gas, fo, ws, n_bad_dev, variant, int(g), s));
+  return device_status(gh::launch_mhm_batched<T>(a, gas, fo, ws, n_bad_dev, work_dev, variant, int(g), s));
 }
 
 // A level of ngx x ngy x ngz groups: cell indices along each axis (plus
@@ -665,6 +668,22 @@ int hydro_advance_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int3
                     kDefaultBatchedVariant, &variant);
   if (st != HYDRO_OK) return st;
   return batched_launch(levels_host, n_levels, dtype, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant,
+                        static_cast<hipStream_t>(stream));
+}
+
+int hydro_advance_batched_noalloc(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels,
+                                  int32_t dtype, double gamma, int32_t scheme, double theta, int32_t* n_bad_dev,
+                                  int32_t grid, void* stream) {
+  if ((dtype != HYDRO_F64 && dtype != HYDRO_F32) || !(std::isfinite(gamma) && gamma > 1.0) ||
+      !valid_scheme(scheme, theta) || grid < 0)
+    return HYDRO_EINVAL;
+  int st = validate_levels(levels_host, n_levels, dtype);
+  if (st != HYDRO_OK) return st;
+  int variant = 0;
+  st = select_shape(ctx, batched_key(dtype, levels_host, n_levels), ctx ? &ctx->batched_sel[dtype] : nullptr,
+                    kDefaultBatchedVariant, &variant);
+  if (st != HYDRO_OK) return st;
+  return batched_launch(levels_host, n_levels, dtype, gamma, scheme, theta, n_bad_dev, nullptr, grid, variant,
                         static_cast<hipStream_t>(stream));
 }
 

@@ -60,6 +60,12 @@ template <typename T>
 hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
                               unsigned int* work, int variant, int grid, hipStream_t stream);
 
+// The same launch with the work counters in the library's own per-device
+// array (kBatchWorkWords words), cleared before the launch in stream order.
+template <typename T>
+hipError_t launch_mhm_batched_noalloc(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws,
+                                      int* n_bad, int variant, int grid, hipStream_t stream);
+
 // Adjoint of the step (mhm_adj.hip).  Workspace in elements of T:
 // adjoint_workspace_elems(G, level).
 size_t adjoint_workspace_elems(int64_t n_groups, bool level);

@@ -8,9 +8,16 @@
 // level step, so results are bit-identical to one launch per level, in any
 // order of items.
 
+#include <mutex>
+
 #include "mhm_group.h"
 
 namespace gh {
+
+// Work counters of the allocation-free entry point (hydro_advance_batched_noalloc):
+// one copy per device, alive until the process ends.  In host code `scratch`
+// only names the symbol; its device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned int scratch[kBatchWorkWords];
 
 namespace {
 
@@ -164,6 +171,56 @@ hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int f
   }
   return hipGetLastError();
 }
+
+namespace {
+
+__global__ void clear_words_kernel(unsigned int* __restrict__ p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0u;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned int* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+hipError_t scratch_address(unsigned int** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = static_cast<unsigned int*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_mhm_batched_noalloc(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws,
+                                      int* n_bad, int variant, int grid, hipStream_t stream) {
+  if (args.total == 0) return hipSuccess;
+  unsigned int* work = nullptr;
+  hipError_t e = scratch_address(&work);
+  if (e != hipSuccess) return e;
+  // the counters must start at zero: clear them in stream order (a kernel,
+  // not a memset, so that the call can be captured into a graph)
+  hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(64), 0, stream, work, kBatchWorkWords);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_mhm_batched<T>(args, gas, first_order, ws, n_bad, work, variant, grid, stream);
+}
+
+template hipError_t launch_mhm_batched_noalloc<double>(const BatchArgs<double>&, const Gas<double>&, int, int, int*,
+                                                       int, int, hipStream_t);
+template hipError_t launch_mhm_batched_noalloc<float>(const BatchArgs<float>&, const Gas<float>&, int, int, int*, int,
+                                                      int, hipStream_t);
 
 template hipError_t launch_mhm_batched<double>(const BatchArgs<double>&, const Gas<double>&, int, int, int*,
                                                unsigned int*, int, int, hipStream_t);

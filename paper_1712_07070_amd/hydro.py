@@ -84,6 +84,7 @@ def load():
         "hydro_variant_name": (i32, [i32, ctypes.c_char_p, i32]),
         "hydro_autotune": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, P, i64, i32, P, P]),
         "hydro_advance_batched": (i32, [P, P, i32, i32, f64, i32, f64, P, P, i32, P]),
+        "hydro_advance_batched_noalloc": (i32, [P, P, i32, i32, f64, i32, f64, P, i32, P]),
         "hydro_set_batched_variant": (i32, [P, i32, i32]),
         "hydro_get_batched_variant": (i32, [P, i32]),
         "hydro_autotune_batched": (i32, [P, P, i32, i32, f64, P, i32, P, P]),
@@ -434,6 +435,18 @@ def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5
                                       float(gamma), int(scheme), float(theta), _opt(n_bad, "n_bad", torch.int32),
                                       _dev(work, "work"), int(grid), _stream())
     _check(st, "hydro_advance_batched")
+
+
+def advance_batched_noalloc(levels, gamma: float, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC,
+                            n_bad: Optional[torch.Tensor] = None, grid: int = 0, ctx: Optional[Context] = None) -> None:
+    """advance_batched without a work buffer (hydro_advance_batched_noalloc):
+    the library keeps the work counters in its own per-device array, so the
+    call allocates nothing; calls overlapping on one device race."""
+    arr, _ = _levels_array(levels)
+    st = load().hydro_advance_batched_noalloc(_ctx(ctx), ctypes.cast(arr, ctypes.c_void_p), len(levels),
+                                              _dtype_code(levels[0][0]), float(gamma), int(scheme), float(theta),
+                                              _opt(n_bad, "n_bad", torch.int32), int(grid), _stream())
+    _check(st, "hydro_advance_batched_noalloc")
 
 
 def autotune_batched(levels, gamma: float, work: torch.Tensor, reps: int = 5,
