@@ -81,6 +81,22 @@ typedef struct hydro_ctx hydro_ctx;
 #define HYDRO_WAVESPEED_ROE (0 << 8)
 #define HYDRO_WAVESPEED_DAVIS (1 << 8)
 #define HYDRO_FIRST_ORDER (1 << 10)
+/* Further scheme-word fields (Sec. 2.2), accepted by hydro_advance_ext only:
+ * bits 0-7 scheme id MHM (= HYDRO_SCHEME_MHM_PLM_HLLC) or CTU (6 Riemann
+ * solves per cell); bits 11-12 slope limiter; bit 13 limit characteristic
+ * instead of primitive variables; bit 14 PPM instead of PLM; bits 16-17
+ * Riemann solver. */
+#define HYDRO_SCHEME_MHM 1
+#define HYDRO_SCHEME_CTU 2
+#define HYDRO_LIMITER_GMINMOD (0 << 11)
+#define HYDRO_LIMITER_VANLEER (1 << 11)
+#define HYDRO_LIMITER_VANALBADA (2 << 11)
+#define HYDRO_LIMITER_HYBRID (3 << 11)
+#define HYDRO_CHARACTERISTIC (1 << 13)
+#define HYDRO_PPM (1 << 14)
+#define HYDRO_RIEMANN_HLLC (0 << 16)
+#define HYDRO_RIEMANN_ROE (1 << 16)
+#define HYDRO_RIEMANN_HLLE (2 << 16)
 
 #define HYDRO_BC_PERIODIC 0
 #define HYDRO_BC_OUTFLOW 1
@@ -134,6 +150,91 @@ int hydro_check_unphysical(const int32_t* n_bad_dev, void* stream, int32_t* n_ba
 int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost,
                   int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
                   double theta, const double* dt_dev, int32_t* n_bad_dev, void* stream);
+
+/* hydro_advance_ext -- one step of G padded groups with any scheme of
+ * Sec. 2.2 that the scheme word names (hydro_advance's arguments and
+ * semantics, plus a workspace):
+ *   MHM: face values, then the conservative Hancock half step with the three
+ *        axes' face-value flux differences, then a Riemann solve at every
+ *        face, then the conservative update;
+ *   CTU (Colella 1990, 6 Riemann solves per cell): face values and a half
+ *        step with each axis' own flux difference; first Riemann solves at
+ *        every face; each axis' states corrected by dt/(2dx) times the other
+ *        two axes' first-solve flux differences; second solves; update.
+ *   Face values: PLM (W0 -+ s/2) or PPM (Colella & Woodward 1984: fourth-
+ *   order interface values from the limited slopes of the three nearest
+ *   cells, then the monotonicity constraints), with slopes limited on
+ *   primitive or characteristic variables (left/right eigenvectors of the
+ *   primitive Euler system of the cell); limiters: generalized minmod
+ *   (theta), van Leer (harmonic mean), van Albada, hybrid (the smaller of
+ *   generalized minmod and van Leer).  Solvers: HLLC, HLLE (Einfeldt), Roe
+ *   (no entropy fix; a face whose linearized intermediate states are
+ *   unphysical takes the HLLC flux, the first step of the paper's procedure
+ *   for unphysical results).
+ *   ghost       >= 2, and >= 3 with PPM
+ *   work_dev    device scratch of work_bytes bytes, at least
+ *               hydro_ext_workspace_bytes(1, ghost, dtype, scheme); groups are
+ *               processed in chunks of as many groups as it holds (all at
+ *               once with hydro_ext_workspace_bytes(G, ...)); must not overlap
+ *               U_pad_dev or U_out_dev
+ *   n_bad_dev   as for hydro_advance (faces with unphysical input states plus
+ *               updated cells with rho <= 0 or p <= 0)
+ * hydro_ext_workspace_bytes returns the bytes for n_groups groups, or
+ * HYDRO_EINVAL for an invalid scheme word / ghost / dtype. */
+int64_t hydro_ext_workspace_bytes(int64_t n_groups, int32_t ghost, int32_t dtype, int32_t scheme);
+int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
+                      double dt, double dx, double gamma, int32_t scheme, double theta, const double* dt_dev,
+                      int32_t* n_bad_dev, void* work_dev, int64_t work_bytes, void* stream);
+
+/* Procedure for unphysical results (Sec. 2.2: a cell whose update gives
+ * rho <= 0 or p <= 0 is (ii) recomputed first-order in space and time,
+ * dimensionally unsplit; (iii) if that fails, first-order and dimensionally
+ * split; (iv)-(v) if that fails too, the whole level is recomputed with the
+ * time-step reduced by a fixed ratio until nothing fails or a minimum
+ * time-step is reached).  Step (i), the switch of Roe's solver to HLLC on a
+ * face with an unphysical intermediate state, is part of the Roe solver.
+ *
+ * hydro_repair_unphysical -- steps (ii)-(iii) on a level after a step:
+ *   level_in_dev   [G][5][16^3] the step's input level (not modified)
+ *   level_out_dev  [G][5][16^3] the step's output; every cell with rho <= 0 or
+ *                  p <= 0 is replaced by its first-order unsplit recomputation
+ *                  from level_in_dev (Riemann fluxes of the scheme's solver on
+ *                  the cell averages of its six faces, summed x, y, z), or, if
+ *                  that is unphysical too, by its first-order split
+ *                  recomputation (x, y, z sweeps over the 3x3x3 block around
+ *                  it); neighbours beyond the level follow bc_host
+ *   scheme         only the Riemann solver and wave-speed fields are used
+ *   dt, dt_dev     the step's time-step (dt_dev: device double read instead)
+ *   counts_dev     3 device int32, ADDED to: cells repaired unsplit, cells
+ *                  repaired split, cells still unphysical
+ *   Asynchronous on stream; level limits as hydro_advance_level.
+ *
+ * hydro_fallback_workspace_bytes -- device scratch hydro_advance_level_fallback
+ *   needs for a level (256 B of counters; for scheme words other than the
+ *   fused step's, also a padded copy with 3 ghosts and the
+ *   hydro_advance_ext workspace), or HYDRO_EINVAL.
+ *
+ * hydro_advance_level_fallback -- steps (ii)-(v): one step of the level
+ *   (hydro_advance_level for the default scheme word, else hydro_fill_ghosts
+ *   + hydro_advance_ext), then, if the step counted unphysical items,
+ *   hydro_repair_unphysical; while cells remain unphysical and dt * ratio >=
+ *   dt_min, the level is recomputed from level_in_dev with dt *= ratio.
+ *   ratio in (0, 1) (0.8 in the paper), dt_min >= 0.
+ *   work_dev, work_bytes  at least hydro_fallback_workspace_bytes(...)
+ *   info_host      4 doubles: the dt of the last attempt, the number of
+ *                  retries, the cells repaired unsplit and split in it
+ *   Returns HYDRO_OK (no cell left unphysical), HYDRO_UNPHYSICAL (cells still
+ *   unphysical at the last dt allowed; level_out_dev holds that attempt) or
+ *   an error.  SYNCHRONOUS: waits on `stream` after each attempt.
+ */
+int hydro_repair_unphysical(const void* level_in_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                            const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                            const double* dt_dev, int32_t* counts_dev, void* stream);
+int64_t hydro_fallback_workspace_bytes(int32_t ngx, int32_t ngy, int32_t ngz, int32_t dtype, int32_t scheme);
+int hydro_advance_level_fallback(hydro_ctx* ctx, const void* level_in_dev, void* level_out_dev, int32_t ngx,
+                                 int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt,
+                                 double dt_min, double ratio, double dx, double gamma, int32_t scheme, double theta,
+                                 void* work_dev, int64_t work_bytes, double* info_host, void* stream);
 
 /* hydro_advance_level -- one MHM step of every patch group of a level, read
  * directly from level storage (Sec. 2.2 scheme; Sec. 3.4 ghost zones; Sec. 2.6

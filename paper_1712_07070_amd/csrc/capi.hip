@@ -1,6 +1,7 @@
 // extern "C" entry points of libhydro: argument validation and dispatch to
 // the kernels.  Declarations and documentation: include/hydro.h.
 
+#include <algorithm>
 #include <atomic>
 #include <cctype>
 #include <cmath>
@@ -12,6 +13,7 @@
 #include <set>
 #include <string>
 
+#include "ext_device.h"
 #include "hydro.h"
 #include "kernels.h"
 
@@ -186,6 +188,25 @@ bool valid_scheme(int32_t scheme, double theta) {
   const int ws = (scheme >> 8) & 3;
   if (ws > 1) return false;
   if (scheme & ~(0xff | (3 << 8) | HYDRO_FIRST_ORDER)) return false;
+  return std::isfinite(theta) && theta >= 1.0 && theta <= 2.0;
+}
+
+// Scheme words of hydro_advance_ext: any id, solver, limiter and
+// reconstruction bit; the reconstruction must fit in the ghost zones.
+bool valid_ext_scheme(int32_t scheme, double theta, int32_t ghost, gh::ExtOpts* o) {
+  const int id = scheme & 0xff;
+  if (id != HYDRO_SCHEME_MHM && id != HYDRO_SCHEME_CTU) return false;
+  const int known = 0xff | (3 << 8) | HYDRO_FIRST_ORDER | (3 << 11) | HYDRO_CHARACTERISTIC | HYDRO_PPM | (3 << 16);
+  if (scheme & ~known) return false;
+  o->ctu = id == HYDRO_SCHEME_CTU;
+  o->ws = (scheme >> 8) & 3;
+  o->first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
+  o->lim = (scheme >> 11) & 3;
+  o->chr = (scheme & HYDRO_CHARACTERISTIC) ? 1 : 0;
+  o->ppm = (scheme & HYDRO_PPM) ? 1 : 0;
+  o->solver = (scheme >> 16) & 3;
+  if (o->ws > 1 || o->solver > 2) return false;
+  if (ghost < o->radius() + 1 || ghost < 2) return false;
   return std::isfinite(theta) && theta >= 1.0 && theta <= 2.0;
 }
 
@@ -553,6 +574,197 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
     e = gh::launch_mhm_fwd(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups, ghost,
                            make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, first_order, ws, n_bad_dev, s);
   return device_status(e);
+}
+
+// ------------------------------------------------------- other schemes ----
+int64_t hydro_ext_workspace_bytes(int64_t n_groups, int32_t ghost, int32_t dtype, int32_t scheme) {
+  gh::ExtOpts o;
+  if (n_groups < 0 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32) ||
+      !valid_ext_scheme(scheme, 1.5, ghost, &o))
+    return HYDRO_EINVAL;
+  return gh::ext_workspace_elems(n_groups, ghost, o) * int64_t(dtype_size(dtype));
+}
+
+int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
+                      double dt, double dx, double gamma, int32_t scheme, double theta, const double* dt_dev,
+                      int32_t* n_bad_dev, void* work_dev, int64_t work_bytes, void* stream) {
+  gh::ExtOpts o;
+  if (n_groups < 0 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_ext_scheme(scheme, theta, ghost, &o))
+    return HYDRO_EINVAL;
+  if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
+  if (n_groups == 0) return HYDRO_OK;
+  if (U_pad_dev == nullptr || U_out_dev == nullptr || work_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t P = 16 + 2 * ghost;
+  const size_t es = dtype_size(dtype);
+  const int64_t per_group = gh::ext_workspace_elems(1, ghost, o) * int64_t(es);
+  if (work_bytes < per_group) return HYDRO_EINVAL;
+  const size_t pad_b = size_t(n_groups) * 5 * P * P * P * es, out_b = size_t(n_groups) * 5 * 4096 * es;
+  const int64_t chunk = std::min<int64_t>(n_groups, work_bytes / per_group);
+  const size_t work_b = size_t(gh::ext_workspace_elems(chunk, ghost, o)) * es;
+  if (overlap(U_pad_dev, pad_b, U_out_dev, out_b) || overlap(work_dev, work_b, U_pad_dev, pad_b) ||
+      overlap(work_dev, work_b, U_out_dev, out_b))
+    return HYDRO_EINVAL;
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // groups in chunks that fit the caller's workspace, one after another on the stream
+  for (int64_t g0 = 0; g0 < n_groups; g0 += chunk) {
+    const int64_t G = std::min(chunk, n_groups - g0);
+    hipError_t e;
+    if (dtype == HYDRO_F64)
+      e = gh::launch_ext_step(static_cast<const double*>(U_pad_dev) + g0 * 5 * P * P * P,
+                              static_cast<double*>(U_out_dev) + g0 * 5 * 4096, G, ghost,
+                              make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, o, n_bad_dev,
+                              static_cast<double*>(work_dev), s);
+    else
+      e = gh::launch_ext_step(static_cast<const float*>(U_pad_dev) + g0 * 5 * P * P * P,
+                              static_cast<float*>(U_out_dev) + g0 * 5 * 4096, G, ghost,
+                              make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, o, n_bad_dev,
+                              static_cast<float*>(work_dev), s);
+    if (e != hipSuccess) return device_status(e);
+  }
+  return HYDRO_OK;
+}
+
+// ------------------------------------- procedure for unphysical results ----
+namespace {
+
+// Level arguments shared by the two fallback entry points (scheme: any word
+// hydro_advance_ext accepts).
+int check_fallback_args(const void* in, const void* out, int32_t ngx, int32_t ngy, int32_t ngz, const int32_t* bc,
+                        int32_t dtype, double dx, double gamma, int32_t scheme, double theta, gh::LevelGeom* geo,
+                        gh::ExtOpts* o) {
+  if (!level_geom_ok(ngx, ngy, ngz) || bc == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_ext_scheme(scheme, theta, 3, o))
+    return HYDRO_EINVAL;
+  geo->ngx = ngx;
+  geo->ngy = ngy;
+  geo->ngz = ngz;
+  for (int i = 0; i < 6; ++i) {
+    if (bc[i] != HYDRO_BC_PERIODIC && bc[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
+    geo->bc[i] = bc[i];
+  }
+  if (in == nullptr || out == nullptr) return HYDRO_EINVAL;
+  const size_t bytes = size_t(int64_t(ngx) * ngy * ngz) * 5 * 4096 * dtype_size(dtype);
+  if (overlap(in, bytes, out, bytes)) return HYDRO_EINVAL;
+  return HYDRO_OK;
+}
+
+int repair_launch(const void* in, void* out, const gh::LevelGeom& geo, int32_t dtype, double dt, double dx,
+                  double gamma, const gh::ExtOpts& o, const double* dt_dev, int32_t* counts, hipStream_t s) {
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_repair(static_cast<const double*>(in), static_cast<double*>(out), geo,
+                          make_gas<double>(gamma, 1.5, dt_host, dx), dt_dev, dx, o, counts, s);
+  else
+    e = gh::launch_repair(static_cast<const float*>(in), static_cast<float*>(out), geo,
+                          make_gas<float>(gamma, 1.5, dt_host, dx), dt_dev, dx, o, counts, s);
+  return device_status(e);
+}
+
+constexpr int64_t kFallbackCounterBytes = 256;
+
+int64_t fallback_pad_bytes(int64_t G, int32_t dtype) {
+  return (G * 5 * 22 * 22 * 22 * int64_t(dtype_size(dtype)) + 255) / 256 * 256;
+}
+
+}  // namespace
+
+int hydro_repair_unphysical(const void* level_in_dev, void* level_out_dev, int32_t ngx, int32_t ngy, int32_t ngz,
+                            const int32_t* bc_host, int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
+                            const double* dt_dev, int32_t* counts_dev, void* stream) {
+  gh::LevelGeom geo;
+  gh::ExtOpts o;
+  int st = check_fallback_args(level_in_dev, level_out_dev, ngx, ngy, ngz, bc_host, dtype, dx, gamma, scheme, 1.5,
+                               &geo, &o);
+  if (st != HYDRO_OK) return st;
+  if (counts_dev == nullptr || (dt_dev == nullptr && !finite_pos(dt))) return HYDRO_EINVAL;
+  return repair_launch(level_in_dev, level_out_dev, geo, dtype, dt, dx, gamma, o, dt_dev, counts_dev,
+                       static_cast<hipStream_t>(stream));
+}
+
+int64_t hydro_fallback_workspace_bytes(int32_t ngx, int32_t ngy, int32_t ngz, int32_t dtype, int32_t scheme) {
+  gh::ExtOpts o;
+  if (!level_geom_ok(ngx, ngy, ngz) || (dtype != HYDRO_F64 && dtype != HYDRO_F32) ||
+      !valid_ext_scheme(scheme, 1.5, 3, &o))
+    return HYDRO_EINVAL;
+  if (valid_scheme(scheme, 1.5)) return kFallbackCounterBytes;  // the fused level step needs no more
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  return kFallbackCounterBytes + fallback_pad_bytes(G, dtype) +
+         gh::ext_workspace_elems(G, 3, o) * int64_t(dtype_size(dtype));
+}
+
+int hydro_advance_level_fallback(hydro_ctx* ctx, const void* level_in_dev, void* level_out_dev, int32_t ngx,
+                                 int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt,
+                                 double dt_min, double ratio, double dx, double gamma, int32_t scheme, double theta,
+                                 void* work_dev, int64_t work_bytes, double* info_host, void* stream) {
+  gh::LevelGeom geo;
+  gh::ExtOpts o;
+  int st = check_fallback_args(level_in_dev, level_out_dev, ngx, ngy, ngz, bc_host, dtype, dx, gamma, scheme, theta,
+                               &geo, &o);
+  if (st != HYDRO_OK) return st;
+  if (!finite_pos(dt) || !(ratio > 0.0 && ratio < 1.0) || !(dt_min >= 0.0) || std::isnan(dt_min) ||
+      work_dev == nullptr || info_host == nullptr)
+    return HYDRO_EINVAL;
+  const int64_t need = hydro_fallback_workspace_bytes(ngx, ngy, ngz, dtype, scheme);
+  if (need < 0 || work_bytes < need) return HYDRO_EINVAL;
+  const int64_t G = int64_t(ngx) * ngy * ngz;
+  const size_t lb = size_t(G) * 5 * 4096 * dtype_size(dtype);
+  if (overlap(work_dev, size_t(need), level_in_dev, lb) || overlap(work_dev, size_t(need), level_out_dev, lb))
+    return HYDRO_EINVAL;
+  const bool fused = valid_scheme(scheme, theta);
+  int variant = 0;
+  if (fused) {
+    st = select_shape(ctx, level_key(dtype, false, ngx, ngy, ngz), ctx ? &ctx->level_sel[dtype][0] : nullptr,
+                      kDefaultLevelVariant, &variant);
+    if (st != HYDRO_OK) return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t* cnt = static_cast<int32_t*>(work_dev);  // [0..2] repair counters, [3] unphysical count of the step
+  char* pad = static_cast<char*>(work_dev) + kFallbackCounterBytes;
+  char* ext_work = pad + fallback_pad_bytes(G, dtype);
+  int retries = 0;
+  for (;;) {
+    hipError_t e = gh::launch_zero_ints(cnt, 4, s);
+    if (e != hipSuccess) return device_status(e);
+    if (fused) {
+      st = level_launch(level_in_dev, level_out_dev, geo, dtype, dt, dx, gamma, scheme, theta, nullptr, cnt + 3, 0.0,
+                        nullptr, nullptr, nullptr, variant, s);
+    } else {
+      e = dtype == HYDRO_F64
+              ? gh::launch_fill_ghosts(static_cast<const double*>(level_in_dev), reinterpret_cast<double*>(pad), ngx,
+                                       ngy, ngz, 3, geo.bc, s)
+              : gh::launch_fill_ghosts(static_cast<const float*>(level_in_dev), reinterpret_cast<float*>(pad), ngx,
+                                       ngy, ngz, 3, geo.bc, s);
+      if (e != hipSuccess) return device_status(e);
+      st = hydro_advance_ext(pad, level_out_dev, G, 3, dtype, dt, dx, gamma, scheme, theta, nullptr, cnt + 3,
+                             ext_work, need - kFallbackCounterBytes - fallback_pad_bytes(G, dtype), stream);
+    }
+    if (st != HYDRO_OK) return st;
+    int32_t h[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_status(e);
+    if (h[3] > 0) {
+      // the step counted unphysical items: scan its output and repair
+      st = repair_launch(level_in_dev, level_out_dev, geo, dtype, dt, dx, gamma, o, nullptr, cnt, s);
+      if (st != HYDRO_OK) return st;
+      e = hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return device_status(e);
+    }
+    const double next = dt * ratio;
+    if (h[2] == 0 || next < dt_min) {
+      info_host[0] = dt;
+      info_host[1] = retries;
+      info_host[2] = h[0];
+      info_host[3] = h[1];
+      return h[2] == 0 ? HYDRO_OK : HYDRO_UNPHYSICAL;
+    }
+    dt = next;
+    ++retries;
+  }
 }
 
 // --------------------------------------------------------- level step ----

@@ -104,6 +104,22 @@ hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost,
                           const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
                           hipStream_t stream);
 
+// The other schemes of the scheme word (scheme_ext.hip): workspace size in
+// elements of T for G groups of ghost width `ghost`, and the step.
+struct ExtOpts;
+int64_t ext_workspace_elems(int64_t n_groups, int ghost, const ExtOpts& o);
+template <typename T>
+hipError_t launch_ext_step(const T* U_pad, T* U_out, int64_t G, int ghost, const Gas<T>& gas, const double* dt_dev,
+                           double dx, const ExtOpts& o, int* n_bad, T* work, hipStream_t stream);
+
+// Steps (ii)-(iii) of the procedure for unphysical results on a level
+// (fallback.hip); counts[3] device int32, added to: repaired unsplit,
+// repaired split, still unphysical.
+template <typename T>
+hipError_t launch_repair(const T* level_in, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
+                         const double* dt_dev, double dx, const ExtOpts& o, int* counts, hipStream_t stream);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t stream);
+
 template <typename T>
 hipError_t launch_fill_ghosts(const T* level, T* U_pad, int ngx, int ngy, int ngz, int ghost, const int bc[6],
                               hipStream_t stream);

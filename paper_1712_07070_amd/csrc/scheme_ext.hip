@@ -1,0 +1,349 @@
+// The other schemes of GAMER-2's fluid solver (Sec. 2.2) on padded patch
+// groups: MHM or CTU (6 Riemann solves per cell), PLM or PPM on primitive or
+// characteristic variables, generalized minmod / van Leer / van Albada /
+// hybrid limiters, HLLC / Roe / HLLE solvers.  The default scheme (MHM, PLM
+// on primitive variables, generalized minmod, HLLC) has its own fused
+// kernels (mhm_fwd.hip); this path trades their on-chip staging for a
+// general form: a chain of kernels, one thread per cell or face, passing
+// primitive states, face states and fluxes through a caller-owned workspace
+// in HBM, in the order the step defines them:
+//   1. ext_prim:    cons -> prim on the padded block                 W [5][P^3]
+//   2. ext_states:  face values and half step of every cell of
+//                   [-1, 16]^3 (MHM: Hancock with the three axes'
+//                   flux differences; CTU: the own axis' only)       S [6][5][18^3]
+//   3. ext_flux1:   CTU only: first Riemann solves on every face
+//                   between two cells of [-1, 16]^3                  F1 [3][5][17 18 18]
+//   4. ext_correct: CTU only: transverse correction of the states
+//                   with the other axes' first-solve fluxes         S in place
+//   5. ext_flux:    Riemann solves at the faces of the interior      F [3][5][17 16 16]
+//   6. ext_update:  U^{n+1} = U^n - dt/dx sum of flux differences (x, y, z)
+// Per-group arrays are indexed (group, field, cell); face arrays by (axis,
+// field, face) with face = ((b * NB + a) * 17 + n): n the normal coordinate
+// 0..16 (the face between n-1 and n), a, b the transverse coordinates in
+// the cyclic order (axis+1, axis+2).
+
+#include "ext_device.h"
+#include "kernels.h"
+
+namespace gh {
+
+namespace {
+
+constexpr int kS = 18;              // state cells per axis: -1 .. 16
+constexpr int kS3 = kS * kS * kS;   // 5832
+constexpr int kF1 = 17 * 18 * 18;   // first-solve faces per axis (transverse -1 .. 16)
+constexpr int kF = 17 * 16 * 16;    // interior faces per axis
+
+__device__ __forceinline__ int64_t cell_p(int P, int gh, int x, int y, int z) {
+  return (int64_t(z + gh) * P + (y + gh)) * P + (x + gh);
+}
+__device__ __forceinline__ int cell_s(int x, int y, int z) { return ((z + 1) * kS + (y + 1)) * kS + (x + 1); }
+
+// Sum over the wave (the caller adds it to the counter once per wave).
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// dt from the device double if given (dt_dev), as the fused kernels do.
+template <typename T>
+__device__ __forceinline__ void ext_set_dt(Gas<T>& gas, const double* dt_dev, double dx) {
+  if (dt_dev != nullptr) {
+    const double dt = *dt_dev;
+    gas.dtdx = T(dt / dx);
+    gas.half_dtdx = T(0.5 * (dt / dx));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ext_prim_kernel(const T* __restrict__ Upad, T* __restrict__ W, int64_t G,
+                                                       int P, Gas<T> gas) {
+  const int64_t P3 = int64_t(P) * P * P;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= P3) continue;
+    const T* u = Upad + g * 5 * P3 + i;
+    T U[5], Wc[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) U[q] = u[q * P3];
+    cons_to_prim(U, gas, Wc);
+    T* w = W + g * 5 * P3 + i;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) w[q * P3] = Wc[q];
+  }
+}
+
+// Face values of the cell (x, y, z) along axis D read from the primitive block.
+template <int D, typename T>
+__device__ __forceinline__ void load_stencil(const T* __restrict__ Wg, int64_t P3, int P, int gh, int x, int y, int z,
+                                             int R, T st[5][5]) {
+#pragma unroll
+  for (int j = -2; j <= 2; ++j) {
+    const int o = (j < -R || j > R) ? 0 : j;
+    const int xx = x + (D == 0 ? o : 0), yy = y + (D == 1 ? o : 0), zz = z + (D == 2 ? o : 0);
+    const int64_t c = cell_p(P, gh, xx, yy, zz);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) st[j + 2][q] = Wg[q * P3 + c];
+  }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void axis_states(const T* __restrict__ Wg, int64_t P3, int P, int gh, int x, int y, int z,
+                                            const Gas<T>& gas, const ExtOpts& o, T Ut[2][5], T Ff[2][5]) {
+  T st[5][5], Wf[2][5];
+  load_stencil<D>(Wg, P3, P, gh, x, y, z, o.radius(), st);
+  ext_face_values<D>(st, gas, o, Wf);
+  ext_cons_flux<D>(Wf[0], gas, Ut[0], Ff[0]);
+  ext_cons_flux<D>(Wf[1], gas, Ut[1], Ff[1]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ext_states_kernel(const T* __restrict__ W, T* __restrict__ S, int64_t G, int P,
+                                                         int gh, Gas<T> gas, const double* __restrict__ dt_dev,
+                                                         double dx, ExtOpts o) {
+  ext_set_dt(gas, dt_dev, dx);
+  const int64_t P3 = int64_t(P) * P * P;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kS3) return;
+  const int x = i % kS - 1, y = (i / kS) % kS - 1, z = i / (kS * kS) - 1;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    const T* Wg = W + g * 5 * P3;
+    T Ut[3][2][5], Ff[3][2][5];
+    axis_states<0>(Wg, P3, P, gh, x, y, z, gas, o, Ut[0], Ff[0]);
+    axis_states<1>(Wg, P3, P, gh, x, y, z, gas, o, Ut[1], Ff[1]);
+    axis_states<2>(Wg, P3, P, gh, x, y, z, gas, o, Ut[2], Ff[2]);
+    if (o.ctu) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const T dU = gas.half_dtdx * (Ff[d][0][q] - Ff[d][1][q]);
+          Ut[d][0][q] = Ut[d][0][q] + dU;
+          Ut[d][1][q] = Ut[d][1][q] + dU;
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        T s = Ff[0][0][q] - Ff[0][1][q];
+        s = s + (Ff[1][0][q] - Ff[1][1][q]);
+        s = s + (Ff[2][0][q] - Ff[2][1][q]);
+        const T dU = gas.half_dtdx * s;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          Ut[d][0][q] = Ut[d][0][q] + dU;
+          Ut[d][1][q] = Ut[d][1][q] + dU;
+        }
+      }
+    }
+    T* Sg = S + g * 30 * int64_t(kS3) + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Sg[((d * 2 + s) * 5 + q) * int64_t(kS3)] = Ut[d][s][q];
+  }
+}
+
+// Cell coordinates from (axis D, normal n, transverse a, b in cyclic order).
+template <int D>
+__device__ __forceinline__ void face_cell(int n, int a, int b, int& x, int& y, int& z) {
+  if (D == 0) { x = n; y = a; z = b; }
+  if (D == 1) { y = n; z = a; x = b; }
+  if (D == 2) { z = n; x = a; y = b; }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void load_state(const T* __restrict__ Sg, int x, int y, int z, int side, T U[5]) {
+  const int c = cell_s(x, y, z);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) U[q] = Sg[((D * 2 + side) * 5 + q) * int64_t(kS3) + c];
+}
+
+// Riemann solve of the face (D, n, a, b) between cell - e_D (its high state)
+// and cell (its low state); returns the unphysical flag.
+template <int D, typename T>
+__device__ __forceinline__ int solve_face(const T* __restrict__ Sg, int n, int a, int b, const Gas<T>& gas,
+                                          const ExtOpts& o, T F[5]) {
+  int x, y, z;
+  face_cell<D>(n, a, b, x, y, z);
+  T L[5], R[5];
+  load_state<D>(Sg, x - (D == 0), y - (D == 1), z - (D == 2), 1, L);
+  load_state<D>(Sg, x, y, z, 0, R);
+  return riemann_any<D>(L, R, gas, o, F) ? 1 : 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ext_flux1_kernel(const T* __restrict__ S, T* __restrict__ F1, int64_t G,
+                                                        Gas<T> gas, ExtOpts o) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * kF1) return;
+  const int d = i / kF1, f = i % kF1;
+  const int n = f % 17, a = (f / 17) % 18 - 1, b = f / (17 * 18) - 1;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    const T* Sg = S + g * 30 * int64_t(kS3);
+    T F[5];
+    if (d == 0) solve_face<0>(Sg, n, a, b, gas, o, F);
+    else if (d == 1) solve_face<1>(Sg, n, a, b, gas, o, F);
+    else solve_face<2>(Sg, n, a, b, gas, o, F);
+    T* out = F1 + g * 15 * int64_t(kF1) + d * 5 * int64_t(kF1) + f;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q * int64_t(kF1)] = F[q];
+  }
+}
+
+// First-solve flux of the face of axis E at cell coordinates (x, y, z) (the
+// face between (x, y, z) - e_E and (x, y, z)).
+template <typename T>
+__device__ __forceinline__ const T* f1_at(const T* __restrict__ F1g, int E, int x, int y, int z) {
+  int n, a, b;
+  if (E == 0) { n = x; a = y; b = z; }
+  else if (E == 1) { n = y; a = z; b = x; }
+  else { n = z; a = x; b = y; }
+  return F1g + E * 5 * int64_t(kF1) + ((b + 1) * 18 + (a + 1)) * 17 + n;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ext_correct_kernel(T* __restrict__ S, const T* __restrict__ F1, int64_t G,
+                                                          Gas<T> gas, const double* __restrict__ dt_dev, double dx) {
+  ext_set_dt(gas, dt_dev, dx);
+  constexpr int kPer = 18 * 16 * 16;  // normal -1..16, transverse 0..15
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * kPer) return;
+  const int d = i / kPer, f = i % kPer;
+  const int n = f % 18 - 1, a = (f / 18) % 16, b = f / (18 * 16);
+  int x, y, z;
+  if (d == 0) { x = n; y = a; z = b; }
+  else if (d == 1) { y = n; z = a; x = b; }
+  else { z = n; x = a; y = b; }
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    const T* F1g = F1 + g * 15 * int64_t(kF1);
+    T corr[5];
+    bool first = true;
+    for (int e = 0; e < 3; ++e) {
+      if (e == d) continue;
+      const T* Fp = f1_at(F1g, e, x + (e == 0), y + (e == 1), z + (e == 2));
+      const T* Fm = f1_at(F1g, e, x, y, z);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T dq = Fp[q * int64_t(kF1)] - Fm[q * int64_t(kF1)];
+        corr[q] = first ? dq : corr[q] + dq;
+      }
+      first = false;
+    }
+    T* Sg = S + g * 30 * int64_t(kS3) + cell_s(x, y, z);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        T& v = Sg[((d * 2 + s) * 5 + q) * int64_t(kS3)];
+        v = v - gas.half_dtdx * corr[q];
+      }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ext_flux_kernel(const T* __restrict__ S, T* __restrict__ F, int64_t G,
+                                                       Gas<T> gas, ExtOpts o, int* __restrict__ n_bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < 3 * kF;
+  const int d = live ? i / kF : 0, f = live ? i % kF : 0;
+  const int n = f % 17, a = (f / 17) % 16, b = f / (17 * 16);
+  int bad = 0;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    if (!live) continue;
+    const T* Sg = S + g * 30 * int64_t(kS3);
+    T Fv[5];
+    if (d == 0) bad += solve_face<0>(Sg, n, a, b, gas, o, Fv);
+    else if (d == 1) bad += solve_face<1>(Sg, n, a, b, gas, o, Fv);
+    else bad += solve_face<2>(Sg, n, a, b, gas, o, Fv);
+    T* out = F + g * 15 * int64_t(kF) + d * 5 * int64_t(kF) + f;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q * int64_t(kF)] = Fv[q];
+  }
+  bad = wave_sum(bad);
+  if (n_bad != nullptr && (threadIdx.x & 63) == 0 && bad != 0) atomicAdd(n_bad, bad);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ext_update_kernel(const T* __restrict__ Upad, const T* __restrict__ F,
+                                                         T* __restrict__ Uout, int64_t G, int P, int gh, Gas<T> gas,
+                                                         const double* __restrict__ dt_dev, double dx,
+                                                         int* __restrict__ n_bad) {
+  ext_set_dt(gas, dt_dev, dx);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // < 4096 (grid sized exactly)
+  const int x = i & 15, y = (i >> 4) & 15, z = i >> 8;
+  const int64_t P3 = int64_t(P) * P * P;
+  int bad = 0;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    const T* Fg = F + g * 15 * int64_t(kF);
+    // face index of the low face of this cell along each axis
+    const int fx = (z * 16 + y) * 17 + x;   // axis 0: n = x, a = y, b = z
+    const int fy = (x * 16 + z) * 17 + y;   // axis 1: n = y, a = z, b = x
+    const int fz = (y * 16 + x) * 17 + z;   // axis 2: n = z, a = x, b = y
+    T Un[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const T* Fx = Fg + (0 * 5 + q) * int64_t(kF);
+      const T* Fy = Fg + (1 * 5 + q) * int64_t(kF);
+      const T* Fz = Fg + (2 * 5 + q) * int64_t(kF);
+      T acc = Fx[fx + 1] - Fx[fx];
+      acc = acc + (Fy[fy + 1] - Fy[fy]);
+      acc = acc + (Fz[fz + 1] - Fz[fz]);
+      Un[q] = Upad[g * 5 * P3 + q * P3 + cell_p(P, gh, x, y, z)] - gas.dtdx * acc;
+      Uout[g * 5 * 4096 + q * 4096 + i] = Un[q];
+    }
+    bad += unphysical(Un, gas) ? 1 : 0;
+  }
+  bad = wave_sum(bad);
+  if (n_bad != nullptr && (threadIdx.x & 63) == 0 && bad != 0) atomicAdd(n_bad, bad);
+}
+
+unsigned grid_y(int64_t G) { return unsigned(G < 65535 ? G : 65535); }
+
+}  // namespace
+
+int64_t ext_workspace_elems(int64_t n_groups, int ghost, const ExtOpts& o) {
+  const int64_t P = 16 + 2 * ghost;
+  auto up = [](int64_t v) { return (v + 63) / 64 * 64; };
+  return n_groups * (up(5 * P * P * P) + up(30 * int64_t(kS3)) + (o.ctu ? up(15 * int64_t(kF1)) : 0) +
+                     up(15 * int64_t(kF)));
+}
+
+template <typename T>
+hipError_t launch_ext_step(const T* U_pad, T* U_out, int64_t G, int ghost, const Gas<T>& gas, const double* dt_dev,
+                           double dx, const ExtOpts& o, int* n_bad, T* work, hipStream_t stream) {
+  if (G == 0) return hipSuccess;
+  const int P = 16 + 2 * ghost;
+  const int64_t P3 = int64_t(P) * P * P;
+  auto up = [](int64_t v) { return (v + 63) / 64 * 64; };
+  T* W = work;
+  T* S = W + G * up(5 * P3);
+  T* F1 = S + G * up(30 * int64_t(kS3));
+  T* F = F1 + (o.ctu ? G * up(15 * int64_t(kF1)) : 0);
+  // per-group strides of the arrays are the unpadded sizes; the padded sizes
+  // above only separate the arrays
+  const unsigned gy = grid_y(G);
+  hipLaunchKernelGGL(ext_prim_kernel<T>, dim3(unsigned((P3 + 255) / 256), gy), dim3(256), 0, stream, U_pad, W, G, P,
+                     gas);
+  hipLaunchKernelGGL(ext_states_kernel<T>, dim3(unsigned((kS3 + 255) / 256), gy), dim3(256), 0, stream, W, S, G, P,
+                     ghost, gas, dt_dev, dx, o);
+  if (o.ctu) {
+    hipLaunchKernelGGL(ext_flux1_kernel<T>, dim3(unsigned((3 * kF1 + 255) / 256), gy), dim3(256), 0, stream, S, F1, G,
+                       gas, o);
+    hipLaunchKernelGGL(ext_correct_kernel<T>, dim3(unsigned((3 * 18 * 256 + 255) / 256), gy), dim3(256), 0, stream, S,
+                       F1, G, gas, dt_dev, dx);
+  }
+  hipLaunchKernelGGL(ext_flux_kernel<T>, dim3(unsigned((3 * kF + 255) / 256), gy), dim3(256), 0, stream, S, F, G, gas,
+                     o, n_bad);
+  hipLaunchKernelGGL(ext_update_kernel<T>, dim3(16u, gy), dim3(256), 0, stream, U_pad, F, U_out, G, P, ghost, gas,
+                     dt_dev, dx, n_bad);
+  return hipGetLastError();
+}
+
+template hipError_t launch_ext_step<double>(const double*, double*, int64_t, int, const Gas<double>&, const double*,
+                                            double, const ExtOpts&, int*, double*, hipStream_t);
+template hipError_t launch_ext_step<float>(const float*, float*, int64_t, int, const Gas<float>&, const double*, double,
+                                           const ExtOpts&, int*, float*, hipStream_t);
+
+}  // namespace gh

@@ -29,6 +29,12 @@ WAVESPEED_ROE = 0 << 8
 WAVESPEED_DAVIS = 1 << 8
 FIRST_ORDER = 1 << 10
 BC_PERIODIC, BC_OUTFLOW = 0, 1
+# scheme-word fields of hydro_advance_ext (include/hydro.h)
+SCHEME_MHM, SCHEME_CTU = 1, 2
+LIMITER_GMINMOD, LIMITER_VANLEER, LIMITER_VANALBADA, LIMITER_HYBRID = 0 << 11, 1 << 11, 2 << 11, 3 << 11
+CHARACTERISTIC = 1 << 13
+PPM = 1 << 14
+RIEMANN_HLLC, RIEMANN_ROE, RIEMANN_HLLE = 0 << 16, 1 << 16, 2 << 16
 BATCH_WORK_WORDS = 16       # uint32 words of the batched kernel's work buffer
 BATCHED_VARIANTS = 12       # launch shapes of the batched kernel
 
@@ -69,6 +75,12 @@ def load():
         "hydro_ctx_num_tuned": (i32, [P]),
         "hydro_check_unphysical": (i32, [P, P, P]),
         "hydro_advance": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P, P]),
+        "hydro_ext_workspace_bytes": (i64, [i64, i32, i32, i32]),
+        "hydro_advance_ext": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P, P, i64, P]),
+        "hydro_repair_unphysical": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, P, P, P]),
+        "hydro_fallback_workspace_bytes": (i64, [i32, i32, i32, i32, i32]),
+        "hydro_advance_level_fallback": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, f64, f64, i32, f64,
+                                               P, i64, P, P]),
         "hydro_advance_level": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, f64, P, P, P,
                                       P]),
         "hydro_dt": (i32, [P, i64, i32, i32, f64, f64, f64, P, P, P]),
@@ -228,6 +240,100 @@ def advance(U_pad: torch.Tensor, dt: float, dx: float, gamma: float, theta: floa
                               _opt(dt_dev, "dt_dev", torch.float64), _opt(n_bad, "n_bad", torch.int32), _stream())
     _check(st, "hydro_advance")
     return out
+
+
+def ext_workspace(n_groups: int, ghost: int, dtype, scheme: int, device="cuda") -> torch.Tensor:
+    """A uint8 device workspace for hydro_advance_ext on n_groups groups."""
+    nb = load().hydro_ext_workspace_bytes(int(n_groups), int(ghost), F64 if dtype == torch.float64 else F32,
+                                          int(scheme))
+    if nb < 0:
+        raise HydroError("hydro_ext_workspace_bytes", int(nb))
+    return torch.empty(max(int(nb), 1), dtype=torch.uint8, device=device)
+
+
+def advance_ext(U_pad: torch.Tensor, dt: float, dx: float, gamma: float, scheme: int, theta: float = 1.5,
+                out: Optional[torch.Tensor] = None, n_bad: Optional[torch.Tensor] = None,
+                dt_dev: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One step of any scheme word (MHM / CTU, PLM / PPM, primitive /
+    characteristic, any limiter, HLLC / Roe / HLLE): U_pad[G,5,P,P,P] ->
+    U_out[G,5,16,16,16] (hydro_advance_ext).  work: uint8 device tensor of at
+    least hydro_ext_workspace_bytes(1, ...) bytes (default: enough for all
+    groups at once)."""
+    gh = ghost_of(U_pad)
+    G = U_pad.shape[0]
+    if out is None:
+        out = torch.empty((G, 5, 16, 16, 16), dtype=U_pad.dtype, device=U_pad.device)
+    if out.dtype != U_pad.dtype or tuple(out.shape) != (G, 5, 16, 16, 16):
+        raise ValueError("out must be [G,5,16,16,16] of the input dtype")
+    if work is None:
+        work = ext_workspace(G, gh, U_pad.dtype, scheme, U_pad.device)
+    if work.dtype != torch.uint8:
+        raise ValueError("work must be a uint8 tensor")
+    st = load().hydro_advance_ext(_dev(U_pad, "U_pad"), _dev(out, "out"), G, gh, _dtype_code(U_pad), float(dt),
+                                  float(dx), float(gamma), int(scheme), float(theta),
+                                  _opt(dt_dev, "dt_dev", torch.float64), _opt(n_bad, "n_bad", torch.int32),
+                                  _dev(work, "work"), work.numel(), _stream())
+    _check(st, "hydro_advance_ext")
+    return out
+
+
+def repair_unphysical(level_in: torch.Tensor, level_out: torch.Tensor, ng: Sequence[int], bc: Sequence[int],
+                      dt: float, dx: float, gamma: float, scheme: int = SCHEME_MHM_PLM_HLLC,
+                      counts: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Steps (ii)-(iii) of the procedure for unphysical results on level_out
+    (hydro_repair_unphysical); returns the int32 counters [repaired unsplit,
+    repaired split, still unphysical] (added to `counts` if given)."""
+    ngx, ngy, ngz = (int(v) for v in ng)
+    G = ngx * ngy * ngz
+    if tuple(level_in.shape) != (G, 5, 16, 16, 16) or level_out.shape != level_in.shape or \
+            level_out.dtype != level_in.dtype:
+        raise ValueError("levels must be [G,5,16,16,16] of one dtype")
+    if counts is None:
+        counts = torch.zeros(3, dtype=torch.int32, device=level_in.device)
+    if counts.dtype != torch.int32 or counts.numel() < 3:
+        raise ValueError("counts must hold 3 int32")
+    b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
+    st = load().hydro_repair_unphysical(_dev(level_in, "level_in"), _dev(level_out, "level_out"), ngx, ngy, ngz, b,
+                                        _dtype_code(level_in), float(dt), float(dx), float(gamma), int(scheme), None,
+                                        _dev(counts, "counts"), _stream())
+    _check(st, "hydro_repair_unphysical")
+    return counts
+
+
+def advance_level_fallback(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt: float, dx: float,
+                           gamma: float, theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, dt_min: float = 0.0,
+                           ratio: float = 0.8, out: Optional[torch.Tensor] = None,
+                           work: Optional[torch.Tensor] = None, ctx: Optional[Context] = None):
+    """One level step with the procedure for unphysical results
+    (hydro_advance_level_fallback, synchronous).  Returns (out, ok, info) with
+    ok False if cells remained unphysical at the smallest dt allowed and
+    info = dict(dt, retries, unsplit, split) of the last attempt."""
+    ngx, ngy, ngz = (int(v) for v in ng)
+    G = ngx * ngy * ngz
+    if tuple(level.shape) != (G, 5, 16, 16, 16):
+        raise ValueError("level must be [G,5,16,16,16] with G = ngx*ngy*ngz")
+    if out is None:
+        out = torch.empty_like(level)
+    if out.dtype != level.dtype or out.shape != level.shape:
+        raise ValueError("out must match the level")
+    code = _dtype_code(level)
+    if work is None:
+        nb = load().hydro_fallback_workspace_bytes(ngx, ngy, ngz, code, int(scheme))
+        if nb < 0:
+            raise HydroError("hydro_fallback_workspace_bytes", int(nb))
+        work = torch.empty(int(nb), dtype=torch.uint8, device=level.device)
+    if work.dtype != torch.uint8:
+        raise ValueError("work must be a uint8 tensor")
+    info = (ctypes.c_double * 4)()
+    b = (ctypes.c_int32 * 6)(*[int(v) for v in bc])
+    st = load().hydro_advance_level_fallback(_ctx(ctx), _dev(level, "level"), _dev(out, "out"), ngx, ngy, ngz, b, code,
+                                             float(dt), float(dt_min), float(ratio), float(dx), float(gamma),
+                                             int(scheme), float(theta), _dev(work, "work"), work.numel(), info,
+                                             _stream())
+    if st not in (HYDRO_OK, HYDRO_UNPHYSICAL):
+        raise HydroError("hydro_advance_level_fallback", st)
+    return out, st == HYDRO_OK, {"dt": info[0], "retries": int(info[1]), "unsplit": int(info[2]),
+                                 "split": int(info[3])}
 
 
 def advance_level(level: torch.Tensor, ng: Sequence[int], bc: Sequence[int], dt: float, dx: float, gamma: float,
