@@ -104,6 +104,8 @@ def _load():
         "oracle_level_step_any": (i64, [P, P, i32, i32, i32, i32, P, f64, f64, f64, f64, i32]),
         "oracle_level_step_fallback": (i64, [P, P, i32, i32, i32, i32, P, f64, f64, f64, f64, f64, f64, i32, P]),
         "oracle_first_order_cell": (None, [P, i32, i32, i32, P, i32, i32, i32, f64, f64, i32, i32, P]),
+        "oracle_amr_step": (i64, [i32, P, P, P, P, P, i32, f64, f64, f64, f64, i32]),
+        "oracle_amr_fill": (i32, [i32, P, P, P, P, P, i32, P, P, f64, i32, P]),
         "oracle_num_threads": (i32, []),
         "oracle_set_num_threads": (None, [i32]),
     }
@@ -435,3 +437,44 @@ def first_order_cell(level, ng, bc, X, Y, Z, dtdx, gamma, scheme=SCHEME_MHM_PLM_
     out = np.empty(5, np.float64)
     _load().oracle_first_order_cell(_p(L), *ng, _p(_bc(bc)), X, Y, Z, dtdx, gamma, scheme, int(split), _p(out))
     return out
+
+
+# --------------------------------------------------- coarse-fine coupling --
+
+def _amr_pack(n0, positions, states):
+    G = np.ascontiguousarray([len(p) for p in positions], np.int64)
+    pos = np.ascontiguousarray(np.concatenate([np.asarray(p, np.int32).reshape(-1, 3) for p in positions]), np.int32)
+    U = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float64) for u in states]), np.float64)
+    n = np.ascontiguousarray(n0, np.int32)
+    return n, G, pos, U
+
+
+def amr_step(n0, positions, states, bc, dt0, dx0, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC, ghost=3):
+    """One coarse step of a nested AMR hierarchy (W-cycle with ghost-zone
+    interpolation, flux registers, restriction and flux fix-up): returns
+    (new states per level, n_bad)."""
+    n, G, pos, U = _amr_pack(n0, positions, states)
+    nb = _load().oracle_amr_step(len(positions), _p(n), _p(G), _p(pos), _p(U), _p(_bc(bc)), ghost, dt0, dx0, gamma,
+                                 theta, scheme)
+    if nb < 0:
+        raise ValueError("oracle_amr_step: bad arguments (positions, nesting or scheme)")
+    out, o = [], 0
+    for g in G:
+        out.append(U[o:o + g].copy())
+        o += g
+    return out, int(nb)
+
+
+def amr_fill(n0, positions, states, bc, level, coarse_old, coarse_new, a, ghost=3):
+    """Padded groups of one level of a hierarchy: ghosts from sibling groups,
+    else interpolated from the coarse level between coarse_old and coarse_new."""
+    n, G, pos, U = _amr_pack(n0, positions, states)
+    P = 16 + 2 * ghost
+    pad = np.empty((G[level], 5, P, P, P), np.float64)
+    co = _f64(coarse_old) if level > 0 else np.zeros(1)
+    cn = _f64(coarse_new) if level > 0 else np.zeros(1)
+    st = _load().oracle_amr_fill(len(positions), _p(n), _p(G), _p(pos), _p(U), _p(_bc(bc)), level, _p(co), _p(cn),
+                                 float(a), ghost, _p(pad))
+    if st != 0:
+        raise ValueError("oracle_amr_fill: bad arguments")
+    return pad

@@ -31,6 +31,9 @@
 //   unsplit, then split recompute of failed cells, then
 //   level retries at dt * 0.8                         (level_step_repaired,
 //                                                      oracle_level_step_fallback)
+//   coarse-fine coupling in a W-cycle: ghost zones
+//   interpolated from the coarse level, flux registers,
+//   restriction, flux fix-up                          (amr_advance)
 //
 // Readings where the paper is silent (each stated in the function it governs):
 //   * MHM predictor is the conservative unsplit Hancock step, no Riemann solve
@@ -966,9 +969,14 @@ inline int recon_radius(int scheme) {
 //     5. conservative update with the second-solve fluxes.
 // Needs ghost >= 2 (PLM) or 3 (PPM); the update order and unphysical count
 // are those of mhm_step_block.
+// face_flux (optional, 16^3 blocks only): the fluxes of the faces on the
+// patch boundaries, [9][5][16][16]: plane p = 3 * axis + k holds the faces of
+// that axis at normal coordinate 8 k (the face between 8k - 1 and 8k), entry
+// [p][q][b][a] with (a, b) the transverse coordinates in the cyclic order
+// (axis + 1, axis + 2).
 template <class T>
 int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double dx, double gamma, double theta,
-                       int scheme) {
+                       int scheme, T* face_flux = nullptr) {
   const bool ctu = (scheme & SCHEME_ID_MASK) == SCHEME_CTU;
   const int R = recon_radius(scheme);
   const T dtdx = T(dt) / T(dx);
@@ -1098,6 +1106,17 @@ int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double
     for (int y = 0; y < b.ny; ++y)
       for (int x = 0; x < b.nx; ++x)
         n_bad += riemann_flux(state(x, y, z - 1, 2, 1), state(x, y, z, 2, 0), 2, gamma, scheme, &Fz[fzi(x, y, z)]);
+  if (face_flux != nullptr) {
+    for (int k = 0; k < 3; ++k)
+      for (int q = 0; q < 5; ++q)
+        for (int bb = 0; bb < 16; ++bb)
+          for (int a = 0; a < 16; ++a) {
+            const int n = 8 * k;
+            face_flux[((0 * 3 + k) * 5 + q) * 256 + bb * 16 + a] = Fx[fxi(n, a, bb) + q];   // a = y, b = z
+            face_flux[((1 * 3 + k) * 5 + q) * 256 + bb * 16 + a] = Fy[fyi(bb, n, a) + q];   // a = z, b = x
+            face_flux[((2 * 3 + k) * 5 + q) * 256 + bb * 16 + a] = Fz[fzi(a, bb, n) + q];   // a = x, b = y
+          }
+  }
   const T gm1 = T(gamma - 1.0);
   for (int z = 0; z < b.nz; ++z)
     for (int y = 0; y < b.ny; ++y)
@@ -1230,6 +1249,277 @@ int64_t level_step_repaired(const double* level, double* level_out, int ngx, int
   if (n_unsplit) *n_unsplit = nu;
   if (n_split) *n_split = ns;
   return left;
+}
+
+// ===================================================== coarse-fine coupling ==
+// Sec. 2.1 (AMR: patches of 8^3 cells, refinement ratio 2, groups of 2x2x2
+// sibling patches, levels advanced in a W-cycle with dt_l = dt_0 / 2^l) and
+// Sec. 2.2 (fix-up operations): the children of one coarse patch form one
+// fine patch group (16^3 fine cells over 8^3 coarse cells).  A level is a set
+// of groups at positions of its group lattice (level l: n_0 * 2^l groups per
+// axis over the domain); level 0 covers the domain.
+//   ghost zones of a fine group: copied from the sibling group that holds the
+//     cell, else interpolated from the coarse level (conservative linear
+//     interpolation: coarse value plus the minmod-limited slopes of the
+//     conserved variables times the child's offset of +-1/4 coarse cell,
+//     summed x, y, z), with the coarse state taken linearly in time between
+//     the coarse step's input and output: (1 - a) U_old + a U_new;
+//   flux registers: the time- and area-average of the fine fluxes over each
+//     coarse face of the fine level's boundary, accumulated over the fine
+//     substeps as sum_s (dt_f / dt_c) (1/4) (sum of the 2x2 fine faces);
+//   restriction: a coarse cell covered by a fine group becomes the mean of
+//     its 8 children;
+//   fix-up: an uncovered coarse cell next to the fine region replaces the
+//     coarse flux of that face by the register's, U += dt_c/dx_c (R - F_c)
+//     on its low face, -= on its high face, faces taken x-, x+, y-, y+, z-, z+.
+// Readings (the paper states the operations, not their formulas): the
+// interpolation above, and refinement by whole coarse patches with at least
+// one coarse patch of buffer (proper nesting), so that every coarse cell an
+// interpolation reads exists.
+struct AmrLevel {
+  int n[3];            // group lattice of the level over the domain
+  int64_t G;
+  const int* pos;      // [G][3] group positions (x, y, z)
+  std::vector<int> map;  // dense lattice -> group index or -1
+  double* U;           // [G][5][16^3]
+  void build_map() {
+    map.assign(size_t(n[0]) * n[1] * n[2], -1);
+    for (int64_t g = 0; g < G; ++g)
+      map[(size_t(pos[3 * g + 2]) * n[1] + pos[3 * g + 1]) * n[0] + pos[3 * g]] = int(g);
+  }
+  int group_at(int gx, int gy, int gz) const { return map[(size_t(gz) * n[1] + gy) * n[0] + gx]; }
+};
+
+// Cell index along an axis of N cells through the boundary condition; -1 if
+// it leaves the domain on an outflow face (clamped instead) is not needed:
+// outflow clamps.
+inline int amr_wrap(int i, int N, int lo, int hi) { return bc_index(i, N, lo, hi); }
+
+// Value of cell (X, Y, Z) (global, already mapped) of a level: the group must exist.
+inline const double* amr_cell(const AmrLevel& L, const double* U, int X, int Y, int Z, int64_t* g_out = nullptr) {
+  const int g = L.group_at(X >> 4, Y >> 4, Z >> 4);
+  if (g_out) *g_out = g;
+  if (g < 0) return nullptr;
+  return U + (int64_t(g) * 5) * 4096 + ((Z & 15) * 16 + (Y & 15)) * 16 + (X & 15);
+}
+
+inline double minmod2(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return std::fabs(a) < std::fabs(b) ? a : b;
+}
+
+// Interpolated value of fine cell (X, Y, Z) (global fine indices, mapped)
+// from the coarse level at time weight a.
+void amr_interp(const AmrLevel& C, const double* Uold, const double* Unew, double a, const int bc[6], int X, int Y,
+                int Z, double out[5]) {
+  const int N[3] = {16 * C.n[0], 16 * C.n[1], 16 * C.n[2]};
+  const int c[3] = {X >> 1, Y >> 1, Z >> 1};
+  const double off[3] = {(X & 1) ? 0.25 : -0.25, (Y & 1) ? 0.25 : -0.25, (Z & 1) ? 0.25 : -0.25};
+  auto at = [&](int dx, int dy, int dz, double v[5]) {
+    const int x = amr_wrap(c[0] + dx, N[0], bc[0], bc[1]);
+    const int y = amr_wrap(c[1] + dy, N[1], bc[2], bc[3]);
+    const int z = amr_wrap(c[2] + dz, N[2], bc[4], bc[5]);
+    const double* o = amr_cell(C, Uold, x, y, z);
+    const double* w = amr_cell(C, Unew, x, y, z);
+    for (int q = 0; q < 5; ++q) v[q] = (1.0 - a) * o[q * 4096] + a * w[q * 4096];
+  };
+  double U0[5];
+  at(0, 0, 0, U0);
+  double s[3][5];
+  for (int d = 0; d < 3; ++d) {
+    double Um[5], Up[5];
+    at(-(d == 0), -(d == 1), -(d == 2), Um);
+    at(d == 0, d == 1, d == 2, Up);
+    for (int q = 0; q < 5; ++q) s[d][q] = minmod2(U0[q] - Um[q], Up[q] - U0[q]);
+  }
+  for (int q = 0; q < 5; ++q) out[q] = ((U0[q] + s[0][q] * off[0]) + s[1][q] * off[1]) + s[2][q] * off[2];
+}
+
+// Padded blocks [G][5][P^3] of a level: cells from the level's own groups,
+// else interpolated from the coarse level (level 0: own groups only).
+void amr_fill(const AmrLevel& F, const AmrLevel* C, const double* Cold, const double* Cnew, double a, const int bc[6],
+              int ghost, double* pad) {
+  const int P = 16 + 2 * ghost;
+  const int N[3] = {16 * F.n[0], 16 * F.n[1], 16 * F.n[2]};
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < F.G; ++g)
+    for (int z = 0; z < P; ++z)
+      for (int y = 0; y < P; ++y)
+        for (int x = 0; x < P; ++x) {
+          const int X = amr_wrap(16 * F.pos[3 * g] + x - ghost, N[0], bc[0], bc[1]);
+          const int Y = amr_wrap(16 * F.pos[3 * g + 1] + y - ghost, N[1], bc[2], bc[3]);
+          const int Z = amr_wrap(16 * F.pos[3 * g + 2] + z - ghost, N[2], bc[4], bc[5]);
+          const double* src = amr_cell(F, F.U, X, Y, Z);
+          double v[5];
+          if (src != nullptr) {
+            for (int q = 0; q < 5; ++q) v[q] = src[q * 4096];
+          } else {
+            amr_interp(*C, Cold, Cnew, a, bc, X, Y, Z, v);
+          }
+          for (int q = 0; q < 5; ++q) pad[((g * 5 + q) * P + z) * int64_t(P) * P + int64_t(y) * P + x] = v[q];
+        }
+}
+
+// Side s = 2 * axis + (0 low, 1 high) of a fine group has a coarse-fine
+// interface if the group across it does not exist (a face on an outflow
+// domain boundary has none).
+bool amr_interface(const AmrLevel& F, int64_t g, int s, const int bc[6]) {
+  const int d = s >> 1, hi = s & 1;
+  int p[3] = {F.pos[3 * g], F.pos[3 * g + 1], F.pos[3 * g + 2]};
+  p[d] += hi ? 1 : -1;
+  if (p[d] < 0 || p[d] >= F.n[d]) {
+    if (bc[2 * d + hi] != 0) return false;
+    p[d] = (p[d] + F.n[d]) % F.n[d];
+  }
+  return F.group_at(p[0], p[1], p[2]) < 0;
+}
+
+// R[g][6][5][8][8] += w * (1/4) * (sum of the 2x2 fine faces) on interface sides.
+void amr_accumulate(const AmrLevel& F, const double* face_flux, double w, const int bc[6], double* R) {
+  for (int64_t g = 0; g < F.G; ++g)
+    for (int s = 0; s < 6; ++s) {
+      if (!amr_interface(F, g, s, bc)) continue;
+      const int d = s >> 1, k = (s & 1) ? 2 : 0;
+      const double* Fp = face_flux + (g * 9 + d * 3 + k) * 5 * 256;
+      double* r = R + (g * 6 + s) * 5 * 64;
+      for (int q = 0; q < 5; ++q)
+        for (int j = 0; j < 8; ++j)
+          for (int i = 0; i < 8; ++i) {
+            const double* f = Fp + q * 256;
+            const double sum = (f[(2 * j) * 16 + 2 * i] + f[(2 * j) * 16 + 2 * i + 1]) +
+                               (f[(2 * j + 1) * 16 + 2 * i] + f[(2 * j + 1) * 16 + 2 * i + 1]);
+            r[q * 64 + j * 8 + i] = r[q * 64 + j * 8 + i] + w * (0.25 * sum);
+          }
+    }
+}
+
+// Coarse cells covered by fine group g become the mean of their children.
+void amr_restrict(const AmrLevel& F, AmrLevel& C) {
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < F.G; ++g) {
+    const int px = F.pos[3 * g], py = F.pos[3 * g + 1], pz = F.pos[3 * g + 2];  // = coarse patch
+    const int gc = C.group_at(px >> 1, py >> 1, pz >> 1);
+    for (int z = 0; z < 8; ++z)
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 8; ++x) {
+          const int cx = (px & 1) * 8 + x, cy = (py & 1) * 8 + y, cz = (pz & 1) * 8 + z;
+          for (int q = 0; q < 5; ++q) {
+            // pairwise: x pairs, then y, then z (a uniform state restricts exactly)
+            auto ch = [&](int dx, int dy, int dz) {
+              return F.U[(g * 5 + q) * 4096 + ((2 * z + dz) * 16 + (2 * y + dy)) * 16 + (2 * x + dx)];
+            };
+            const double s0 = (ch(0, 0, 0) + ch(1, 0, 0)) + (ch(0, 1, 0) + ch(1, 1, 0));
+            const double s1 = (ch(0, 0, 1) + ch(1, 0, 1)) + (ch(0, 1, 1) + ch(1, 1, 1));
+            C.U[(int64_t(gc) * 5 + q) * 4096 + (cz * 16 + cy) * 16 + cx] = 0.125 * (s0 + s1);
+          }
+        }
+  }
+}
+
+// Fix-up of the uncovered coarse cells next to the fine level.
+void amr_fixup(AmrLevel& C, const AmrLevel& F, const double* cface_flux, const double* R, double dtdx,
+               const int bc[6]) {
+  const int N[3] = {16 * C.n[0], 16 * C.n[1], 16 * C.n[2]};
+  auto refined = [&](int X, int Y, int Z, int64_t* gf) {  // coarse cell's patch has children
+    const int g = F.group_at(X >> 3, Y >> 3, Z >> 3);
+    if (gf) *gf = g;
+    return g >= 0;
+  };
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < C.G; ++g)
+    for (int c = 0; c < 4096; ++c) {
+      const int X = 16 * C.pos[3 * g] + (c & 15), Y = 16 * C.pos[3 * g + 1] + ((c >> 4) & 15),
+                Z = 16 * C.pos[3 * g + 2] + (c >> 8);
+      if (refined(X, Y, Z, nullptr)) continue;
+      const int xyz[3] = {X, Y, Z};
+      for (int s = 0; s < 6; ++s) {
+        const int d = s >> 1, hi = s & 1;
+        int nb[3] = {X, Y, Z};
+        nb[d] += hi ? 1 : -1;
+        if (nb[d] < 0 || nb[d] >= N[d]) {
+          if (bc[2 * d + hi] != 0) continue;
+          nb[d] = (nb[d] + N[d]) % N[d];
+        }
+        int64_t gf;
+        if (!refined(nb[0], nb[1], nb[2], &gf)) continue;
+        // coarse flux of the face: plane k of this cell's group (local normal
+        // coordinate 0, 8 or 16)
+        const int local = (xyz[d] & 15) + hi;
+        const int k = local >> 3;
+        const int a = xyz[(d + 1) % 3] & 15, b = xyz[(d + 2) % 3] & 15;
+        const double* Fc = cface_flux + (g * 9 + d * 3 + k) * 5 * 256 + b * 16 + a;
+        // the fine group's register on its side facing this cell
+        const int fs = 2 * d + (hi ? 0 : 1);
+        const int i = xyz[(d + 1) % 3] & 7, j = xyz[(d + 2) % 3] & 7;
+        const double* r = R + (gf * 6 + fs) * 5 * 64 + j * 8 + i;
+        for (int q = 0; q < 5; ++q) {
+          const double corr = dtdx * (r[q * 64] - Fc[q * 256]);
+          double& u = C.U[(g * 5 + q) * 4096 + c];
+          u = hi ? u - corr : u + corr;
+        }
+      }
+    }
+}
+
+// One step of a level from its padded blocks; face fluxes captured.
+int64_t amr_step_level(AmrLevel& L, const double* pad, int ghost, double dt, double dx, double gamma, double theta,
+                       int scheme, double* face_flux) {
+  const Block b(16, 16, 16, ghost);
+  int64_t n_bad = 0;
+  std::vector<double> out(size_t(L.G) * 5 * 4096);
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
+  for (int64_t g = 0; g < L.G; ++g)
+    n_bad += step_block_any(pad + g * b.cells() * 5, out.data() + g * 5 * 4096, b, dt, dx, gamma, theta, scheme,
+                            face_flux + g * 9 * 5 * 256);
+  std::memcpy(L.U, out.data(), sizeof(double) * out.size());
+  return n_bad;
+}
+
+// Advance level l by dt (and, recursively, the finer levels by two steps of
+// dt/2 each), given the coarse state before and after its current step
+// (a0, a1: the time weights of this step's start and end within it).
+int64_t amr_advance(std::vector<AmrLevel>& Ls, int l, double dt, double dx0, double gamma, double theta, int scheme,
+                    int ghost, const int bc[6], const double* Cold, const double* Cnew, double a, double* R_parent) {
+  AmrLevel& L = Ls[l];
+  const double dx = dx0 / double(1 << l);
+  const int P = 16 + 2 * ghost;
+  std::vector<double> pad(size_t(L.G) * 5 * P * P * P), flux(size_t(L.G) * 9 * 5 * 256);
+  std::vector<double> old(L.U, L.U + L.G * 5 * 4096);
+  amr_fill(L, l > 0 ? &Ls[l - 1] : nullptr, Cold, Cnew, a, bc, ghost, pad.data());
+  int64_t n_bad = amr_step_level(L, pad.data(), ghost, dt, dx, gamma, theta, scheme, flux.data());
+  if (R_parent != nullptr) amr_accumulate(L, flux.data(), 0.5, bc, R_parent);
+  if (l + 1 < int(Ls.size())) {
+    std::vector<double> R(size_t(Ls[l + 1].G) * 6 * 5 * 64, 0.0);
+    std::vector<double> nw(L.U, L.U + L.G * 5 * 4096);
+    n_bad += amr_advance(Ls, l + 1, 0.5 * dt, dx0, gamma, theta, scheme, ghost, bc, old.data(), nw.data(), 0.0,
+                         R.data());
+    n_bad += amr_advance(Ls, l + 1, 0.5 * dt, dx0, gamma, theta, scheme, ghost, bc, old.data(), nw.data(), 0.5,
+                         R.data());
+    amr_restrict(Ls[l + 1], L);
+    amr_fixup(L, Ls[l + 1], flux.data(), R.data(), dt / dx, bc);
+  }
+  return n_bad;
+}
+
+// Proper nesting: the 27 coarse patches around every fine group's parent
+// patch exist on the coarse level (so every coarse cell a fine ghost zone or
+// its interpolation slopes read exists).
+bool amr_nested(const AmrLevel& F, const AmrLevel& C, const int bc[6]) {
+  const int np[3] = {2 * C.n[0], 2 * C.n[1], 2 * C.n[2]};  // coarse patches per axis
+  for (int64_t g = 0; g < F.G; ++g)
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int p[3] = {F.pos[3 * g] + dx, F.pos[3 * g + 1] + dy, F.pos[3 * g + 2] + dz};
+          bool skip = false;
+          for (int d = 0; d < 3; ++d)
+            if (p[d] < 0 || p[d] >= np[d]) {
+              if (bc[2 * d + (p[d] >= np[d])] != 0) skip = true;  // beyond an outflow face: clamped inside
+              p[d] = (p[d] + np[d]) % np[d];
+            }
+          if (!skip && C.group_at(p[0] >> 1, p[1] >> 1, p[2] >> 1) < 0) return false;
+        }
+  return true;
 }
 
 }  // namespace
@@ -1644,6 +1934,58 @@ void oracle_first_order_cell(const double* level, int ngx, int ngy, int ngz, con
   const LevelView lv{level, ngx, ngy, ngz, bc};
   if (mode == 0) first_order_unsplit(lv, X, Y, Z, dtdx, gamma, scheme | FIRST_ORDER_BIT, out);
   else first_order_split(lv, X, Y, Z, dtdx, gamma, scheme | FIRST_ORDER_BIT, out);
+}
+
+// ------------------------------------------------ coarse-fine coupling ABI ---
+// Levels concatenated: G[l] groups of level l, positions pos [sum G][3]
+// (x, y, z in the level's group lattice, n0 * 2^l per axis), states U
+// [sum G][5][16^3] (in/out).  One coarse step of dt0 (W-cycle: level l takes
+// 2^l steps of dt0 / 2^l).  Returns the unphysical count, or -1 on bad
+// arguments (a position off the lattice or repeated, a level not properly
+// nested, level 0 not covering the domain).
+static bool amr_setup(int n_levels, const int* n0, const int64_t* G, const int* pos, double* U,
+                      std::vector<AmrLevel>& Ls, const int* bc) {
+  if (n_levels < 1 || n_levels > 8 || n0[0] < 1 || n0[1] < 1 || n0[2] < 1) return false;
+  Ls.resize(n_levels);
+  int64_t off = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    AmrLevel& L = Ls[l];
+    for (int d = 0; d < 3; ++d) L.n[d] = n0[d] << l;
+    L.G = G[l];
+    L.pos = pos + 3 * off;
+    L.U = U + off * 5 * 4096;
+    for (int64_t g = 0; g < L.G; ++g)
+      for (int d = 0; d < 3; ++d)
+        if (L.pos[3 * g + d] < 0 || L.pos[3 * g + d] >= L.n[d]) return false;
+    L.build_map();
+    int64_t filled = 0;
+    for (int v : L.map) filled += v >= 0;
+    if (filled != L.G) return false;                                 // repeated positions
+    if (l == 0 && L.G != int64_t(L.n[0]) * L.n[1] * L.n[2]) return false;  // level 0 covers the domain
+    if (l > 0 && !amr_nested(L, Ls[l - 1], bc)) return false;
+    off += G[l];
+  }
+  return true;
+}
+
+int64_t oracle_amr_step(int n_levels, const int* n0, const int64_t* G, const int* pos, double* U, const int* bc,
+                        int ghost, double dt0, double dx0, double gamma, double theta, int scheme) {
+  if (ghost > 16 || !valid_any_scheme(scheme, ghost)) return -1;
+  std::vector<AmrLevel> Ls;
+  if (!amr_setup(n_levels, n0, G, pos, U, Ls, bc)) return -1;
+  return amr_advance(Ls, 0, dt0, dx0, gamma, theta, scheme, ghost, bc, nullptr, nullptr, 0.0, nullptr);
+}
+
+// Padded blocks of level `lev` of a hierarchy (ghosts from siblings, else
+// interpolated from level lev-1 between Cold and Cnew at weight a; level
+// lev-1's states are taken from Cold / Cnew, U supplies the positions and
+// level lev's own states).  pad: [G[lev]][5][P^3].
+int oracle_amr_fill(int n_levels, const int* n0, const int64_t* G, const int* pos, double* U, const int* bc,
+                    int lev, const double* Cold, const double* Cnew, double a, int ghost, double* pad) {
+  std::vector<AmrLevel> Ls;
+  if (ghost < 0 || ghost > 16 || lev < 0 || lev >= n_levels || !amr_setup(n_levels, n0, G, pos, U, Ls, bc)) return -1;
+  amr_fill(Ls[lev], lev > 0 ? &Ls[lev - 1] : nullptr, Cold, Cnew, a, bc, ghost, pad);
+  return 0;
 }
 
 }  // extern "C"

@@ -212,6 +212,108 @@ def sedov_levels(ng_levels=AMR_LEVEL_GROUPS, dx0: float = 1.0 / 128, gamma: floa
     return levels
 
 
+# Workload 3 as a coupled hierarchy: level 0 is the 8^3-group domain; level l
+# refines the level-(l-1) patches in a half-open box (patch indices of level
+# l-1, x, y, z), mirror-symmetric about the domain centre: 16 x 12 x 8 = 1536
+# level-1 groups and 24 x 16 x 8 = 3072 level-2 groups, each level nested in
+# its parent with at least one parent patch of buffer.
+AMR_NESTED_BOXES = (((0, 16), (2, 14), (4, 12)), ((4, 28), (8, 24), (12, 20)))
+
+
+class AmrHierarchy:
+    """Levels of a nested hierarchy: positions[l] [G_l, 3] (group lattice of
+    level l: n0 * 2^l per axis), states[l] [G_l, 5, 16, 16, 16], dx0, bc."""
+
+    def __init__(self, n0, positions, states, dx0, gamma, bc=(BC_PERIODIC,) * 6, meta=None):
+        self.n0 = tuple(int(v) for v in n0)
+        self.positions = [np.ascontiguousarray(p, np.int32) for p in positions]
+        self.states = [np.ascontiguousarray(u) for u in states]
+        self.dx0, self.gamma, self.bc = float(dx0), float(gamma), tuple(bc)
+        self.meta = meta or {}
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.positions)
+
+    def lattice(self, l: int) -> Tuple[int, int, int]:
+        return tuple(v << l for v in self.n0)
+
+    def dense_map(self, l: int) -> np.ndarray:
+        """[n2, n1, n0] group index of level l at each lattice position, -1 if absent."""
+        n = self.lattice(l)
+        m = np.full((n[2], n[1], n[0]), -1, np.int32)
+        p = self.positions[l]
+        m[p[:, 2], p[:, 1], p[:, 0]] = np.arange(len(p), dtype=np.int32)
+        return m
+
+    def cells_per_coarse_step(self) -> int:
+        return sum(len(p) * 4096 * 2 ** l for l, p in enumerate(self.positions))
+
+
+def nested_positions(n0: int, boxes) -> List[np.ndarray]:
+    """Level 0: all n0^3 groups (brick order, x fastest); level l: the children
+    (one fine group each) of the level-(l-1) patches in boxes[l-1]."""
+    out = [np.array([(x, y, z) for z in range(n0) for y in range(n0) for x in range(n0)], np.int32)]
+    for bx, by, bz in boxes:
+        out.append(np.array([(x, y, z) for z in range(*bz) for y in range(*by) for x in range(*bx)], np.int32))
+    return out
+
+
+def _level_cells(pos: np.ndarray, dx: float):
+    """Cell-centre coordinates [G, 16, 16, 16] (x, y, z) of a level's groups."""
+    i = (np.arange(N) + 0.5) * dx
+    ox = pos[:, 0, None, None, None] * N * dx
+    oy = pos[:, 1, None, None, None] * N * dx
+    oz = pos[:, 2, None, None, None] * N * dx
+    X = ox + i[None, None, None, :]
+    Y = oy + i[None, None, :, None]
+    Z = oz + i[None, :, None, None]
+    return np.broadcast_arrays(X, Y, Z)
+
+
+def restrict_states(h: "AmrHierarchy") -> None:
+    """Coarse cells covered by a finer group take the mean of their children
+    (finest level first), so that the initial hierarchy is consistent."""
+    for l in range(h.n_levels - 1, 0, -1):
+        cm = h.dense_map(l - 1)
+        for g, (px, py, pz) in enumerate(h.positions[l]):
+            f = h.states[l][g]
+            c = f.reshape(5, 8, 2, 8, 2, 8, 2).mean(axis=(2, 4, 6))
+            gc = cm[pz >> 1, py >> 1, px >> 1]
+            h.states[l - 1][gc][:, (pz & 1) * 8:(pz & 1) * 8 + 8, (py & 1) * 8:(py & 1) * 8 + 8,
+                                (px & 1) * 8:(px & 1) * 8 + 8] = c
+
+
+def sedov_hierarchy(n0: int = 8, boxes=AMR_NESTED_BOXES, gamma: float = 5.0 / 3.0, e_blast: float = 1.0,
+                    p_bg: float = 1e-5) -> AmrHierarchy:
+    """Workload 3 on a coupled hierarchy: rho = 1, p = p_bg, thermal energy
+    density exp(-r^2 / 2 sigma^2) with sigma = 2 cells of the finest level at
+    the domain centre (a cell corner), normalized to e_blast on the finest
+    level's cells; every level sampled at its cell centres, then coarse cells
+    under finer groups replaced by their children's mean.  Unit domain:
+    dx0 = 1 / (16 n0)."""
+    dx0 = 1.0 / (N * n0)
+    pos = nested_positions(n0, boxes)
+    nl = len(pos)
+    sigma = 2.0 * dx0 / 2 ** (nl - 1)
+    states = []
+    norm = None
+    for l in range(nl - 1, -1, -1):
+        dx = dx0 / 2 ** l
+        X, Y, Z = _level_cells(pos[l], dx)
+        r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2
+        g = np.exp(-r2 / (2.0 * sigma * sigma))
+        if norm is None:
+            norm = e_blast / (g.sum() * dx ** 3)
+        U = np.empty((len(pos[l]), 5, N, N, N))
+        U[:] = conserved(1.0, 0.0, 0.0, 0.0, p_bg, gamma)[None, :, None, None, None]
+        U[:, 4] += g * norm
+        states.insert(0, U)
+    h = AmrHierarchy((n0,) * 3, pos, states, dx0, gamma, meta={"name": "sedov-amr", "sigma": sigma})
+    restrict_states(h)
+    return h
+
+
 def smooth_wave(n: int = 128, config_id: int = 4, gamma: float = 5.0 / 3.0, amp: float = 0.01,
                 v=(0.1, 0.05, 0.0), p0: float = 1.0, smooth_vp: float = 0.0) -> Tuple[Level, np.ndarray]:
     """Workload 4: rho = 1 + amp sin(2 pi (x+y+z)), uniform v and p (an exact
