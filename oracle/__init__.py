@@ -51,6 +51,7 @@ PPM = 1 << 14
 RIEMANN_HLLC = 0 << 16
 RIEMANN_ROE = 1 << 16
 RIEMANN_HLLE = 2 << 16
+DUAL_ENERGY = 1 << 18
 
 
 def build_library(force: bool = True) -> str:
@@ -96,6 +97,8 @@ def _load():
         "oracle_step_block_any": (i64, [P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32]),
         "oracle_step_any_jvp": (i64, [P, P, P, P, i64, i32, f64, f64, f64, f64, i32]),
         "oracle_riemann": (i32, [P, P, i32, f64, i32, P]),
+        "oracle_step_any_de": (i64, [P, P, i64, i32, f64, f64, f64, f64, i32, f64]),
+        "oracle_step_block_any_de": (i64, [P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32, f64]),
         "oracle_limit_diffs": (f64, [f64, f64, f64, f64, i32]),
         "oracle_limited_slopes": (None, [P, P, P, i32, f64, f64, i32, P]),
         "oracle_face_values": (None, [P, i32, f64, f64, i32, P]),
@@ -478,3 +481,27 @@ def amr_fill(n0, positions, states, bc, level, coarse_old, coarse_new, a, ghost=
     if st != 0:
         raise ValueError("oracle_amr_fill: bad arguments")
     return pad
+
+
+def step_any_de(U_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM | DUAL_ENERGY, xi=0.01):
+    """Dual-energy step of padded groups with 6 fields (field 5 the entropy
+    s = p / rho^(gamma-1)): U_pad[G,6,P,P,P] -> (U_out[G,6,16,16,16], n_bad)."""
+    U = _f64(U_pad)
+    G, P = U.shape[0], U.shape[2]
+    assert U.shape[1] == 6
+    out = np.empty((G, 6, 16, 16, 16), np.float64)
+    n_bad = _load().oracle_step_any_de(_p(U), _p(out), G, (P - 16) // 2, dt, dx, gamma, theta, scheme, xi)
+    if n_bad < 0:
+        raise ValueError("oracle_step_any_de: bad arguments")
+    return out, int(n_bad)
+
+
+def step_block_any_de(U_pad, ghost, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM | DUAL_ENERGY, xi=0.01):
+    """Dual-energy step of one padded block [6, nz+2g, ny+2g, nx+2g]: (U_out[6,nz,ny,nx], n_bad)."""
+    U = _f64(U_pad)
+    nz, ny, nx = (s - 2 * ghost for s in U.shape[1:])
+    out = np.empty((6, nz, ny, nx), np.float64)
+    n_bad = _load().oracle_step_block_any_de(_p(U), _p(out), nx, ny, nz, ghost, dt, dx, gamma, theta, scheme, xi)
+    if n_bad < 0:
+        raise ValueError("oracle_step_block_any_de: bad arguments")
+    return out, int(n_bad)

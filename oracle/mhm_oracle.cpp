@@ -99,6 +99,11 @@ inline Cnt tsqrt(Cnt a) { g_ops.sqrt++; return Cnt(std::sqrt(a.v)); }
 inline double val(Cnt a) { return a.v; }
 
 inline double tsqrt(double a) { return std::sqrt(a); }
+inline double tpow(double a, double e) { return std::pow(a, e); }
+inline Dual tpow(Dual a, double e) {
+  const double p = std::pow(a.v, e);
+  return Dual(p, e * std::pow(a.v, e - 1.0) * a.d);
+}
 inline double val(double a) { return a; }
 
 // ------------------------------------------------------ branch record ----
@@ -652,11 +657,13 @@ int64_t rollout_box(std::vector<T> cur, int nx, int ny, int nz, int n_steps, dou
 //   bit 13      limit characteristic instead of primitive variables
 //   bit 14      PPM instead of PLM
 //   bits 16-17  Riemann solver: 0 HLLC, 1 Roe, 2 HLLE
+//   bit 18      dual energy: a sixth field, the entropy per unit volume
 constexpr int SCHEME_CTU = 2;
 constexpr int LIMITER_SHIFT = 11;
 constexpr int CHARACTERISTIC_BIT = 1 << 13;
 constexpr int PPM_BIT = 1 << 14;
 constexpr int RIEMANN_SHIFT = 16;
+constexpr int DUAL_ENERGY_BIT = 1 << 18;  // 6 fields: the entropy s = p / rho^(gamma-1) as field 5
 
 // Limited slope from the one-sided differences dm = q0 - q[-1], dp = q[+1] - q0
 // and the central difference dc (zero unless dm and dp have one strict sign):
@@ -736,6 +743,28 @@ void limited_slopes(const T Wm[5], const T Wc[5], const T Wp[5], int d, double g
   from_characteristic(as, d, Wc[0], c, s);
 }
 
+// PPM interface values of one variable from its cells -1, 0, +1 (qm, q0, qp)
+// and their limited slopes, with the monotonicity constraints.
+template <class T>
+void ppm_scalar(T qm, T q0, T qp, T sm, T s0, T sp, T& qL, T& qR) {
+  qL = T(0.5) * (qm + q0) - (s0 - sm) / T(6.0);
+  qR = T(0.5) * (q0 + qp) - (sp - s0) / T(6.0);
+  const bool extremum = !(val((qR - q0) * (q0 - qL)) > 0.0);
+  sig_mix(extremum ? 15 : 16);
+  if (extremum) {
+    qL = q0;
+    qR = q0;
+  } else {
+    const T dq = qR - qL;
+    const T q6 = T(6.0) * (q0 - T(0.5) * (qL + qR));
+    const bool over_l = val(dq * q6) > val(dq * dq);
+    const bool over_r = !over_l && val(-(dq * dq)) > val(dq * q6);
+    sig_mix(over_l ? 17 : over_r ? 18 : 19);
+    if (over_l) qL = T(3.0) * q0 - T(2.0) * qR;
+    if (over_r) qR = T(3.0) * q0 - T(2.0) * qL;
+  }
+}
+
 // Face values (primitive) of a cell along axis d from the stencil Ws[0..4] =
 // cells at -2..+2 (PLM reads -1..+1 only):
 //   PLM: W_{-,+} = W0 -+ s0/2
@@ -765,26 +794,27 @@ void face_values(const T* const Ws[5], int d, double gamma, double theta, int sc
   limited_slopes(Ws[0], Ws[1], Ws[2], d, gamma, theta, scheme, sm);
   limited_slopes(Ws[1], Ws[2], Ws[3], d, gamma, theta, scheme, s0);
   limited_slopes(Ws[2], Ws[3], Ws[4], d, gamma, theta, scheme, sp);
-  for (int q = 0; q < 5; ++q) {
-    T qL = T(0.5) * (Ws[1][q] + Wc[q]) - (s0[q] - sm[q]) / T(6.0);
-    T qR = T(0.5) * (Wc[q] + Ws[3][q]) - (sp[q] - s0[q]) / T(6.0);
-    const bool extremum = !(val((qR - Wc[q]) * (Wc[q] - qL)) > 0.0);
-    sig_mix(extremum ? 15 : 16);
-    if (extremum) {
-      qL = Wc[q];
-      qR = Wc[q];
-    } else {
-      const T dq = qR - qL;
-      const T q6 = T(6.0) * (Wc[q] - T(0.5) * (qL + qR));
-      const bool over_l = val(dq * q6) > val(dq * dq);
-      const bool over_r = !over_l && val(-(dq * dq)) > val(dq * q6);
-      sig_mix(over_l ? 17 : over_r ? 18 : 19);
-      if (over_l) qL = T(3.0) * Wc[q] - T(2.0) * qR;
-      if (over_r) qR = T(3.0) * Wc[q] - T(2.0) * qL;
-    }
-    Wf[0][q] = qL;
-    Wf[1][q] = qR;
+  for (int q = 0; q < 5; ++q) ppm_scalar(Ws[1][q], Wc[q], Ws[3][q], sm[q], s0[q], sp[q], Wf[0][q], Wf[1][q]);
+}
+
+// Face values of a passively advected scalar q (the stencil q[0..4] at cells
+// -2..+2), reconstructed as a primitive variable whatever the characteristic
+// option (it is a wave of its own, moving with the flow).
+template <class T>
+void passive_face_values(const T q[5], double theta, int scheme, T out[2]) {
+  if (scheme & FIRST_ORDER_BIT) {
+    out[0] = out[1] = q[2];
+    return;
   }
+  const int lim = (scheme >> LIMITER_SHIFT) & 3;
+  auto slope = [&](int j) { return limit_diffs(q[j] - q[j - 1], q[j + 1] - q[j], T(0.5) * (q[j + 1] - q[j - 1]), theta, lim); };
+  if (!(scheme & PPM_BIT)) {
+    const T sl = slope(2);
+    out[0] = q[2] - T(0.5) * sl;
+    out[1] = q[2] + T(0.5) * sl;
+    return;
+  }
+  ppm_scalar(q[1], q[2], q[3], slope(1), slope(2), slope(3), out[0], out[1]);
 }
 
 // Normal-frame quantities of a face's two conserved states (shared by the
@@ -941,6 +971,20 @@ bool riemann_flux(const T UL[5], const T UR[5], int d, double gamma, int scheme,
   }
 }
 
+// Riemann flux of the nf = 5 Euler fields, plus, for nf = 6, the flux of a
+// passive scalar carried by mass: F_5 = F_rho * (s/rho of the upwind side,
+// by the sign of the mass flux).
+template <class T>
+bool riemann_nf(const T UL[], const T UR[], int d, double gamma, int scheme, int nf, T F[]) {
+  const bool bad = riemann_flux(UL, UR, d, gamma, scheme, F);
+  if (nf == 6) {
+    const bool left = val(F[0]) >= 0.0;
+    sig_mix(left ? 25 : 26);
+    F[5] = F[0] * (left ? UL[5] / UL[0] : UR[5] / UR[0]);
+  }
+  return bad;
+}
+
 // Cons and flux of a primitive face state.
 template <class T>
 void face_cons_flux(const T W[5], int d, double gamma, T U[5], T F[5]) {
@@ -969,6 +1013,13 @@ inline int recon_radius(int scheme) {
 //     5. conservative update with the second-solve fluxes.
 // Needs ghost >= 2 (PLM) or 3 (PPM); the update order and unphysical count
 // are those of mhm_step_block.
+// Dual energy (the scheme word's bit 18; Sec. 2.2): a sixth field, the
+// entropy per unit volume s = p / rho^(gamma-1), is advected as a passive
+// scalar -- its specific value s/rho reconstructed like the primitive
+// variables, its face values s = rho * (s/rho), its flux s u_n in the half
+// steps and the mass flux times s/rho of the upwind side in the Riemann
+// solves -- and after the update E is taken from s where E_th < xi E_kin,
+// while s is reset from E elsewhere.
 // face_flux (optional, 16^3 blocks only): the fluxes of the faces on the
 // patch boundaries, [9][5][16][16]: plane p = 3 * axis + k holds the faces of
 // that axis at normal coordinate 8 k (the face between 8k - 1 and 8k), entry
@@ -976,8 +1027,10 @@ inline int recon_radius(int scheme) {
 // (axis + 1, axis + 2).
 template <class T>
 int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double dx, double gamma, double theta,
-                       int scheme, T* face_flux = nullptr) {
+                       int scheme, T* face_flux = nullptr, double xi = 0.01) {
   const bool ctu = (scheme & SCHEME_ID_MASK) == SCHEME_CTU;
+  const bool de = (scheme & DUAL_ENERGY_BIT) != 0;
+  const int nf = de ? 6 : 5;
   const int R = recon_radius(scheme);
   const T dtdx = T(dt) / T(dx);
   const T half_dtdx = T(0.5) * dtdx;
@@ -988,44 +1041,54 @@ int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double
   const int m = R + 1;
   const int wx = b.nx + 2 * m, wy = b.ny + 2 * m, wz = b.nz + 2 * m;
   auto wi = [&](int x, int y, int z) { return ((int64_t(z + m) * wy + (y + m)) * wx + (x + m)); };
-  std::vector<T> W(size_t(wx) * wy * wz * 5);
+  std::vector<T> W(size_t(wx) * wy * wz * nf);
   for (int z = -m; z < b.nz + m; ++z)
     for (int y = -m; y < b.ny + m; ++y)
       for (int x = -m; x < b.nx + m; ++x) {
         T U[5];
         for (int f = 0; f < 5; ++f) U[f] = Upad[b.at(f, x, y, z)];
-        cons_to_prim(U, gamma, &W[wi(x, y, z) * 5]);
+        cons_to_prim(U, gamma, &W[wi(x, y, z) * nf]);
+        if (de) W[wi(x, y, z) * nf + 5] = Upad[b.at(5, x, y, z)] / U[0];  // entropy per unit mass
       }
 
   // face states of every cell of [-1, n]^3: MHM's Hancock states, or CTU's
   // one-axis predicted states
   const int sx = b.nx + 2, sy = b.ny + 2, sz = b.nz + 2;
   auto si = [&](int x, int y, int z) { return ((int64_t(z + 1) * sy + (y + 1)) * sx + (x + 1)); };
-  std::vector<T> S(size_t(sx) * sy * sz * 30);
+  std::vector<T> S(size_t(sx) * sy * sz * 6 * nf);
   for (int z = -1; z < b.nz + 1; ++z)
     for (int y = -1; y < b.ny + 1; ++y)
       for (int x = -1; x < b.nx + 1; ++x) {
-        T Wf[3][2][5];
+        T Wf[3][2][5], Pf[3][2];
         for (int d = 0; d < 3; ++d) {
           const T* Ws[5];
+          T ph[5];
           for (int j = -2; j <= 2; ++j) {
             const int o = (j < -R || j > R) ? 0 : j;  // cells beyond the radius are not read
-            Ws[j + 2] = &W[wi(x + o * ex[d][0], y + o * ex[d][1], z + o * ex[d][2]) * 5];
+            Ws[j + 2] = &W[wi(x + o * ex[d][0], y + o * ex[d][1], z + o * ex[d][2]) * nf];
+            if (de) ph[j + 2] = Ws[j + 2][5];
           }
           face_values(Ws, d, gamma, theta, scheme, Wf[d]);
+          if (de) passive_face_values(ph, theta, scheme, Pf[d]);
         }
-        T Ut[3][2][5], Ff[3][2][5];
+        T Ut[3][2][6], Ff[3][2][6];
         for (int d = 0; d < 3; ++d)
-          for (int s = 0; s < 2; ++s) face_cons_flux(Wf[d][s], d, gamma, Ut[d][s], Ff[d][s]);
+          for (int s = 0; s < 2; ++s) {
+            face_cons_flux(Wf[d][s], d, gamma, Ut[d][s], Ff[d][s]);
+            if (de) {
+              Ut[d][s][5] = Wf[d][s][0] * Pf[d][s];
+              Ff[d][s][5] = Ut[d][s][5] * Wf[d][s][1 + d];
+            }
+          }
         if (ctu) {
           for (int d = 0; d < 3; ++d)
-            for (int q = 0; q < 5; ++q) {
+            for (int q = 0; q < nf; ++q) {
               const T dU = half_dtdx * (Ff[d][0][q] - Ff[d][1][q]);
               Ut[d][0][q] = Ut[d][0][q] + dU;
               Ut[d][1][q] = Ut[d][1][q] + dU;
             }
         } else {
-          for (int q = 0; q < 5; ++q) {
+          for (int q = 0; q < nf; ++q) {
             T s = Ff[0][0][q] - Ff[0][1][q];
             s = s + (Ff[1][0][q] - Ff[1][1][q]);
             s = s + (Ff[2][0][q] - Ff[2][1][q]);
@@ -1036,21 +1099,21 @@ int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double
             }
           }
         }
-        T* dst = &S[si(x, y, z) * 30];
+        T* dst = &S[si(x, y, z) * 6 * nf];
         for (int d = 0; d < 3; ++d)
           for (int s = 0; s < 2; ++s)
-            for (int q = 0; q < 5; ++q) dst[(d * 2 + s) * 5 + q] = Ut[d][s][q];
+            for (int q = 0; q < nf; ++q) dst[(d * 2 + s) * nf + q] = Ut[d][s][q];
       }
-  auto state = [&](int x, int y, int z, int d, int s) -> T* { return &S[si(x, y, z) * 30 + (d * 2 + s) * 5]; };
+  auto state = [&](int x, int y, int z, int d, int s) -> T* { return &S[si(x, y, z) * 6 * nf + (d * 2 + s) * nf]; };
 
   if (ctu) {
     // first solves on faces between two cells of [-1, n]^3: face (d, x, y, z)
     // lies between the cell at (x, y, z) - e_d and (x, y, z), for the normal
     // coordinate 0..n and the transverse ones -1..n
     auto f1i = [&](int d, int x, int y, int z) {
-      return (((int64_t(d) * (b.nz + 2) + (z + 1)) * (b.ny + 2) + (y + 1)) * (b.nx + 2) + (x + 1)) * 5;
+      return (((int64_t(d) * (b.nz + 2) + (z + 1)) * (b.ny + 2) + (y + 1)) * (b.nx + 2) + (x + 1)) * nf;
     };
-    std::vector<T> F1(size_t(3) * (b.nx + 2) * (b.ny + 2) * (b.nz + 2) * 5);
+    std::vector<T> F1(size_t(3) * (b.nx + 2) * (b.ny + 2) * (b.nz + 2) * nf);
     for (int d = 0; d < 3; ++d)
       for (int z = -1; z <= b.nz; ++z)
         for (int y = -1; y <= b.ny; ++y)
@@ -1058,7 +1121,7 @@ int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double
             const int c[3] = {x, y, z};
             if (c[d] < 0) continue;
             const int lx = x - ex[d][0], ly = y - ex[d][1], lz = z - ex[d][2];
-            riemann_flux(state(lx, ly, lz, d, 1), state(x, y, z, d, 0), d, gamma, scheme, &F1[f1i(d, x, y, z)]);
+            riemann_nf(state(lx, ly, lz, d, 1), state(x, y, z, d, 0), d, gamma, scheme, nf, &F1[f1i(d, x, y, z)]);
           }
     // transverse corrections of the states the second solves need: axis d's
     // states of cells with the normal coordinate in -1..n and the transverse
@@ -1072,40 +1135,40 @@ int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double
             for (int e = 0; e < 3; ++e)
               if (e != d && (c[e] < 0 || c[e] >= nn[e])) inside = false;
             if (!inside) continue;
-            T corr[5];
+            T corr[6];
             bool first = true;
             for (int e = 0; e < 3; ++e) {
               if (e == d) continue;
               const T* Fp = &F1[f1i(e, x + ex[e][0], y + ex[e][1], z + ex[e][2])];
               const T* Fm = &F1[f1i(e, x, y, z)];
-              for (int q = 0; q < 5; ++q) corr[q] = first ? (Fp[q] - Fm[q]) : corr[q] + (Fp[q] - Fm[q]);
+              for (int q = 0; q < nf; ++q) corr[q] = first ? (Fp[q] - Fm[q]) : corr[q] + (Fp[q] - Fm[q]);
               first = false;
             }
             for (int s = 0; s < 2; ++s) {
               T* st = state(x, y, z, d, s);
-              for (int q = 0; q < 5; ++q) st[q] = st[q] - half_dtdx * corr[q];
+              for (int q = 0; q < nf; ++q) st[q] = st[q] - half_dtdx * corr[q];
             }
           }
   }
 
   // (second) Riemann solves at the faces of the interior cells, update
-  auto fxi = [&](int x, int y, int z) { return ((int64_t(z) * b.ny + y) * (b.nx + 1) + x) * 5; };
-  auto fyi = [&](int x, int y, int z) { return ((int64_t(z) * (b.ny + 1) + y) * b.nx + x) * 5; };
-  auto fzi = [&](int x, int y, int z) { return ((int64_t(z) * b.ny + y) * b.nx + x) * 5; };
-  std::vector<T> Fx(size_t(b.nz) * b.ny * (b.nx + 1) * 5), Fy(size_t(b.nz) * (b.ny + 1) * b.nx * 5),
-      Fz(size_t(b.nz + 1) * b.ny * b.nx * 5);
+  auto fxi = [&](int x, int y, int z) { return ((int64_t(z) * b.ny + y) * (b.nx + 1) + x) * nf; };
+  auto fyi = [&](int x, int y, int z) { return ((int64_t(z) * (b.ny + 1) + y) * b.nx + x) * nf; };
+  auto fzi = [&](int x, int y, int z) { return ((int64_t(z) * b.ny + y) * b.nx + x) * nf; };
+  std::vector<T> Fx(size_t(b.nz) * b.ny * (b.nx + 1) * nf), Fy(size_t(b.nz) * (b.ny + 1) * b.nx * nf),
+      Fz(size_t(b.nz + 1) * b.ny * b.nx * nf);
   for (int z = 0; z < b.nz; ++z)
     for (int y = 0; y < b.ny; ++y)
       for (int x = 0; x <= b.nx; ++x)
-        n_bad += riemann_flux(state(x - 1, y, z, 0, 1), state(x, y, z, 0, 0), 0, gamma, scheme, &Fx[fxi(x, y, z)]);
+        n_bad += riemann_nf(state(x - 1, y, z, 0, 1), state(x, y, z, 0, 0), 0, gamma, scheme, nf, &Fx[fxi(x, y, z)]);
   for (int z = 0; z < b.nz; ++z)
     for (int y = 0; y <= b.ny; ++y)
       for (int x = 0; x < b.nx; ++x)
-        n_bad += riemann_flux(state(x, y - 1, z, 1, 1), state(x, y, z, 1, 0), 1, gamma, scheme, &Fy[fyi(x, y, z)]);
+        n_bad += riemann_nf(state(x, y - 1, z, 1, 1), state(x, y, z, 1, 0), 1, gamma, scheme, nf, &Fy[fyi(x, y, z)]);
   for (int z = 0; z <= b.nz; ++z)
     for (int y = 0; y < b.ny; ++y)
       for (int x = 0; x < b.nx; ++x)
-        n_bad += riemann_flux(state(x, y, z - 1, 2, 1), state(x, y, z, 2, 0), 2, gamma, scheme, &Fz[fzi(x, y, z)]);
+        n_bad += riemann_nf(state(x, y, z - 1, 2, 1), state(x, y, z, 2, 0), 2, gamma, scheme, nf, &Fz[fzi(x, y, z)]);
   if (face_flux != nullptr) {
     for (int k = 0; k < 3; ++k)
       for (int q = 0; q < 5; ++q)
@@ -1121,14 +1184,27 @@ int64_t step_block_any(const T* Upad, T* Uout, const Block& b, double dt, double
   for (int z = 0; z < b.nz; ++z)
     for (int y = 0; y < b.ny; ++y)
       for (int x = 0; x < b.nx; ++x) {
-        T Un[5];
-        for (int q = 0; q < 5; ++q) {
+        T Un[6];
+        for (int q = 0; q < nf; ++q) {
           T acc = Fx[fxi(x + 1, y, z) + q] - Fx[fxi(x, y, z) + q];
           acc = acc + (Fy[fyi(x, y + 1, z) + q] - Fy[fyi(x, y, z) + q]);
           acc = acc + (Fz[fzi(x, y, z + 1) + q] - Fz[fzi(x, y, z) + q]);
           Un[q] = Upad[b.at(q, x, y, z)] - dtdx * acc;
-          Uout[((int64_t(q) * b.nz + z) * b.ny + y) * b.nx + x] = Un[q];
         }
+        if (de) {
+          // dual energy (Sec. 2.2): where the thermal energy from the total
+          // energy is below xi times the kinetic energy, take it from the
+          // entropy, p = s rho^(gamma-1); elsewhere the entropy is set from
+          // the total energy
+          const T ekin = T(0.5) * (Un[1] * Un[1] + Un[2] * Un[2] + Un[3] * Un[3]) / Un[0];
+          const T eth = Un[4] - ekin;
+          const T rg = tpow(Un[0], gamma - 1.0);
+          const bool use_s = val(eth) < xi * val(ekin);
+          sig_mix(use_s ? 27 : 28);
+          if (use_s) Un[4] = Un[5] * rg / gm1 + ekin;
+          else Un[5] = gm1 * eth / rg;
+        }
+        for (int q = 0; q < nf; ++q) Uout[((int64_t(q) * b.nz + z) * b.ny + y) * b.nx + x] = Un[q];
         const T p = gm1 * (Un[4] - T(0.5) * (Un[1] * Un[1] + Un[2] * Un[2] + Un[3] * Un[3]) / Un[0]);
         if (!(val(Un[0]) > 0.0 && val(p) > 0.0)) ++n_bad;
       }
@@ -1803,6 +1879,9 @@ void oracle_count_ops(const double* U, const double* Wc, const double* Wm, const
 // ------------------------------------------------- other schemes (C ABI) ---
 static bool valid_any_scheme(int scheme, int ghost) {
   const int id = scheme & SCHEME_ID_MASK;
+  if (scheme & ~(0xff | (3 << 8) | FIRST_ORDER_BIT | (3 << LIMITER_SHIFT) | CHARACTERISTIC_BIT | PPM_BIT |
+                 (3 << RIEMANN_SHIFT) | DUAL_ENERGY_BIT))
+    return false;
   if (id != SCHEME_MHM_PLM_HLLC && id != SCHEME_CTU) return false;
   if (((scheme >> RIEMANN_SHIFT) & 3) == 3) return false;
   return ghost >= recon_radius(scheme) + 1 && ghost >= 2;
@@ -1811,7 +1890,7 @@ static bool valid_any_scheme(int scheme, int ghost) {
 // One step of G padded 16^3 groups with any scheme of the scheme word.
 int64_t oracle_step_any(const double* Upad, double* Uout, int64_t G, int ghost, double dt, double dx, double gamma,
                         double theta, int scheme) {
-  if (G < 0 || !valid_any_scheme(scheme, ghost)) return -1;
+  if (G < 0 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT)) return -1;
   const Block b(16, 16, 16, ghost);
   int64_t n_bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : n_bad)
@@ -1822,14 +1901,14 @@ int64_t oracle_step_any(const double* Upad, double* Uout, int64_t G, int ghost, 
 
 int64_t oracle_step_block_any(const double* Upad, double* Uout, int nx, int ny, int nz, int ghost, double dt,
                               double dx, double gamma, double theta, int scheme) {
-  if (nx < 1 || ny < 1 || nz < 1 || !valid_any_scheme(scheme, ghost)) return -1;
+  if (nx < 1 || ny < 1 || nz < 1 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT)) return -1;
   return step_block_any(Upad, Uout, Block(nx, ny, nz, ghost), dt, dx, gamma, theta, scheme);
 }
 
 // Dual-number JVP of oracle_step_any.
 int64_t oracle_step_any_jvp(const double* Upad, const double* Tpad, double* Uout, double* Tout, int64_t G, int ghost,
                             double dt, double dx, double gamma, double theta, int scheme) {
-  if (G < 0 || !valid_any_scheme(scheme, ghost)) return -1;
+  if (G < 0 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT)) return -1;
   const Block b(16, 16, 16, ghost);
   const int64_t np = b.cells() * 5;
   int64_t n_bad = 0;
@@ -1844,6 +1923,27 @@ int64_t oracle_step_any_jvp(const double* Upad, const double* Tpad, double* Uout
     }
   }
   return n_bad;
+}
+
+// Dual-energy steps (scheme bit 18): 6 fields per cell, [G][6][P^3] ->
+// [G][6][16^3], and one block [6][nz+2g][ny+2g][nx+2g] -> [6][nz][ny][nx].
+int64_t oracle_step_any_de(const double* Upad, double* Uout, int64_t G, int ghost, double dt, double dx,
+                           double gamma, double theta, int scheme, double xi) {
+  if (G < 0 || !valid_any_scheme(scheme, ghost) || !(scheme & DUAL_ENERGY_BIT) || !(xi >= 0.0)) return -1;
+  const Block b(16, 16, 16, ghost);
+  int64_t n_bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
+  for (int64_t g = 0; g < G; ++g)
+    n_bad += step_block_any(Upad + g * b.cells() * 6, Uout + g * 6 * 4096, b, dt, dx, gamma, theta, scheme,
+                            (double*)nullptr, xi);
+  return n_bad;
+}
+
+int64_t oracle_step_block_any_de(const double* Upad, double* Uout, int nx, int ny, int nz, int ghost, double dt,
+                                 double dx, double gamma, double theta, int scheme, double xi) {
+  if (nx < 1 || ny < 1 || nz < 1 || !valid_any_scheme(scheme, ghost) || !(scheme & DUAL_ENERGY_BIT) || !(xi >= 0.0))
+    return -1;
+  return step_block_any(Upad, Uout, Block(nx, ny, nz, ghost), dt, dx, gamma, theta, scheme, (double*)nullptr, xi);
 }
 
 // Riemann flux of the scheme word's solver (tests).  Returns 1 if an input
@@ -1882,7 +1982,8 @@ void oracle_from_characteristic(const double* a, int d, double rho, double c, do
 // unphysical results.  Returns the unphysical count.
 int64_t oracle_level_step_any(const double* level, double* level_out, int ngx, int ngy, int ngz, int ghost,
                               const int* bc, double dt, double dx, double gamma, double theta, int scheme) {
-  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost > 16 || !valid_any_scheme(scheme, ghost)) return -1;
+  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost > 16 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT))
+    return -1;
   const int P = 16 + 2 * ghost;
   const int64_t G = int64_t(ngx) * ngy * ngz;
   std::vector<double> pad(size_t(G) * 5 * P * P * P);
@@ -1906,7 +2007,8 @@ int64_t oracle_level_step_any(const double* level, double* level_out, int ngx, i
 int64_t oracle_level_step_fallback(const double* level, double* level_out, int ngx, int ngy, int ngz, int ghost,
                                    const int* bc, double dt, double dt_min, double ratio, double dx, double gamma,
                                    double theta, int scheme, double* out_info) {
-  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost > 16 || !valid_any_scheme(scheme, ghost) || !(dt > 0.0) ||
+  if (ngx < 1 || ngy < 1 || ngz < 1 || ghost > 16 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT) ||
+      !(dt > 0.0) ||
       !(ratio > 0.0 && ratio < 1.0) || !(dt_min >= 0.0))
     return -1;
   int retries = 0;
@@ -1970,7 +2072,7 @@ static bool amr_setup(int n_levels, const int* n0, const int64_t* G, const int* 
 
 int64_t oracle_amr_step(int n_levels, const int* n0, const int64_t* G, const int* pos, double* U, const int* bc,
                         int ghost, double dt0, double dx0, double gamma, double theta, int scheme) {
-  if (ghost > 16 || !valid_any_scheme(scheme, ghost)) return -1;
+  if (ghost > 16 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT)) return -1;
   std::vector<AmrLevel> Ls;
   if (!amr_setup(n_levels, n0, G, pos, U, Ls, bc)) return -1;
   return amr_advance(Ls, 0, dt0, dx0, gamma, theta, scheme, ghost, bc, nullptr, nullptr, 0.0, nullptr);
