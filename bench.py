@@ -119,6 +119,8 @@ def parse():
     ap.add_argument("--amr-coarse-steps", type=int, default=4)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fwd+adjoint rollout measurements")
     ap.add_argument("--fd-samples", type=int, default=64)
+    ap.add_argument("--no-ext", action="store_true",
+                    help="skip the other schemes, the unphysical-result procedure and the coupled AMR hierarchy")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="after the run, copy a device buffer of this size (reference for HBM byte counters)")
     return ap.parse_args()
@@ -382,6 +384,114 @@ def differentiation_workloads(hydro, torch, W, fd_samples):
     return out
 
 
+# Scheme words of the other schemes measured on the shear layer (the AMR runs
+# of the paper's comparisons use MHM + PPM + HLLC with the hybrid limiter, and
+# CTU with Roe's solver)
+EXT_SCHEMES = {
+    "mhm-ppm-hllc-hybrid": 1 | (1 << 14) | (3 << 11),
+    "ctu-plm-roe": 2 | (1 << 16),
+    "mhm-plm-char-vanleer-hllc": 1 | (1 << 13) | (1 << 11),
+    "mhm-plm-hlle": 1 | (2 << 16),
+}
+
+
+def ext_schemes(hydro, torch, W, reps=5):
+    """One step (ghost fill + the multi-kernel step) of the 256^3 shear layer
+    per scheme word, timed with events on the stream the kernels run on."""
+    lv = W.shear_layer(256)
+    out = {"workload": "shear-layer 256^3 (4096 groups), 3 ghost zones, one step at the initial CFL time-step"}
+    for dtype in ("f64", "f32"):
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        U = torch.from_numpy(np.ascontiguousarray(lv.U.astype(np.float64 if dtype == "f64" else np.float32))).cuda()
+        pad = hydro.fill_ghosts(U, lv.ng, 3, lv.bc)
+        dt = float(hydro.cfl_dt(pad, lv.dx, lv.gamma, 0.5).min())
+        for name, sch in EXT_SCHEMES.items():
+            if dtype == "f32" and name != "mhm-ppm-hllc-hybrid":
+                continue
+            work = hydro.ext_workspace(lv.n_groups, 3, tdt, sch)
+            O = torch.empty_like(U)
+
+            def step():
+                hydro.fill_ghosts(U, lv.ng, 3, lv.bc, out=pad)
+                hydro.advance_ext(pad, dt, lv.dx, lv.gamma, sch, out=O, work=work)
+            ms = time_events(torch, step, reps)
+            out["%s/%s" % (name, dtype)] = {"ms_per_step": ms, "cell_updates_per_s": lv.n_cells / (ms * 1e-3),
+                                           "scheme_word": sch, "workspace_bytes": work.numel()}
+            del work, O
+            torch.cuda.empty_cache()
+        del U, pad
+        torch.cuda.empty_cache()
+    # dual energy (6 fields, the entropy s = p / rho^(gamma-1) as field 5) with
+    # the AGORA scheme word, FP64
+    U5 = lv.U
+    r = U5[:, 0]
+    ekin = 0.5 * (U5[:, 1] ** 2 + U5[:, 2] ** 2 + U5[:, 3] ** 2) / r
+    ent = (lv.gamma - 1.0) * (U5[:, 4] - ekin) / r ** (lv.gamma - 1.0)
+    Ud = torch.from_numpy(np.ascontiguousarray(U5)).cuda()
+    Ed = torch.from_numpy(np.ascontiguousarray(np.repeat(ent[:, None], 5, axis=1))).cuda()
+    pad6 = torch.cat([hydro.fill_ghosts(Ud, lv.ng, 3, lv.bc), hydro.fill_ghosts(Ed, lv.ng, 3, lv.bc)[:, :1]], dim=1)
+    del Ud, Ed
+    torch.cuda.empty_cache()
+    sch = EXT_SCHEMES["mhm-ppm-hllc-hybrid"] | (1 << 18)
+    dt = float(hydro.cfl_dt(pad6[:, :5].contiguous(), lv.dx, lv.gamma, 0.5).min())
+    work = hydro.ext_workspace(lv.n_groups, 3, torch.float64, sch)
+    O = torch.empty((lv.n_groups, 6, 16, 16, 16), dtype=torch.float64, device="cuda")
+    ms = time_events(torch, lambda: hydro.advance_ext(pad6, dt, lv.dx, lv.gamma, sch, out=O, work=work, xi=0.01), reps)
+    out["mhm-ppm-hllc-hybrid-dual-energy/f64"] = {"ms_per_step": ms, "cell_updates_per_s": lv.n_cells / (ms * 1e-3),
+                                                 "scheme_word": sch, "fill_in_timed_region": False}
+    del pad6, work, O
+    torch.cuda.empty_cache()
+    return out
+
+
+def fallback_workload(hydro, torch, W, reps=3):
+    """The procedure for unphysical results on a 128^3 low-pressure white-noise
+    state at its CFL time-step: MHM's update fails on ~0.15% of the cells,
+    which are recomputed first-order; the plain step is timed beside it."""
+    n = 128
+    rng = np.random.default_rng(20171219 + 6)
+    rho = rng.uniform(0.05, 2, (n, n, n))
+    p = np.exp(rng.uniform(np.log(1e-3), np.log(2.0), (n, n, n)))
+    v = rng.normal(0, 0.5, (3, n, n, n))
+    Uh = W.grid_to_groups(W.conserved(rho, v[0], v[1], v[2], p, 5.0 / 3.0))
+    ng, bc, dx = (n // 16,) * 3, (0,) * 6, 1.0 / n
+    U = torch.from_numpy(Uh).cuda()
+    pad = hydro.fill_ghosts(U, ng, 3, bc)
+    dt = float(hydro.cfl_dt(pad, dx, 5.0 / 3.0, 0.5).min())
+    del pad
+    O = torch.empty_like(U)
+    work = torch.empty(int(hydro.load().hydro_fallback_workspace_bytes(*ng, 0, 1)), dtype=torch.uint8, device="cuda")
+    info = {}
+
+    def fb():
+        _, ok, inf = hydro.advance_level_fallback(U, ng, bc, dt, dx, 5.0 / 3.0, out=O, work=work)
+        info.update(inf, ok=ok)
+    ms_fb = time_events(torch, fb, reps)
+    ms_plain = time_events(torch, lambda: hydro.advance_level(U, ng, bc, dt, dx, 5.0 / 3.0, out=O), reps)
+    return {"workload": "white noise 128^3, rho U(0.05,2), p log-uniform [1e-3, 2], v N(0, 0.5), CFL 0.5, FP64",
+            "ms_fallback_step": ms_fb, "ms_plain_step": ms_plain, "repaired": info,
+            "cell_updates_per_s": Uh.shape[0] * 4096 / (ms_fb * 1e-3)}
+
+
+def amr_coupled(hydro, torch, W, coarse_steps=2):
+    """The blast workload on a coupled hierarchy (512 / 1536 / 3072 groups,
+    nested, W-cycle with ghost interpolation, flux registers, restriction and
+    fix-up): coarse steps timed with events, FP64, MHM+PLM+HLLC."""
+    h = W.sedov_hierarchy()
+    dev = [torch.from_numpy(np.ascontiguousarray(s)).cuda() for s in h.states]
+    solver = hydro.AmrSolver(h.n0, h.positions, dev, h.dx0, h.gamma, h.bc)
+    dt0 = 1.25e-6
+    solver.step(dt0)                                   # warm-up
+    torch.cuda.synchronize()
+    ms = time_events(torch, lambda: solver.step(dt0), coarse_steps)
+    cells = solver.cells_per_coarse_step()
+    return {"workload": "coupled blast hierarchy: 8^3 level-0 groups, 16x12x8 level-1 and 24x16x8 level-2 groups "
+                        "(nested boxes), dt_l = dt_0 / 2^l, FP64",
+            "groups": [len(p) for p in h.positions], "ms_per_coarse_step": ms,
+            "cells_per_coarse_step": cells, "cell_updates_per_s": cells / (ms * 1e-3),
+            "n_bad": int(solver.n_bad.cpu()[0])}
+
+
 def cpu_baseline(lv_factory, seconds):
     """The oracle (fill + CFL + MHM step) on a bounded sample of the workload."""
     import oracle
@@ -410,6 +520,7 @@ def cpu_baseline(lv_factory, seconds):
         steps1, el1 = timed(seconds / 3)
     finally:
         oracle.set_num_threads(threads)
+    others = cpu_other_workloads(seconds / 3)
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -422,7 +533,44 @@ def cpu_baseline(lv_factory, seconds):
                       "the workload as its own periodic brick), FP64, OpenMP over groups" %
                       (steps, nsub, ngx * 16, ngy * 16, 32, ngx, ngy),
             "single_thread": {"value": cells * steps1 / el1, "steps": steps1},
+            "other_workloads": others,
             "host": {"cpu_count": os.cpu_count(), "model": model}}
+
+
+def cpu_other_workloads(budget):
+    """The oracle on bounded samples of the other workloads (all host threads):
+    the blast levels (one level-2 brick step), the 128^3 smooth wave (its
+    8-step rollout) and a 2-group-deep slab of the 384^3 turbulence state, in
+    cell-updates/s."""
+    import oracle
+    from paper_1712_07070_amd import workloads as W
+    out = {}
+
+    def rate(run, cells):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            run()
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return cells * n / el, n
+
+    lv = W.sedov_levels()[2]
+    r, n = rate(lambda: oracle.rollout(lv.U, lv.ng, 3, lv.bc, 1, lv.dx, lv.gamma, dt=1e-7), lv.n_cells)
+    out["blast_level2_3072_groups"] = {"value": r, "steps": n}
+    lv, _ = W.smooth_wave(128)
+    r, n = rate(lambda: oracle.rollout(lv.U, lv.ng, 3, lv.bc, 8, lv.dx, lv.gamma, dt=0.2 * lv.dx),
+                lv.n_cells * 8)
+    out["smooth_wave_128_rollout_8_steps"] = {"value": r, "rollouts": n}
+    lv = W.turbulence(384)
+    ngx, ngy, _ = lv.ng
+    nsub = ngx * ngy * 2
+    U = np.ascontiguousarray(lv.U[:nsub])
+    r, n = rate(lambda: oracle.rollout(U, (ngx, ngy, 2), 3, lv.bc, 1, lv.dx, lv.gamma), nsub * 4096)
+    out["turbulence_384_slab_1152_groups"] = {"value": r, "steps": n}
+    out["unit"] = "cell-updates/s"
+    out["cores"] = oracle.num_threads()
+    return out
 
 
 def main():
@@ -501,6 +649,16 @@ def main():
     if not args.no_adjoint:
         print("bench: differentiation workloads", file=sys.stderr, flush=True)
         extra["adjoint"] = differentiation_workloads(hydro, torch, W, args.fd_samples)
+        torch.cuda.empty_cache()
+    if not args.no_ext:
+        print("bench: other schemes", file=sys.stderr, flush=True)
+        extra["schemes"] = ext_schemes(hydro, torch, W)
+        torch.cuda.empty_cache()
+        print("bench: procedure for unphysical results", file=sys.stderr, flush=True)
+        extra["fallback"] = fallback_workload(hydro, torch, W)
+        torch.cuda.empty_cache()
+        print("bench: coupled AMR hierarchy", file=sys.stderr, flush=True)
+        extra["amr_coupled"] = amr_coupled(hydro, torch, W)
         torch.cuda.empty_cache()
     if args.calibrate_copy > 0:
         # a plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE

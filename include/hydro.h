@@ -85,7 +85,7 @@ typedef struct hydro_ctx hydro_ctx;
  * bits 0-7 scheme id MHM (= HYDRO_SCHEME_MHM_PLM_HLLC) or CTU (6 Riemann
  * solves per cell); bits 11-12 slope limiter; bit 13 limit characteristic
  * instead of primitive variables; bit 14 PPM instead of PLM; bits 16-17
- * Riemann solver. */
+ * Riemann solver; bit 18 dual energy (a sixth field per cell). */
 #define HYDRO_SCHEME_MHM 1
 #define HYDRO_SCHEME_CTU 2
 #define HYDRO_LIMITER_GMINMOD (0 << 11)
@@ -97,6 +97,7 @@ typedef struct hydro_ctx hydro_ctx;
 #define HYDRO_RIEMANN_HLLC (0 << 16)
 #define HYDRO_RIEMANN_ROE (1 << 16)
 #define HYDRO_RIEMANN_HLLE (2 << 16)
+#define HYDRO_DUAL_ENERGY (1 << 18)
 
 #define HYDRO_BC_PERIODIC 0
 #define HYDRO_BC_OUTFLOW 1
@@ -171,6 +172,13 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
  *   (no entropy fix; a face whose linearized intermediate states are
  *   unphysical takes the HLLC flux, the first step of the paper's procedure
  *   for unphysical results).
+ *   Dual energy (HYDRO_DUAL_ENERGY, Sec. 2.2): every state array has 6
+ *   fields, [G][6][P^3] in and [G][6][16^3] out, field 5 the entropy per
+ *   unit volume s = p / rho^(gamma-1), advected as a passive scalar (s/rho
+ *   reconstructed like a primitive variable; Riemann flux = mass flux times
+ *   s/rho of the upwind side); after the update E = s rho^(gamma-1)/(gamma-1)
+ *   + E_kin where E - E_kin < xi E_kin, else s is reset from E.  xi >= 0 (the
+ *   paper's typical 1e-2); ignored without the bit.  Not with face_flux_dev.
  *   ghost       >= 2, and >= 3 with PPM
  *   work_dev    device scratch of work_bytes bytes, at least
  *               hydro_ext_workspace_bytes(1, ghost, dtype, scheme); groups are
@@ -179,12 +187,20 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
  *               U_pad_dev or U_out_dev
  *   n_bad_dev   as for hydro_advance (faces with unphysical input states plus
  *               updated cells with rho <= 0 or p <= 0)
+ *   face_flux_dev  optional [G][9][5][16][16] output: the fluxes the update
+ *               used on the faces of the patch boundaries of every group (the
+ *               flux registers of coarse-fine coupling): plane p = 3 axis + k
+ *               holds that axis' faces at normal coordinate 8 k (the face
+ *               between cells 8k-1 and 8k), entry [p][field][b][a] with a, b
+ *               the transverse coordinates in the cyclic order (axis+1,
+ *               axis+2); must not overlap the other buffers
  * hydro_ext_workspace_bytes returns the bytes for n_groups groups, or
  * HYDRO_EINVAL for an invalid scheme word / ghost / dtype. */
 int64_t hydro_ext_workspace_bytes(int64_t n_groups, int32_t ghost, int32_t dtype, int32_t scheme);
 int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
-                      double dt, double dx, double gamma, int32_t scheme, double theta, const double* dt_dev,
-                      int32_t* n_bad_dev, void* work_dev, int64_t work_bytes, void* stream);
+                      double dt, double dx, double gamma, int32_t scheme, double theta, double xi,
+                      const double* dt_dev, int32_t* n_bad_dev, void* work_dev, int64_t work_bytes,
+                      void* face_flux_dev, void* stream);
 
 /* Procedure for unphysical results (Sec. 2.2: a cell whose update gives
  * rho <= 0 or p <= 0 is (ii) recomputed first-order in space and time,
@@ -235,6 +251,62 @@ int hydro_advance_level_fallback(hydro_ctx* ctx, const void* level_in_dev, void*
                                  int32_t ngy, int32_t ngz, const int32_t* bc_host, int32_t dtype, double dt,
                                  double dt_min, double ratio, double dx, double gamma, int32_t scheme, double theta,
                                  void* work_dev, int64_t work_bytes, double* info_host, void* stream);
+
+/* Coarse-fine coupling of AMR levels (Sec. 2.1: patches of 8^3 cells,
+ * refinement ratio 2, the 8 children of a coarse patch form one fine patch
+ * group; levels advance in a W-cycle with dt_l = dt_0 / 2^l.  Sec. 2.2: after
+ * a coarse level is synchronized with its children, coarse cells covered by
+ * them are restricted and uncovered coarse cells at the coarse-fine
+ * interface are corrected by the difference of coarse and fine fluxes.
+ * Sec. 3.2: ghost zones of a fine group come from sibling groups or by
+ * interpolation from the coarse level).
+ *
+ * A level is described by hydro_amr_level_t: its states, its group
+ * positions on the level's group lattice (level l has n_0 * 2^l groups per
+ * axis over the domain; a fine group at position p covers coarse patch p,
+ * i.e. coarse cells 8p .. 8p+7 per axis) and the dense map of that lattice
+ * (group index, or -1 where the level has no group), all device memory.
+ * Level 0 covers the domain.  A fine level must be properly nested: the 27
+ * coarse patches around the parent patch of every fine group exist on the
+ * coarse level (the caller guarantees it; the Python binding checks it). */
+typedef struct {
+  void* U_dev;             /* [G][5][16^3] states of the level */
+  const int32_t* pos_dev;  /* [G][3] group positions (x, y, z) */
+  const int32_t* map_dev;  /* [n[2]][n[1]][n[0]] group index or -1 */
+  int64_t n_groups;
+  int32_t n[3];            /* group lattice of the level over the domain */
+} hydro_amr_level_t;
+
+/* hydro_amr_fill_ghosts -- padded groups [G][5][P^3] of level `fine`
+ *   (P = 16 + 2 ghost, 0 <= ghost <= 16): a ghost cell is copied from the
+ *   sibling group holding it, else interpolated from `coarse` (NULL only for
+ *   level 0): time-linear between coarse_old_dev and coarse_new_dev (the
+ *   coarse step's input and output, [G_c][5][16^3]) at weight a in [0, 1],
+ *   space-conservative-linear (coarse value + minmod-limited slopes of the
+ *   conserved variables times the +-1/4-cell offsets of the child, summed x,
+ *   y, z).  bc_host: the domain's boundary conditions.
+ * hydro_amr_flux_accumulate -- flux registers reg_dev [G_f][6][5][8][8]
+ *   (sides x-, x+, y-, y+, z-, z+; field; the coarse face's transverse
+ *   coordinates (b, a) in cyclic order) ADD weight * (1/4) * the sum of the
+ *   2x2 fine faces over each coarse face, from face_flux_dev (the
+ *   [G_f][9][5][16][16] output of hydro_advance_ext), on every side of a
+ *   fine group with no sibling group across it (weight = dt_f / dt_c).
+ * hydro_amr_restrict -- every coarse cell covered by a fine group becomes the
+ *   mean of its 8 children (coarse->U_dev is written).
+ * hydro_amr_fixup -- every uncovered coarse cell sharing a face with a fine
+ *   group: U += dt_over_dx (R - F_c) if the face is its low face, -= if its
+ *   high face, sides in the order x-, x+, y-, y+, z-, z+; F_c from
+ *   coarse_face_flux_dev (the coarse step's hydro_advance_ext face fluxes),
+ *   R from reg_dev.
+ * All asynchronous on stream; dtype of every state / flux array. */
+int hydro_amr_fill_ghosts(const hydro_amr_level_t* fine, const hydro_amr_level_t* coarse, const void* coarse_old_dev,
+                          const void* coarse_new_dev, double a, const int32_t* bc_host, int32_t ghost, int32_t dtype,
+                          void* U_pad_dev, void* stream);
+int hydro_amr_flux_accumulate(const hydro_amr_level_t* fine, const void* face_flux_dev, double weight,
+                              const int32_t* bc_host, int32_t dtype, void* reg_dev, void* stream);
+int hydro_amr_restrict(const hydro_amr_level_t* fine, const hydro_amr_level_t* coarse, int32_t dtype, void* stream);
+int hydro_amr_fixup(const hydro_amr_level_t* coarse, const hydro_amr_level_t* fine, const void* coarse_face_flux_dev,
+                    const void* reg_dev, double dt_over_dx, const int32_t* bc_host, int32_t dtype, void* stream);
 
 /* hydro_advance_level -- one MHM step of every patch group of a level, read
  * directly from level storage (Sec. 2.2 scheme; Sec. 3.4 ghost zones; Sec. 2.6

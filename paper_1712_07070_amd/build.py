@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhydro.so")
-SOURCES = ["capi.hip", "mhm_fwd.hip", "mhm_batched.hip", "mhm_adj.hip", "aux_kernels.hip", "scheme_ext.hip", "fallback.hip"]
+SOURCES = ["capi.hip", "mhm_fwd.hip", "mhm_batched.hip", "mhm_adj.hip", "aux_kernels.hip", "scheme_ext.hip", "fallback.hip", "amr.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -196,7 +196,8 @@ bool valid_scheme(int32_t scheme, double theta) {
 bool valid_ext_scheme(int32_t scheme, double theta, int32_t ghost, gh::ExtOpts* o) {
   const int id = scheme & 0xff;
   if (id != HYDRO_SCHEME_MHM && id != HYDRO_SCHEME_CTU) return false;
-  const int known = 0xff | (3 << 8) | HYDRO_FIRST_ORDER | (3 << 11) | HYDRO_CHARACTERISTIC | HYDRO_PPM | (3 << 16);
+  const int known =
+      0xff | (3 << 8) | HYDRO_FIRST_ORDER | (3 << 11) | HYDRO_CHARACTERISTIC | HYDRO_PPM | (3 << 16) | HYDRO_DUAL_ENERGY;
   if (scheme & ~known) return false;
   o->ctu = id == HYDRO_SCHEME_CTU;
   o->ws = (scheme >> 8) & 3;
@@ -205,6 +206,8 @@ bool valid_ext_scheme(int32_t scheme, double theta, int32_t ghost, gh::ExtOpts* 
   o->chr = (scheme & HYDRO_CHARACTERISTIC) ? 1 : 0;
   o->ppm = (scheme & HYDRO_PPM) ? 1 : 0;
   o->solver = (scheme >> 16) & 3;
+  o->de = (scheme & HYDRO_DUAL_ENERGY) ? 1 : 0;
+  o->xi = 0.0;
   if (o->ws > 1 || o->solver > 2) return false;
   if (ghost < o->radius() + 1 || ghost < 2) return false;
   return std::isfinite(theta) && theta >= 1.0 && theta <= 2.0;
@@ -586,12 +589,16 @@ int64_t hydro_ext_workspace_bytes(int64_t n_groups, int32_t ghost, int32_t dtype
 }
 
 int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
-                      double dt, double dx, double gamma, int32_t scheme, double theta, const double* dt_dev,
-                      int32_t* n_bad_dev, void* work_dev, int64_t work_bytes, void* stream) {
+                      double dt, double dx, double gamma, int32_t scheme, double theta, double xi,
+                      const double* dt_dev, int32_t* n_bad_dev, void* work_dev, int64_t work_bytes,
+                      void* face_flux_dev, void* stream) {
   gh::ExtOpts o;
   if (n_groups < 0 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
   if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_ext_scheme(scheme, theta, ghost, &o))
     return HYDRO_EINVAL;
+  if (o.de && (!(xi >= 0.0) || std::isnan(xi) || face_flux_dev != nullptr)) return HYDRO_EINVAL;
+  o.xi = xi;
+  const int64_t nf = o.de ? 6 : 5;
   if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
   if (n_groups == 0) return HYDRO_OK;
   if (U_pad_dev == nullptr || U_out_dev == nullptr || work_dev == nullptr) return HYDRO_EINVAL;
@@ -599,11 +606,16 @@ int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, 
   const size_t es = dtype_size(dtype);
   const int64_t per_group = gh::ext_workspace_elems(1, ghost, o) * int64_t(es);
   if (work_bytes < per_group) return HYDRO_EINVAL;
-  const size_t pad_b = size_t(n_groups) * 5 * P * P * P * es, out_b = size_t(n_groups) * 5 * 4096 * es;
+  const size_t pad_b = size_t(n_groups) * nf * P * P * P * es, out_b = size_t(n_groups) * nf * 4096 * es;
   const int64_t chunk = std::min<int64_t>(n_groups, work_bytes / per_group);
   const size_t work_b = size_t(gh::ext_workspace_elems(chunk, ghost, o)) * es;
   if (overlap(U_pad_dev, pad_b, U_out_dev, out_b) || overlap(work_dev, work_b, U_pad_dev, pad_b) ||
       overlap(work_dev, work_b, U_out_dev, out_b))
+    return HYDRO_EINVAL;
+  const size_t ff_b = size_t(n_groups) * 9 * 5 * 256 * es;
+  if (face_flux_dev != nullptr && (overlap(face_flux_dev, ff_b, U_pad_dev, pad_b) ||
+                                   overlap(face_flux_dev, ff_b, U_out_dev, out_b) ||
+                                   overlap(face_flux_dev, ff_b, work_dev, work_b)))
     return HYDRO_EINVAL;
   const double dt_host = dt_dev != nullptr ? 1.0 : dt;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -612,18 +624,143 @@ int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, 
     const int64_t G = std::min(chunk, n_groups - g0);
     hipError_t e;
     if (dtype == HYDRO_F64)
-      e = gh::launch_ext_step(static_cast<const double*>(U_pad_dev) + g0 * 5 * P * P * P,
-                              static_cast<double*>(U_out_dev) + g0 * 5 * 4096, G, ghost,
+      e = gh::launch_ext_step(static_cast<const double*>(U_pad_dev) + g0 * nf * P * P * P,
+                              static_cast<double*>(U_out_dev) + g0 * nf * 4096, G, ghost,
                               make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, o, n_bad_dev,
-                              static_cast<double*>(work_dev), s);
+                              static_cast<double*>(work_dev),
+                              face_flux_dev ? static_cast<double*>(face_flux_dev) + g0 * 9 * 5 * 256 : nullptr, s);
     else
-      e = gh::launch_ext_step(static_cast<const float*>(U_pad_dev) + g0 * 5 * P * P * P,
-                              static_cast<float*>(U_out_dev) + g0 * 5 * 4096, G, ghost,
+      e = gh::launch_ext_step(static_cast<const float*>(U_pad_dev) + g0 * nf * P * P * P,
+                              static_cast<float*>(U_out_dev) + g0 * nf * 4096, G, ghost,
                               make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, o, n_bad_dev,
-                              static_cast<float*>(work_dev), s);
+                              static_cast<float*>(work_dev),
+                              face_flux_dev ? static_cast<float*>(face_flux_dev) + g0 * 9 * 5 * 256 : nullptr, s);
     if (e != hipSuccess) return device_status(e);
   }
   return HYDRO_OK;
+}
+
+// ------------------------------------------------ coarse-fine coupling ----
+static_assert(sizeof(hydro_amr_level_t) == 48 && offsetof(hydro_amr_level_t, n_groups) == 24 &&
+                  offsetof(hydro_amr_level_t, n) == 32,
+              "hydro_amr_level_t layout");
+
+namespace {
+
+bool amr_level_ok(const hydro_amr_level_t* L, bool need_states) {
+  if (L == nullptr || L->n_groups < 0 || L->pos_dev == nullptr || L->map_dev == nullptr) return false;
+  if (need_states && L->U_dev == nullptr && L->n_groups > 0) return false;
+  for (int d = 0; d < 3; ++d)
+    if (L->n[d] < 1 || L->n[d] > (1 << 20)) return false;
+  const int64_t cells = int64_t(L->n[0]) * L->n[1] * L->n[2];
+  return L->n_groups <= cells && int64_t(L->n[0]) * 16 < (1ll << 30) && int64_t(L->n[1]) * 16 < (1ll << 30) &&
+         int64_t(L->n[2]) * 16 < (1ll << 30);
+}
+
+// fine lattice = 2 x coarse lattice
+bool amr_pair_ok(const hydro_amr_level_t* F, const hydro_amr_level_t* C) {
+  return F->n[0] == 2 * C->n[0] && F->n[1] == 2 * C->n[1] && F->n[2] == 2 * C->n[2];
+}
+
+gh::AmrLevelArgs amr_args(const hydro_amr_level_t* L) {
+  gh::AmrLevelArgs a;
+  a.pos = L->pos_dev;
+  a.map = L->map_dev;
+  a.G = L->n_groups;
+  for (int d = 0; d < 3; ++d) a.n[d] = L->n[d];
+  return a;
+}
+
+bool bc_ok(const int32_t* bc) {
+  if (bc == nullptr) return false;
+  for (int i = 0; i < 6; ++i)
+    if (bc[i] != HYDRO_BC_PERIODIC && bc[i] != HYDRO_BC_OUTFLOW) return false;
+  return true;
+}
+
+}  // namespace
+
+int hydro_amr_fill_ghosts(const hydro_amr_level_t* fine, const hydro_amr_level_t* coarse, const void* coarse_old_dev,
+                          const void* coarse_new_dev, double a, const int32_t* bc_host, int32_t ghost, int32_t dtype,
+                          void* U_pad_dev, void* stream) {
+  if (!amr_level_ok(fine, true) || !bc_ok(bc_host) || ghost < 0 || ghost > 16 || U_pad_dev == nullptr ||
+      (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+    return HYDRO_EINVAL;
+  gh::AmrLevelArgs C{};
+  if (coarse != nullptr) {
+    if (!amr_level_ok(coarse, false) || !amr_pair_ok(fine, coarse) || coarse_old_dev == nullptr ||
+        coarse_new_dev == nullptr || !(a >= 0.0 && a <= 1.0))
+      return HYDRO_EINVAL;
+    C = amr_args(coarse);
+  } else if (fine->n_groups != int64_t(fine->n[0]) * fine->n[1] * fine->n[2]) {
+    return HYDRO_EINVAL;  // only a level covering the domain needs no coarse level
+  }
+  const int64_t P = 16 + 2 * ghost;
+  const size_t es = dtype_size(dtype);
+  if (overlap(U_pad_dev, size_t(fine->n_groups) * 5 * P * P * P * es, fine->U_dev,
+              size_t(fine->n_groups) * 5 * 4096 * es))
+    return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_amr_fill(static_cast<const double*>(fine->U_dev), amr_args(fine),
+                            static_cast<const double*>(coarse_old_dev), static_cast<const double*>(coarse_new_dev), C,
+                            a, bc_host, ghost, static_cast<double*>(U_pad_dev), s);
+  else
+    e = gh::launch_amr_fill(static_cast<const float*>(fine->U_dev), amr_args(fine),
+                            static_cast<const float*>(coarse_old_dev), static_cast<const float*>(coarse_new_dev), C, a,
+                            bc_host, ghost, static_cast<float*>(U_pad_dev), s);
+  return device_status(e);
+}
+
+int hydro_amr_flux_accumulate(const hydro_amr_level_t* fine, const void* face_flux_dev, double weight,
+                              const int32_t* bc_host, int32_t dtype, void* reg_dev, void* stream) {
+  if (!amr_level_ok(fine, false) || !bc_ok(bc_host) || face_flux_dev == nullptr || reg_dev == nullptr ||
+      !std::isfinite(weight) || (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+    return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_amr_accumulate(amr_args(fine), static_cast<const double*>(face_flux_dev), weight, bc_host,
+                                  static_cast<double*>(reg_dev), s);
+  else
+    e = gh::launch_amr_accumulate(amr_args(fine), static_cast<const float*>(face_flux_dev), weight, bc_host,
+                                  static_cast<float*>(reg_dev), s);
+  return device_status(e);
+}
+
+int hydro_amr_restrict(const hydro_amr_level_t* fine, const hydro_amr_level_t* coarse, int32_t dtype, void* stream) {
+  if (!amr_level_ok(fine, true) || !amr_level_ok(coarse, true) || !amr_pair_ok(fine, coarse) ||
+      (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+    return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_amr_restrict(static_cast<const double*>(fine->U_dev), amr_args(fine),
+                                static_cast<double*>(coarse->U_dev), amr_args(coarse), s);
+  else
+    e = gh::launch_amr_restrict(static_cast<const float*>(fine->U_dev), amr_args(fine),
+                                static_cast<float*>(coarse->U_dev), amr_args(coarse), s);
+  return device_status(e);
+}
+
+int hydro_amr_fixup(const hydro_amr_level_t* coarse, const hydro_amr_level_t* fine, const void* coarse_face_flux_dev,
+                    const void* reg_dev, double dt_over_dx, const int32_t* bc_host, int32_t dtype, void* stream) {
+  if (!amr_level_ok(fine, false) || !amr_level_ok(coarse, true) || !amr_pair_ok(fine, coarse) || !bc_ok(bc_host) ||
+      coarse_face_flux_dev == nullptr || reg_dev == nullptr || !finite_pos(dt_over_dx) ||
+      (dtype != HYDRO_F64 && dtype != HYDRO_F32))
+    return HYDRO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dtype == HYDRO_F64)
+    e = gh::launch_amr_fixup(static_cast<double*>(coarse->U_dev), amr_args(coarse), amr_args(fine),
+                             static_cast<const double*>(coarse_face_flux_dev), static_cast<const double*>(reg_dev),
+                             dt_over_dx, bc_host, s);
+  else
+    e = gh::launch_amr_fixup(static_cast<float*>(coarse->U_dev), amr_args(coarse), amr_args(fine),
+                             static_cast<const float*>(coarse_face_flux_dev), static_cast<const float*>(reg_dev),
+                             dt_over_dx, bc_host, s);
+  return device_status(e);
 }
 
 // ------------------------------------- procedure for unphysical results ----
@@ -635,7 +772,7 @@ int check_fallback_args(const void* in, const void* out, int32_t ngx, int32_t ng
                         int32_t dtype, double dx, double gamma, int32_t scheme, double theta, gh::LevelGeom* geo,
                         gh::ExtOpts* o) {
   if (!level_geom_ok(ngx, ngy, ngz) || bc == nullptr || (dtype != HYDRO_F64 && dtype != HYDRO_F32)) return HYDRO_EINVAL;
-  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_ext_scheme(scheme, theta, 3, o))
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_ext_scheme(scheme, theta, 3, o) || o->de)
     return HYDRO_EINVAL;
   geo->ngx = ngx;
   geo->ngy = ngy;
@@ -687,7 +824,7 @@ int hydro_repair_unphysical(const void* level_in_dev, void* level_out_dev, int32
 int64_t hydro_fallback_workspace_bytes(int32_t ngx, int32_t ngy, int32_t ngz, int32_t dtype, int32_t scheme) {
   gh::ExtOpts o;
   if (!level_geom_ok(ngx, ngy, ngz) || (dtype != HYDRO_F64 && dtype != HYDRO_F32) ||
-      !valid_ext_scheme(scheme, 1.5, 3, &o))
+      !valid_ext_scheme(scheme, 1.5, 3, &o) || o.de)
     return HYDRO_EINVAL;
   if (valid_scheme(scheme, 1.5)) return kFallbackCounterBytes;  // the fused level step needs no more
   const int64_t G = int64_t(ngx) * ngy * ngz;
@@ -738,8 +875,8 @@ int hydro_advance_level_fallback(hydro_ctx* ctx, const void* level_in_dev, void*
               : gh::launch_fill_ghosts(static_cast<const float*>(level_in_dev), reinterpret_cast<float*>(pad), ngx,
                                        ngy, ngz, 3, geo.bc, s);
       if (e != hipSuccess) return device_status(e);
-      st = hydro_advance_ext(pad, level_out_dev, G, 3, dtype, dt, dx, gamma, scheme, theta, nullptr, cnt + 3,
-                             ext_work, need - kFallbackCounterBytes - fallback_pad_bytes(G, dtype), stream);
+      st = hydro_advance_ext(pad, level_out_dev, G, 3, dtype, dt, dx, gamma, scheme, theta, 0.0, nullptr, cnt + 3,
+                             ext_work, need - kFallbackCounterBytes - fallback_pad_bytes(G, dtype), nullptr, stream);
     }
     if (st != HYDRO_OK) return st;
     int32_t h[4] = {0, 0, 0, 0};

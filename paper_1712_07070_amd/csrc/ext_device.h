@@ -21,6 +21,8 @@ struct ExtOpts {
   int chr;          // limit characteristic variables
   int ppm;          // PPM face values
   int solver;       // 0 HLLC, 1 Roe, 2 HLLE
+  int de;           // dual energy: a sixth field, the entropy s = p / rho^(gamma-1)
+  double xi;        // dual energy: E is taken from s where E_th < xi E_kin
   // cells of reconstruction reach on each side of a cell along an axis
   __host__ __device__ int radius() const { return first_order ? 0 : (ppm ? 2 : 1); }
 };
@@ -88,6 +90,24 @@ __device__ __forceinline__ void ext_slopes(const T Wm[5], const T Wc[5], const T
   s[4] = (c * c) * (a[0] + a[4]);
 }
 
+// PPM interface values of one variable from cells -1, 0, +1 and their
+// limited slopes, then the monotonicity constraints.
+template <typename T>
+__device__ __forceinline__ void ppm_scalar(T qm, T q0, T qp, T sm, T s0, T sp, T& qL, T& qR) {
+  const T sixth = T(1) / T(6);
+  qL = T(0.5) * (qm + q0) - (s0 - sm) * sixth;
+  qR = T(0.5) * (q0 + qp) - (sp - s0) * sixth;
+  if (!((qR - q0) * (q0 - qL) > T(0))) {
+    qL = q0;
+    qR = q0;
+  } else {
+    const T dq = qR - qL;
+    const T q6 = T(6) * (q0 - T(0.5) * (qL + qR));
+    if (dq * q6 > dq * dq) qL = T(3) * q0 - T(2) * qR;
+    else if (-(dq * dq) > dq * q6) qR = T(3) * q0 - T(2) * qL;
+  }
+}
+
 // Face values (low Wf[0], high Wf[1]) of the cell W[2] along axis D from the
 // stencil W[0..4] = cells -2..+2 (PLM reads W[1..3]).  PPM (Colella &
 // Woodward 1984): qL = (q-1 + q0)/2 - (s0 - s-1)/6, qR = (q0 + q+1)/2 -
@@ -116,24 +136,27 @@ __device__ __forceinline__ void ext_face_values(const T W[5][5], const Gas<T>& g
   ext_slopes<D>(W[0], W[1], W[2], g, o, sm);
   ext_slopes<D>(W[1], W[2], W[3], g, o, s0);
   ext_slopes<D>(W[2], W[3], W[4], g, o, sp);
-  const T sixth = T(1) / T(6);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    const T q0 = W[2][q];
-    T qL = T(0.5) * (W[1][q] + q0) - (s0[q] - sm[q]) * sixth;
-    T qR = T(0.5) * (q0 + W[3][q]) - (sp[q] - s0[q]) * sixth;
-    if (!((qR - q0) * (q0 - qL) > T(0))) {
-      qL = q0;
-      qR = q0;
-    } else {
-      const T dq = qR - qL;
-      const T q6 = T(6) * (q0 - T(0.5) * (qL + qR));
-      if (dq * q6 > dq * dq) qL = T(3) * q0 - T(2) * qR;
-      else if (-(dq * dq) > dq * q6) qR = T(3) * q0 - T(2) * qL;
-    }
-    Wf[0][q] = qL;
-    Wf[1][q] = qR;
+  for (int q = 0; q < 5; ++q) ppm_scalar(W[1][q], W[2][q], W[3][q], sm[q], s0[q], sp[q], Wf[0][q], Wf[1][q]);
+}
+
+// Face values of a passively advected scalar from its stencil q[0..4]
+// (cells -2..+2): limited like a primitive variable (no characteristic
+// projection: it is a wave of its own), PLM or PPM.
+template <typename T>
+__device__ __forceinline__ void passive_face_values(const T q[5], const Gas<T>& g, const ExtOpts& o, T out[2]) {
+  if (o.first_order) {
+    out[0] = out[1] = q[2];
+    return;
   }
+  auto slope = [&](int j) { return ext_limit(q[j] - q[j - 1], q[j + 1] - q[j], T(0.5) * (q[j + 1] - q[j - 1]), g.theta, o.lim); };
+  if (!o.ppm) {
+    const T sl = slope(2);
+    out[0] = q[2] - T(0.5) * sl;
+    out[1] = q[2] + T(0.5) * sl;
+    return;
+  }
+  ppm_scalar(q[1], q[2], q[3], slope(1), slope(2), slope(3), out[0], out[1]);
 }
 
 // Conserved form and physical flux along D of a primitive face state.
@@ -292,6 +315,16 @@ __device__ __forceinline__ bool riemann_any(const T UL[5], const T UR[5], const 
   if (o.solver == 1) return roe_flux<D>(UL, UR, g, o.ws, F);
   if (o.solver == 2) return hlle_flux<D>(UL, UR, g, o.ws, F);
   return hllc_flux<D>(UL, UR, g, o.ws, F);
+}
+
+// The Riemann flux of the Euler fields plus, with NF = 6, the flux of the
+// passive entropy field: the mass flux times s/rho of the upwind side.
+template <int D, int NF, typename T>
+__device__ __forceinline__ bool riemann_nf(const T UL[NF], const T UR[NF], const Gas<T>& g, const ExtOpts& o,
+                                           T F[NF]) {
+  const bool bad = riemann_any<D>(UL, UR, g, o, F);
+  if constexpr (NF == 6) F[5] = F[0] * (F[0] >= T(0) ? Fp<T>::div(UL[5], UL[0]) : Fp<T>::div(UR[5], UR[0]));
+  return bad;
 }
 
 }  // namespace gh

@@ -108,9 +108,10 @@ hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost,
 // elements of T for G groups of ghost width `ghost`, and the step.
 struct ExtOpts;
 int64_t ext_workspace_elems(int64_t n_groups, int ghost, const ExtOpts& o);
+// face_flux (optional): [G][9][5][256] fluxes on the patch-boundary faces.
 template <typename T>
 hipError_t launch_ext_step(const T* U_pad, T* U_out, int64_t G, int ghost, const Gas<T>& gas, const double* dt_dev,
-                           double dx, const ExtOpts& o, int* n_bad, T* work, hipStream_t stream);
+                           double dx, const ExtOpts& o, int* n_bad, T* work, T* face_flux, hipStream_t stream);
 
 // Steps (ii)-(iii) of the procedure for unphysical results on a level
 // (fallback.hip); counts[3] device int32, added to: repaired unsplit,
@@ -119,6 +120,26 @@ template <typename T>
 hipError_t launch_repair(const T* level_in, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
                          const double* dt_dev, double dx, const ExtOpts& o, int* counts, hipStream_t stream);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t stream);
+
+// Coarse-fine coupling (amr.hip).  A level: group positions [G][3] and the
+// dense map of its group lattice (n[2] x n[1] x n[0] entries, -1 if absent).
+struct AmrLevelArgs {
+  const int* pos;
+  const int* map;
+  int64_t G;
+  int n[3];
+};
+template <typename T>
+hipError_t launch_amr_fill(const T* Uf, const AmrLevelArgs& F, const T* Cold, const T* Cnew, const AmrLevelArgs& C,
+                           double a, const int bc[6], int ghost, T* pad, hipStream_t stream);
+template <typename T>
+hipError_t launch_amr_accumulate(const AmrLevelArgs& F, const T* face_flux, double w, const int bc[6], T* R,
+                                 hipStream_t stream);
+template <typename T>
+hipError_t launch_amr_restrict(const T* Uf, const AmrLevelArgs& F, T* Uc, const AmrLevelArgs& C, hipStream_t stream);
+template <typename T>
+hipError_t launch_amr_fixup(T* Uc, const AmrLevelArgs& C, const AmrLevelArgs& F, const T* cflux, const T* R,
+                            double dtdx, const int bc[6], hipStream_t stream);
 
 template <typename T>
 hipError_t launch_fill_ghosts(const T* level, T* U_pad, int ngx, int ngy, int ngz, int ghost, const int bc[6],

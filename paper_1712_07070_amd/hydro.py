@@ -35,6 +35,7 @@ LIMITER_GMINMOD, LIMITER_VANLEER, LIMITER_VANALBADA, LIMITER_HYBRID = 0 << 11, 1
 CHARACTERISTIC = 1 << 13
 PPM = 1 << 14
 RIEMANN_HLLC, RIEMANN_ROE, RIEMANN_HLLE = 0 << 16, 1 << 16, 2 << 16
+DUAL_ENERGY = 1 << 18
 BATCH_WORK_WORDS = 16       # uint32 words of the batched kernel's work buffer
 BATCHED_VARIANTS = 12       # launch shapes of the batched kernel
 
@@ -46,6 +47,12 @@ class HydroLevel(ctypes.Structure):
     _fields_ = [("level_dev", ctypes.c_void_p), ("level_out_dev", ctypes.c_void_p), ("ngx", ctypes.c_int32),
                 ("ngy", ctypes.c_int32), ("ngz", ctypes.c_int32), ("bc", ctypes.c_int32 * 6), ("dt", ctypes.c_double),
                 ("dx", ctypes.c_double), ("dt_dev", ctypes.c_void_p)]
+
+
+class HydroAmrLevel(ctypes.Structure):
+    """hydro_amr_level_t of include/hydro.h."""
+    _fields_ = [("U_dev", ctypes.c_void_p), ("pos_dev", ctypes.c_void_p), ("map_dev", ctypes.c_void_p),
+                ("n_groups", ctypes.c_int64), ("n", ctypes.c_int32 * 3)]
 
 
 class HydroError(RuntimeError):
@@ -76,11 +83,15 @@ def load():
         "hydro_check_unphysical": (i32, [P, P, P]),
         "hydro_advance": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P, P]),
         "hydro_ext_workspace_bytes": (i64, [i64, i32, i32, i32]),
-        "hydro_advance_ext": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P, P, i64, P]),
+        "hydro_advance_ext": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, f64, P, P, P, i64, P, P]),
         "hydro_repair_unphysical": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, P, P, P]),
         "hydro_fallback_workspace_bytes": (i64, [i32, i32, i32, i32, i32]),
         "hydro_advance_level_fallback": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, f64, f64, i32, f64,
                                                P, i64, P, P]),
+        "hydro_amr_fill_ghosts": (i32, [P, P, P, P, f64, P, i32, i32, P, P]),
+        "hydro_amr_flux_accumulate": (i32, [P, P, f64, P, i32, P, P]),
+        "hydro_amr_restrict": (i32, [P, P, i32, P]),
+        "hydro_amr_fixup": (i32, [P, P, P, P, f64, P, i32, P]),
         "hydro_advance_level": (i32, [P, P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, f64, P, P, f64, P, P, P,
                                       P]),
         "hydro_dt": (i32, [P, i64, i32, i32, f64, f64, f64, P, P, P]),
@@ -253,26 +264,37 @@ def ext_workspace(n_groups: int, ghost: int, dtype, scheme: int, device="cuda") 
 
 def advance_ext(U_pad: torch.Tensor, dt: float, dx: float, gamma: float, scheme: int, theta: float = 1.5,
                 out: Optional[torch.Tensor] = None, n_bad: Optional[torch.Tensor] = None,
-                dt_dev: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None) -> torch.Tensor:
+                dt_dev: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None,
+                face_flux: Optional[torch.Tensor] = None, xi: float = 0.01) -> torch.Tensor:
     """One step of any scheme word (MHM / CTU, PLM / PPM, primitive /
     characteristic, any limiter, HLLC / Roe / HLLE): U_pad[G,5,P,P,P] ->
     U_out[G,5,16,16,16] (hydro_advance_ext).  work: uint8 device tensor of at
     least hydro_ext_workspace_bytes(1, ...) bytes (default: enough for all
-    groups at once)."""
-    gh = ghost_of(U_pad)
+    groups at once).  face_flux: optional [G,9,5,16,16] output, the fluxes
+    on the patch-boundary faces (flux registers of coarse-fine coupling).
+    With DUAL_ENERGY the arrays have 6 fields (field 5 the entropy s = p /
+    rho^(gamma-1)) and xi is the dual-energy threshold."""
     G = U_pad.shape[0]
+    nf = 6 if scheme & DUAL_ENERGY else 5
+    if U_pad.dim() != 5 or U_pad.shape[1] != nf or U_pad.shape[2] != U_pad.shape[3] or \
+            U_pad.shape[3] != U_pad.shape[4] or (U_pad.shape[2] - 16) % 2:
+        raise ValueError("U_pad must be [G,%d,P,P,P]" % nf)
+    gh = (U_pad.shape[2] - 16) // 2
     if out is None:
-        out = torch.empty((G, 5, 16, 16, 16), dtype=U_pad.dtype, device=U_pad.device)
-    if out.dtype != U_pad.dtype or tuple(out.shape) != (G, 5, 16, 16, 16):
-        raise ValueError("out must be [G,5,16,16,16] of the input dtype")
+        out = torch.empty((G, nf, 16, 16, 16), dtype=U_pad.dtype, device=U_pad.device)
+    if out.dtype != U_pad.dtype or tuple(out.shape) != (G, nf, 16, 16, 16):
+        raise ValueError("out must be [G,%d,16,16,16] of the input dtype" % nf)
     if work is None:
         work = ext_workspace(G, gh, U_pad.dtype, scheme, U_pad.device)
     if work.dtype != torch.uint8:
         raise ValueError("work must be a uint8 tensor")
+    if face_flux is not None and (face_flux.dtype != U_pad.dtype or tuple(face_flux.shape) != (G, 9, 5, 16, 16)):
+        raise ValueError("face_flux must be [G,9,5,16,16] of the input dtype")
     st = load().hydro_advance_ext(_dev(U_pad, "U_pad"), _dev(out, "out"), G, gh, _dtype_code(U_pad), float(dt),
-                                  float(dx), float(gamma), int(scheme), float(theta),
+                                  float(dx), float(gamma), int(scheme), float(theta), float(xi),
                                   _opt(dt_dev, "dt_dev", torch.float64), _opt(n_bad, "n_bad", torch.int32),
-                                  _dev(work, "work"), work.numel(), _stream())
+                                  _dev(work, "work"), work.numel(),
+                                  None if face_flux is None else _dev(face_flux, "face_flux"), _stream())
     _check(st, "hydro_advance_ext")
     return out
 
@@ -910,3 +932,118 @@ class Rollout(torch.autograd.Function):
                 advance_level_adjoint(states[n - n0], g, ng, bc, dt, dx, gamma, theta, scheme, out=gin, work=work)
                 g, gin = gin, g
         return (g,) + (None,) * 9
+
+
+
+# ------------------------------------------------------ coarse-fine coupling --
+
+class AmrSolver:
+    """Coarse steps of a nested AMR hierarchy on the device (Sec. 2.1 W-cycle:
+    level l takes two steps of dt_l / 2 ... down the hierarchy, 2^l steps per
+    coarse step; Sec. 2.2 restriction and flux fix-up; Sec. 3.2 ghost zones
+    from siblings or interpolated from the coarse level).  Every operation is
+    one of the library's kernels: hydro_amr_fill_ghosts, hydro_advance_ext
+    (with its patch-boundary face fluxes), hydro_amr_flux_accumulate,
+    hydro_amr_restrict and hydro_amr_fixup.
+
+    positions[l]: int [G_l, 3] group positions on level l's lattice (n0 * 2^l
+    per axis); states[l]: [G_l, 5, 16, 16, 16] device tensors (advanced in
+    place).  Level 0 must cover the domain; each finer level must be properly
+    nested (the 27 coarse patches around each fine group's parent exist)."""
+
+    def __init__(self, n0, positions, states, dx0: float, gamma: float, bc=(0,) * 6,
+                 scheme: int = SCHEME_MHM_PLM_HLLC, theta: float = 1.5, ghost: int = 3):
+        import numpy as np
+        self.n0 = tuple(int(v) for v in n0)
+        self.nl = len(positions)
+        self.dx0, self.gamma, self.bc = float(dx0), float(gamma), tuple(int(v) for v in bc)
+        self.scheme, self.theta, self.ghost = int(scheme), float(theta), int(ghost)
+        self.U = list(states)
+        dtype, device = self.U[0].dtype, self.U[0].device
+        self.maps, self.pos, self.pad, self.work, self.flux, self.old, self.reg = [], [], [], [], [], [], []
+        maps_np = []
+        for l, p in enumerate(positions):
+            p = np.ascontiguousarray(p, np.int32).reshape(-1, 3)
+            n = [v << l for v in self.n0]
+            m = np.full((n[2], n[1], n[0]), -1, np.int32)
+            if np.any(p < 0) or np.any(p >= np.array(n)):
+                raise ValueError("level %d: a position is off the lattice" % l)
+            m[p[:, 2], p[:, 1], p[:, 0]] = np.arange(len(p), dtype=np.int32)
+            if int((m >= 0).sum()) != len(p):
+                raise ValueError("level %d: repeated positions" % l)
+            if l == 0 and len(p) != n[0] * n[1] * n[2]:
+                raise ValueError("level 0 must cover the domain")
+            if l > 0:
+                self._check_nested(p, maps_np[l - 1], [v << (l - 1) for v in self.n0])
+            maps_np.append(m)
+            G = len(p)
+            if tuple(self.U[l].shape) != (G, 5, 16, 16, 16) or self.U[l].dtype != dtype:
+                raise ValueError("level %d: states must be [G,5,16,16,16] of one dtype" % l)
+            self.pos.append(torch.from_numpy(p).to(device))
+            self.maps.append(torch.from_numpy(m).to(device))
+            P = 16 + 2 * self.ghost
+            self.pad.append(torch.empty((G, 5, P, P, P), dtype=dtype, device=device))
+            self.work.append(ext_workspace(G, self.ghost, dtype, self.scheme, device))
+            self.flux.append(torch.empty((G, 9, 5, 16, 16), dtype=dtype, device=device))
+            self.old.append(torch.empty_like(self.U[l]) if l + 1 < self.nl else None)
+            self.reg.append(torch.zeros((G, 6, 5, 8, 8), dtype=dtype, device=device) if l > 0 else None)
+        self.n_bad = torch.zeros(1, dtype=torch.int32, device=device)
+        self._bcarr = (ctypes.c_int32 * 6)(*self.bc)
+
+    @staticmethod
+    def _check_nested(p, cmap, nc):
+        np_ = [2 * v for v in nc]
+        for gx, gy, gz in p:
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        q = [(gx + dx) % np_[0], (gy + dy) % np_[1], (gz + dz) % np_[2]]
+                        if cmap[q[2] >> 1, q[1] >> 1, q[0] >> 1] < 0:
+                            raise ValueError("a fine group at %s is not properly nested" % ((gx, gy, gz),))
+
+    def _lvl(self, l: int, U=None) -> HydroAmrLevel:
+        L = HydroAmrLevel()
+        L.U_dev = _dev(self.U[l] if U is None else U, "states")
+        L.pos_dev = self.pos[l].data_ptr()
+        L.map_dev = self.maps[l].data_ptr()
+        L.n_groups = self.pos[l].shape[0]
+        for d in range(3):
+            L.n[d] = self.n0[d] << l
+        return L
+
+    def cells_per_coarse_step(self) -> int:
+        return sum(int(self.pos[l].shape[0]) * 4096 * 2 ** l for l in range(self.nl))
+
+    def step(self, dt0: float) -> None:
+        """One coarse step of dt0 (asynchronous on the current stream)."""
+        self._advance(0, float(dt0), None, None, 0.0, None)
+
+    def _advance(self, l, dt, cold, cnew, a, R_parent):
+        lib, s = load(), _stream()
+        code = _dtype_code(self.U[l])
+        dx = self.dx0 / 2 ** l
+        if l + 1 < self.nl:
+            self.old[l].copy_(self.U[l])
+        fine = self._lvl(l)
+        coarse = self._lvl(l - 1) if l > 0 else None
+        st = lib.hydro_amr_fill_ghosts(ctypes.byref(fine), None if coarse is None else ctypes.byref(coarse),
+                                       None if cold is None else _dev(cold, "cold"),
+                                       None if cnew is None else _dev(cnew, "cnew"), float(a), self._bcarr,
+                                       self.ghost, code, _dev(self.pad[l], "pad"), s)
+        _check(st, "hydro_amr_fill_ghosts")
+        advance_ext(self.pad[l], dt, dx, self.gamma, self.scheme, self.theta, out=self.U[l], n_bad=self.n_bad,
+                    work=self.work[l], face_flux=self.flux[l])
+        if R_parent is not None:
+            st = lib.hydro_amr_flux_accumulate(ctypes.byref(fine), _dev(self.flux[l], "flux"), 0.5, self._bcarr, code,
+                                               _dev(R_parent, "reg"), s)
+            _check(st, "hydro_amr_flux_accumulate")
+        if l + 1 < self.nl:
+            R = self.reg[l + 1]
+            R.zero_()
+            self._advance(l + 1, 0.5 * dt, self.old[l], self.U[l], 0.0, R)
+            self._advance(l + 1, 0.5 * dt, self.old[l], self.U[l], 0.5, R)
+            child = self._lvl(l + 1)
+            _check(lib.hydro_amr_restrict(ctypes.byref(child), ctypes.byref(fine), code, s), "hydro_amr_restrict")
+            st = lib.hydro_amr_fixup(ctypes.byref(fine), ctypes.byref(child), _dev(self.flux[l], "flux"),
+                                     _dev(R, "reg"), dt / dx, self._bcarr, code, s)
+            _check(st, "hydro_amr_fixup")

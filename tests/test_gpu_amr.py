@@ -1,0 +1,95 @@
+"""GPU parity of the coarse-fine coupling (hydro_amr_* with hydro_advance_ext
+in the W-cycle of AmrSolver) against the oracle's coarse step of the same
+hierarchy: every level of every group within the parity bar (1e-12 FP64,
+field-scaled and rho / E per cell; 1e-5 FP32 from the FP32-rounded state),
+for a small three-level hierarchy over two coarse steps with several scheme
+words, and for the coupled blast workload (512 / 1536 / 3072 groups)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_07070_amd import workloads as W
+from tests.oracle_runs import assert_parity
+from tests.test_oracle_amr import SMALL3
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1712_07070_amd import hydro as h
+    h.load()
+    return h
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flowing_blast(n0=2, boxes=SMALL3):
+    h = W.sedov_hierarchy(n0=n0, boxes=boxes)
+    for l in range(h.n_levels):
+        X, Y, Z = W._level_cells(h.positions[l], h.dx0 / 2 ** l)
+        h.states[l][:, 1] += 0.3 * np.sin(2 * np.pi * Y)
+        h.states[l][:, 2] += 0.2 * np.cos(2 * np.pi * Z)
+        h.states[l][:, 3] += 0.1 * np.sin(2 * np.pi * X)
+        h.states[l][:, 4] += 0.5
+    W.restrict_states(h)
+    return h
+
+
+SCHEMES = {"mhm": oracle.SCHEME_MHM, "ctu-roe-ppm": oracle.SCHEME_CTU | oracle.RIEMANN_ROE | oracle.PPM,
+           "mhm-hlle-vanleer": oracle.SCHEME_MHM | oracle.RIEMANN_HLLE | oracle.LIMITER_VANLEER,
+           "mhm-char-hybrid": oracle.SCHEME_MHM | oracle.CHARACTERISTIC | oracle.LIMITER_HYBRID}
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("name", list(SCHEMES))
+def test_amr_coarse_steps_match_oracle(hydro, name, dtype):
+    say("amr", name, dtype.__name__)
+    sch = SCHEMES[name]
+    h = flowing_blast()
+    states = [s.astype(dtype).astype(np.float64) for s in h.states]
+    dev = [torch.from_numpy(np.ascontiguousarray(s.astype(dtype))).cuda() for s in states]
+    solver = hydro.AmrSolver(h.n0, h.positions, dev, h.dx0, h.gamma, h.bc, scheme=sch)
+    ref = states
+    for _ in range(2):
+        ref, nb = oracle.amr_step(h.n0, h.positions, ref, h.bc, 2e-4, h.dx0, h.gamma, scheme=sch)
+        solver.step(2e-4)
+    torch.cuda.synchronize()
+    assert nb == 0 and int(solver.n_bad.cpu()[0]) == 0
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    for l in range(h.n_levels):
+        assert_parity(dev[l].cpu().numpy(), ref[l], tol, "%s level %d" % (name, l))
+
+
+def test_amr_blast_workload_full(hydro):
+    """The coupled blast workload (8^3 level-0 groups, 1536 level-1 and 3072
+    level-2 groups), one coarse step, every cell of every level."""
+    say("amr blast workload")
+    h = W.sedov_hierarchy()
+    assert [len(p) for p in h.positions] == [512, 1536, 3072]
+    dev = [torch.from_numpy(np.ascontiguousarray(s)).cuda() for s in h.states]
+    solver = hydro.AmrSolver(h.n0, h.positions, dev, h.dx0, h.gamma, h.bc)
+    dt0 = 1.25e-6
+    solver.step(dt0)
+    ref, nb = oracle.amr_step(h.n0, h.positions, h.states, h.bc, dt0, h.dx0, h.gamma)
+    torch.cuda.synchronize()
+    assert nb == 0
+    for l in range(h.n_levels):
+        assert_parity(dev[l].cpu().numpy(), ref[l], 1e-12, "level %d" % l)
+
+
+def test_amr_rejects_unnested_level(hydro):
+    h = W.sedov_hierarchy(n0=2, boxes=SMALL3)
+    pos = [h.positions[0], h.positions[1], np.array([[2, 2, 2]], np.int32)]  # level-1 patch 2 has no buffer
+    dev = [torch.from_numpy(np.ascontiguousarray(s)).cuda() for s in h.states[:2]]
+    dev.append(torch.zeros((1, 5, 16, 16, 16), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        hydro.AmrSolver(h.n0, pos, dev, h.dx0, h.gamma)

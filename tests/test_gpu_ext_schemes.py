@@ -178,3 +178,27 @@ def test_ext_shear_layer_256_sampled(hydro, name, dtype):
     ref, nb = oracle.step_any(p, dt, lv.dx, lv.gamma, 1.5, sch)
     assert_parity(host(got[torch.from_numpy(gs).cuda()]), ref, TOL[dtype], name)
     assert nb == 0
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("name", ["mhm-plm-gminmod-hllc", "ppm-char-hybrid", "ctu-roe"])
+@pytest.mark.parametrize("xi", [0.01, 1e300])
+def test_ext_dual_energy_matches_oracle(hydro, name, dtype, xi):
+    """Dual energy (6 fields, field 5 the entropy s = p / rho^(gamma-1)):
+    xi = 0.01 (the paper's typical threshold) and xi = inf (E always from s);
+    the entropy field within tol of its largest value."""
+    from tests.test_oracle_dual_energy import with_entropy
+    say("ext dual energy", name, dtype.__name__, xi)
+    sch = SCHEMES[name] | oracle.DUAL_ENERGY
+    lv = W.white_noise(32)
+    U6 = with_entropy(lv.U).astype(dtype).astype(np.float64)
+    pad5 = oracle.fill_ghosts(U6[:, :5], lv.ng, 3, lv.bc)
+    pads = oracle.fill_ghosts(np.repeat(U6[:, 5:], 5, axis=1), lv.ng, 3, lv.bc)[:, :1]
+    pad = np.concatenate([pad5, pads], axis=1)
+    dt = cfl_dt(U6[:, :5], lv.ng, lv.bc, lv.dx, lv.gamma)
+    ref, nb = oracle.step_any_de(pad, dt, lv.dx, lv.gamma, 1.5, sch, xi)
+    n_bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got = host(hydro.advance_ext(dev(pad, dtype), dt, lv.dx, lv.gamma, sch, n_bad=n_bad, xi=xi)).astype(np.float64)
+    assert_parity(got[:, :5], ref[:, :5], TOL[dtype], name)
+    assert np.abs(got[:, 5] - ref[:, 5]).max() <= TOL[dtype] * np.abs(ref[:, 5]).max(), name
+    assert int(host(n_bad)[0]) == nb == 0
