@@ -268,7 +268,7 @@ def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171
 
     g = grad.cpu().numpy()
     acc, rejected, draws = [], 0, 0
-    while len(errs) < samples and draws < max_draws:
+    while len(acc) < samples and draws < max_draws:
         draws += 1
         idx = tuple(int(rng.integers(0, s)) for s in U0.shape)
         up, um = U0.copy(), U0.copy()

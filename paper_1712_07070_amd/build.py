@@ -1,17 +1,21 @@
-"""Compile libhydro.so (HIP, gfx950) in-tree with hipcc."""
+"""Compile libhydro.so (HIP, gfx950) in-tree with hipcc: every source to an
+object in parallel, then one link."""
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhydro.so")
-SOURCES = ["capi.hip", "mhm_fwd.hip", "mhm_batched.hip", "mhm_adj.hip", "aux_kernels.hip", "scheme_ext.hip", "fallback.hip", "amr.hip"]
+OBJ = os.path.join(ROOT, "_build")
+SOURCES = ["capi.hip", "mhm_fwd.hip", "mhm_batched.hip", "mhm_adj.hip", "aux_kernels.hip", "scheme_ext.hip",
+           "fallback.hip", "amr.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # one rounding per source expression, identical at every inlined site
     "-ffp-contract=on",
     # keep the compiler from forming packed FP32 (v_pk_*_f32) instructions
@@ -20,15 +24,31 @@ HIPCC_FLAGS = [
 ]
 
 
-def build_library(extra_flags=(), verbose=False) -> str:
+def build_library(extra_flags=(), verbose=False, jobs=None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, *HIPCC_FLAGS, *extra_flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.makedirs(OBJ, exist_ok=True)
+    tag = "%d" % os.getpid()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+    def compile_one(src):
+        obj = os.path.join(OBJ, src.replace(".hip", ".%s.o" % tag))
+        cmd = [hipcc, *HIPCC_FLAGS, *extra_flags, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    tmp = LIB + ".tmp" + tag
+    try:
+        subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], check=True)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

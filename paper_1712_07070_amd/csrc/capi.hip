@@ -954,8 +954,9 @@ int hydro_set_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant) {
 
 int hydro_variant_name(int32_t variant, char* buf, int32_t len) {
   if (variant < 0 || variant >= gh::kLevelVariants || buf == nullptr || len < 1) return HYDRO_EINVAL;
-  std::snprintf(buf, size_t(len), "%s order, %s occupancy target", (variant & 1) ? "plain" : "xcd-blocked",
-                (variant & 2) ? "low" : "high");
+  std::snprintf(buf, size_t(len), "%s %s order, %s occupancy target, %s LDS rows",
+                (variant & 1) ? "plain" : "xcd-blocked", (variant & 4) ? "brick" : "linear",
+                (variant & 2) ? "low" : "high", (variant & 8) ? "padded" : "packed");
   return HYDRO_OK;
 }
 

@@ -76,10 +76,16 @@ __device__ __forceinline__ void load_prim(const Src& src, typename Src::Off col,
   cons_to_prim(U, g, W);
 }
 
-template <typename T>
+// LDS of one group's march.  kL pads the rows of the primitive and state
+// tiles by kL elements (an LDS-layout option of the launch shapes: the same
+// values at other addresses, so results are bit-identical).
+template <typename T, int kL = 0>
 struct Smem {
-  T P[5][kPW * kPW];     // primitive plane k
-  T S[2][5][kSW * kSW];  // x+ and y+ half-step states of plane k
+  static constexpr int PW = kPW + kL, SW = kSW + kL;
+  static __device__ __forceinline__ int pi(int x, int y) { return (y + 2) * PW + (x + 2); }
+  static __device__ __forceinline__ int si(int x, int y) { return (y + 1) * SW + (x + 1); }
+  T P[5][PW * PW];       // primitive plane k
+  T S[2][5][SW * SW];    // x+ and y+ half-step states of plane k
   T F[2][5][17 * 16];    // x and y fluxes of plane k
   T H[5][32];            // high-side states of the last faces: x = 16 (slot y), y = 16 (slot 16 + x)
 };
@@ -121,9 +127,9 @@ __device__ __forceinline__ void fwd_col_init(FwdCol<T, kI, typename Src::Off>& c
 }
 
 // Next plane of the column (prefetched one iteration ahead); publish plane k.
-template <typename T, bool kI, class Src>
+template <typename T, bool kI, class Src, int kL>
 __device__ __forceinline__ void fwd_col_publish(FwdCol<T, kI, typename Src::Off>& c, const Src& src, int k, const Gas<T>& gas,
-                                                Smem<T>& sm) {
+                                                Smem<T, kL>& sm) {
   // Convert the plane that arrived, then issue the next one.  The load is
   // unconditional (plane index clamped to the column's last plane, re-read
   // harmlessly near the top) and issued after the conversion, so the loaded
@@ -133,7 +139,7 @@ __device__ __forceinline__ void fwd_col_publish(FwdCol<T, kI, typename Src::Off>
   asm volatile("" ::: "memory");
   load_cons(src, c.col, k + 2 <= c.zhi ? k + 2 : c.zhi, c.Un);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) sm.P[q][pidx(c.cx, c.cy)] = c.Wc[q];
+  for (int q = 0; q < 5; ++q) sm.P[q][sm.pi(c.cx, c.cy)] = c.Wc[q];
 }
 
 // CFL signal-speed maxima of a group live in LDS as [z half][patch xy][64
@@ -149,9 +155,9 @@ __device__ __forceinline__ int cfl_slot(int tid) {
 
 // Half-step face states of the column's state cell at plane k.  Interior
 // columns also solve the z-face k-1/2 and complete plane k-1.
-template <typename T, bool kI, class Src>
+template <typename T, bool kI, class Src, int kL>
 __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& c, const Src& src, T* __restrict__ out, int k,
-                                              const Gas<T>& gas, int first_order, int ws, Smem<T>& sm, double* smax,
+                                              const Gas<T>& gas, int first_order, int ws, Smem<T, kL>& sm, double* smax,
                                               double gamma_d) {
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
@@ -168,10 +174,10 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
   T Wn[3][2][5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    Wn[0][0][q] = sm.P[q][pidx(cx - 1, cy)];
-    Wn[0][1][q] = sm.P[q][pidx(cx + 1, cy)];
-    Wn[1][0][q] = sm.P[q][pidx(cx, cy - 1)];
-    Wn[1][1][q] = sm.P[q][pidx(cx, cy + 1)];
+    Wn[0][0][q] = sm.P[q][sm.pi(cx - 1, cy)];
+    Wn[0][1][q] = sm.P[q][sm.pi(cx + 1, cy)];
+    Wn[1][0][q] = sm.P[q][sm.pi(cx, cy - 1)];
+    Wn[1][1][q] = sm.P[q][sm.pi(cx, cy + 1)];
     Wn[2][0][q] = c.Wm[q];
     Wn[2][1][q] = c.Wp[q];
   }
@@ -179,8 +185,8 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
   hancock_states(c.Wc, Wn, gas, first_order != 0, Ut);
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    sm.S[0][q][sidx(cx, cy)] = Ut[0][1][q];
-    sm.S[1][q][sidx(cx, cy)] = Ut[1][1][q];
+    sm.S[0][q][sm.si(cx, cy)] = Ut[0][1][q];
+    sm.S[1][q][sm.si(cx, cy)] = Ut[1][1][q];
     if (kI) {
       c.Ux[q] = Ut[0][0][q];
       c.Uy[q] = Ut[1][0][q];
@@ -227,15 +233,15 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
 
 // x and y faces of plane k that an interior column solves: its low x and low
 // y face.
-template <typename T, bool kI, typename Off>
-__device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const Gas<T>& gas, int ws, Smem<T>& sm) {
+template <typename T, bool kI, typename Off, int kL>
+__device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm) {
   if (!kI || k < 0 || k > 15) return 0;
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
   {
     T L[5], F[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sidx(cx - 1, cy)];
+    for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sm.si(cx - 1, cy)];
     bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
@@ -243,7 +249,7 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
   {
     T L[5], F[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sidx(cx, cy - 1)];
+    for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sm.si(cx, cy - 1)];
     bad += hllc_flux<1>(L, c.Uy, gas, ws, F);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
@@ -257,16 +263,16 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
 // m_y, m_z), the same arithmetic on the same values as the y-normal solver,
 // and the flux rotated back.  The halo wave wrote the high-side states to
 // H; this pass runs on another wave, which has no halo work.
-template <typename T>
-__device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, int ws, Smem<T>& sm) {
+template <typename T, int kL>
+__device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm) {
   if (k < 0 || k > 15 || lane >= 32) return 0;
   const bool yf = lane >= 16;
   const int i = lane & 15;
-  const T* Sb = yf ? &sm.S[1][0][sidx(i, 15)] : &sm.S[0][0][sidx(15, i)];
+  const T* Sb = yf ? &sm.S[1][0][sm.si(i, 15)] : &sm.S[0][0][sm.si(15, i)];
   T L[5], R[5], Lr[5], Rr[5], F[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    L[q] = Sb[q * kSW * kSW];
+    L[q] = Sb[q * sm.SW * sm.SW];
     R[q] = sm.H[q][lane];
   }
   Lr[0] = L[0];
@@ -304,9 +310,9 @@ enum WaveRole { kRoleHalo = 0, kRoleLastFaces = 1, kRolePlain = 2 };
 // The z-march of one wave: interior role, plus the halo roles (kRoleHalo,
 // wave 0) or the solve of the 32 last faces (kRoleLastFaces, wave 2).  Every
 // instantiation passes the same barriers in the same order.
-template <typename T, class Src, int kRole>
+template <typename T, class Src, int kRole, int kL>
 __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, const Gas<T>& gas, int first_order,
-                                           int ws, Smem<T>& sm, double* smax, double gamma_d, int tid) {
+                                           int ws, Smem<T, kL>& sm, double* smax, double gamma_d, int tid) {
   // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
   // 0..3 also one of the 4 edge columns
   const int lane = tid & 63;
@@ -348,10 +354,10 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
       load_cons(src, col_edge, kn, Ue);
       if (k >= 0 && k <= 15) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) sm.P[q][pidx(ox, oy)] = Wo[q];
+        for (int q = 0; q < 5; ++q) sm.P[q][sm.pi(ox, oy)] = Wo[q];
         if (has_edge) {
 #pragma unroll
-          for (int q = 0; q < 5; ++q) sm.P[q][pidx(ex, ey)] = We[q];
+          for (int q = 0; q < 5; ++q) sm.P[q][sm.pi(ex, ey)] = We[q];
         }
       }
     }
@@ -391,9 +397,9 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 // waves per SIMD (FP32, high occupancy) the step is 6-8% faster; with two
 // (FP64, FP32 low occupancy) 2-5% slower, so those kernels keep equal
 // priorities.
-template <typename T, bool kPrio, class Src>
+template <typename T, bool kPrio, class Src, int kL>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
-                                             int first_order, int ws, Smem<T>& sm, double* smax,
+                                             int first_order, int ws, Smem<T, kL>& sm, double* smax,
                                              double gamma_d, int tid = threadIdx.x) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if constexpr (kPrio) {
