@@ -121,6 +121,9 @@ def parse():
     ap.add_argument("--fd-samples", type=int, default=64)
     ap.add_argument("--no-ext", action="store_true",
                     help="skip the other schemes, the unphysical-result procedure and the coupled AMR hierarchy")
+    ap.add_argument("--counter-sweep", type=int, default=0, metavar="REPS",
+                    help="only launch every shape of the fused level step (with the CFL epilogue), FP64 then FP32, "
+                         "REPS launches each in a fixed order, for hardware-counter runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="after the run, copy a device buffer of this size (reference for HBM byte counters)")
     return ap.parse_args()
@@ -208,6 +211,27 @@ def amr_workload(hydro, torch, W, coarse_steps):
     res.update(out)
     res["batched_over_per_level"] = out["batched_graph"]["cell_updates_per_s"] / out["per_level_graph"][
         "cell_updates_per_s"]
+    # the adaptive W-cycle: the batched launches also reduce the next coarse
+    # step's dt_0 = min_l 2^l dt_l (Eq. 2, C = 0.5) on the device; a graph of
+    # six coarse steps (the period of the buffer and time-step-word rotation)
+    ml = hydro.MultiLevel(geo, lvs[0].gamma, dt0, batched=True, adaptive=True, c_cfl=0.5)
+    for l, U in enumerate(states):
+        ml.load_state(l, U)
+    ml.autotune(reps=3)
+    g = ml.capture(6)
+    g.replay()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    res["batched_adaptive_graph"] = {"cell_updates_per_s": ml.cells_per_coarse_step() * 6 / best,
+                                     "ms_per_coarse_step": best / 6 * 1e3, "n_bad": int(ml.n_bad.cpu()[0]),
+                                     "dt0_next": float(ml.dt_coarse().cpu()[0])}
+    g.close()
     return res
 
 
@@ -573,6 +597,37 @@ def cpu_other_workloads(budget):
     return out
 
 
+def counter_sweep(hydro, torch, W, n, reps, calibrate_mib):
+    """Launch every shape of the fused level step with the CFL epilogue (the
+    bench's timed kernel) on the n^3 shear layer, FP64 then FP32, `reps`
+    launches per shape in shape order, then the calibration copy: a counter
+    run maps the kernel's dispatches to shapes by this order."""
+    lv = W.shear_layer(n)
+    order = []
+    for dtype in (torch.float64, torch.float32):
+        solver = hydro.LevelSolver(lv.ng, lv.dx, lv.gamma, lv.bc, ghost=3, dtype=dtype, fused=True)
+        U0 = torch.from_numpy(np.ascontiguousarray(lv.U.astype(np.float64 if dtype == torch.float64 else np.float32)))
+        solver.load_state(U0.cuda())
+        for v in range(hydro.num_variants()):
+            hydro.set_level_variant(dtype, True, v)
+            for _ in range(reps):
+                solver.step()
+            torch.cuda.synchronize()
+            order.append({"dtype": "f64" if dtype == torch.float64 else "f32", "variant": v, "launches": reps,
+                          "name": hydro.variant_name(v)})
+        del solver
+        torch.cuda.empty_cache()
+    if calibrate_mib > 0:
+        m = calibrate_mib * (1 << 20) // 8
+        src = torch.ones(m, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    print(json.dumps({"counter_sweep": order, "cells_per_launch": lv.n_cells,
+                      "copy_calibration_bytes": calibrate_mib * (1 << 20)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -585,6 +640,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.counter_sweep > 0:
+        counter_sweep(hydro, torch, W, args.n, args.counter_sweep, args.calibrate_copy)
+        return
     print("bench: building workload", file=sys.stderr, flush=True)
     lv = W.shear_layer(args.n)
     cells = lv.n_cells
@@ -640,6 +698,9 @@ def main():
                         "hbm_frac": b32 * r32 / 1e9 / HBM_PEAK_GBS,
                         "alu_frac": ALG_FLOPS_PER_CELL * r32 / 1e12 / FP32_VEC_PEAK_TFLOPS, "n_bad": nb32,
                         "launch_shape": tune32}
+        if fused:
+            shape32 = tune32["variant"] if tune32 else hydro.get_variant(torch.float32)
+            extra["f32"]["traffic"] = measured_traffic("mhm_level_kernel<float, true>", shape32)
     del solver
     torch.cuda.empty_cache()
     if not args.no_amr:

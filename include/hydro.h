@@ -184,7 +184,11 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
  *               hydro_ext_workspace_bytes(1, ghost, dtype, scheme); groups are
  *               processed in chunks of as many groups as it holds (all at
  *               once with hydro_ext_workspace_bytes(G, ...)); must not overlap
- *               U_pad_dev or U_out_dev
+ *               U_pad_dev or U_out_dev.  Words of MHM + PLM on primitive
+ *               variables + generalized minmod + HLLC without dual energy
+ *               (either wave-speed option, second or first order) run on the
+ *               fused per-group kernel of hydro_advance and need no workspace
+ *               (their hydro_ext_workspace_bytes is 0; work_dev may be NULL)
  *   n_bad_dev   as for hydro_advance (faces with unphysical input states plus
  *               updated cells with rho <= 0 or p <= 0)
  *   face_flux_dev  optional [G][9][5][16][16] output: the fluxes the update
@@ -413,8 +417,25 @@ int hydro_autotune_adjoint(hydro_ctx* ctx, const void* level_dev, const void* g_
 /* One level of a batched launch (hydro_advance_batched).  Pointers are
  * device memory; bc holds the x-, x+, y-, y+, z-, z+ boundary conditions;
  * dt is this level's time-step (dt_l = dt_0 / 2^l in the W-cycle of Sec. 2.1)
- * unless dt_dev is non-NULL, in which case it is read from that device double;
- * dx is this level's cell width. */
+ * unless dt_dev is non-NULL, in which case it is *dt_dev times dt_dev_scale
+ * (0 is taken as 1; a power of two keeps it exact, e.g. 2^-l with dt_dev the
+ * coarse dt_0); dx is this level's cell width.
+ * CFL outputs of the state the launch writes for this level (Sec. 2.6 Eq. 2,
+ * reduced in the same pass as in hydro_advance_level; all optional, NULL for
+ * none; c_cfl > 0 when any is given):
+ *   dt_patch_next_dev  [G_l][8] per-patch time-steps (bit-identical to
+ *                      hydro_dt on the output)
+ *   dt_next_dev        the level's minimum times dt_next_scale (0 is taken
+ *                      as 1) is folded in with an exact, order-independent
+ *                      minimum; it must hold +inf or a larger value when the
+ *                      launch starts.  Levels may share it: with dt_next_scale
+ *                      = 2^l every level folds the coarse step its state
+ *                      allows, min_l 2^l dt_l
+ *   dt_reset_dev       set to +inf at the start of the launch (before any
+ *                      other use in it), so that three words can rotate over
+ *                      coarse steps (read dt_0 from A, reduce into B, reset
+ *                      C); must differ from every level's dt_dev and
+ *                      dt_next_dev */
 typedef struct {
   const void* level_dev;  /* [G_l][5][16^3] input level storage */
   void* level_out_dev;    /* [G_l][5][16^3] output level storage */
@@ -423,6 +444,12 @@ typedef struct {
   double dt;
   double dx;
   const double* dt_dev;
+  double dt_dev_scale;
+  double c_cfl;
+  double dt_next_scale;
+  double* dt_next_dev;
+  double* dt_patch_next_dev;
+  double* dt_reset_dev;
 } hydro_level_t;
 
 /* hydro_advance_batched -- one MHM step of every group of n_levels levels in

@@ -95,6 +95,7 @@ def _load():
         "oracle_rollout_box": (i64, [P, P, P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32, P]),
         "oracle_step_any": (i64, [P, P, i64, i32, f64, f64, f64, f64, i32]),
         "oracle_step_block_any": (i64, [P, P, i32, i32, i32, i32, f64, f64, f64, f64, i32]),
+        "oracle_step_any_flux": (i64, [P, P, P, i64, i32, f64, f64, f64, f64, i32]),
         "oracle_step_any_jvp": (i64, [P, P, P, P, i64, i32, f64, f64, f64, f64, i32]),
         "oracle_riemann": (i32, [P, P, i32, f64, i32, P]),
         "oracle_step_any_de": (i64, [P, P, i64, i32, f64, f64, f64, f64, i32, f64]),
@@ -337,6 +338,22 @@ def step_any(U_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
     if n_bad < 0:
         raise ValueError("oracle_step_any: bad arguments")
     return out, int(n_bad)
+
+
+def step_any_flux(U_pad, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):
+    """step_any that also returns the fluxes the update used on the faces of
+    the patch boundaries: (U_out[G,5,16,16,16], face_flux[G,9,5,16,16],
+    n_bad); plane 3 axis + k holds the axis' faces at normal coordinate 8 k,
+    entry [field][b][a] with (a, b) the transverse coordinates in cyclic
+    order."""
+    U = _f64(U_pad)
+    G, P = U.shape[0], U.shape[2]
+    out = np.empty((G, 5, 16, 16, 16), np.float64)
+    ff = np.empty((G, 9, 5, 16, 16), np.float64)
+    n_bad = _load().oracle_step_any_flux(_p(U), _p(out), _p(ff), G, (P - 16) // 2, dt, dx, gamma, theta, scheme)
+    if n_bad < 0:
+        raise ValueError("oracle_step_any_flux: bad arguments")
+    return out, ff, int(n_bad)
 
 
 def step_block_any(U_pad, ghost, dt, dx, gamma, theta=1.5, scheme=SCHEME_MHM_PLM_HLLC):

@@ -1899,6 +1899,20 @@ int64_t oracle_step_any(const double* Upad, double* Uout, int64_t G, int ghost, 
   return n_bad;
 }
 
+// oracle_step_any that also returns the fluxes of the patch-boundary faces of
+// every group, [G][9][5][256] (step_block_any's face_flux layout).
+int64_t oracle_step_any_flux(const double* Upad, double* Uout, double* face_flux, int64_t G, int ghost, double dt,
+                             double dx, double gamma, double theta, int scheme) {
+  if (G < 0 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT)) return -1;
+  const Block b(16, 16, 16, ghost);
+  int64_t n_bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_bad)
+  for (int64_t g = 0; g < G; ++g)
+    n_bad += step_block_any(Upad + g * b.cells() * 5, Uout + g * 5 * 4096, b, dt, dx, gamma, theta, scheme,
+                            face_flux + g * 9 * 5 * 256);
+  return n_bad;
+}
+
 int64_t oracle_step_block_any(const double* Upad, double* Uout, int nx, int ny, int nz, int ghost, double dt,
                               double dx, double gamma, double theta, int scheme) {
   if (nx < 1 || ny < 1 || nz < 1 || !valid_any_scheme(scheme, ghost) || (scheme & DUAL_ENERGY_BIT)) return -1;

@@ -20,8 +20,9 @@
 #include <cstddef>
 
 // the Python binding mirrors this layout with ctypes
-static_assert(sizeof(hydro_level_t) == 80 && offsetof(hydro_level_t, dt) == 56 &&
-                  offsetof(hydro_level_t, dt_dev) == 72,
+static_assert(sizeof(hydro_level_t) == 128 && offsetof(hydro_level_t, dt) == 56 &&
+                  offsetof(hydro_level_t, dt_dev) == 72 && offsetof(hydro_level_t, dt_dev_scale) == 80 &&
+                  offsetof(hydro_level_t, dt_reset_dev) == 120,
               "hydro_level_t layout");
 
 namespace {
@@ -70,7 +71,11 @@ std::string adjoint_key(int32_t dtype, int ngx, int ngy, int ngz) {
 }
 
 std::string batched_key(int32_t dtype, const hydro_level_t* lv, int n) {
-  std::string k = std::string("batched/") + dtype_name(dtype) + "/";
+  // the kernel form with the CFL epilogue is tuned on its own
+  bool cfl = false;
+  for (int l = 0; l < n; ++l)
+    cfl = cfl || lv[l].dt_next_dev != nullptr || lv[l].dt_patch_next_dev != nullptr || lv[l].dt_reset_dev != nullptr;
+  std::string k = std::string(cfl ? "batched-cfl/" : "batched/") + dtype_name(dtype) + "/";
   for (int l = 0; l < n; ++l) {
     char b[64];
     std::snprintf(b, sizeof b, "%s%dx%dx%d", l ? "+" : "", lv[l].ngx, lv[l].ngy, lv[l].ngz);
@@ -213,6 +218,13 @@ bool valid_ext_scheme(int32_t scheme, double theta, int32_t ghost, gh::ExtOpts* 
   return std::isfinite(theta) && theta >= 1.0 && theta <= 2.0;
 }
 
+// Scheme words the fused per-group kernel computes (MHM, PLM on primitive
+// variables, generalized minmod, HLLC, any wave-speed option, second or first
+// order): hydro_advance_ext runs them there, with no workspace.
+bool fused_ext_scheme(const gh::ExtOpts& o) {
+  return !o.ctu && o.lim == 0 && !o.chr && !o.ppm && o.solver == 0 && !o.de;
+}
+
 template <typename T>
 gh::Gas<T> make_gas(double gamma, double theta, double dt, double dx) {
   gh::Gas<T> g;
@@ -231,6 +243,7 @@ int batched_impl(const hydro_level_t* lv, int32_t n_levels, double gamma, int32_
                  int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid, int variant, hipStream_t s) {
   gh::BatchArgs<T> a;
   a.n_levels = n_levels;
+  a.cfl = 0;
   long long total = 0;
   for (int l = 0; l < n_levels; ++l) {
     gh::BatchLevel<T>& b = a.lv[l];
@@ -245,11 +258,22 @@ int batched_impl(const hydro_level_t* lv, int32_t n_levels, double gamma, int32_
     b.dtdx = T(dt / lv[l].dx);
     b.half_dtdx = T(0.5 * (dt / lv[l].dx));
     b.dt_dev = lv[l].dt_dev;
+    b.dt_scale = lv[l].dt_dev_scale == 0.0 ? 1.0 : lv[l].dt_dev_scale;
     b.dx = lv[l].dx;
+    b.dt_patch = lv[l].dt_patch_next_dev;
+    b.dt_min = reinterpret_cast<unsigned long long*>(lv[l].dt_next_dev);
+    b.reset = reinterpret_cast<unsigned long long*>(lv[l].dt_reset_dev);
+    b.c_cfl_dx = lv[l].c_cfl * lv[l].dx;
+    b.fold_scale = lv[l].dt_next_scale == 0.0 ? 1.0 : lv[l].dt_next_scale;
+    a.cfl = a.cfl || b.dt_patch != nullptr || b.dt_min != nullptr || b.reset != nullptr;
     total += (long long)lv[l].ngx * lv[l].ngy * lv[l].ngz;
   }
-  for (int l = n_levels; l < gh::kMaxLevels; ++l) a.lv[l] = a.lv[0];
+  for (int l = n_levels; l < gh::kMaxLevels; ++l) {
+    a.lv[l] = a.lv[0];
+    a.lv[l].reset = nullptr;
+  }
   a.total = total;
+  a.gamma = gamma;
   if (total == 0) return HYDRO_OK;
   const int per_cu = sizeof(T) == 8 ? 2 : 4;  // workgroups that fit in one CU's LDS
   long long g = grid > 0 ? grid : (long long)device_cus() * per_cu;
@@ -289,6 +313,16 @@ int validate_levels(const hydro_level_t* lv, int32_t n_levels, int32_t dtype) {
     for (int i = 0; i < 6; ++i)
       if (L.bc[i] != HYDRO_BC_PERIODIC && L.bc[i] != HYDRO_BC_OUTFLOW) return HYDRO_EINVAL;
     if (L.level_dev == nullptr || L.level_out_dev == nullptr) return HYDRO_EINVAL;
+    if (L.dt_dev != nullptr && L.dt_dev_scale != 0.0 && !finite_pos(L.dt_dev_scale)) return HYDRO_EINVAL;
+    const bool want_cfl = L.dt_next_dev != nullptr || L.dt_patch_next_dev != nullptr || L.dt_reset_dev != nullptr;
+    if (want_cfl && !finite_pos(L.c_cfl)) return HYDRO_EINVAL;
+    if (L.dt_next_scale != 0.0 && !finite_pos(L.dt_next_scale)) return HYDRO_EINVAL;
+    for (int m = 0; m < n_levels; ++m) {
+      const hydro_level_t& M = lv[m];
+      if (L.dt_reset_dev != nullptr && (L.dt_reset_dev == M.dt_dev || L.dt_reset_dev == M.dt_next_dev))
+        return HYDRO_EINVAL;
+      if (L.dt_next_dev != nullptr && L.dt_next_dev == M.dt_dev) return HYDRO_EINVAL;
+    }
     total += (long long)L.ngx * L.ngy * L.ngz;
   }
   if (total >= (1ll << 32) - (1ll << 20)) return HYDRO_EINVAL;  // the work counter is 32-bit
@@ -585,6 +619,7 @@ int64_t hydro_ext_workspace_bytes(int64_t n_groups, int32_t ghost, int32_t dtype
   if (n_groups < 0 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32) ||
       !valid_ext_scheme(scheme, 1.5, ghost, &o))
     return HYDRO_EINVAL;
+  if (fused_ext_scheme(o)) return 0;
   return gh::ext_workspace_elems(n_groups, ghost, o) * int64_t(dtype_size(dtype));
 }
 
@@ -601,9 +636,31 @@ int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, 
   const int64_t nf = o.de ? 6 : 5;
   if (dt_dev == nullptr && !finite_pos(dt)) return HYDRO_EINVAL;
   if (n_groups == 0) return HYDRO_OK;
-  if (U_pad_dev == nullptr || U_out_dev == nullptr || work_dev == nullptr) return HYDRO_EINVAL;
   const int64_t P = 16 + 2 * ghost;
   const size_t es = dtype_size(dtype);
+  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (fused_ext_scheme(o)) {
+    // the fused per-group kernel; the workspace is not used
+    if (U_pad_dev == nullptr || U_out_dev == nullptr) return HYDRO_EINVAL;
+    const size_t pad_b = size_t(n_groups) * 5 * P * P * P * es, out_b = size_t(n_groups) * 5 * 4096 * es;
+    const size_t ff_b = size_t(n_groups) * 9 * 5 * 256 * es;
+    if (overlap(U_pad_dev, pad_b, U_out_dev, out_b) ||
+        (face_flux_dev != nullptr &&
+         (overlap(face_flux_dev, ff_b, U_pad_dev, pad_b) || overlap(face_flux_dev, ff_b, U_out_dev, out_b))))
+      return HYDRO_EINVAL;
+    hipError_t e;
+    if (dtype == HYDRO_F64)
+      e = gh::launch_mhm_fwd(static_cast<const double*>(U_pad_dev), static_cast<double*>(U_out_dev), n_groups, ghost,
+                             make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, o.first_order, o.ws, n_bad_dev,
+                             s, static_cast<double*>(face_flux_dev));
+    else
+      e = gh::launch_mhm_fwd(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups, ghost,
+                             make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, o.first_order, o.ws, n_bad_dev,
+                             s, static_cast<float*>(face_flux_dev));
+    return device_status(e);
+  }
+  if (U_pad_dev == nullptr || U_out_dev == nullptr || work_dev == nullptr) return HYDRO_EINVAL;
   const int64_t per_group = gh::ext_workspace_elems(1, ghost, o) * int64_t(es);
   if (work_bytes < per_group) return HYDRO_EINVAL;
   const size_t pad_b = size_t(n_groups) * nf * P * P * P * es, out_b = size_t(n_groups) * nf * 4096 * es;
@@ -617,8 +674,6 @@ int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, 
                                    overlap(face_flux_dev, ff_b, U_out_dev, out_b) ||
                                    overlap(face_flux_dev, ff_b, work_dev, work_b)))
     return HYDRO_EINVAL;
-  const double dt_host = dt_dev != nullptr ? 1.0 : dt;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   // groups in chunks that fit the caller's workspace, one after another on the stream
   for (int64_t g0 = 0; g0 < n_groups; g0 += chunk) {
     const int64_t G = std::min(chunk, n_groups - g0);

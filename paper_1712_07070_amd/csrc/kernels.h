@@ -41,7 +41,14 @@ struct BatchLevel {
   long long g_begin;  // items [g_begin, next level's g_begin) are this level's groups
   T dtdx, half_dtdx;
   const double* dt_dev;
+  double dt_scale;  // with dt_dev: dt = *dt_dev * dt_scale
   double dx;
+  // CFL outputs of the level's written state (launches with the epilogue)
+  double* dt_patch;              // [G][8] per-patch time-steps, or null
+  unsigned long long* dt_min;    // minimum x fold_scale folded in (bits of a double), or null
+  unsigned long long* reset;     // set to +inf at the start of the launch, or null
+  double c_cfl_dx;               // C_CFL * dx
+  double fold_scale;
 };
 
 constexpr int kMaxLevels = 8;
@@ -51,6 +58,8 @@ struct BatchArgs {
   BatchLevel<T> lv[kMaxLevels];
   int n_levels;
   long long total;  // number of work items (groups over all levels)
+  int cfl;          // some level requests CFL outputs (the launch runs the epilogue form)
+  double gamma;     // adiabatic index in double (Eq. 2 signal speeds)
 };
 
 // work: kBatchWorkWords device uint32 (kQueues ticket counters and one
@@ -104,7 +113,7 @@ static_assert(kQueues + 1 <= kBatchWorkWords, "work buffer too small");
 template <typename T>
 hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost, const Gas<T>& gas,
                           const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
-                          hipStream_t stream);
+                          hipStream_t stream, T* face_flux = nullptr);
 
 // The other schemes of the scheme word (scheme_ext.hip): workspace size in
 // elements of T for G groups of ghost width `ghost`, and the step.

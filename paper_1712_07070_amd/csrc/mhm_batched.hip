@@ -43,12 +43,21 @@ __device__ __forceinline__ double uniform(double v) {
 // that class share).  Every mode hands every item out exactly once.
 //
 // The ticket for the next item is taken when an item starts and decoded when
-// it ends, so the atomic's round trip overlaps the whole group step.
-template <typename T, int kWaves, typename Off>
+// it ends, so the atomic's return overlaps the whole group step.
+//
+// kCfl: levels with CFL outputs get the Eq. 2 time-steps of the state they
+// write, reduced in the same pass as in the level kernel (per-patch values,
+// and the level minimum times the level's fold_scale folded into a device
+// word, so that the levels of a W-cycle can fold min_l 2^l dt_l, the next
+// coarse step, into one word).
+template <typename T, int kWaves, typename Off, bool kCfl>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_batched_kernel(
     BatchArgs<T> args, Gas<T> gas, int first_order, int ws, int* __restrict__ n_bad,
     unsigned int* __restrict__ work, int order, int queues) {
   __shared__ Smem<T> sm;
+  __shared__ double cfl_slots[kCfl ? 2 * kCflHalfStride : 1];
+  if (kCfl && blockIdx.x == 0 && threadIdx.x < unsigned(args.n_levels) && args.lv[threadIdx.x].reset != nullptr)
+    *args.lv[threadIdx.x].reset = 0x7ff0000000000000ull;
   __shared__ long long item_slot;
   __shared__ int tried;  // queues found empty / static items taken (ticket thread only)
   const int home = int(blockIdx.x % unsigned(kQueues));
@@ -86,12 +95,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   __shared__ T lv_dtdx[kMaxLevels], lv_half_dtdx[kMaxLevels];
   if (threadIdx.x < unsigned(args.n_levels)) {
     const BatchLevel<T>& L = args.lv[threadIdx.x];
-    Gas<T> gl = gas;
-    gl.dtdx = L.dtdx;
-    gl.half_dtdx = L.half_dtdx;
-    set_dt(gl, L.dt_dev, L.dx);
-    lv_dtdx[threadIdx.x] = gl.dtdx;
-    lv_half_dtdx[threadIdx.x] = gl.half_dtdx;
+    T dtdx = L.dtdx, half_dtdx = L.half_dtdx;
+    if (L.dt_dev != nullptr) {
+      const double dt = *L.dt_dev * L.dt_scale;  // exact for a power-of-two scale
+      dtdx = T(dt / L.dx);
+      half_dtdx = T(0.5 * (dt / L.dx));
+    }
+    lv_dtdx[threadIdx.x] = dtdx;
+    lv_half_dtdx[threadIdx.x] = half_dtdx;
   }
   // tickets are taken and resolved by the first lane of the last wave: the
   // atomic's return then holds up a wave without halo roles (the halo wave
@@ -126,8 +137,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     // whole group step and cost registers / occupancy)
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int bad = process_group<T, (kWaves >= 4)>(src, L.out + int64_t(g) * 5 * 4096, gl, first_order, ws, sm, nullptr, 0.0, tid);
+    double* smax = nullptr;
+    if (kCfl && (L.dt_min != nullptr || L.dt_patch != nullptr)) {
+      // the previous item's epilogue read the slots before the item barrier
+      smax = cfl_slots + cfl_slot(tid);
+      smax[0] = 0.0;
+      smax[kCflHalfStride] = 0.0;
+    }
+    const int bad = process_group<T, (kWaves >= 4)>(src, L.out + int64_t(g) * 5 * 4096, gl, first_order, ws, sm, smax,
+                                                    args.gamma, tid);
     if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
+    if (kCfl && smax != nullptr) {
+      // the level kernel's epilogue, with the folded minimum scaled
+      __syncthreads();
+      if (tid < 8) {
+        double m = 0.0;
+        for (int i = 0; i < 64; ++i) {
+          const double sp = cfl_slots[tid * 64 + i];
+          if (sp > m) m = sp;
+        }
+        const double dt = L.c_cfl_dx / m;
+        if (L.dt_patch != nullptr) L.dt_patch[int64_t(g) * 8 + tid] = dt;
+        if (L.dt_min != nullptr)
+          atomicMin(L.dt_min, (unsigned long long)__double_as_longlong(dt * L.fold_scale));
+      }
+    }
     // every thread has read item_slot (first barrier of the group step)
     if (taker) item_slot = resolve(ticket);
     __syncthreads();
@@ -141,13 +175,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   }
 }
 
+template <typename T, typename Off, bool kCfl>
+void launch_batched_cfl(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
+                        unsigned int* work, int variant, int grid, hipStream_t stream) {
+  const int order = variant & 1, queues = (variant >> 2) & 3;
+  if (variant & 2)
+    hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo, Off, kCfl>), dim3(unsigned(grid)), dim3(kThreads), 0,
+                       stream, args, gas, first_order, ws, n_bad, work, order, queues);
+  else
+    hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi, Off, kCfl>), dim3(unsigned(grid)), dim3(kThreads), 0,
+                       stream, args, gas, first_order, ws, n_bad, work, order, queues);
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int first_order, int ws, int* n_bad,
                               unsigned int* work, int variant, int grid, hipStream_t stream) {
   if (args.total == 0) return hipSuccess;
-  const int order = variant & 1, queues = (variant >> 2) & 3;
   // 32-bit element offsets when every level's elements have one
   bool small = true;
   for (int l = 0; l < args.n_levels; ++l) {
@@ -155,19 +200,15 @@ hipError_t launch_mhm_batched(const BatchArgs<T>& args, const Gas<T>& gas, int f
     small = small && int64_t(g.ngx) * g.ngy * g.ngz * 5 * 4096 <= int64_t(0xffffffffu);
   }
   if (small) {
-    if (variant & 2)
-      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo, unsigned int>), dim3(unsigned(grid)), dim3(kThreads),
-                         0, stream, args, gas, first_order, ws, n_bad, work, order, queues);
+    if (args.cfl)
+      launch_batched_cfl<T, unsigned int, true>(args, gas, first_order, ws, n_bad, work, variant, grid, stream);
     else
-      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi, unsigned int>), dim3(unsigned(grid)), dim3(kThreads),
-                         0, stream, args, gas, first_order, ws, n_bad, work, order, queues);
+      launch_batched_cfl<T, unsigned int, false>(args, gas, first_order, ws, n_bad, work, variant, grid, stream);
   } else {
-    if (variant & 2)
-      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::lo, int64_t>), dim3(unsigned(grid)), dim3(kThreads), 0,
-                         stream, args, gas, first_order, ws, n_bad, work, order, queues);
+    if (args.cfl)
+      launch_batched_cfl<T, int64_t, true>(args, gas, first_order, ws, n_bad, work, variant, grid, stream);
     else
-      hipLaunchKernelGGL((mhm_batched_kernel<T, MinWaves<T>::hi, int64_t>), dim3(unsigned(grid)), dim3(kThreads), 0,
-                         stream, args, gas, first_order, ws, n_bad, work, order, queues);
+      launch_batched_cfl<T, int64_t, false>(args, gas, first_order, ws, n_bad, work, variant, grid, stream);
   }
   return hipGetLastError();
 }

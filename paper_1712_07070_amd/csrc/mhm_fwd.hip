@@ -44,18 +44,21 @@ namespace {
 
 // ------------------------------------------------------------- kernels ----
 
-template <typename T, int kWaves>
+// kFlux: also write the fluxes of the patch-boundary faces of every group to
+// face_flux [G][9][5][256] (process_group's layout).
+template <typename T, int kWaves, bool kFlux>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_padded_kernel(const T* __restrict__ Upad, T* __restrict__ Uout,
                                                               int gh, Gas<T> gas, const double* __restrict__ dt_dev,
                                                               double dx, int first_order, int ws,
-                                                              int* __restrict__ n_bad) {
+                                                              int* __restrict__ n_bad, T* __restrict__ face_flux) {
   __shared__ Smem<T> sm;
   set_dt(gas, dt_dev, dx);
   const int P = 16 + 2 * gh;
   const int64_t P3 = int64_t(P) * P * P;
   PaddedSource<T> src{Upad + int64_t(blockIdx.x) * 5 * P3, P, gh};
+  T* ff = kFlux ? face_flux + int64_t(blockIdx.x) * 9 * 5 * 256 : nullptr;
   const int bad = process_group<T, (kWaves >= 4)>(src, Uout + int64_t(blockIdx.x) * 5 * 4096, gas, first_order, ws, sm, nullptr,
-                                   0.0);
+                                   0.0, threadIdx.x, ff);
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
 }
 
@@ -173,7 +176,7 @@ hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& g
 template <typename T>
 hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost, const Gas<T>& gas,
                           const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
-                          hipStream_t stream) {
+                          hipStream_t stream, T* face_flux) {
   if (n_groups == 0) return hipSuccess;
   // one workgroup per group; very large batches go in launches of at most
   // 2^30 workgroups
@@ -182,8 +185,14 @@ hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost,
   const int64_t P3 = int64_t(P) * P * P;
   for (int64_t g0 = 0; g0 < n_groups; g0 += chunk) {
     const int64_t n = n_groups - g0 < chunk ? n_groups - g0 : chunk;
-    hipLaunchKernelGGL((mhm_padded_kernel<T, MinWaves<T>::value>), dim3(unsigned(n)), dim3(kThreads), 0, stream, U_pad + g0 * 5 * P3,
-                       U_out + g0 * 5 * 4096, ghost, gas, dt_dev, dx, first_order, ws, n_bad);
+    if (face_flux != nullptr)
+      hipLaunchKernelGGL((mhm_padded_kernel<T, MinWaves<T>::value, true>), dim3(unsigned(n)), dim3(kThreads), 0, stream,
+                         U_pad + g0 * 5 * P3, U_out + g0 * 5 * 4096, ghost, gas, dt_dev, dx, first_order, ws, n_bad,
+                         face_flux + g0 * 9 * 5 * 256);
+    else
+      hipLaunchKernelGGL((mhm_padded_kernel<T, MinWaves<T>::value, false>), dim3(unsigned(n)), dim3(kThreads), 0,
+                         stream, U_pad + g0 * 5 * P3, U_out + g0 * 5 * 4096, ghost, gas, dt_dev, dx, first_order, ws,
+                         n_bad, (T*)nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -206,9 +215,9 @@ hipError_t launch_mhm_level(const T* level, T* level_out, const LevelGeom& geo, 
 }
 
 template hipError_t launch_mhm_fwd<double>(const double*, double*, int64_t, int, const Gas<double>&,
-                                           const double*, double, int, int, int*, hipStream_t);
+                                           const double*, double, int, int, int*, hipStream_t, double*);
 template hipError_t launch_mhm_fwd<float>(const float*, float*, int64_t, int, const Gas<float>&,
-                                          const double*, double, int, int, int*, hipStream_t);
+                                          const double*, double, int, int, int*, hipStream_t, float*);
 template hipError_t launch_mhm_level<double>(const double*, double*, const LevelGeom&, const Gas<double>&,
                                              const double*, double, int, int, int*, const CflOut&, int, hipStream_t);
 template hipError_t launch_mhm_level<float>(const float*, float*, const LevelGeom&, const Gas<float>&,

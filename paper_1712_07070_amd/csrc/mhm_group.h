@@ -158,7 +158,7 @@ __device__ __forceinline__ int cfl_slot(int tid) {
 template <typename T, bool kI, class Src, int kL>
 __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& c, const Src& src, T* __restrict__ out, int k,
                                               const Gas<T>& gas, int first_order, int ws, Smem<T, kL>& sm, double* smax,
-                                              double gamma_d) {
+                                              double gamma_d, T* __restrict__ ff) {
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
   // x/y flux differences of plane k-1 (fluxes written last iteration)
@@ -203,6 +203,12 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
     if (k >= 0) {
       T Fz1[5];
       bad += hllc_flux<2>(c.Uz, Ut[2][0], gas, ws, Fz1);
+      if (ff != nullptr && (k & 7) == 0) {
+        // z faces on a patch boundary (z = 0, 8, 16): plane 6 + k/8, entry y*16 + x
+        T* o = ff + (6 + (k >> 3)) * 5 * 256 + cy * 16 + cx;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q * 256] = Fz1[q];
+      }
       if (k >= 1) {
         // complete plane k-1: U^{n+1} = U^n - dt/dx [(x) + (y) + (z)]
         const typename Src::Off o = c.col + src.plane(k - 1);
@@ -234,7 +240,8 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
 // x and y faces of plane k that an interior column solves: its low x and low
 // y face.
 template <typename T, bool kI, typename Off, int kL>
-__device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm) {
+__device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm,
+                                             T* __restrict__ ff) {
   if (!kI || k < 0 || k > 15) return 0;
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
@@ -245,6 +252,12 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
     bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
+    if (ff != nullptr && (cx & 7) == 0) {
+      // x faces at x = 0, 8: plane x/8, entry z*16 + y
+      T* o = ff + (cx >> 3) * 5 * 256 + k * 16 + cy;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) o[q * 256] = F[q];
+    }
   }
   {
     T L[5], F[5];
@@ -253,6 +266,12 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
     bad += hllc_flux<1>(L, c.Uy, gas, ws, F);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
+    if (ff != nullptr && (cy & 7) == 0) {
+      // y faces at y = 0, 8: plane 3 + y/8, entry x*16 + z
+      T* o = ff + (3 + (cy >> 3)) * 5 * 256 + cx * 16 + k;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) o[q * 256] = F[q];
+    }
   }
   return bad;
 }
@@ -264,7 +283,8 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
 // and the flux rotated back.  The halo wave wrote the high-side states to
 // H; this pass runs on another wave, which has no halo work.
 template <typename T, int kL>
-__device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm) {
+__device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm,
+                                          T* __restrict__ ff) {
   if (k < 0 || k > 15 || lane >= 32) return 0;
   const bool yf = lane >= 16;
   const int i = lane & 15;
@@ -292,6 +312,15 @@ __device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, in
   Fb[2 * 17 * 16] = yf ? F[1] : F[2];
   Fb[3 * 17 * 16] = yf ? F[2] : F[3];
   Fb[4 * 17 * 16] = F[4];
+  if (ff != nullptr) {
+    // x = 16: plane 2, entry z*16 + y; y = 16: plane 5, entry x*16 + z
+    T* o = ff + (yf ? 5 * 5 * 256 + i * 16 + k : 2 * 5 * 256 + k * 16 + i);
+    o[0] = F[0];
+    o[1 * 256] = yf ? F[3] : F[1];
+    o[2 * 256] = yf ? F[1] : F[2];
+    o[3 * 256] = yf ? F[2] : F[3];
+    o[4 * 256] = F[4];
+  }
   return bad;
 }
 
@@ -312,7 +341,8 @@ enum WaveRole { kRoleHalo = 0, kRoleLastFaces = 1, kRolePlain = 2 };
 // instantiation passes the same barriers in the same order.
 template <typename T, class Src, int kRole, int kL>
 __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, const Gas<T>& gas, int first_order,
-                                           int ws, Smem<T, kL>& sm, double* smax, double gamma_d, int tid) {
+                                           int ws, Smem<T, kL>& sm, double* smax, double gamma_d, int tid,
+                                           T* __restrict__ ff) {
   // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
   // 0..3 also one of the 4 edge columns
   const int lane = tid & 63;
@@ -364,13 +394,13 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
     __syncthreads();
 
     // ---- half-step face states of plane k; z-face and update of plane k-1
-    bad += fwd_col_states(ci, src, out, k, gas, first_order, ws, sm, smax, gamma_d);
-    if (kHalo) bad += fwd_col_states(ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d);
+    bad += fwd_col_states(ci, src, out, k, gas, first_order, ws, sm, smax, gamma_d, ff);
+    if (kHalo) bad += fwd_col_states(ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d, (T*)nullptr);
     __syncthreads();
 
     // ---- x and y faces of plane k
-    bad += fwd_col_faces(ci, k, gas, ws, sm);
-    if (kRole == kRoleLastFaces) bad += last_faces(lane, k, gas, ws, sm);
+    bad += fwd_col_faces(ci, k, gas, ws, sm, ff);
+    if (kRole == kRoleLastFaces) bad += last_faces(lane, k, gas, ws, sm, ff);
 
     fwd_col_shift(ci);
     if (kHalo) fwd_col_shift(ch);
@@ -382,7 +412,11 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 // (field stride 4096).  Returns this thread's unphysical count.  If smax is
 // non-null (the thread's cfl_slot in an LDS array, both halves set to 0),
 // also leaves there the maximum CFL signal speed of the thread's interior
-// cells in patch-z halves 0..7 and 8..15.  `tid` is the thread's index in the
+// cells in patch-z halves 0..7 and 8..15.  If ff is non-null, also writes the
+// fluxes of the faces on the patch boundaries (normal coordinate 0, 8, 16 of
+// each axis) to ff as [9][5][256]: plane 3 axis + k holds the faces at 8 k,
+// entry b * 16 + a with (a, b) the transverse coordinates in cyclic order
+// (the flux registers of coarse-fine coupling).  `tid` is the thread's index in the
 // workgroup (a loop over groups passes it opaque, so that the compiler keeps
 // thread-derived addresses out of the loop's live set).  Wave 0 runs the
 // march with the halo roles, wave 2 with the last faces, waves 1 and 3 with
@@ -400,21 +434,21 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 template <typename T, bool kPrio, class Src, int kL>
 __device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
                                              int first_order, int ws, Smem<T, kL>& sm, double* smax,
-                                             double gamma_d, int tid = threadIdx.x) {
+                                             double gamma_d, int tid = threadIdx.x, T* __restrict__ ff = nullptr) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if constexpr (kPrio) {
     if (wave == 0) __builtin_amdgcn_s_setprio(2);
     if (wave == 2) __builtin_amdgcn_s_setprio(1);
   }
   if (first_order == 0) {
-    if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
-    if (wave == 2) return march_group<T, Src, kRoleLastFaces>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
-    return march_group<T, Src, kRolePlain>(src, out, gas, 0, ws, sm, smax, gamma_d, tid);
+    if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff);
+    if (wave == 2) return march_group<T, Src, kRoleLastFaces>(src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff);
+    return march_group<T, Src, kRolePlain>(src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff);
   }
-  if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+  if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff);
   if (wave == 2)
-    return march_group<T, Src, kRoleLastFaces>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
-  return march_group<T, Src, kRolePlain>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid);
+    return march_group<T, Src, kRoleLastFaces>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff);
+  return march_group<T, Src, kRolePlain>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff);
 }
 
 // Reduce the per-thread signal-speed maxima of one group (the LDS array

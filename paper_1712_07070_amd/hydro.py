@@ -46,7 +46,9 @@ class HydroLevel(ctypes.Structure):
     """hydro_level_t of include/hydro.h."""
     _fields_ = [("level_dev", ctypes.c_void_p), ("level_out_dev", ctypes.c_void_p), ("ngx", ctypes.c_int32),
                 ("ngy", ctypes.c_int32), ("ngz", ctypes.c_int32), ("bc", ctypes.c_int32 * 6), ("dt", ctypes.c_double),
-                ("dx", ctypes.c_double), ("dt_dev", ctypes.c_void_p)]
+                ("dx", ctypes.c_double), ("dt_dev", ctypes.c_void_p), ("dt_dev_scale", ctypes.c_double),
+                ("c_cfl", ctypes.c_double), ("dt_next_scale", ctypes.c_double), ("dt_next_dev", ctypes.c_void_p),
+                ("dt_patch_next_dev", ctypes.c_void_p), ("dt_reset_dev", ctypes.c_void_p)]
 
 
 class HydroAmrLevel(ctypes.Structure):
@@ -533,6 +535,7 @@ def _levels_array(levels):
     for i, L in enumerate(levels):
         lin, lout, ng, bc, dt, dx = L[:6]
         dt_dev = L[6] if len(L) > 6 else None
+        cfl = L[7] if len(L) > 7 and L[7] is not None else {}
         dtype = lin.dtype if dtype is None else dtype
         if lin.dtype != dtype or lout.dtype != dtype or lin.shape != lout.shape:
             raise ValueError("batched levels must share one dtype and match in/out shapes")
@@ -547,6 +550,15 @@ def _levels_array(levels):
         arr[i].dt = float(dt)
         arr[i].dx = float(dx)
         arr[i].dt_dev = _opt(dt_dev, "dt_dev", torch.float64)
+        arr[i].dt_dev_scale = float(cfl.get("dt_dev_scale", 1.0))
+        arr[i].c_cfl = float(cfl.get("c_cfl", 0.0))
+        arr[i].dt_next_scale = float(cfl.get("dt_next_scale", 1.0))
+        arr[i].dt_next_dev = _opt(cfl.get("dt_next"), "dt_next", torch.float64)
+        dtp = cfl.get("dt_patch")
+        if dtp is not None and dtp.numel() < 8 * G:
+            raise ValueError("dt_patch must hold 8 doubles per group")
+        arr[i].dt_patch_next_dev = _opt(dtp, "dt_patch", torch.float64)
+        arr[i].dt_reset_dev = _opt(cfl.get("dt_reset"), "dt_reset", torch.float64)
     return arr, dtype
 
 
@@ -554,7 +566,10 @@ def advance_batched(levels, gamma: float, work: torch.Tensor, theta: float = 1.5
                     n_bad: Optional[torch.Tensor] = None, grid: int = 0, ctx: Optional[Context] = None) -> None:
     """One step of several levels in one persistent launch (hydro_advance_batched).
 
-    levels: sequence of (level_in, level_out, ng, bc, dt, dx[, dt_dev]);
+    levels: sequence of (level_in, level_out, ng, bc, dt, dx[, dt_dev[, cfl]]),
+    cfl an optional dict of the level's CFL outputs and dt scale (keys
+    dt_dev_scale, c_cfl, dt_next_scale, and device float64 tensors dt_next,
+    dt_patch [G*8], dt_reset: the fields of hydro_level_t);
     work: int32 device tensor of BATCH_WORK_WORDS zeros (re-armed by every launch)."""
     if work.dtype != torch.int32 or work.numel() < BATCH_WORK_WORDS:
         raise ValueError("work must hold %d int32" % BATCH_WORK_WORDS)
@@ -651,10 +666,19 @@ class MultiLevel:
     s % 2^(L-1-l) == 0.  batched=True runs each stage as one persistent launch
     over the union of the stage's groups; batched=False launches
     hydro_advance_level once per level per stage.  Levels are independent
-    periodic bricks (no coarse-fine coupling)."""
+    periodic bricks (no coarse-fine coupling).
+
+    adaptive=True (batched only): the coarse time-step is chosen on the
+    device (Sec. 2.6 Eq. 2 with C = c_cfl): the launch of each level's last
+    substep of a coarse step reduces the Eq. 2 time-step of the state it
+    writes, scaled by 2^l, into one device word, so that the next coarse step
+    takes dt_0 = min_l 2^l dt_l and level l reads dt_0 / 2^l from it; three
+    words rotate over coarse steps (read, reduce, reset), so nothing is
+    synchronized with the host.  dt0 is the first coarse step's time-step."""
 
     def __init__(self, levels, gamma: float, dt0: float, dtype=torch.float64, batched: bool = True,
-                 theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, device=None, ctx: Optional[Context] = None):
+                 theta: float = 1.5, scheme: int = SCHEME_MHM_PLM_HLLC, device=None, ctx: Optional[Context] = None,
+                 adaptive: bool = False, c_cfl: float = 0.5):
         dev = torch.device("cuda") if device is None else torch.device(device)
         self.ctx = ctx
         self.geo = [(tuple(int(v) for v in lv[0]), float(lv[1]), tuple(int(v) for v in lv[2])) for lv in levels]
@@ -667,6 +691,17 @@ class MultiLevel:
         self.dtype = dtype
         self.work = torch.zeros(BATCH_WORK_WORDS, dtype=torch.int32, device=dev)
         self.n_bad = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.adaptive, self.c_cfl = bool(adaptive), float(c_cfl)
+        if self.adaptive:
+            if not self.batched:
+                raise ValueError("the adaptive coarse step runs in the batched form")
+            self.dtw = torch.full((3,), float("inf"), dtype=torch.float64, device=dev)
+            self.dtw[0] = self.dt0
+            self.rot = 0
+
+    def dt_coarse(self) -> torch.Tensor:
+        """Device word holding the time-step of the next coarse step (adaptive)."""
+        return self.dtw[self.rot:self.rot + 1]
 
     def load_state(self, l: int, U: torch.Tensor):
         self.bufs[l][self.cur[l]].copy_(U)
@@ -680,16 +715,26 @@ class MultiLevel:
     def stage_levels(self, s: int):
         return [l for l in range(self.L) if s % 2 ** (self.L - 1 - l) == 0]
 
-    def _entries(self, lvls):
+    def _entries(self, lvls, s: int = 0):
         out = []
+        n_stages = 2 ** (self.L - 1)
         for l in lvls:
             ng, dx, bc = self.geo[l]
-            out.append((self.bufs[l][self.cur[l]], self.bufs[l][1 - self.cur[l]], ng, bc, self.dt0 / 2 ** l, dx))
+            e = (self.bufs[l][self.cur[l]], self.bufs[l][1 - self.cur[l]], ng, bc, self.dt0 / 2 ** l, dx)
+            if self.adaptive:
+                a, b, c = self.rot, (self.rot + 1) % 3, (self.rot + 2) % 3
+                cfl = {"dt_dev_scale": 2.0 ** -l}
+                if s == n_stages - 2 ** (self.L - 1 - l):   # the level's last substep of the coarse step
+                    cfl.update(c_cfl=self.c_cfl, dt_next_scale=2.0 ** l, dt_next=self.dtw[b:b + 1])
+                if s == 0 and l == lvls[0]:
+                    cfl.update(c_cfl=self.c_cfl, dt_reset=self.dtw[c:c + 1])
+                e = e + (self.dtw[a:a + 1], cfl)
+            out.append(e)
         return out
 
     def stage(self, s: int) -> None:
         lvls = self.stage_levels(s)
-        ent = self._entries(lvls)
+        ent = self._entries(lvls, s)
         if self.batched:
             advance_batched(ent, self.gamma, self.work, self.theta, self.scheme, n_bad=self.n_bad, ctx=self.ctx)
         else:
@@ -702,19 +747,32 @@ class MultiLevel:
     def coarse_step(self) -> None:
         for s in range(2 ** (self.L - 1)):
             self.stage(s)
+        if self.adaptive:
+            self.rot = (self.rot + 1) % 3
 
     def autotune(self, reps: int = 3) -> Tuple[int, list]:
         """Choose the batched launch shape by the time of a whole coarse step:
         hydro_autotune_batched times every shape on each distinct stage (its
         outputs go to the scratch halves, the state is kept) and the stage
         times are summed with the number of times the stage occurs."""
-        counts = {}
-        for s in range(2 ** (self.L - 1)):
-            key = tuple(self.stage_levels(s))
+        n_stages = 2 ** (self.L - 1)
+        counts, first = {}, {}
+        for s in range(n_stages):
+            lvls = tuple(self.stage_levels(s))
+            # stages differ also in which levels reduce their CFL time-step
+            key = (lvls, tuple(e[7].get("dt_next") is not None for e in self._entries(lvls, s))
+                   if self.adaptive else ())
             counts[key] = counts.get(key, 0) + 1
+            first.setdefault(key, s)
         total = [0.0] * BATCHED_VARIANTS
-        for lvls, c in counts.items():
-            _, times = autotune_batched(self._entries(lvls), self.gamma, self.work, reps, ctx=self.ctx)
+        # the tuner's launches write the CFL outputs too: give them scratch words
+        scratch = torch.full((2,), float("inf"), dtype=torch.float64, device=self.work.device)
+        for key, c in counts.items():
+            ent = self._entries(list(key[0]), first[key])
+            if self.adaptive:
+                ent = [e[:7] + ({**e[7], **({"dt_next": scratch[0:1]} if "dt_next" in e[7] else {}),
+                                 **({"dt_reset": scratch[1:2]} if "dt_reset" in e[7] else {})},) for e in ent]
+            _, times = autotune_batched(ent, self.gamma, self.work, reps, ctx=self.ctx)
             total = [a + c * t for a, t in zip(total, times)]
         best = min(range(len(total)), key=total.__getitem__)
         set_batched_variant(self.dtype, best, ctx=self.ctx)
@@ -722,10 +780,13 @@ class MultiLevel:
 
     def capture(self, n_coarse: int = 2) -> Graph:
         """Graph of n_coarse coarse steps (an even count returns every level's
-        state to the buffer it started in, so the graph can be replayed)."""
+        state to the buffer it started in, and with adaptive=True a multiple
+        of 6 also the time-step words to their roles, so the graph can be
+        replayed)."""
         start = list(self.cur)
+        rot = getattr(self, "rot", 0)
         g = Graph(self.ctx).capture(lambda: [self.coarse_step() for _ in range(n_coarse)])
-        if self.cur != start:
+        if self.cur != start or getattr(self, "rot", 0) != rot:
             raise ValueError("captured steps must return every level to its starting buffer")
         return g
 

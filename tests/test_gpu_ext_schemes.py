@@ -202,3 +202,30 @@ def test_ext_dual_energy_matches_oracle(hydro, name, dtype, xi):
     assert_parity(got[:, :5], ref[:, :5], TOL[dtype], name)
     assert np.abs(got[:, 5] - ref[:, 5]).max() <= TOL[dtype] * np.abs(ref[:, 5]).max(), name
     assert int(host(n_bad)[0]) == nb == 0
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("name", ["default", "davis", "first-order"])
+def test_fused_face_fluxes_match_oracle(hydro, name, dtype):
+    """Words the fused kernel computes (MHM, primitive PLM, generalized
+    minmod, HLLC) run there, with no workspace; the patch-boundary face
+    fluxes it reports equal the oracle's within tol (|o| + max |o| of the
+    field), the state as for the other words."""
+    sch = {"default": MHM, "davis": MHM | oracle.WAVESPEED_DAVIS, "first-order": MHM | oracle.FIRST_ORDER}[name]
+    say("fused face fluxes", name, dtype.__name__)
+    assert hydro.load().hydro_ext_workspace_bytes(8, 3, 0, sch) == 0
+    lv = W.white_noise(32)
+    U = lv.U.astype(dtype).astype(np.float64)
+    pad = oracle.fill_ghosts(U, lv.ng, 3, lv.bc)
+    dt = cfl_dt(U, lv.ng, lv.bc, lv.dx, lv.gamma)
+    ref, ffo, nb = oracle.step_any_flux(pad, dt, lv.dx, lv.gamma, 1.5, sch)
+    ff = torch.full((lv.n_groups, 9, 5, 16, 16), float("nan"), dtype=torch.float64 if dtype == np.float64 else
+                    torch.float32, device="cuda")
+    got = hydro.advance_ext(dev(pad, dtype), dt, lv.dx, lv.gamma, sch, face_flux=ff)
+    assert_parity(host(got), ref, TOL[dtype], name)
+    f = host(ff).astype(np.float64)
+    assert np.isfinite(f).all()
+    scale = np.abs(ffo).max(axis=(0, 1, 3, 4))[None, None, :, None, None]
+    err = np.abs(f - ffo) / (np.abs(ffo) + scale)
+    assert err.max() <= TOL[dtype], (name, float(err.max()))
+    assert nb == 0

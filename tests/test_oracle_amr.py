@@ -141,3 +141,32 @@ def test_centred_blast_stays_mirror_symmetric():
             b = out[l][gm][:, :, :, ::-1].copy()
             b[1] *= -1
             assert field_scale_error(a, b) < 1e-13 or np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("scheme", [oracle.SCHEME_MHM_PLM_HLLC, oracle.SCHEME_CTU | oracle.PPM | oracle.RIEMANN_ROE])
+def test_patch_boundary_fluxes_balance_each_patch(scheme):
+    """The fluxes step_any_flux reports on the patch-boundary faces are the
+    ones the update used: for every 8^3 patch of every group, the change of
+    the patch's sum of U equals -dt/dx times the net flux through its six
+    faces (to round-off).  A wrong plane, a transposed (a, b) pair or a
+    flipped orientation breaks the balance of some patch."""
+    lv = W.white_noise(32)
+    pad = oracle.fill_ghosts(lv.U, lv.ng, 3, lv.bc)
+    dt = 1e-3
+    out, ff, nb = oracle.step_any_flux(pad, dt, lv.dx, lv.gamma, 1.5, scheme)
+    ref, _ = oracle.step_any(pad, dt, lv.dx, lv.gamma, 1.5, scheme)
+    assert nb == 0 and np.array_equal(out, ref)
+    dU = out - lv.U
+    dtdx = dt / lv.dx
+    for g in range(lv.n_groups):
+        for pz in range(2):
+            for py in range(2):
+                for px in range(2):
+                    zs, ys, xs = (slice(8 * v, 8 * v + 8) for v in (pz, py, px))
+                    lhs = dU[g][:, zs, ys, xs].sum(axis=(1, 2, 3))
+                    fx = ff[g, px + 1][:, zs, ys].sum(axis=(1, 2)) - ff[g, px][:, zs, ys].sum(axis=(1, 2))
+                    fy = ff[g, 3 + py + 1][:, xs, zs].sum(axis=(1, 2)) - ff[g, 3 + py][:, xs, zs].sum(axis=(1, 2))
+                    fz = ff[g, 6 + pz + 1][:, ys, xs].sum(axis=(1, 2)) - ff[g, 6 + pz][:, ys, xs].sum(axis=(1, 2))
+                    rhs = -dtdx * (fx + fy + fz)
+                    scale = np.abs(dU[g][:, zs, ys, xs]).sum(axis=(1, 2, 3)) + 1e-300
+                    assert np.all(np.abs(lhs - rhs) <= 1e-12 * scale + 1e-15), (g, px, py, pz, lhs, rhs)
