@@ -267,25 +267,28 @@ def adjoint_rollout(hydro, torch, lv, dtype, n_steps, k_ckpt, dt, target=None, r
 def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171223, eps=1e-7, max_draws=None):
     """Central differences of the loss at seeded (cell, field) entries, each
     perturbed by +-eps (eps = 1e-7), against the adjoint gradient.  A draw is
-    rejected and redrawn when a branch decision (limiter case, min/max
-    argument, HLLC branch) changes within +-eps, which shows as a difference
-    between the two one-sided differences (f(+eps) - f(0))/eps and
-    (f(0) - f(-eps))/eps of more than 2e-6 relative: on one smooth piece they
-    differ by eps f'' (~1e-7 relative here), across a switch by the jump in
-    the derivative.  Up to max_draws (default 4 x samples) draws are taken
-    until `samples` are accepted; the rejection count is reported.  The loss
-    differences are formed as sum (r1 - r2)(r1 + r2) to avoid cancelling two
-    large sums."""
+    rejected when the +eps and -eps rollouts take different branches anywhere
+    (limiter case or argument, wave-speed argument, HLLC region): each
+    rollout runs with the library's branch record (hydro_branch_record, the
+    step's own decisions per group and step, bitwise the same states), and a
+    draw whose two record sequences differ straddles a switch, where central
+    differences do not measure the derivative the adjoint follows.  Up to
+    max_draws (default 4 x samples) draws are taken until `samples` are
+    accepted; the rejection count is reported.  The loss differences are
+    formed as sum (r1 - r2)(r1 + r2) to avoid cancelling two large sums."""
     U0 = lv.U
     tgt = torch.from_numpy(np.ascontiguousarray(target)).cuda()
     rng = np.random.default_rng(seed)
     max_draws = max_draws or 4 * samples
 
-    def resid(U):
-        out = hydro.Rollout.apply(torch.from_numpy(U).cuda(), lv.ng, lv.bc, n_steps, dt, lv.dx, lv.gamma, n_steps)
-        return out[:, 0] - tgt
-
-    r0 = resid(U0)
+    def run(U):
+        x = torch.from_numpy(U).cuda()
+        recs = []
+        for _ in range(n_steps):
+            pad = hydro.fill_ghosts(x, lv.ng, 3, lv.bc)
+            x, rec = hydro.branch_record(pad, dt, lv.dx, lv.gamma)
+            recs.append(rec)
+        return x[:, 0] - tgt, torch.stack(recs)
 
     def dloss(ra, rb):
         return float(((ra - rb) * (ra + rb)).sum())
@@ -298,9 +301,8 @@ def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171
         up, um = U0.copy(), U0.copy()
         up[idx] += eps
         um[idx] -= eps
-        rp, rm = resid(up), resid(um)
-        dp, dm = dloss(rp, r0) / eps, dloss(r0, rm) / eps
-        if abs(dp - dm) > 2e-6 * max(abs(dp), abs(dm), 1e-300):
+        (rp, sp), (rm, sm) = run(up), run(um)
+        if not torch.equal(sp, sm):
             rejected += 1
             continue
         fd = dloss(rp, rm) / (2 * eps)
@@ -317,7 +319,7 @@ def fd_protocol(hydro, torch, lv, target, n_steps, dt, grad, samples, seed=20171
     e = np.array([abs(fd - gv) / (abs(gv) + ref[key[f]]) for f, fd, gv in acc]) if acc else np.array([np.nan])
     r = np.array([abs(fd - gv) / max(abs(fd), abs(gv), 1e-300) for f, fd, gv in acc]) if acc else np.array([np.nan])
     return {"draws": draws, "rejected": rejected, "accepted": len(acc), "eps": eps,
-            "rule": "reject when the one-sided differences at +-eps differ by > 2e-6 relative",
+            "rule": "reject when the +eps and -eps rollouts' branch records (every group, every step) differ",
             "norm": "|fd - g| / (|g| + max |g| of the field among accepted entries)",
             "max_err": float(np.nanmax(e)), "median_err": float(np.nanmedian(e)),
             "within_1e-6": int(np.sum(e <= 1e-6)), "all_accepted_within_1e-6": bool(np.all(e <= 1e-6)),

@@ -152,6 +152,22 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
                   int32_t dtype, double dt, double dx, double gamma, int32_t scheme,
                   double theta, const double* dt_dev, int32_t* n_bad_dev, void* stream);
 
+/* hydro_branch_record -- hydro_advance (FP64 only, dt on the host, no
+ * unphysical count) that also writes every group's branch record to
+ * record_dev[G] (device uint32): each thread of the group hashes the code of
+ * every decision the step's arithmetic takes -- the limiter case and the
+ * argument attaining its minimum (first on ties), the first or second
+ * argument of each wave-speed minimum / maximum, the HLLC region -- in its
+ * own order, and the threads' hashes are combined by XOR.  Two steps whose
+ * records agree took the same branches (up to a 2^-32 collision), so their
+ * results lie on one smooth piece of the step: the check a finite-
+ * difference test of the adjoint needs (Sec. 2.2 arithmetic; the record is a
+ * diagnostic of this library, not of the paper).  The state written equals
+ * hydro_advance's bit for bit.  HYDRO_EINVAL for FP32 or invalid arguments. */
+int hydro_branch_record(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
+                        double dt, double dx, double gamma, int32_t scheme, double theta, uint32_t* record_dev,
+                        void* stream);
+
 /* hydro_advance_ext -- one step of G padded groups with any scheme of
  * Sec. 2.2 that the scheme word names (hydro_advance's arguments and
  * semantics, plus a workspace):
@@ -184,11 +200,13 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
  *               hydro_ext_workspace_bytes(1, ghost, dtype, scheme); groups are
  *               processed in chunks of as many groups as it holds (all at
  *               once with hydro_ext_workspace_bytes(G, ...)); must not overlap
- *               U_pad_dev or U_out_dev.  Words of MHM + PLM on primitive
- *               variables + generalized minmod + HLLC without dual energy
- *               (either wave-speed option, second or first order) run on the
- *               fused per-group kernel of hydro_advance and need no workspace
- *               (their hydro_ext_workspace_bytes is 0; work_dev may be NULL)
+ *               U_pad_dev or U_out_dev.  MHM + PLM words without dual
+ *               energy (any limiter, primitive or characteristic variables,
+ *               any solver or wave-speed option, second or first order) run
+ *               in the fused per-group kernel of hydro_advance (the default
+ *               word in its own specialized copy) and need no workspace
+ *               (their hydro_ext_workspace_bytes is 0; work_dev may be NULL);
+ *               CTU, PPM and dual energy run as a chain of kernels through it
  *   n_bad_dev   as for hydro_advance (faces with unphysical input states plus
  *               updated cells with rho <= 0 or p <= 0)
  *   face_flux_dev  optional [G][9][5][16][16] output: the fluxes the update

@@ -1,7 +1,7 @@
 // Ghost-zone fill (Sec. 3.4, boundary conditions of Sec. 2.2) and the
 // per-patch CFL time-step (Sec. 2.6 Eq. 2) of padded patch groups.
 
-#include "kernels.h"
+#include "mhm_group.h"
 
 namespace gh {
 
@@ -70,20 +70,9 @@ __global__ __launch_bounds__(256) void cfl_dt_kernel(const T* __restrict__ U_pad
   const int col = (y & 7) * 8 + (x & 7);
   red[0][pxy][col] = smax[0];
   red[1][pxy][col] = smax[1];
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    const int p = threadIdx.x;  // (pz*2 + py)*2 + px
-    double m = 0.0;
-    for (int i = 0; i < 64; ++i) {
-      const double s = red[p >> 2][p & 3][i];
-      if (s > m) m = s;
-    }
-    const double dt = (c_cfl * dx) / m;
-    dt_patch[int64_t(blockIdx.x) * 8 + p] = dt;
-    // non-negative doubles order like their bit patterns: an integer minimum
-    // is exact and independent of the order the workgroups arrive in
-    if (dt_min != nullptr) atomicMin(dt_min, (unsigned long long)__double_as_longlong(dt));
-  }
+  // patch p = (pz*2 + py)*2 + px owns red[p >> 2][p & 3][0..63]: the fused
+  // step's epilogue layout and reduction (wave w: patches 2w, 2w+1)
+  cfl_epilogue(&red[0][0][0], c_cfl * dx, dt_patch + int64_t(blockIdx.x) * 8, dt_min);
 }
 
 __global__ void set_inf_kernel(unsigned long long* p) {

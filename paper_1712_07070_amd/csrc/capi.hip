@@ -225,6 +225,13 @@ bool fused_ext_scheme(const gh::ExtOpts& o) {
   return !o.ctu && o.lim == 0 && !o.chr && !o.ppm && o.solver == 0 && !o.de;
 }
 
+// The other MHM + PLM words (any limiter, primitive or characteristic
+// variables, HLLC / Roe / HLLE, either wave-speed option, second or first
+// order; no dual energy) run in the same fused kernel with run-time options,
+// also without a workspace; CTU, PPM and dual energy take the chain of
+// per-cell / per-face kernels.
+bool fused_plm_scheme(const gh::ExtOpts& o) { return !o.ctu && !o.ppm && !o.de; }
+
 template <typename T>
 gh::Gas<T> make_gas(double gamma, double theta, double dt, double dx) {
   gh::Gas<T> g;
@@ -613,13 +620,31 @@ int hydro_advance(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int3
   return device_status(e);
 }
 
+int hydro_branch_record(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, int32_t ghost, int32_t dtype,
+                        double dt, double dx, double gamma, int32_t scheme, double theta, uint32_t* record_dev,
+                        void* stream) {
+  if (n_groups < 0 || ghost < 2 || ghost > 16 || dtype != HYDRO_F64) return HYDRO_EINVAL;
+  if (!finite_pos(dx) || !(std::isfinite(gamma) && gamma > 1.0) || !valid_scheme(scheme, theta) || !finite_pos(dt))
+    return HYDRO_EINVAL;
+  if (n_groups == 0) return HYDRO_OK;
+  if (U_pad_dev == nullptr || U_out_dev == nullptr || record_dev == nullptr) return HYDRO_EINVAL;
+  const int64_t P = 16 + 2 * ghost;
+  if (overlap(U_pad_dev, size_t(n_groups) * 5 * P * P * P * 8, U_out_dev, size_t(n_groups) * 5 * 4096 * 8))
+    return HYDRO_EINVAL;
+  const int first_order = (scheme & HYDRO_FIRST_ORDER) ? 1 : 0;
+  const int ws = (scheme >> 8) & 3;
+  return device_status(gh::launch_mhm_record(static_cast<const double*>(U_pad_dev), static_cast<double*>(U_out_dev),
+                                             n_groups, ghost, make_gas<double>(gamma, theta, dt, dx), nullptr, dx,
+                                             first_order, ws, nullptr, record_dev, static_cast<hipStream_t>(stream)));
+}
+
 // ------------------------------------------------------- other schemes ----
 int64_t hydro_ext_workspace_bytes(int64_t n_groups, int32_t ghost, int32_t dtype, int32_t scheme) {
   gh::ExtOpts o;
   if (n_groups < 0 || ghost > 16 || (dtype != HYDRO_F64 && dtype != HYDRO_F32) ||
       !valid_ext_scheme(scheme, 1.5, ghost, &o))
     return HYDRO_EINVAL;
-  if (fused_ext_scheme(o)) return 0;
+  if (fused_plm_scheme(o)) return 0;
   return gh::ext_workspace_elems(n_groups, ghost, o) * int64_t(dtype_size(dtype));
 }
 
@@ -640,7 +665,7 @@ int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, 
   const size_t es = dtype_size(dtype);
   const double dt_host = dt_dev != nullptr ? 1.0 : dt;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (fused_ext_scheme(o)) {
+  if (fused_plm_scheme(o)) {
     // the fused per-group kernel; the workspace is not used
     if (U_pad_dev == nullptr || U_out_dev == nullptr) return HYDRO_EINVAL;
     const size_t pad_b = size_t(n_groups) * 5 * P * P * P * es, out_b = size_t(n_groups) * 5 * 4096 * es;
@@ -650,14 +675,24 @@ int hydro_advance_ext(const void* U_pad_dev, void* U_out_dev, int64_t n_groups, 
          (overlap(face_flux_dev, ff_b, U_pad_dev, pad_b) || overlap(face_flux_dev, ff_b, U_out_dev, out_b))))
       return HYDRO_EINVAL;
     hipError_t e;
-    if (dtype == HYDRO_F64)
-      e = gh::launch_mhm_fwd(static_cast<const double*>(U_pad_dev), static_cast<double*>(U_out_dev), n_groups, ghost,
-                             make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, o.first_order, o.ws, n_bad_dev,
-                             s, static_cast<double*>(face_flux_dev));
-    else
-      e = gh::launch_mhm_fwd(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups, ghost,
-                             make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, o.first_order, o.ws, n_bad_dev,
-                             s, static_cast<float*>(face_flux_dev));
+    if (fused_ext_scheme(o)) {
+      if (dtype == HYDRO_F64)
+        e = gh::launch_mhm_fwd(static_cast<const double*>(U_pad_dev), static_cast<double*>(U_out_dev), n_groups,
+                               ghost, make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, o.first_order, o.ws,
+                               n_bad_dev, s, static_cast<double*>(face_flux_dev));
+      else
+        e = gh::launch_mhm_fwd(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups,
+                               ghost, make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, o.first_order, o.ws,
+                               n_bad_dev, s, static_cast<float*>(face_flux_dev));
+    } else if (dtype == HYDRO_F64) {
+      e = gh::launch_mhm_fwd_ext(static_cast<const double*>(U_pad_dev), static_cast<double*>(U_out_dev), n_groups,
+                                 ghost, make_gas<double>(gamma, theta, dt_host, dx), dt_dev, dx, o, n_bad_dev, s,
+                                 static_cast<double*>(face_flux_dev));
+    } else {
+      e = gh::launch_mhm_fwd_ext(static_cast<const float*>(U_pad_dev), static_cast<float*>(U_out_dev), n_groups,
+                                 ghost, make_gas<float>(gamma, theta, dt_host, dx), dt_dev, dx, o, n_bad_dev, s,
+                                 static_cast<float*>(face_flux_dev));
+    }
     return device_status(e);
   }
   if (U_pad_dev == nullptr || U_out_dev == nullptr || work_dev == nullptr) return HYDRO_EINVAL;

@@ -23,21 +23,27 @@ __device__ __forceinline__ double fmin_(double a, double b) { return __builtin_f
 __device__ __forceinline__ float fmin_(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double copysign_(double a, double b) { return __builtin_copysign(a, b); }
 __device__ __forceinline__ float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <typename T> struct Fp;
 
-// FP64: hardware reciprocal / reciprocal square root refined by Newton steps
-// (error about 1 ulp, far inside the 1e-12 parity bound) instead of the
+// FP64: hardware reciprocal / reciprocal square root refined by one Newton /
+// Goldschmidt step (relative error about 2^-47, far inside the 1e-12 parity
+// bound; a division corrects its quotient once more) instead of the
 // correctly rounded IEEE sequences, which cost two to three times as many
 // instructions.
 template <> struct Fp<double> {
   // the hardware reciprocal is good to about 2^-24; one Newton step gives
-  // about 2^-48 relative (div corrects its quotient once more)
+  // about 2^-48 relative
   static __device__ __forceinline__ double rcp(double x) {
     const double r = __builtin_amdgcn_rcp(x);
     const double e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
   }
+  // a times the refined reciprocal of b, corrected once with the exact
+  // residual a - b q: nearly always the correctly rounded quotient, and a / a
+  // is exactly 1 (which keeps a stationary contact exactly invariant)
   static __device__ __forceinline__ double div(double a, double b) {
     const double r = rcp(b);
     const double q = a * r;
@@ -49,19 +55,17 @@ template <> struct Fp<double> {
     const double q = a * rb;
     return __builtin_fma(__builtin_fma(-b, q, a), rb, q);
   }
-  // Goldschmidt iteration from the hardware reciprocal square root.  The
-  // estimate is taken at x + 2^-1074, which equals x for every x >= 2^-1020
-  // and keeps it finite at x = 0, where every step then yields 0 (x itself
-  // enters the iteration, so sqrt(+-0) = +-0; negative or NaN x give NaN).
+  // One Goldschmidt step from the hardware reciprocal square root y ~ 1/sqrt(x):
+  // g = x y, h = y/2, r = 1/2 - g h, sqrt(x) ~ g + g r (about 2^-47 relative).
+  // The estimate is taken at x + 2^-1074, which equals x for every x >=
+  // 2^-1020 and keeps it finite at x = 0, where the step then yields 0 (x
+  // itself enters, so sqrt(+-0) = +-0; negative or NaN x give NaN).
   // Subnormal x (never a density or pressure here) get a coarser estimate.
   static __device__ __forceinline__ double sqrt(double x) {
     const double y = __builtin_amdgcn_rsq(x + 0x1p-1074);
-    double g = x * y, h = 0.5 * y;
+    const double g = x * y, h = 0.5 * y;
     const double r = __builtin_fma(-g, h, 0.5);
-    g = __builtin_fma(g, r, g);
-    h = __builtin_fma(h, r, h);
-    const double d = __builtin_fma(-g, g, x);
-    return __builtin_fma(d, h, g);
+    return __builtin_fma(g, r, g);
   }
 };
 
@@ -88,6 +92,16 @@ template <typename T> struct Gas {
   T half_dtdx;  // dt / (2 dx)
 };
 
+// ------------------------------------------------------- branch record ----
+// Diagnostic: a thread folds the code of every decision its arithmetic takes
+// (limiter case and argument, wave-speed argument, HLLC region) into a
+// 32-bit hash (FNV-1a steps), so that two evaluations with equal records took
+// the same branches (up to a hash collision).  A null pointer records
+// nothing and compiles to nothing.
+__device__ __forceinline__ void record(unsigned* rec, unsigned code) {
+  if (rec != nullptr) *rec = (*rec ^ code) * 16777619u;
+}
+
 // ------------------------------------------------- a1: cons -> primitive --
 // W = (rho, u, v, w, p), p = (gamma-1) (E - (m.u)/2).
 template <typename T>
@@ -108,12 +122,23 @@ __device__ __forceinline__ void cons_to_prim(const T U[5], const Gas<T>& g, T W[
 // one-sign test is dm*dp > 0: it differs from testing the signs separately
 // only when the product underflows (|dm|, |dp| < 1e-154 in FP64), where the
 // slope itself is below any resolvable level.
+// Recorded decision: 0 when the slope is zero, else 1 + the argument that
+// attains the minimum (theta|dm|, |dc|, theta|dp|; the first on ties).
 template <typename T>
-__device__ __forceinline__ T half_slope(T qm, T q0, T qp, T half_theta) {
+__device__ __forceinline__ T half_slope(T qm, T q0, T qp, T half_theta, unsigned* rec = nullptr) {
   const T dm = q0 - qm;
   const T dp = qp - q0;
-  T h = fmin_(half_theta * fabs_(dm), T(0.25) * fabs_(qp - qm));
-  h = fmin_(h, half_theta * fabs_(dp));
+  const T a = half_theta * fabs_(dm), b = T(0.25) * fabs_(qp - qm), c = half_theta * fabs_(dp);
+  T h = fmin_(a, b);
+  h = fmin_(h, c);
+  if (rec != nullptr) {
+    unsigned code = 0;
+    if (dm * dp > T(0)) {
+      const T m = b < a ? b : a;
+      code = c < m ? 3u : (b < a ? 2u : 1u);
+    }
+    record(rec, code);
+  }
   return dm * dp > T(0) ? copysign_(h, dp) : T(0);
 }
 
@@ -126,19 +151,19 @@ __device__ __forceinline__ T half_slope(T qm, T q0, T qp, T half_theta) {
 //   dU = dt/(2dx) sum_d [F_d(U_{d,-}) - F_d(U_{d,+})];   Ut = U + dU
 template <typename T>
 __device__ __forceinline__ void hancock_states(const T Wc[5], const T Wn[3][2][5], const Gas<T>& g,
-                                               bool first_order, T Ut[3][2][5]) {
+                                               bool first_order, T Ut[3][2][5], unsigned* rec = nullptr) {
   T s[5];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    T dF[5];
+    T dF[5], h[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      h[q] = first_order ? T(0) : half_slope(Wn[d][0][q], Wc[q], Wn[d][1][q], g.half_theta, rec);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       T W[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        const T h = first_order ? T(0) : half_slope(Wn[d][0][q], Wc[q], Wn[d][1][q], g.half_theta);
-        W[q] = side == 0 ? Wc[q] - h : Wc[q] + h;
-      }
+      for (int q = 0; q < 5; ++q) W[q] = side == 0 ? Wc[q] - h[q] : Wc[q] + h[q];
       T* U = Ut[d][side];
       U[0] = W[0];
       U[1] = W[0] * W[1];
@@ -162,11 +187,10 @@ __device__ __forceinline__ void hancock_states(const T Wc[5], const T Wn[3][2][5
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    const T dU = g.half_dtdx * s[q];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      Ut[d][0][q] = Ut[d][0][q] + dU;
-      Ut[d][1][q] = Ut[d][1][q] + dU;
+      Ut[d][0][q] = fma_(g.half_dtdx, s[q], Ut[d][0][q]);
+      Ut[d][1][q] = fma_(g.half_dtdx, s[q], Ut[d][1][q]);
     }
   }
 }
@@ -188,8 +212,11 @@ __device__ __forceinline__ T max_first(T a, T b) { return b > a ? b : a; }
 //                        E_K + (S* - u_K)(rho_K S* + p_K / (S_K - u_K))),
 // r_K = (S_K - u_K) / (S_K - S*).  Returns true when an input state has
 // rho <= 0 or p <= 0 (or is NaN); the flux is evaluated regardless.
+// Recorded decision: bit 0 S_L from its first argument, bit 1 S_R from its
+// first argument, bits 2-3 the region (0 F_L, 1 F_R, 2 F*_L, 3 F*_R).
 template <int D, typename T>
-__device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<T>& g, int ws, T F[5]) {
+__device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<T>& g, int ws, T F[5],
+                                          unsigned* rec = nullptr) {
   constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
   const T rL = L[0], rR = R[0];
   const T iL = Fp<T>::rcp(rL), iR = Fp<T>::rcp(rR);
@@ -202,9 +229,14 @@ __device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<
   const T cR = Fp<T>::sqrt(g.gamma * pR * iR);
 
   T SL, SR;
+  bool sl_first = true, sr_first = true;
   if (ws == 1) {
     SL = min_first(uL - cL, uR - cR);
     SR = max_first(uL + cL, uR + cR);
+    if (rec != nullptr) {
+      sl_first = !(uR - cR < uL - cL);
+      sr_first = !(uR + cR > uL + cL);
+    }
   } else {
     const T sL = Fp<T>::sqrt(rL), sR = Fp<T>::sqrt(rR);
     const T iw = Fp<T>::rcp(sL + sR);
@@ -215,46 +247,48 @@ __device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<
     const T ca = Fp<T>::sqrt(g.gm1 * (Ha - T(0.5) * (ua * ua + va * va + wa * wa)));
     SL = min_first(uL - cL, ua - ca);
     SR = max_first(uR + cR, ua + ca);
+    if (rec != nullptr) {
+      sl_first = !(ua - ca < uL - cL);
+      sr_first = !(ua + ca > uR + cR);
+    }
   }
   const T aL = SL - uL, aR = SR - uR;
   const T Ss = Fp<T>::div(pR - pL + rL * uL * aL - rR * uR * aR, rL * aL - rR * aR);
 
-  // branch order: S_L >= 0 -> F_L; else S* >= 0 -> F*_L; else S_R > 0 -> F*_R; else F_R
+  // Regions in the order S_L >= 0 -> F_L; else S* >= 0 -> F*_L; else
+  // S_R > 0 -> F*_R; else F_R.  Only one side K enters (left when S_L >= 0 or
+  // S* >= 0): the flux is F_K + Sc (U*_K - U_K) with Sc = S_K in the two star
+  // regions and Sc = 0 in the two supersonic ones, where it is F_K exactly:
+  // there U*_K is formed from S_K - u_K = 0, S* = 0 and the divisor 1, so it
+  // stays finite whenever F_K is (also for an unphysical state whose S* or
+  // S_K is NaN).  One set of selects of the side's inputs replaces three
+  // candidate fluxes.
+  const bool left = SL >= T(0) || Ss >= T(0);
+  const bool star = left ? !(SL >= T(0)) : SR > T(0);
+  const T r = left ? rL : rR, u = left ? uL : uR, p = left ? pL : pR;
+  const T mn = left ? L[n] : R[n], m1 = left ? L[t1] : R[t1], m2 = left ? L[t2] : R[t2];
+  const T E = left ? L[4] : R[4];
+  const T S = left ? SL : SR, a = left ? aL : aR;
+  if (rec != nullptr)
+    record(rec, unsigned(sl_first) | unsigned(sr_first) << 1 | (left ? (star ? 2u : 0u) : (star ? 3u : 1u)) << 2);
+  const T Sc = star ? S : T(0);
+  const T den = star ? S - Ss : T(1);
+  const T Sx = star ? Ss : T(0), ax = star ? a : T(0);
+  // r_K p_K / (S_K - u_K) = p_K / (S_K - S*): the energy term takes the
+  // reciprocal of S_K - S* that r_K's division already formed
+  T t;
+  const T rr = Fp<T>::div(ax, den, t);
+  const T Us0 = rr * r;
+  const T Us1 = rr * (r * Sx);
+  const T Us2 = rr * m1;
+  const T Us3 = rr * m2;
+  const T Us4 = rr * E + (Sx - u) * (Us1 + p * t);
   T Fn[5];
-  if (SL >= T(0)) {
-    Fn[0] = L[n];
-    Fn[1] = L[n] * uL + pL;
-    Fn[2] = L[t1] * uL;
-    Fn[3] = L[t2] * uL;
-    Fn[4] = (L[4] + pL) * uL;
-  } else if (!(Ss >= T(0)) && !(SR > T(0))) {
-    Fn[0] = R[n];
-    Fn[1] = R[n] * uR + pR;
-    Fn[2] = R[t1] * uR;
-    Fn[3] = R[t2] * uR;
-    Fn[4] = (R[4] + pR) * uR;
-  } else {
-    // subsonic: one of the two star fluxes F_K + S_K (U*_K - U_K)
-    const bool left = Ss >= T(0);
-    const T r = left ? rL : rR, u = left ? uL : uR, p = left ? pL : pR;
-    const T mn = left ? L[n] : R[n], m1 = left ? L[t1] : R[t1], m2 = left ? L[t2] : R[t2];
-    const T E = left ? L[4] : R[4];
-    const T S = left ? SL : SR, a = left ? aL : aR;
-    // r_K p_K / (S_K - u_K) = p_K / (S_K - S*): the energy term takes the
-    // reciprocal of S_K - S* that r_K's division already formed
-    T t;
-    const T rr = Fp<T>::div(a, S - Ss, t);
-    const T Us0 = rr * r;
-    const T Us1 = rr * (r * Ss);
-    const T Us2 = rr * m1;
-    const T Us3 = rr * m2;
-    const T Us4 = rr * E + (Ss - u) * (Us1 + p * t);
-    Fn[0] = mn + S * (Us0 - r);
-    Fn[1] = (mn * u + p) + S * (Us1 - mn);
-    Fn[2] = m1 * u + S * (Us2 - m1);
-    Fn[3] = m2 * u + S * (Us3 - m2);
-    Fn[4] = (E + p) * u + S * (Us4 - E);
-  }
+  Fn[0] = mn + Sc * (Us0 - r);
+  Fn[1] = (mn * u + p) + Sc * (Us1 - mn);
+  Fn[2] = m1 * u + Sc * (Us2 - m1);
+  Fn[3] = m2 * u + Sc * (Us3 - m2);
+  Fn[4] = (E + p) * u + Sc * (Us4 - E);
   F[0] = Fn[0];
   F[n] = Fn[1];
   F[t1] = Fn[2];

@@ -115,6 +115,19 @@ hipError_t launch_mhm_fwd(const T* U_pad, T* U_out, int64_t n_groups, int ghost,
                           const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
                           hipStream_t stream, T* face_flux = nullptr);
 
+// The padded step for the other MHM + PLM words (ExtOpts with ctu, ppm and
+// de all 0), in the fused per-group kernel.
+struct ExtOpts;
+template <typename T>
+hipError_t launch_mhm_fwd_ext(const T* U_pad, T* U_out, int64_t n_groups, int ghost, const Gas<T>& gas,
+                              const double* dt_dev, double dx, const ExtOpts& o, int* n_bad, hipStream_t stream,
+                              T* face_flux);
+
+// The padded step that also writes every group's branch record (FP64).
+hipError_t launch_mhm_record(const double* U_pad, double* U_out, int64_t n_groups, int ghost, const Gas<double>& gas,
+                             const double* dt_dev, double dx, int first_order, int ws, int* n_bad, unsigned* record,
+                             hipStream_t stream);
+
 // The other schemes of the scheme word (scheme_ext.hip): workspace size in
 // elements of T for G groups of ghost width `ghost`, and the step.
 struct ExtOpts;

@@ -147,21 +147,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     const int bad = process_group<T, (kWaves >= 4)>(src, L.out + int64_t(g) * 5 * 4096, gl, first_order, ws, sm, smax,
                                                     args.gamma, tid);
     if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
-    if (kCfl && smax != nullptr) {
-      // the level kernel's epilogue, with the folded minimum scaled
-      __syncthreads();
-      if (tid < 8) {
-        double m = 0.0;
-        for (int i = 0; i < 64; ++i) {
-          const double sp = cfl_slots[tid * 64 + i];
-          if (sp > m) m = sp;
-        }
-        const double dt = L.c_cfl_dx / m;
-        if (L.dt_patch != nullptr) L.dt_patch[int64_t(g) * 8 + tid] = dt;
-        if (L.dt_min != nullptr)
-          atomicMin(L.dt_min, (unsigned long long)__double_as_longlong(dt * L.fold_scale));
-      }
-    }
+    if (kCfl && smax != nullptr)
+      cfl_epilogue(cfl_slots, L.c_cfl_dx, L.dt_patch != nullptr ? L.dt_patch + int64_t(g) * 8 : nullptr, L.dt_min,
+                   L.fold_scale, tid);
     // every thread has read item_slot (first barrier of the group step)
     if (taker) item_slot = resolve(ticket);
     __syncthreads();

@@ -5,6 +5,9 @@
 // columns and roles is described at "one patch group" below).
 #pragma once
 
+#include <type_traits>
+
+#include "ext_device.h"
 #include "hydro_device.h"
 #include "kernels.h"
 
@@ -90,6 +93,95 @@ struct Smem {
   T H[5][32];            // high-side states of the last faces: x = 16 (slot y), y = 16 (slot 16 + x)
 };
 
+// ------------------------------------------------------------- schemes ----
+// The march computes one of two families of MHM + PLM steps:
+//   DefaultScheme  generalized minmod on primitive variables and HLLC (the
+//                  limiter specialized in its own inlined copy, see
+//                  process_group), with the optional branch record;
+//   ExtScheme      any MHM + PLM word of the other options (run-time
+//                  ExtOpts: generalized minmod, van Leer, van Albada or
+//                  hybrid limiter, on primitive or characteristic variables;
+//                  HLLC, Roe or HLLE; either wave-speed option; first order):
+//                  the same half step with the slopes of ext_slopes and the
+//                  fluxes of riemann_any.
+struct DefaultScheme {};
+struct ExtScheme {
+  ExtOpts o;
+};
+
+template <typename T>
+__device__ __forceinline__ void scheme_half_step(const DefaultScheme&, const T Wc[5], const T Wn[3][2][5],
+                                                 const Gas<T>& g, bool first_order, T Ut[3][2][5], unsigned* rec) {
+  hancock_states(Wc, Wn, g, first_order, Ut, rec);
+}
+
+// The half step with full limited slopes s: face states Wc -+ s/2 (as the
+// oracle's face values), then hancock_states' conserved form, fluxes and
+// flux differences.
+template <typename T>
+__device__ __forceinline__ void scheme_half_step(const ExtScheme& sch, const T Wc[5], const T Wn[3][2][5],
+                                                 const Gas<T>& g, bool, T Ut[3][2][5], unsigned*) {
+  T sum[5];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T sl[5];
+    if (sch.o.first_order) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sl[q] = T(0);
+    } else if (d == 0) {
+      ext_slopes<0>(Wn[0][0], Wc, Wn[0][1], g, sch.o, sl);
+    } else if (d == 1) {
+      ext_slopes<1>(Wn[1][0], Wc, Wn[1][1], g, sch.o, sl);
+    } else {
+      ext_slopes<2>(Wn[2][0], Wc, Wn[2][1], g, sch.o, sl);
+    }
+    T dF[5];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      T W[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) W[q] = side == 0 ? Wc[q] - T(0.5) * sl[q] : Wc[q] + T(0.5) * sl[q];
+      T* U = Ut[d][side];
+      U[0] = W[0];
+      U[1] = W[0] * W[1];
+      U[2] = W[0] * W[2];
+      U[3] = W[0] * W[3];
+      U[4] = W[4] * g.inv_gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+      const T un = W[1 + d];
+      T F[5];
+      F[0] = U[0] * un;
+      F[1] = U[1] * un;
+      F[2] = U[2] * un;
+      F[3] = U[3] * un;
+      F[1 + d] = F[1 + d] + W[4];
+      F[4] = (U[4] + W[4]) * un;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) dF[q] = side == 0 ? F[q] : dF[q] - F[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sum[q] = d == 0 ? dF[q] : sum[q] + dF[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Ut[d][0][q] = fma_(g.half_dtdx, sum[q], Ut[d][0][q]);
+      Ut[d][1][q] = fma_(g.half_dtdx, sum[q], Ut[d][1][q]);
+    }
+  }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ bool scheme_flux(const DefaultScheme&, const T L[5], const T R[5], const Gas<T>& g, int ws,
+                                            T F[5], unsigned* rec) {
+  return hllc_flux<D>(L, R, g, ws, F, rec);
+}
+template <int D, typename T>
+__device__ __forceinline__ bool scheme_flux(const ExtScheme& sch, const T L[5], const T R[5], const Gas<T>& g, int,
+                                            T F[5], unsigned*) {
+  return riemann_any<D>(L, R, g, sch.o, F);
+}
+
 // ---------------------------------------------------- one patch group ----
 // Workgroup of 256 threads (4 waves; the hardware gives each wave of a
 // workgroup its own SIMD).  Every thread owns one interior (x, y) column; the
@@ -155,12 +247,16 @@ __device__ __forceinline__ int cfl_slot(int tid) {
 
 // Half-step face states of the column's state cell at plane k.  Interior
 // columns also solve the z-face k-1/2 and complete plane k-1.
-template <typename T, bool kI, class Src, int kL>
-__device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& c, const Src& src, T* __restrict__ out, int k,
+template <typename T, bool kI, class Src, int kL, class Sch>
+__device__ __forceinline__ int fwd_col_states(const Sch& sch, FwdCol<T, kI, typename Src::Off>& c, const Src& src, T* __restrict__ out, int k,
                                               const Gas<T>& gas, int first_order, int ws, Smem<T, kL>& sm, double* smax,
-                                              double gamma_d, T* __restrict__ ff) {
+                                              double gamma_d, T* __restrict__ ff, unsigned* rec) {
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
+  // U^n of plane k-1 for its update at the end of this phase, issued first
+  // so that the load's latency overlaps the half step and the z-face solve
+  T Uold[5];
+  if (kI && k >= 1) load_cons(src, c.col, k - 1, Uold);
   // x/y flux differences of plane k-1 (fluxes written last iteration)
   T acc[5];
   if (kI && k >= 1) {
@@ -182,7 +278,7 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
     Wn[2][1][q] = c.Wp[q];
   }
   T Ut[3][2][5];
-  hancock_states(c.Wc, Wn, gas, first_order != 0, Ut);
+  scheme_half_step(sch, c.Wc, Wn, gas, first_order != 0, Ut, rec);
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     sm.S[0][q][sm.si(cx, cy)] = Ut[0][1][q];
@@ -202,7 +298,7 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
   if (kI) {
     if (k >= 0) {
       T Fz1[5];
-      bad += hllc_flux<2>(c.Uz, Ut[2][0], gas, ws, Fz1);
+      bad += scheme_flux<2>(sch, c.Uz, Ut[2][0], gas, ws, Fz1, rec);
       if (ff != nullptr && (k & 7) == 0) {
         // z faces on a patch boundary (z = 0, 8, 16): plane 6 + k/8, entry y*16 + x
         T* o = ff + (6 + (k >> 3)) * 5 * 256 + cy * 16 + cx;
@@ -211,13 +307,11 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
       }
       if (k >= 1) {
         // complete plane k-1: U^{n+1} = U^n - dt/dx [(x) + (y) + (z)]
-        const typename Src::Off o = c.col + src.plane(k - 1);
-        const typename Src::Off fs = src.fstride();
         T Un[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
           const T a = acc[q] + (Fz1[q] - c.Fz0[q]);
-          Un[q] = src.base[o + q * fs] - gas.dtdx * a;
+          Un[q] = Uold[q] - gas.dtdx * a;
           out[q * 4096 + ((k - 1) * 16 + cy) * 16 + cx] = Un[q];
         }
         bad += unphysical(Un, gas);
@@ -239,9 +333,9 @@ __device__ __forceinline__ int fwd_col_states(FwdCol<T, kI, typename Src::Off>& 
 
 // x and y faces of plane k that an interior column solves: its low x and low
 // y face.
-template <typename T, bool kI, typename Off, int kL>
-__device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm,
-                                             T* __restrict__ ff) {
+template <typename T, bool kI, typename Off, int kL, class Sch>
+__device__ __forceinline__ int fwd_col_faces(const Sch& sch, FwdCol<T, kI, Off>& c, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm,
+                                             T* __restrict__ ff, unsigned* rec) {
   if (!kI || k < 0 || k > 15) return 0;
   const int cx = c.cx, cy = c.cy;
   int bad = 0;
@@ -249,7 +343,7 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
     T L[5], F[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sm.si(cx - 1, cy)];
-    bad += hllc_flux<0>(L, c.Ux, gas, ws, F);
+    bad += scheme_flux<0>(sch, L, c.Ux, gas, ws, F, rec);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
     if (ff != nullptr && (cx & 7) == 0) {
@@ -263,7 +357,7 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
     T L[5], F[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sm.si(cx, cy - 1)];
-    bad += hllc_flux<1>(L, c.Uy, gas, ws, F);
+    bad += scheme_flux<1>(sch, L, c.Uy, gas, ws, F, rec);
 #pragma unroll
     for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
     if (ff != nullptr && (cy & 7) == 0) {
@@ -282,9 +376,9 @@ __device__ __forceinline__ int fwd_col_faces(FwdCol<T, kI, Off>& c, int k, const
 // m_y, m_z), the same arithmetic on the same values as the y-normal solver,
 // and the flux rotated back.  The halo wave wrote the high-side states to
 // H; this pass runs on another wave, which has no halo work.
-template <typename T, int kL>
-__device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm,
-                                          T* __restrict__ ff) {
+template <typename T, int kL, class Sch>
+__device__ __forceinline__ int last_faces(const Sch& sch, int lane, int k, const Gas<T>& gas, int ws, Smem<T, kL>& sm,
+                                          T* __restrict__ ff, unsigned* rec) {
   if (k < 0 || k > 15 || lane >= 32) return 0;
   const bool yf = lane >= 16;
   const int i = lane & 15;
@@ -305,7 +399,7 @@ __device__ __forceinline__ int last_faces(int lane, int k, const Gas<T>& gas, in
   Rr[2] = yf ? R[3] : R[2];
   Rr[3] = yf ? R[1] : R[3];
   Rr[4] = R[4];
-  const int bad = hllc_flux<0>(Lr, Rr, gas, ws, F);
+  const int bad = scheme_flux<0>(sch, Lr, Rr, gas, ws, F, rec);
   T* Fb = yf ? &sm.F[1][0][fyidx(i, 16)] : &sm.F[0][0][fxidx(16, i)];
   Fb[0] = F[0];
   Fb[1 * 17 * 16] = yf ? F[3] : F[1];
@@ -339,10 +433,10 @@ enum WaveRole { kRoleHalo = 0, kRoleLastFaces = 1, kRolePlain = 2 };
 // The z-march of one wave: interior role, plus the halo roles (kRoleHalo,
 // wave 0) or the solve of the 32 last faces (kRoleLastFaces, wave 2).  Every
 // instantiation passes the same barriers in the same order.
-template <typename T, class Src, int kRole, int kL>
-__device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, const Gas<T>& gas, int first_order,
+template <typename T, class Src, int kRole, int kL, class Sch>
+__device__ __forceinline__ int march_group(const Sch& sch, const Src& src, T* __restrict__ out, const Gas<T>& gas, int first_order,
                                            int ws, Smem<T, kL>& sm, double* smax, double gamma_d, int tid,
-                                           T* __restrict__ ff) {
+                                           T* __restrict__ ff, unsigned* rec) {
   // halo role: side 0..3 = x-, x+, y-, y+; the column two cells out; lanes
   // 0..3 also one of the 4 edge columns
   const int lane = tid & 63;
@@ -394,13 +488,13 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
     __syncthreads();
 
     // ---- half-step face states of plane k; z-face and update of plane k-1
-    bad += fwd_col_states(ci, src, out, k, gas, first_order, ws, sm, smax, gamma_d, ff);
-    if (kHalo) bad += fwd_col_states(ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d, (T*)nullptr);
+    bad += fwd_col_states(sch, ci, src, out, k, gas, first_order, ws, sm, smax, gamma_d, ff, rec);
+    if (kHalo) bad += fwd_col_states(sch, ch, src, out, k, gas, first_order, ws, sm, nullptr, gamma_d, (T*)nullptr, rec);
     __syncthreads();
 
     // ---- x and y faces of plane k
-    bad += fwd_col_faces(ci, k, gas, ws, sm, ff);
-    if (kRole == kRoleLastFaces) bad += last_faces(lane, k, gas, ws, sm, ff);
+    bad += fwd_col_faces(sch, ci, k, gas, ws, sm, ff, rec);
+    if (kRole == kRoleLastFaces) bad += last_faces(sch, lane, k, gas, ws, sm, ff, rec);
 
     fwd_col_shift(ci);
     if (kHalo) fwd_col_shift(ch);
@@ -431,44 +525,90 @@ __device__ __forceinline__ int march_group(const Src& src, T* __restrict__ out, 
 // waves per SIMD (FP32, high occupancy) the step is 6-8% faster; with two
 // (FP64, FP32 low occupancy) 2-5% slower, so those kernels keep equal
 // priorities.
-template <typename T, bool kPrio, class Src, int kL>
-__device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
-                                             int first_order, int ws, Smem<T, kL>& sm, double* smax,
-                                             double gamma_d, int tid = threadIdx.x, T* __restrict__ ff = nullptr) {
+template <typename T, bool kPrio, class Src, int kL, class Sch>
+__device__ __forceinline__ int march_roles(const Sch& sch, const Src& src, T* __restrict__ out, const Gas<T>& gas,
+                                           int first_order, int ws, Smem<T, kL>& sm, double* smax, double gamma_d,
+                                           int tid, T* __restrict__ ff, unsigned* rec) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if constexpr (kPrio) {
     if (wave == 0) __builtin_amdgcn_s_setprio(2);
     if (wave == 2) __builtin_amdgcn_s_setprio(1);
   }
-  if (first_order == 0) {
-    if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff);
-    if (wave == 2) return march_group<T, Src, kRoleLastFaces>(src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff);
-    return march_group<T, Src, kRolePlain>(src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff);
+  if constexpr (!std::is_same<Sch, DefaultScheme>::value) {
+    // the other words: one copy (their options are run-time anyway)
+    if (wave == 0) return march_group<T, Src, kRoleHalo>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    if (wave == 2)
+      return march_group<T, Src, kRoleLastFaces>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    return march_group<T, Src, kRolePlain>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+  } else {
+    if (first_order == 0) {
+      if (wave == 0) return march_group<T, Src, kRoleHalo>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
+      if (wave == 2)
+        return march_group<T, Src, kRoleLastFaces>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
+      return march_group<T, Src, kRolePlain>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
+    }
+    if (wave == 0)
+      return march_group<T, Src, kRoleHalo>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    if (wave == 2)
+      return march_group<T, Src, kRoleLastFaces>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    return march_group<T, Src, kRolePlain>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
   }
-  if (wave == 0) return march_group<T, Src, kRoleHalo>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff);
-  if (wave == 2)
-    return march_group<T, Src, kRoleLastFaces>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff);
-  return march_group<T, Src, kRolePlain>(src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff);
+}
+
+// rec_out (diagnostic, optional): the group's branch record -- every
+// thread's decisions hashed in its own order (record()), the threads' hashes
+// combined by XOR, which is independent of the order they arrive in.
+template <typename T, bool kPrio, class Src, int kL, class Sch = DefaultScheme>
+__device__ __forceinline__ int process_group(const Src& src, T* __restrict__ out, const Gas<T>& gas,
+                                             int first_order, int ws, Smem<T, kL>& sm, double* smax,
+                                             double gamma_d, int tid = threadIdx.x, T* __restrict__ ff = nullptr,
+                                             unsigned* __restrict__ rec_out = nullptr, const Sch& sch = Sch()) {
+  if (rec_out == nullptr)
+    return march_roles<T, kPrio>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, nullptr);
+  __shared__ unsigned grp_rec;
+  if (tid == 0) grp_rec = 0u;  // the march's first barrier orders this before any XOR
+  unsigned h = 2166136261u ^ (unsigned(tid) * 0x9E3779B9u);
+  const int bad = march_roles<T, kPrio>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, &h);
+  atomicXor(&grp_rec, h);
+  __syncthreads();
+  if (tid == 0) *rec_out = grp_rec;
+  return bad;
 }
 
 // Reduce the per-thread signal-speed maxima of one group (the LDS array
-// `slots` of cfl_slot's layout, 512 doubles) to its 8 patch time-steps (patch
-// p = (pz*2 + py)*2 + px).  Optionally stores dt_patch[8] and folds the
-// minimum into *dt_min (integer minimum of non-negative doubles: exact and
-// order-independent).
+// `slots` of cfl_slot's layout, 512 doubles: patch p = (pz*2 + py)*2 + px owns
+// slots [64 p, 64 p + 64)) to its 8 patch time-steps.  Wave w reduces patches
+// 2w and 2w+1 across its 64 lanes by butterfly shuffles (a maximum is exact
+// in any order; NaN and negative speeds count as 0, as in a scan from 0).
+// Lane 0 stores dt_patch[p] (optional) and folds dt * fold_scale into
+// *dt_min (optional; integer minimum of non-negative doubles: exact and
+// order-independent).  Every thread of the workgroup must call it.
 __device__ __forceinline__ void cfl_epilogue(const double* slots, double c_cfl_dx,
-                                             double* __restrict__ dt_patch, unsigned long long* __restrict__ dt_min) {
-  const int tid = threadIdx.x;
+                                             double* __restrict__ dt_patch, unsigned long long* __restrict__ dt_min,
+                                             double fold_scale = 1.0, int tid = threadIdx.x) {
   __syncthreads();
-  if (tid < 8) {
-    double m = 0.0;
-    for (int i = 0; i < 64; ++i) {
-      const double s = slots[tid * 64 + i];
-      if (s > m) m = s;
+  const int w = tid >> 6, l = tid & 63;
+  double m[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double v = slots[(2 * w + j) * 64 + l];
+    m[j] = v > 0.0 ? v : 0.0;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double o = __shfl_xor(m[j], off, 64);
+      m[j] = o > m[j] ? o : m[j];
     }
-    const double dt = c_cfl_dx / m;
-    if (dt_patch != nullptr) dt_patch[tid] = dt;
-    if (dt_min != nullptr) atomicMin(dt_min, (unsigned long long)__double_as_longlong(dt));
+  }
+  if (l == 0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double dt = c_cfl_dx / m[j];
+      if (dt_patch != nullptr) dt_patch[2 * w + j] = dt;
+      if (dt_min != nullptr) atomicMin(dt_min, (unsigned long long)__double_as_longlong(dt * fold_scale));
+    }
   }
 }
 

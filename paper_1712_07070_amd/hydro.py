@@ -84,6 +84,7 @@ def load():
         "hydro_ctx_num_tuned": (i32, [P]),
         "hydro_check_unphysical": (i32, [P, P, P]),
         "hydro_advance": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P, P]),
+        "hydro_branch_record": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, P, P]),
         "hydro_ext_workspace_bytes": (i64, [i64, i32, i32, i32]),
         "hydro_advance_ext": (i32, [P, P, i64, i32, i32, f64, f64, f64, i32, f64, f64, P, P, P, i64, P, P]),
         "hydro_repair_unphysical": (i32, [P, P, i32, i32, i32, P, i32, f64, f64, f64, i32, P, P, P]),
@@ -253,6 +254,30 @@ def advance(U_pad: torch.Tensor, dt: float, dx: float, gamma: float, theta: floa
                               _opt(dt_dev, "dt_dev", torch.float64), _opt(n_bad, "n_bad", torch.int32), _stream())
     _check(st, "hydro_advance")
     return out
+
+
+def branch_record(U_pad: torch.Tensor, dt: float, dx: float, gamma: float, theta: float = 1.5,
+                  scheme: int = SCHEME_MHM_PLM_HLLC, out: Optional[torch.Tensor] = None,
+                  record: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """advance (FP64) that also returns every group's branch record, an int32
+    [G] device tensor (hydro_branch_record): equal records, equal branches."""
+    gh = ghost_of(U_pad)
+    G = U_pad.shape[0]
+    if U_pad.dtype != torch.float64:
+        raise ValueError("branch_record runs in FP64")
+    if out is None:
+        out = torch.empty((G, 5, 16, 16, 16), dtype=U_pad.dtype, device=U_pad.device)
+    if record is None:
+        record = torch.empty(G, dtype=torch.int32, device=U_pad.device)
+    if out.dtype != U_pad.dtype or tuple(out.shape) != (G, 5, 16, 16, 16):
+        raise ValueError("out must be [G,5,16,16,16] of the input dtype")
+    if record.dtype != torch.int32 or record.numel() < G:
+        raise ValueError("record must hold G int32")
+    st = load().hydro_branch_record(_dev(U_pad, "U_pad"), _dev(out, "out"), G, gh, _dtype_code(U_pad), float(dt),
+                                    float(dx), float(gamma), int(scheme), float(theta), _dev(record, "record"),
+                                    _stream())
+    _check(st, "hydro_branch_record")
+    return out, record
 
 
 def ext_workspace(n_groups: int, ghost: int, dtype, scheme: int, device="cuda") -> torch.Tensor:

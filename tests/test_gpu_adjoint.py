@@ -418,3 +418,83 @@ def test_fp32_level_adjoint_turbulence_384_sampled(hydro):
     err = np.abs(got - ref) / (np.abs(ref) + scale[fields])
     say("  max scaled error %.2e, median %.2e" % (err.max(), np.median(err)))
     assert err.max() <= 1e-4, err.max()
+
+
+def test_branch_record_equals_advance_and_repeats(hydro):
+    """The recording step writes hydro_advance's state bit for bit, and its
+    records repeat exactly; a perturbation that flips a limiter case (v_x,
+    uniform in this workload, raised by 1e-7 and 2e-7 in two neighbouring
+    cells: the first cell's one-sided differences become equal and
+    positive, so its v_x slope turns from zero to active) changes the record
+    of the perturbed group and of no other (no other group reads those
+    cells)."""
+    say("branch record")
+    lv, _ = W.smooth_wave(64)
+    pad = hydro.fill_ghosts(dev(lv.U), lv.ng, 3, lv.bc)
+    dt = 0.2 * lv.dx
+    ref = hydro.advance(pad, dt, lv.dx, lv.gamma)
+    out, r1 = hydro.branch_record(pad, dt, lv.dx, lv.gamma)
+    _, r2 = hydro.branch_record(pad, dt, lv.dx, lv.gamma)
+    assert torch.equal(out, ref) and torch.equal(r1, r2)
+    U = lv.U.copy()
+    U[5, 1, 8, 8, 8] += 1e-7 * U[5, 0, 8, 8, 8]
+    U[5, 1, 8, 8, 9] += 2e-7 * U[5, 0, 8, 8, 9]
+    pad2 = hydro.fill_ghosts(dev(U), lv.ng, 3, lv.bc)
+    _, r3 = hydro.branch_record(pad2, dt, lv.dx, lv.gamma)
+    diff = (r3 != r1).nonzero().flatten().tolist()
+    assert diff == [5], diff
+
+
+def _fd_gpu_record_protocol(hydro, lv, target, n_steps, draws, eps=1e-7, seed=20171223):
+    """_fd_branch_protocol with the rejection taken from the library's branch
+    records of the +eps and -eps rollouts (every group, every step)."""
+    U0 = lv.U
+    dt = 0.2 * lv.dx
+    tgt = dev(target)
+    x = dev(U0).requires_grad_(True)
+    out = hydro.Rollout.apply(x, lv.ng, lv.bc, n_steps, dt, lv.dx, lv.gamma, 4)
+    ((out[:, 0] - tgt) ** 2).sum().backward()
+    grad = host(x.grad)
+    rng = np.random.default_rng(seed)
+
+    def run(U):
+        s = dev(U)
+        recs = []
+        for _ in range(n_steps):
+            s, r = hydro.branch_record(hydro.fill_ghosts(s, lv.ng, 3, lv.bc), dt, lv.dx, lv.gamma)
+            recs.append(r)
+        return s[:, 0] - tgt, torch.stack(recs)
+
+    acc, rejected = [], 0
+    for _ in range(draws):
+        idx = tuple(int(rng.integers(0, s)) for s in U0.shape)
+        up, um = U0.copy(), U0.copy()
+        up[idx] += eps
+        um[idx] -= eps
+        (rp, sp), (rm, sm) = run(up), run(um)
+        if not torch.equal(sp, sm):
+            rejected += 1
+            continue
+        fd = float(((rp - rm) * (rp + rm)).sum()) / (2 * eps)
+        acc.append((idx[1], fd, float(grad[idx])))
+    key = [0, 1, 1, 1, 4]
+    ref = {}
+    for f, _, gv in acc:
+        ref[key[f]] = max(ref.get(key[f], 0.0), abs(gv))
+    return rejected, [abs(fd - gv) / (abs(gv) + ref[key[f]]) for f, fd, gv in acc]
+
+
+@pytest.mark.parametrize("smooth_vp", [0.0, 0.01])
+def test_rollout_fd_with_library_branch_records(hydro, smooth_vp):
+    """The FD protocol the bench runs: rejection from the GPU's own branch
+    records; every accepted draw agrees to 1e-6 (as stated: nearly all draws
+    straddle a switch; smooth v and p: nearly none)."""
+    say("rollout fd, library branch records, smooth_vp", smooth_vp)
+    lv, target = W.smooth_wave(64, smooth_vp=smooth_vp) if smooth_vp else W.smooth_wave(64)
+    rejected, errs = _fd_gpu_record_protocol(hydro, lv, target, 8, 24)
+    say("  rejected %d of 24, accepted errors %s" % (rejected, ["%.1e" % e for e in errs]))
+    assert all(e <= 1e-6 for e in errs), errs
+    if smooth_vp:
+        assert len(errs) >= 16
+    else:
+        assert rejected >= 1
