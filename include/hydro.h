@@ -610,7 +610,9 @@ int hydro_variant_name(int32_t variant, char* buf, int32_t len);
  * HIP events on `stream`, 1 <= reps <= 1000; a shape's time is the smaller of
  * its two means), record the fastest in ctx (non-NULL) for `dtype` and this
  * lattice and return its index (>= 0), or a negative status (nothing is
- * recorded).  Both kernel forms are timed and tuned separately (without and
+ * recorded).  Shapes within 1.5% of the fastest count as ties, resolved to
+ * the lowest-numbered XCD-blocked shape (the timing relaunches one cached
+ * input, where the plain order's extra HBM reads hardly show).  Both kernel forms are timed and tuned separately (without and
  * with the CFL epilogue; the returned index is the CFL form's).  SYNCHRONOUS:
  * waits on `stream`; allocates nothing on the device.  level_dev is read,
  * scratch_out_dev ([G][5][16^3]) is overwritten, cfl_scratch_dev receives the

@@ -1104,6 +1104,12 @@ class AmrSolver:
         """One coarse step of dt0 (asynchronous on the current stream)."""
         self._advance(0, float(dt0), None, None, 0.0, None)
 
+    def capture(self, dt0: float, n_coarse: int = 1, ctx: Optional[Context] = None) -> Graph:
+        """Graph of n_coarse coarse steps of dt0 (every launch of the W-cycle,
+        the level copies and register clears included); each replay advances
+        the hierarchy by n_coarse steps in place.  Nothing runs at capture."""
+        return Graph(ctx).capture(lambda: [self.step(dt0) for _ in range(n_coarse)])
+
     def _advance(self, l, dt, cold, cnew, a, R_parent):
         lib, s = load(), _stream()
         code = _dtype_code(self.U[l])

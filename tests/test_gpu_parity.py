@@ -448,9 +448,18 @@ def test_autotune_selects_a_shape(hydro):
         n = hydro.num_variants()
         assert 0 <= best < n and len(times) == 2 * n
         assert hydro.get_variant(torch.float64) == best == hydro.get_level_variant(torch.float64, True)
-        assert all(x > 0 for x in times) and times[n + best] == min(times[n:])
-        b0 = hydro.get_level_variant(torch.float64, False)
-        assert times[b0] == min(times[:n])
+        assert all(x > 0 for x in times)
+
+        def expected(ts):
+            # the fastest shape, or the lowest-numbered XCD-blocked (even)
+            # shape within 1.5% of it
+            ts = np.asarray(ts, np.float32)
+            fastest = int(np.argmin(ts))
+            tie = np.float32(1.015) * ts[fastest]
+            return next((v for v in range(0, n, 2) if ts[v] <= tie), fastest)
+
+        assert best == expected(times[n:])
+        assert hydro.get_level_variant(torch.float64, False) == expected(times[:n])
     finally:
         hydro.set_variant(torch.float64, saved)
 
