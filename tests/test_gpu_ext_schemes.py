@@ -161,10 +161,11 @@ def test_ext_argument_errors(hydro):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("name", ["ppm-char-hybrid", "ctu-roe"])
+@pytest.mark.parametrize("name", ["ppm-char-hybrid", "ctu-roe", "char-vanleer", "hlle-davis"])
 def test_ext_shear_layer_256_sampled(hydro, name, dtype):
     """The 256^3 shear layer (4096 groups) in one call; 12 sampled groups
-    against the oracle on their own padded blocks."""
+    against the oracle on their own padded blocks (PPM and CTU words through
+    the chain of kernels, the others through the fused kernel)."""
     say("ext 256^3", name, dtype.__name__)
     sch = SCHEMES[name]
     lv = W.shear_layer(256)
