@@ -124,6 +124,9 @@ def parse():
     ap.add_argument("--counter-sweep", type=int, default=0, metavar="REPS",
                     help="only launch every shape of the fused level step (with the CFL epilogue), FP64 then FP32, "
                          "REPS launches each in a fixed order, for hardware-counter runs")
+    ap.add_argument("--adjoint-counter-run", type=int, default=0, metavar="REPS",
+                    help="only launch the forward level step and the step adjoint (fused form) REPS times each on "
+                         "the 128^3 FP64 smooth wave and the 384^3 FP32 turbulence state, for hardware-counter runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="after the run, copy a device buffer of this size (reference for HBM byte counters)")
     return ap.parse_args()
@@ -652,6 +655,39 @@ def counter_sweep(hydro, torch, W, n, reps, calibrate_mib):
                       "copy_calibration_bytes": calibrate_mib * (1 << 20)}), flush=True)
 
 
+def adjoint_counter_run(hydro, torch, W, reps, calibrate_mib):
+    """Forward level step, then step adjoint (fused form), `reps` launches
+    each, on the 128^3 FP64 smooth wave and then the 384^3 FP32 turbulence
+    state (the differentiation workloads), then the calibration copy."""
+    order = []
+    for name, lv, dtype in (("smooth128_f64", W.smooth_wave(128)[0], np.float64),
+                            ("turb384_f32", W.turbulence(384), np.float32)):
+        U = torch.from_numpy(np.ascontiguousarray(lv.U.astype(dtype))).cuda()
+        tdt = U.dtype
+        dt = float(hydro.cfl_dt(U, lv.dx, lv.gamma, 0.5).min())
+        O = torch.empty_like(U)
+        g = torch.ones_like(U)
+        gi = torch.empty_like(U)
+        work = hydro.adjoint_workspace(lv.n_groups, tdt, True)
+        hydro.set_adjoint_variant(tdt, 0)
+        for _ in range(reps):
+            hydro.advance_level(U, lv.ng, lv.bc, dt, lv.dx, lv.gamma, out=O)
+        for _ in range(reps):
+            hydro.advance_level_adjoint(U, g, lv.ng, lv.bc, dt, lv.dx, lv.gamma, out=gi, work=work)
+        torch.cuda.synchronize()
+        order.append({"workload": name, "groups": lv.n_groups, "launches": reps})
+        del U, O, g, gi, work
+        torch.cuda.empty_cache()
+    if calibrate_mib > 0:
+        m = calibrate_mib * (1 << 20) // 8
+        src = torch.ones(m, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    print(json.dumps({"adjoint_counter_run": order, "copy_calibration_bytes": calibrate_mib * (1 << 20)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -666,6 +702,9 @@ def main():
         sys.exit(1)
     if args.counter_sweep > 0:
         counter_sweep(hydro, torch, W, args.n, args.counter_sweep, args.calibrate_copy)
+        return
+    if args.adjoint_counter_run > 0:
+        adjoint_counter_run(hydro, torch, W, args.adjoint_counter_run, args.calibrate_copy)
         return
     print("bench: building workload", file=sys.stderr, flush=True)
     lv = W.shear_layer(args.n)
