@@ -586,8 +586,10 @@ int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t
  * in the order groups are dealt to workgroups (bit 0: plain, or blocked so
  * that each of the 8 XCDs sweeps a contiguous range of groups and finds
  * neighbour-group halos in its own L2; bit 2: linear, or brick by brick of
- * 2x2x2 groups) and in the LDS layout of the plane tiles (bit 3: packed rows,
- * or rows padded by one element).  The choice is per context, per dtype and per kernel form
+ * 2x2x2 groups), in the LDS layout of the plane tiles (bit 3: packed rows,
+ * or rows padded by one element) and in the threads per workgroup (bit 4:
+ * 256, one group per workgroup, or 512, two groups marched side by side
+ * with their own LDS and shared barriers).  The choice is per context, per dtype and per kernel form
  * (with_cfl: the form that reduces the next CFL time-step, which needs more
  * registers and 4 KB more LDS per workgroup).  Setters need a context;
  * getters with ctx NULL return the default (XCD-blocked, high occupancy).

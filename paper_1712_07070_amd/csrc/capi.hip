@@ -1044,9 +1044,10 @@ int hydro_set_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant) {
 
 int hydro_variant_name(int32_t variant, char* buf, int32_t len) {
   if (variant < 0 || variant >= gh::kLevelVariants || buf == nullptr || len < 1) return HYDRO_EINVAL;
-  std::snprintf(buf, size_t(len), "%s %s order, %s occupancy target, %s LDS rows",
+  std::snprintf(buf, size_t(len), "%s %s order, %s occupancy target, %s LDS rows, %s per workgroup",
                 (variant & 1) ? "plain" : "xcd-blocked", (variant & 4) ? "brick" : "linear",
-                (variant & 2) ? "low" : "high", (variant & 8) ? "padded" : "packed");
+                (variant & 2) ? "low" : "high", (variant & 8) ? "padded" : "packed",
+                (variant & 16) ? "2 groups (512 threads)" : "1 group (256 threads)");
   return HYDRO_OK;
 }
 

@@ -99,8 +99,9 @@ hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGe
 // bit 0 set = groups in plain order instead of XCD-blocked order,
 // bit 1 set = lower occupancy target for the register allocator,
 // bit 2 set = groups in brick order (2x2x2 bricks of groups),
-// bit 3 set = LDS tiles with padded rows.
-constexpr int kLevelVariants = 16;
+// bit 3 set = LDS tiles with padded rows,
+// bit 4 set = two groups per 512-thread workgroup.
+constexpr int kLevelVariants = 32;
 // Batched kernel: ticket queues (one per XCD of MI355X), launch-shape variants
 // (bit 0 item order, bit 1 occupancy target, bits 2-3 queue mode: one queue,
 // per-XCD queues, static round-robin) and the uint32 words of its work buffer

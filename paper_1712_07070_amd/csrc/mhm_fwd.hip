@@ -36,7 +36,7 @@
 //     written or read back.  Optionally the same kernel reduces the CFL
 //     time-step (a8) of the cells it writes, for the next step.
 
-#include "mhm_group.h"
+#include "mhm_level.h"
 
 namespace gh {
 
@@ -84,93 +84,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
 }
 
-// Groups are assigned to workgroups so that each XCD (workgroups are dealt
-// to the 8 XCDs round-robin) sweeps a contiguous range of groups: halo cells
-// read from a neighbouring group then mostly hit the same XCD's L2.
-__device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t G) {
-  const int64_t per = (G + 7) / 8;
-  const int64_t g = (b & 7) * per + (b >> 3);
-  return g;
-}
-
-// Brick order of the groups of a level: the lattice is cut into 2x2x2 bricks
-// of groups, visited brick by brick (x fastest), the 8 groups of a brick x
-// fastest, so that the groups running together share more of their halo
-// cells.  A slot of a partial brick at an odd lattice edge holds no group.
-__device__ __forceinline__ int64_t brick_slots(const LevelGeom& geo) {
-  return int64_t(8) * ((geo.ngx + 1) >> 1) * ((geo.ngy + 1) >> 1) * ((geo.ngz + 1) >> 1);
-}
-__device__ __forceinline__ int64_t brick_group(int64_t s, const LevelGeom& geo) {
-  const int bx = (geo.ngx + 1) >> 1, by = (geo.ngy + 1) >> 1;
-  const int64_t br = s >> 3, bxy = int64_t(bx) * by;
-  const int l = int(s & 7);
-  const int cz = int(br / bxy), rem = int(br % bxy);
-  const int gx = 2 * (rem % bx) + (l & 1), gy = 2 * (rem / bx) + ((l >> 1) & 1), gz = 2 * cz + (l >> 2);
-  if (gx >= geo.ngx || gy >= geo.ngy || gz >= geo.ngz) return -1;
-  return (int64_t(gz) * geo.ngy + gy) * geo.ngx + gx;
-}
-
-// order: bit 0 XCD-blocked (else plain), bit 1 brick order of the groups
-template <typename T, bool kCfl, int kWaves, typename Off, int kL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_level_kernel(const T* __restrict__ level, T* __restrict__ level_out,
-                                                             LevelGeom geo, Gas<T> gas,
-                                                             const double* __restrict__ dt_dev, double dx,
-                                                             int first_order, int ws, int* __restrict__ n_bad,
-                                                             CflOut cfl, int order) {
-  __shared__ Smem<T, kL> sm;
-  set_dt(gas, dt_dev, dx);
-  if (kCfl && cfl.reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cfl.reset = 0x7ff0000000000000ull;
-  const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
-  const int64_t slots = (order & 2) ? brick_slots(geo) : G;
-  int64_t g = (order & 1) ? xcd_group(blockIdx.x, slots) : int64_t(blockIdx.x);
-  if (g >= slots) return;  // whole workgroup leaves together (g is uniform)
-  if (order & 2) {
-    g = brick_group(g, geo);
-    if (g < 0) return;
-  }
-  LevelSource<T, Off> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy),
-                          int(g / (int64_t(geo.ngx) * geo.ngy))};
-  __shared__ double cfl_slots[kCfl ? 2 * kCflHalfStride : 1];
-  double* smax = nullptr;
-  if (kCfl) {
-    smax = cfl_slots + cfl_slot(threadIdx.x);
-    smax[0] = 0.0;
-    smax[kCflHalfStride] = 0.0;
-  }
-  const int bad = process_group<T, (kWaves >= 4)>(src, level_out + g * 5 * 4096, gas, first_order, ws, sm, smax,
-                                                  cfl.gamma);
-  if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
-  if (kCfl)
-    cfl_epilogue(cfl_slots, cfl.c_cfl_dx, cfl.dt_patch != nullptr ? cfl.dt_patch + g * 8 : nullptr, cfl.dt_min);
-}
-
-template <typename T, bool kCfl, typename Off, int kL>
-void launch_level_lds(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas, const double* dt_dev,
-                      double dx, int first_order, int ws, int* n_bad, const CflOut& cfl, int variant, int64_t blocks,
-                      int order, hipStream_t stream) {
-  if (variant & 2)
-    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::lo, Off, kL>), dim3(unsigned(blocks)), dim3(kThreads),
-                       0, stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, order);
-  else
-    hipLaunchKernelGGL((mhm_level_kernel<T, kCfl, MinWaves<T>::hi, Off, kL>), dim3(unsigned(blocks)), dim3(kThreads),
-                       0, stream, level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, order);
-}
-
 template <typename T, bool kCfl, typename Off>
 void launch_level_shape(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
                         const double* dt_dev, double dx, int first_order, int ws, int* n_bad, const CflOut& cfl,
                         int variant, int64_t blocks, int order, hipStream_t stream) {
-  if (variant & 8)
-    launch_level_lds<T, kCfl, Off, 1>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, variant,
-                                      blocks, order, stream);
+  if (variant & 16)
+    launch_level_shape_g2<T, kCfl, Off>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, variant,
+                                        blocks, order, stream);
+  else if (variant & 8)
+    launch_level_lds<T, kCfl, Off, 1, 1>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl,
+                                         variant, blocks, order, stream);
   else
-    launch_level_lds<T, kCfl, Off, 0>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl, variant,
-                                      blocks, order, stream);
+    launch_level_lds<T, kCfl, Off, 0, 1>(level, level_out, geo, gas, dt_dev, dx, first_order, ws, n_bad, cfl,
+                                         variant, blocks, order, stream);
 }
 
 // Launch shapes (bit-identical results): bit 0 plain group order (else
 // XCD-blocked), bit 1 low occupancy target, bit 2 brick order of the groups,
-// bit 3 padded LDS rows.
+// bit 3 padded LDS rows, bit 4 two groups per 512-thread workgroup.
 template <typename T, bool kCfl>
 hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
                                 const double* dt_dev, double dx, int first_order, int ws, int* n_bad,
@@ -178,9 +109,11 @@ hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& g
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   const int xcd = (variant & 1) ? 0 : 1;
   const int brick = (variant & 4) ? 1 : 0;
+  const int gpw = (variant & 16) ? 2 : 1;
   const int64_t slots =
       brick ? int64_t(8) * ((geo.ngx + 1) >> 1) * ((geo.ngy + 1) >> 1) * ((geo.ngz + 1) >> 1) : G;
-  const int64_t blocks = xcd ? ((slots + 7) / 8) * 8 : slots;
+  const int64_t wslots = (slots + gpw - 1) / gpw;
+  const int64_t blocks = xcd ? ((wslots + 7) / 8) * 8 : wslots;
   const int order = xcd | (brick << 1);
   if (blocks > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
   // 32-bit element offsets when every element of the level has one
