@@ -66,7 +66,7 @@ def kernel_source_sha() -> str:
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("hydro_device.h", "mhm_group.h", "mhm_fwd.hip"):
+    for f in ("hydro_device.h", "ext_device.h", "mhm_group.h", "mhm_level.h", "mhm_fwd.hip"):
         with open(os.path.join(ROOT, "paper_1712_07070_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
