@@ -205,55 +205,95 @@ template <typename T>
 __device__ __forceinline__ T max_first(T a, T b) { return b > a ? b : a; }
 
 // ------------------------------------------------------------- a5: HLLC ---
-// HLLC flux across a face normal to axis D between left state L and right
-// state R (conserved).  Normal frame (n, t1, t2) = (D, D+1, D+2) mod 3.
+// HLLC flux between left state L and right state R (conserved) for K
+// independent faces, each given in its normal frame (index 1 the normal
+// momentum, 2 and 3 the transverse ones in cyclic order).
 // Wave speeds: Einfeldt / Roe-averaged (ws == 0) or Davis (ws == 1).
 // Star state U*_K = r_K (rho_K, rho_K S*, m_t1, m_t2,
 //                        E_K + (S* - u_K)(rho_K S* + p_K / (S_K - u_K))),
-// r_K = (S_K - u_K) / (S_K - S*).  Returns true when an input state has
-// rho <= 0 or p <= 0 (or is NaN); the flux is evaluated regardless.
-// Recorded decision: bit 0 S_L from its first argument, bit 1 S_R from its
-// first argument, bits 2-3 the region (0 F_L, 1 F_R, 2 F*_L, 3 F*_R).
-template <int D, typename T>
-__device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<T>& g, int ws, T F[5],
-                                          unsigned* rec = nullptr) {
-  constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
-  const T rL = L[0], rR = R[0];
-  const T iL = Fp<T>::rcp(rL), iR = Fp<T>::rcp(rR);
-  const T uL = L[n] * iL, vL = L[t1] * iL, wL = L[t2] * iL;
-  const T uR = R[n] * iR, vR = R[t1] * iR, wR = R[t2] * iR;
-  const T pL = g.gm1 * (L[4] - T(0.5) * (L[n] * uL + L[t1] * vL + L[t2] * wL));
-  const T pR = g.gm1 * (R[4] - T(0.5) * (R[n] * uR + R[t1] * vR + R[t2] * wR));
-  const bool bad = !(rL > T(0) && pL > T(0) && rR > T(0) && pR > T(0));
-  const T cL = Fp<T>::sqrt(g.gamma * pL * iL);
-  const T cR = Fp<T>::sqrt(g.gamma * pR * iR);
+// r_K = (S_K - u_K) / (S_K - S*).  bad[k] is set when an input state of face
+// k has rho <= 0 or p <= 0 (or is NaN); the flux is evaluated regardless.
+// Every statement is taken for each face in turn: the K dependency chains
+// share instruction blocks, so one face's latencies can be filled with
+// another's work (a face solved alone leaves the wave waiting on each FP64
+// result in turn).  The arithmetic of each face is that of one solve.
+// Recorded decision per face: bit 0 S_L from its first argument, bit 1 S_R
+// from its first argument, bits 2-3 the region (0 F_L, 1 F_R, 2 F*_L, 3 F*_R).
+template <int K, typename T>
+__device__ __forceinline__ void hllc_normal_k(const T L[K][5], const T R[K][5], const Gas<T>& g, int ws, T Fn[K][5],
+                                              bool bad[K], unsigned* rec) {
+  T rL[K], rR[K], iL[K], iR[K], uL[K], vL[K], wL[K], uR[K], vR[K], wR[K], pL[K], pR[K], cL[K], cR[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    rL[k] = L[k][0];
+    rR[k] = R[k][0];
+    iL[k] = Fp<T>::rcp(rL[k]);
+    iR[k] = Fp<T>::rcp(rR[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    uL[k] = L[k][1] * iL[k], vL[k] = L[k][2] * iL[k], wL[k] = L[k][3] * iL[k];
+    uR[k] = R[k][1] * iR[k], vR[k] = R[k][2] * iR[k], wR[k] = R[k][3] * iR[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    pL[k] = g.gm1 * (L[k][4] - T(0.5) * (L[k][1] * uL[k] + L[k][2] * vL[k] + L[k][3] * wL[k]));
+    pR[k] = g.gm1 * (R[k][4] - T(0.5) * (R[k][1] * uR[k] + R[k][2] * vR[k] + R[k][3] * wR[k]));
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    bad[k] = !(rL[k] > T(0) && pL[k] > T(0) && rR[k] > T(0) && pR[k] > T(0));
+    cL[k] = Fp<T>::sqrt(g.gamma * pL[k] * iL[k]);
+    cR[k] = Fp<T>::sqrt(g.gamma * pR[k] * iR[k]);
+  }
 
-  T SL, SR;
-  bool sl_first = true, sr_first = true;
+  T SL[K], SR[K];
+  bool sl_first[K], sr_first[K];
   if (ws == 1) {
-    SL = min_first(uL - cL, uR - cR);
-    SR = max_first(uL + cL, uR + cR);
-    if (rec != nullptr) {
-      sl_first = !(uR - cR < uL - cL);
-      sr_first = !(uR + cR > uL + cL);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      SL[k] = min_first(uL[k] - cL[k], uR[k] - cR[k]);
+      SR[k] = max_first(uL[k] + cL[k], uR[k] + cR[k]);
+      sl_first[k] = !(uR[k] - cR[k] < uL[k] - cL[k]);
+      sr_first[k] = !(uR[k] + cR[k] > uL[k] + cL[k]);
     }
   } else {
-    const T sL = Fp<T>::sqrt(rL), sR = Fp<T>::sqrt(rR);
-    const T iw = Fp<T>::rcp(sL + sR);
-    const T ua = (sL * uL + sR * uR) * iw;
-    const T va = (sL * vL + sR * vR) * iw;
-    const T wa = (sL * wL + sR * wR) * iw;
-    const T Ha = (sL * ((L[4] + pL) * iL) + sR * ((R[4] + pR) * iR)) * iw;  // H = (E + p)/rho
-    const T ca = Fp<T>::sqrt(g.gm1 * (Ha - T(0.5) * (ua * ua + va * va + wa * wa)));
-    SL = min_first(uL - cL, ua - ca);
-    SR = max_first(uR + cR, ua + ca);
-    if (rec != nullptr) {
-      sl_first = !(ua - ca < uL - cL);
-      sr_first = !(ua + ca > uR + cR);
+    T sL[K], sR[K], iw[K], ua[K], va[K], wa[K], Ha[K], ca[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      sL[k] = Fp<T>::sqrt(rL[k]);
+      sR[k] = Fp<T>::sqrt(rR[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) iw[k] = Fp<T>::rcp(sL[k] + sR[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ua[k] = (sL[k] * uL[k] + sR[k] * uR[k]) * iw[k];
+      va[k] = (sL[k] * vL[k] + sR[k] * vR[k]) * iw[k];
+      wa[k] = (sL[k] * wL[k] + sR[k] * wR[k]) * iw[k];
+      Ha[k] = (sL[k] * ((L[k][4] + pL[k]) * iL[k]) + sR[k] * ((R[k][4] + pR[k]) * iR[k])) * iw[k];  // H = (E + p)/rho
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      ca[k] = Fp<T>::sqrt(g.gm1 * (Ha[k] - T(0.5) * (ua[k] * ua[k] + va[k] * va[k] + wa[k] * wa[k])));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      SL[k] = min_first(uL[k] - cL[k], ua[k] - ca[k]);
+      SR[k] = max_first(uR[k] + cR[k], ua[k] + ca[k]);
+      sl_first[k] = !(ua[k] - ca[k] < uL[k] - cL[k]);
+      sr_first[k] = !(ua[k] + ca[k] > uR[k] + cR[k]);
     }
   }
-  const T aL = SL - uL, aR = SR - uR;
-  const T Ss = Fp<T>::div(pR - pL + rL * uL * aL - rR * uR * aR, rL * aL - rR * aR);
+  T aL[K], aR[K], Ss[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    aL[k] = SL[k] - uL[k];
+    aR[k] = SR[k] - uR[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    Ss[k] = Fp<T>::div(pR[k] - pL[k] + rL[k] * uL[k] * aL[k] - rR[k] * uR[k] * aR[k],
+                       rL[k] * aL[k] - rR[k] * aR[k]);
 
   // Regions in the order S_L >= 0 -> F_L; else S* >= 0 -> F*_L; else
   // S_R > 0 -> F*_R; else F_R.  Only one side K enters (left when S_L >= 0 or
@@ -263,38 +303,79 @@ __device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<
   // stays finite whenever F_K is (also for an unphysical state whose S* or
   // S_K is NaN).  One set of selects of the side's inputs replaces three
   // candidate fluxes.
-  const bool left = SL >= T(0) || Ss >= T(0);
-  const bool star = left ? !(SL >= T(0)) : SR > T(0);
-  const T r = left ? rL : rR, u = left ? uL : uR, p = left ? pL : pR;
-  const T mn = left ? L[n] : R[n], m1 = left ? L[t1] : R[t1], m2 = left ? L[t2] : R[t2];
-  const T E = left ? L[4] : R[4];
-  const T S = left ? SL : SR, a = left ? aL : aR;
-  if (rec != nullptr)
-    record(rec, unsigned(sl_first) | unsigned(sr_first) << 1 | (left ? (star ? 2u : 0u) : (star ? 3u : 1u)) << 2);
-  const T Sc = star ? S : T(0);
-  const T den = star ? S - Ss : T(1);
-  const T Sx = star ? Ss : T(0), ax = star ? a : T(0);
-  // r_K p_K / (S_K - u_K) = p_K / (S_K - S*): the energy term takes the
-  // reciprocal of S_K - S* that r_K's division already formed
-  T t;
-  const T rr = Fp<T>::div(ax, den, t);
-  const T Us0 = rr * r;
-  const T Us1 = rr * (r * Sx);
-  const T Us2 = rr * m1;
-  const T Us3 = rr * m2;
-  const T Us4 = rr * E + (Sx - u) * (Us1 + p * t);
-  T Fn[5];
-  Fn[0] = mn + Sc * (Us0 - r);
-  Fn[1] = (mn * u + p) + Sc * (Us1 - mn);
-  Fn[2] = m1 * u + Sc * (Us2 - m1);
-  Fn[3] = m2 * u + Sc * (Us3 - m2);
-  Fn[4] = (E + p) * u + Sc * (Us4 - E);
-  F[0] = Fn[0];
-  F[n] = Fn[1];
-  F[t1] = Fn[2];
-  F[t2] = Fn[3];
-  F[4] = Fn[4];
-  return bad;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool left = SL[k] >= T(0) || Ss[k] >= T(0);
+    const bool star = left ? !(SL[k] >= T(0)) : SR[k] > T(0);
+    const T r = left ? rL[k] : rR[k], u = left ? uL[k] : uR[k], p = left ? pL[k] : pR[k];
+    const T mn = left ? L[k][1] : R[k][1], m1 = left ? L[k][2] : R[k][2], m2 = left ? L[k][3] : R[k][3];
+    const T E = left ? L[k][4] : R[k][4];
+    const T S = left ? SL[k] : SR[k], a = left ? aL[k] : aR[k];
+    if (rec != nullptr)
+      record(rec, unsigned(sl_first[k]) | unsigned(sr_first[k]) << 1 |
+                      (left ? (star ? 2u : 0u) : (star ? 3u : 1u)) << 2);
+    const T Sc = star ? S : T(0);
+    const T den = star ? S - Ss[k] : T(1);
+    const T Sx = star ? Ss[k] : T(0), ax = star ? a : T(0);
+    // r_K p_K / (S_K - u_K) = p_K / (S_K - S*): the energy term takes the
+    // reciprocal of S_K - S* that r_K's division already formed
+    T t;
+    const T rr = Fp<T>::div(ax, den, t);
+    const T Us0 = rr * r;
+    const T Us1 = rr * (r * Sx);
+    const T Us2 = rr * m1;
+    const T Us3 = rr * m2;
+    const T Us4 = rr * E + (Sx - u) * (Us1 + p * t);
+    Fn[k][0] = mn + Sc * (Us0 - r);
+    Fn[k][1] = (mn * u + p) + Sc * (Us1 - mn);
+    Fn[k][2] = m1 * u + Sc * (Us2 - m1);
+    Fn[k][3] = m2 * u + Sc * (Us3 - m2);
+    Fn[k][4] = (E + p) * u + Sc * (Us4 - E);
+  }
+}
+
+// HLLC flux across a face normal to axis D: the states taken into the normal
+// frame (n, t1, t2) = (D, D+1, D+2) mod 3, the flux returned in the axis
+// frame.  Returns true when an input state has rho <= 0 or p <= 0 (or NaN).
+template <int D, typename T>
+__device__ __forceinline__ bool hllc_flux(const T L[5], const T R[5], const Gas<T>& g, int ws, T F[5],
+                                          unsigned* rec = nullptr) {
+  constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
+  const T Ln[1][5] = {{L[0], L[n], L[t1], L[t2], L[4]}};
+  const T Rn[1][5] = {{R[0], R[n], R[t1], R[t2], R[4]}};
+  T Fn[1][5];
+  bool bad[1];
+  hllc_normal_k<1>(Ln, Rn, g, ws, Fn, bad, rec);
+  F[0] = Fn[0][0];
+  F[n] = Fn[0][1];
+  F[t1] = Fn[0][2];
+  F[t2] = Fn[0][3];
+  F[4] = Fn[0][4];
+  return bad[0];
+}
+
+// Two faces at once (normal axes D0 and D1), interleaved as in hllc_normal_k.
+template <int D0, int D1, typename T>
+__device__ __forceinline__ int hllc_flux2(const T L0[5], const T R0[5], const T L1[5], const T R1[5],
+                                          const Gas<T>& g, int ws, T F0[5], T F1[5], unsigned* rec = nullptr) {
+  constexpr int n0 = 1 + D0, a0 = 1 + (D0 + 1) % 3, b0 = 1 + (D0 + 2) % 3;
+  constexpr int n1 = 1 + D1, a1 = 1 + (D1 + 1) % 3, b1 = 1 + (D1 + 2) % 3;
+  const T Ln[2][5] = {{L0[0], L0[n0], L0[a0], L0[b0], L0[4]}, {L1[0], L1[n1], L1[a1], L1[b1], L1[4]}};
+  const T Rn[2][5] = {{R0[0], R0[n0], R0[a0], R0[b0], R0[4]}, {R1[0], R1[n1], R1[a1], R1[b1], R1[4]}};
+  T Fn[2][5];
+  bool bad[2];
+  hllc_normal_k<2>(Ln, Rn, g, ws, Fn, bad, rec);
+  F0[0] = Fn[0][0];
+  F0[n0] = Fn[0][1];
+  F0[a0] = Fn[0][2];
+  F0[b0] = Fn[0][3];
+  F0[4] = Fn[0][4];
+  F1[0] = Fn[1][0];
+  F1[n1] = Fn[1][1];
+  F1[a1] = Fn[1][2];
+  F1[b1] = Fn[1][3];
+  F1[4] = Fn[1][4];
+  return int(bad[0]) + int(bad[1]);
 }
 
 // True when a conserved state has rho <= 0 or p <= 0 (or NaN).

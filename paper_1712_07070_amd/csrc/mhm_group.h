@@ -181,6 +181,18 @@ __device__ __forceinline__ bool scheme_flux(const ExtScheme& sch, const T L[5], 
                                             T F[5], unsigned*) {
   return riemann_any<D>(L, R, g, sch.o, F);
 }
+// Two faces (normal axes D0, D1) at once; the default scheme interleaves
+// their solves.
+template <int D0, int D1, typename T>
+__device__ __forceinline__ int scheme_flux2(const DefaultScheme&, const T L0[5], const T R0[5], const T L1[5],
+                                            const T R1[5], const Gas<T>& g, int ws, T F0[5], T F1[5], unsigned* rec) {
+  return hllc_flux2<D0, D1>(L0, R0, L1, R1, g, ws, F0, F1, rec);
+}
+template <int D0, int D1, typename T>
+__device__ __forceinline__ int scheme_flux2(const ExtScheme& sch, const T L0[5], const T R0[5], const T L1[5],
+                                            const T R1[5], const Gas<T>& g, int, T F0[5], T F1[5], unsigned*) {
+  return int(riemann_any<D0>(L0, R0, g, sch.o, F0)) + int(riemann_any<D1>(L1, R1, g, sch.o, F1));
+}
 
 // ---------------------------------------------------- one patch group ----
 // Workgroup of 256 threads (4 waves; the hardware gives each wave of a
@@ -338,34 +350,29 @@ __device__ __forceinline__ int fwd_col_faces(const Sch& sch, FwdCol<T, kI, Off>&
                                              T* __restrict__ ff, unsigned* rec) {
   if (!kI || k < 0 || k > 15) return 0;
   const int cx = c.cx, cy = c.cy;
-  int bad = 0;
-  {
-    T L[5], F[5];
+  T Lx[5], Fx[5], Ly[5], Fy[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = sm.S[0][q][sm.si(cx - 1, cy)];
-    bad += scheme_flux<0>(sch, L, c.Ux, gas, ws, F, rec);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) sm.F[0][q][fxidx(cx, cy)] = F[q];
-    if (ff != nullptr && (cx & 7) == 0) {
-      // x faces at x = 0, 8: plane x/8, entry z*16 + y
-      T* o = ff + (cx >> 3) * 5 * 256 + k * 16 + cy;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) o[q * 256] = F[q];
-    }
+  for (int q = 0; q < 5; ++q) {
+    Lx[q] = sm.S[0][q][sm.si(cx - 1, cy)];
+    Ly[q] = sm.S[1][q][sm.si(cx, cy - 1)];
   }
-  {
-    T L[5], F[5];
+  const int bad = scheme_flux2<0, 1>(sch, Lx, c.Ux, Ly, c.Uy, gas, ws, Fx, Fy, rec);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) L[q] = sm.S[1][q][sm.si(cx, cy - 1)];
-    bad += scheme_flux<1>(sch, L, c.Uy, gas, ws, F, rec);
+  for (int q = 0; q < 5; ++q) {
+    sm.F[0][q][fxidx(cx, cy)] = Fx[q];
+    sm.F[1][q][fyidx(cx, cy)] = Fy[q];
+  }
+  if (ff != nullptr && (cx & 7) == 0) {
+    // x faces at x = 0, 8: plane x/8, entry z*16 + y
+    T* o = ff + (cx >> 3) * 5 * 256 + k * 16 + cy;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) sm.F[1][q][fyidx(cx, cy)] = F[q];
-    if (ff != nullptr && (cy & 7) == 0) {
-      // y faces at y = 0, 8: plane 3 + y/8, entry x*16 + z
-      T* o = ff + (3 + (cy >> 3)) * 5 * 256 + cx * 16 + k;
+    for (int q = 0; q < 5; ++q) o[q * 256] = Fx[q];
+  }
+  if (ff != nullptr && (cy & 7) == 0) {
+    // y faces at y = 0, 8: plane 3 + y/8, entry x*16 + z
+    T* o = ff + (3 + (cy >> 3)) * 5 * 256 + cx * 16 + k;
 #pragma unroll
-      for (int q = 0; q < 5; ++q) o[q * 256] = F[q];
-    }
+    for (int q = 0; q < 5; ++q) o[q * 256] = Fy[q];
   }
   return bad;
 }
