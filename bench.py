@@ -104,8 +104,9 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=40,
+                    help="untimed steps first: the first few dozen steps after the tuner run up to 10%% slower")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--n", type=int, default=256, help="grid cells per axis (multiple of 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -585,14 +585,17 @@ int hydro_gather_ghost_adjoint(const void* g_pad_dev, void* g_level_dev, int32_t
  * differ in the register budget the compiler was given (occupancy, bit 1),
  * in the order groups are dealt to workgroups (bit 0: plain, or blocked so
  * that each of the 8 XCDs sweeps a contiguous range of groups and finds
- * neighbour-group halos in its own L2; bit 2: linear, or brick by brick of
- * 2x2x2 groups), in the LDS layout of the plane tiles (bit 3: packed rows,
+ * neighbour-group halos in its own L2; bit 2: linear, or column-tile order --
+ * tiles of about 64 groups' rows, each visited layer by layer upward in z,
+ * so that a group's ghost planes in z are still cached from the group below
+ * it), in the LDS layout of the plane tiles (bit 3: packed rows,
  * or rows padded by one element) and in the threads per workgroup (bit 4:
  * 256, one group per workgroup, or 512, two groups marched side by side
  * with their own LDS and shared barriers).  The choice is per context, per dtype and per kernel form
  * (with_cfl: the form that reduces the next CFL time-step, which needs more
  * registers and 4 KB more LDS per workgroup).  Setters need a context;
- * getters with ctx NULL return the default (XCD-blocked, high occupancy).
+ * getters with ctx NULL return the default (6: XCD-blocked, column-tile,
+ * low occupancy target).
  *   hydro_num_variants       number of shapes (>= 1)
  *   hydro_set_level_variant  select one (0 .. n-1) for one form; HYDRO_EINVAL otherwise
  *   hydro_get_level_variant  current selection for a dtype and form
@@ -612,9 +615,12 @@ int hydro_variant_name(int32_t variant, char* buf, int32_t len);
  * HIP events on `stream`, 1 <= reps <= 1000; a shape's time is the smaller of
  * its two means), record the fastest in ctx (non-NULL) for `dtype` and this
  * lattice and return its index (>= 0), or a negative status (nothing is
- * recorded).  Shapes within 1.5% of the fastest count as ties, resolved to
- * the lowest-numbered XCD-blocked shape (the timing relaunches one cached
- * input, where the plain order's extra HBM reads hardly show).  Both kernel forms are timed and tuned separately (without and
+ * recorded).  Shapes within 1.5% of the fastest count as ties, resolved
+ * towards fewer HBM bytes per step: XCD-blocked before plain order,
+ * column-tile before linear, low before high occupancy target, then the
+ * lowest number (the timing relaunches one cached input, where a group
+ * order's extra HBM reads hardly show).  Both kernel forms are timed and
+ * tuned separately (without and
  * with the CFL epilogue; the returned index is the CFL form's).  SYNCHRONOUS:
  * waits on `stream`; allocates nothing on the device.  level_dev is read,
  * scratch_out_dev ([G][5][16^3]) is overwritten, cfl_scratch_dev receives the

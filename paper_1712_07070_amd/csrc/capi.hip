@@ -30,9 +30,10 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 // Measured defaults of the launch shapes (used when a context has no
-// selection): level step XCD-blocked at the high occupancy target (variant
-// 0); fused adjoint (0); batched: one queue, high occupancy (0).
-constexpr int kDefaultLevelVariant = 0;
+// selection): level step XCD-blocked, column-tile order, low occupancy
+// target (variant 6); fused adjoint (0); batched: one queue, high occupancy
+// (0).
+constexpr int kDefaultLevelVariant = 6;
 constexpr int kDefaultAdjointVariant = 0;
 constexpr int kDefaultBatchedVariant = 0;
 
@@ -458,6 +459,12 @@ int batched_launch(const hydro_level_t* levels_host, int32_t n_levels, int32_t d
     return batched_impl<double>(levels_host, n_levels, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant, s);
   return batched_impl<float>(levels_host, n_levels, gamma, scheme, theta, n_bad_dev, work_dev, grid, variant, s);
 }
+
+// Preference among launch shapes that time as ties: XCD-blocked before
+// plain order, column-tile before linear sweep, lower before higher
+// occupancy target (fewer HBM bytes per step at equal speed, measured), then
+// the lower shape number.
+int tie_rank(int v) { return ((v & 1) << 10) | ((~v & 4) << 7) | ((~v & 2) << 7) | v; }
 
 // Times `launch(v)` for v in [0, n): two passes of 1 untimed + reps timed
 // launches each, a shape's time the smaller of its two means (so clock
@@ -1045,7 +1052,7 @@ int hydro_set_variant(hydro_ctx* ctx, int32_t dtype, int32_t variant) {
 int hydro_variant_name(int32_t variant, char* buf, int32_t len) {
   if (variant < 0 || variant >= gh::kLevelVariants || buf == nullptr || len < 1) return HYDRO_EINVAL;
   std::snprintf(buf, size_t(len), "%s %s order, %s occupancy target, %s LDS rows, %s per workgroup",
-                (variant & 1) ? "plain" : "xcd-blocked", (variant & 4) ? "brick" : "linear",
+                (variant & 1) ? "plain" : "xcd-blocked", (variant & 4) ? "column-tile" : "linear",
                 (variant & 2) ? "low" : "high", (variant & 8) ? "padded" : "packed",
                 (variant & 16) ? "2 groups (512 threads)" : "1 group (256 threads)");
   return HYDRO_OK;
@@ -1081,15 +1088,17 @@ int hydro_autotune(hydro_ctx* ctx, const void* level_dev, void* scratch_out_dev,
     });
     if (best[form] < 0) return best[form];
     // The tuner relaunches one input, which stays partly in the caches; a
-    // stepping loop reads each step's fresh output, where the plain group
-    // order's 2.4x HBM reads (measured) cost more than here.  Shapes within
-    // 1.5% of the fastest are ties, resolved towards the XCD-blocked order
-    // (even variant numbers), then the lowest number.
-    for (int v = 0; v < gh::kLevelVariants; v += 2)
-      if (ms[form][v] <= 1.015f * ms[form][best[form]]) {
-        best[form] = v;
-        break;
-      }
+    // stepping loop reads each step's fresh output, where a group order's
+    // extra HBM reads (measured: plain 3x, XCD-blocked linear 1.1x the
+    // XCD-blocked column-tile order's) cost more than here.  Shapes within
+    // 1.5% of the fastest are ties, resolved by tie_rank.
+    {
+      const float tie = 1.015f * ms[form][best[form]];
+      int pick = -1;
+      for (int v = 0; v < gh::kLevelVariants; ++v)
+        if (ms[form][v] <= tie && (pick < 0 || tie_rank(v) < tie_rank(pick))) pick = v;
+      best[form] = pick;
+    }
   }
   if (times_ms_host != nullptr)
     for (int form = 0; form < 2; ++form)

@@ -98,7 +98,7 @@ hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGe
 // Launch shapes of the level step (all give bit-identical results):
 // bit 0 set = groups in plain order instead of XCD-blocked order,
 // bit 1 set = lower occupancy target for the register allocator,
-// bit 2 set = groups in brick order (2x2x2 bricks of groups),
+// bit 2 set = groups in column-tile order (tiles of group rows, marched up in z),
 // bit 3 set = LDS tiles with padded rows,
 // bit 4 set = two groups per 512-thread workgroup.
 constexpr int kLevelVariants = 32;

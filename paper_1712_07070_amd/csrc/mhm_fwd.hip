@@ -100,7 +100,8 @@ void launch_level_shape(const T* level, T* level_out, const LevelGeom& geo, cons
 }
 
 // Launch shapes (bit-identical results): bit 0 plain group order (else
-// XCD-blocked), bit 1 low occupancy target, bit 2 brick order of the groups,
+// XCD-blocked), bit 1 low occupancy target, bit 2 column-tile order of the
+// groups (else linear),
 // bit 3 padded LDS rows, bit 4 two groups per 512-thread workgroup.
 template <typename T, bool kCfl>
 hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
@@ -108,13 +109,11 @@ hipError_t launch_level_variant(const T* level, T* level_out, const LevelGeom& g
                                 const CflOut& cfl, int variant, hipStream_t stream) {
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
   const int xcd = (variant & 1) ? 0 : 1;
-  const int brick = (variant & 4) ? 1 : 0;
+  const int tiled = (variant & 4) ? 1 : 0;
   const int gpw = (variant & 16) ? 2 : 1;
-  const int64_t slots =
-      brick ? int64_t(8) * ((geo.ngx + 1) >> 1) * ((geo.ngy + 1) >> 1) * ((geo.ngz + 1) >> 1) : G;
-  const int64_t wslots = (slots + gpw - 1) / gpw;
+  const int64_t wslots = (G + gpw - 1) / gpw;
   const int64_t blocks = xcd ? ((wslots + 7) / 8) * 8 : wslots;
-  const int order = xcd | (brick << 1);
+  const int order = xcd | (tiled << 1);
   if (blocks > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
   // 32-bit element offsets when every element of the level has one
   if (G * 5 * 4096 <= int64_t(0xffffffffu))

@@ -18,20 +18,37 @@ __device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t G) {
   return g;
 }
 
-// Brick order of the groups of a level: the lattice is cut into 2x2x2 bricks
-// of groups, visited brick by brick (x fastest), the 8 groups of a brick x
-// fastest, so that the groups running together share more of their halo
-// cells.  A slot of a partial brick at an odd lattice edge holds no group.
-__device__ __forceinline__ int64_t brick_slots(const LevelGeom& geo) {
-  return int64_t(8) * ((geo.ngx + 1) >> 1) * ((geo.ngy + 1) >> 1) * ((geo.ngz + 1) >> 1);
+// Column-tile order of the groups of a level: the lattice is cut into tiles
+// of kTileGroups / ngx rows of groups (at least one row; full in x), and the
+// groups are visited tile by tile, within a tile layer by layer upward (z),
+// within a layer x fastest.  With the XCD blocking each XCD then marches one
+// tile upward: the group that replaces a finished one is usually the one
+// above it, which reads as its lower ghost planes the planes the finished
+// group read last, and reads first the planes that group read as its upper
+// ghost planes -- so both still sit in the XCD's L2.  In the linear order
+// the groups of a tile layer run together too, but the layer above runs
+// several tile layers later, and every group fetches its 4 ghost planes
+// (with their halo rows) from HBM.
+constexpr int kTileGroups = 64;
+__device__ __forceinline__ int64_t tile_slots(const LevelGeom& geo) {
+  return int64_t(geo.ngx) * geo.ngy * geo.ngz;
 }
-__device__ __forceinline__ int64_t brick_group(int64_t s, const LevelGeom& geo) {
-  const int bx = (geo.ngx + 1) >> 1, by = (geo.ngy + 1) >> 1;
-  const int64_t br = s >> 3, bxy = int64_t(bx) * by;
-  const int l = int(s & 7);
-  const int cz = int(br / bxy), rem = int(br % bxy);
-  const int gx = 2 * (rem % bx) + (l & 1), gy = 2 * (rem / bx) + ((l >> 1) & 1), gz = 2 * cz + (l >> 2);
-  if (gx >= geo.ngx || gy >= geo.ngy || gz >= geo.ngz) return -1;
+__device__ __forceinline__ int64_t tile_group(int64_t s, const LevelGeom& geo) {
+  const int ty = geo.ngx >= kTileGroups ? 1 : (kTileGroups / geo.ngx < geo.ngy ? kTileGroups / geo.ngx : geo.ngy);
+  const int64_t full_tiles = geo.ngy / ty, tile = int64_t(ty) * geo.ngx * geo.ngz;
+  int64_t t, rows, r;
+  if (s < full_tiles * tile) {
+    t = s / tile;
+    rows = ty;
+    r = s - t * tile;
+  } else {
+    t = full_tiles;
+    rows = geo.ngy - full_tiles * ty;
+    r = s - full_tiles * tile;
+  }
+  const int64_t layer = rows * geo.ngx;
+  const int gz = int(r / layer), rem = int(r % layer);
+  const int gx = rem % geo.ngx, gy = int(t * ty) + rem / geo.ngx;
   return (int64_t(gz) * geo.ngy + gy) * geo.ngx + gx;
 }
 
@@ -57,7 +74,7 @@ __global__ __launch_bounds__(kThreads * kGpw) __attribute__((amdgpu_waves_per_eu
   const int half = kGpw == 2 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 8) : 0;
   const int tid = kGpw == 2 ? (int(threadIdx.x) & 255) ^ (half << 6) : int(threadIdx.x);
   const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
-  const int64_t slots = (order & 2) ? brick_slots(geo) : G;
+  const int64_t slots = (order & 2) ? tile_slots(geo) : G;
   const int64_t wslots = (slots + kGpw - 1) / kGpw;
   const int64_t w = (order & 1) ? xcd_group(blockIdx.x, wslots) : int64_t(blockIdx.x);
   if (w >= wslots) return;  // the whole workgroup leaves together (w is uniform)
@@ -65,7 +82,7 @@ __global__ __launch_bounds__(kThreads * kGpw) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
   for (int h = 0; h < kGpw; ++h) {
     const int64_t sl = w * kGpw + h;
-    gs[h] = sl >= slots ? -1 : ((order & 2) ? brick_group(sl, geo) : sl);
+    gs[h] = sl >= slots ? -1 : ((order & 2) ? tile_group(sl, geo) : sl);
   }
   bool any = false;
 #pragma unroll

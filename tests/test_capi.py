@@ -179,14 +179,14 @@ def test_two_contexts_keep_separate_selections(lib):
         assert lib.hydro_set_batched_variant(b, 1, 5) == 0
         assert lib.hydro_set_adjoint_variant(a, 1, 1) == 0
         assert lib.hydro_get_level_variant(a, 0, 1) == 3
-        assert lib.hydro_get_level_variant(b, 0, 1) == 0          # default
+        assert lib.hydro_get_level_variant(b, 0, 1) == 6          # default
         assert lib.hydro_get_batched_variant(b, 1) == 5
         assert lib.hydro_get_batched_variant(a, 1) == 0
         assert lib.hydro_get_adjoint_variant(a, 1) == 1
         assert lib.hydro_get_adjoint_variant(b, 1) == 0
     # setters need a context, getters without one report the defaults
     assert lib.hydro_set_level_variant(None, 0, 1, 1) == -1
-    assert lib.hydro_get_level_variant(None, 0, 1) == 0
+    assert lib.hydro_get_level_variant(None, 0, 1) == 6
     assert lib.hydro_set_variant(None, 0, 1) == -1
 
 
