@@ -25,6 +25,7 @@
 
 #include "hydro_adjoint.h"
 #include "mhm_group.h"
+#include "mhm_level.h"
 
 namespace gh {
 
@@ -962,6 +963,16 @@ __device__ __forceinline__ void set_dt_adj(Gas<T>& gas, const double* dt_dev, do
   }
 }
 
+// Group of this workgroup in a level adjoint launch (grid rounded up to a
+// multiple of 8): the XCD-blocked column-tile order of the level step, so
+// that each XCD runs a contiguous range of neighbouring groups and finds
+// their shared ghost cells in its L2; -1 for a padding workgroup.
+__device__ __forceinline__ int64_t adj_level_group(const LevelGeom& geo) {
+  const int64_t G = int64_t(geo.ngx) * geo.ngy * geo.ngz;
+  const int64_t w = xcd_group(blockIdx.x, G);
+  return w < G ? tile_group(w, geo) : -1;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(AdjWaves<T>::value, AdjWaves<T>::value))) void adj_fused_padded(const T* __restrict__ Upad, const T* __restrict__ gout_,
                                                              T* __restrict__ gpad, int gh, Gas<T> gas, int first_order,
@@ -986,7 +997,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(Adj
                                                             int first_order, int ws) {
   __shared__ SmemF<T> sm;
   set_dt_adj(gas, dt_dev, dx);
-  const int64_t g = blockIdx.x;
+  const int64_t g = adj_level_group(geo);
+  if (g < 0) return;  // uniform
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
   // the second-order scheme gets its own inlined copy (limiter unconditional)
@@ -1034,7 +1046,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 
     const double* __restrict__ dt_dev, double dx, int first_order, int wsp) {
   __shared__ SmemFaces<T> sm;
   set_dt_adj(gas, dt_dev, dx);
-  const int64_t g = blockIdx.x;
+  const int64_t g = adj_level_group(geo);
+  if (g < 0) return;  // uniform
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   // the second-order scheme gets its own inlined copy (limiter unconditional)
   if (first_order == 0)
@@ -1049,7 +1062,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2, 
     LevelGeom geo, Gas<T> gas, const double* __restrict__ dt_dev, double dx, int first_order) {
   __shared__ SmemCells<T> sm;
   set_dt_adj(gas, dt_dev, dx);
-  const int64_t g = blockIdx.x;
+  const int64_t g = adj_level_group(geo);
+  if (g < 0) return;  // uniform
   LevelSource<T> src{level, geo, int(g % geo.ngx), int((g / geo.ngx) % geo.ngy), int(g / (int64_t(geo.ngx) * geo.ngy))};
   BoxSink<T> sink{gbox + g * 5 * int64_t(kBox * kBox * kBox)};
   // the second-order scheme gets its own inlined copy (limiter unconditional)
@@ -1273,13 +1287,14 @@ hipError_t launch_mhm_adjoint_level(const T* level, const T* g_out, T* g_in, con
   if (geo.ngx >= (1 << 19) || geo.ngy >= (1 << 19) || geo.ngz >= (1 << 19)) return hipErrorInvalidValue;
   T* gbox = work;  // [G][5][20^3]; only reachable positions are written, and only those are read
   T* fws = work + G * 5 * int64_t(kBox * kBox * kBox);
+  const unsigned blocks = unsigned((G + 7) / 8 * 8);  // adj_level_group's padded grid
   if (split) {
-    hipLaunchKernelGGL(adj_faces_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, fws, geo,
+    hipLaunchKernelGGL(adj_faces_level<T>, dim3(blocks), dim3(kAdjThreads), 0, stream, level, g_out, fws, geo,
                        gas, dt_dev, dx, first_order, ws);
-    hipLaunchKernelGGL(adj_cells_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, fws, gbox,
+    hipLaunchKernelGGL(adj_cells_level<T>, dim3(blocks), dim3(kAdjThreads), 0, stream, level, g_out, fws, gbox,
                        geo, gas, dt_dev, dx, first_order);
   } else {
-    hipLaunchKernelGGL(adj_fused_level<T>, dim3(unsigned(G)), dim3(kAdjThreads), 0, stream, level, g_out, gbox, geo,
+    hipLaunchKernelGGL(adj_fused_level<T>, dim3(blocks), dim3(kAdjThreads), 0, stream, level, g_out, gbox, geo,
                        gas, dt_dev, dx, first_order, ws);
   }
   const int64_t ncells = G * 4096;
