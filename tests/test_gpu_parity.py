@@ -260,6 +260,8 @@ LEVEL_CASES = {
     "outflow-x": ((4, 1, 1), (1, 1, 0, 0, 0, 0)),
     "mixed": ((2, 3, 2), (1, 0, 0, 1, 1, 1)),
     "single-group": ((1, 1, 1), (0, 0, 0, 0, 0, 0)),
+    # 32 groups per row: column tiles of 2 rows, the third row a partial tile
+    "partial-tile": ((32, 3, 2), (0, 0, 1, 1, 0, 0)),
 }
 
 
@@ -277,7 +279,7 @@ def test_level_step_equals_fill_then_advance(hydro, dtype, case):
                        rng.uniform(0.5, 2, shape), 5 / 3)
     U = W.grid_to_groups(grid).astype(dtype)
     t = dev(U)
-    dx = 1.0 / n[0]
+    dx = 1.0 / 64   # dt / dx = 0.064: every case well inside the CFL limit
     pad = hydro.fill_ghosts(t, ng, 3, bc)
     a = hydro.advance(pad, 1e-3, dx, 5 / 3)
     nb = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -340,9 +342,10 @@ def test_level_cfl_epilogue_bitwise(hydro, dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("case", ["periodic", "outflow-x", "single-group"])
+@pytest.mark.parametrize("case", ["periodic", "outflow-x", "single-group", "partial-tile"])
 def test_every_shape_with_cfl_on_ragged_group_counts(hydro, dtype, case):
-    """Group counts that are not a multiple of the 8 XCDs (12, 4, 1 groups):
+    """Group counts that are not a multiple of the 8 XCDs (12, 4, 1 groups)
+    and a lattice whose last column tile is partial (32 x 3 x 2 groups):
     in every launch shape, with the CFL epilogue on, the fused step equals
     ghost fill + padded step bit for bit, and its per-patch time-steps equal
     the standalone CFL kernel's on the output and the oracle's."""
@@ -356,7 +359,7 @@ def test_every_shape_with_cfl_on_ragged_group_counts(hydro, dtype, case):
     U = W.grid_to_groups(grid).astype(dtype)
     G = U.shape[0]
     t = dev(U)
-    dx = 1.0 / n[0]
+    dx = 1.0 / 64   # dt / dx = 0.064: every case well inside the CFL limit
     ref = hydro.advance(hydro.fill_ghosts(t, ng, 3, bc), 1e-3, dx, 5 / 3)
     tdt = t.dtype
     saved = hydro.get_level_variant(tdt, True)
