@@ -538,13 +538,15 @@ __device__ __forceinline__ int march_roles(const Sch& sch, const Src& src, T* __
                                            int first_order, int ws, Smem<T, kL>& sm, double* smax, double gamma_d,
                                            int tid, T* __restrict__ ff, unsigned* rec) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // FP32 at the low occupancy target: two planes per loop iteration, so that the
-  // register rotation of a column's planes (Wm <- Wc <- Wp, z-face state and
-  // flux) becomes renaming instead of moves (3% fewer VALU instructions per
-  // plane, step 2% faster).  FP64 (the unrolled loop needs more than 256
-  // VGPRs) and the four-wave FP32 kernels (kPrio; 128 VGPRs, where it
-  // spills) keep one plane per iteration.
-  constexpr int kU = (sizeof(T) == 4 && !kPrio) ? 2 : 1;
+  // Two planes per loop iteration, so that the register rotation of a
+  // column's planes (Wm <- Wc <- Wp, z-face state and flux) becomes renaming
+  // instead of moves (2-3% fewer VALU instructions per plane): every role in
+  // FP32 at the low occupancy target (step 2% faster), the plain and
+  // last-faces roles in FP64 (step 0.5-0.8% faster; the halo role, which
+  // carries a second column, would need more than 256 VGPRs).  The four-wave
+  // FP32 kernels (kPrio; 128 VGPRs, where it spills) keep one plane.
+  constexpr int kU = (sizeof(T) == 4 && !kPrio) ? 2 : 1;   // halo role
+  constexpr int kU2 = !kPrio ? 2 : 1;                       // the other roles
   if constexpr (kPrio) {
     if (wave == 0) __builtin_amdgcn_s_setprio(2);
     if (wave == 2) __builtin_amdgcn_s_setprio(1);
@@ -553,20 +555,20 @@ __device__ __forceinline__ int march_roles(const Sch& sch, const Src& src, T* __
     // the other words: one copy (their options are run-time anyway)
     if (wave == 0) return march_group<T, Src, kRoleHalo, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
     if (wave == 2)
-      return march_group<T, Src, kRoleLastFaces, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
-    return march_group<T, Src, kRolePlain, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+      return march_group<T, Src, kRoleLastFaces, kU2>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    return march_group<T, Src, kRolePlain, kU2>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
   } else {
     if (first_order == 0) {
       if (wave == 0) return march_group<T, Src, kRoleHalo, kU>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
       if (wave == 2)
-        return march_group<T, Src, kRoleLastFaces, kU>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
-      return march_group<T, Src, kRolePlain, kU>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
+        return march_group<T, Src, kRoleLastFaces, kU2>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
+      return march_group<T, Src, kRolePlain, kU2>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
     }
     if (wave == 0)
       return march_group<T, Src, kRoleHalo, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
     if (wave == 2)
-      return march_group<T, Src, kRoleLastFaces, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
-    return march_group<T, Src, kRolePlain, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+      return march_group<T, Src, kRoleLastFaces, kU2>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    return march_group<T, Src, kRolePlain, kU2>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
   }
 }
 
