@@ -544,7 +544,8 @@ __device__ __forceinline__ int march_roles(const Sch& sch, const Src& src, T* __
   // FP32 at the low occupancy target (step 2% faster), the plain and
   // last-faces roles in FP64 (step 0.5-0.8% faster; the halo role, which
   // carries a second column, would need more than 256 VGPRs).  The four-wave
-  // FP32 kernels (kPrio; 128 VGPRs, where it spills) keep one plane.
+  // FP32 kernels (kPrio; 128 VGPRs, where it spills) and the other scheme
+  // words keep one plane.
   constexpr int kU = (sizeof(T) == 4 && !kPrio) ? 2 : 1;   // halo role
   constexpr int kU2 = !kPrio ? 2 : 1;                       // the other roles
   if constexpr (kPrio) {
@@ -552,11 +553,12 @@ __device__ __forceinline__ int march_roles(const Sch& sch, const Src& src, T* __
     if (wave == 2) __builtin_amdgcn_s_setprio(1);
   }
   if constexpr (!std::is_same<Sch, DefaultScheme>::value) {
-    // the other words: one copy (their options are run-time anyway)
-    if (wave == 0) return march_group<T, Src, kRoleHalo, kU>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    // the other words: one copy (their options are run-time anyway), one
+    // plane per loop iteration
+    if (wave == 0) return march_group<T, Src, kRoleHalo, 1>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
     if (wave == 2)
-      return march_group<T, Src, kRoleLastFaces, kU2>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
-    return march_group<T, Src, kRolePlain, kU2>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+      return march_group<T, Src, kRoleLastFaces, 1>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
+    return march_group<T, Src, kRolePlain, 1>(sch, src, out, gas, first_order, ws, sm, smax, gamma_d, tid, ff, rec);
   } else {
     if (first_order == 0) {
       if (wave == 0) return march_group<T, Src, kRoleHalo, kU>(sch, src, out, gas, 0, ws, sm, smax, gamma_d, tid, ff, rec);
