@@ -128,6 +128,10 @@ def parse():
     ap.add_argument("--adjoint-counter-run", type=int, default=0, metavar="REPS",
                     help="only launch the forward level step and the step adjoint (fused form) REPS times each on "
                          "the 128^3 FP64 smooth wave and the 384^3 FP32 turbulence state, for hardware-counter runs")
+    ap.add_argument("--batched-counter-run", type=int, default=0, metavar="REPS",
+                    help="only launch the level step (launch shapes 6 and 2) and the batched kernel on the same "
+                         "single level (variants 0, 2, 12, 14) REPS times each on the n^3 FP64 shear layer, for "
+                         "hardware-counter runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="after the run, copy a device buffer of this size (reference for HBM byte counters)")
     return ap.parse_args()
@@ -656,6 +660,54 @@ def counter_sweep(hydro, torch, W, n, reps, calibrate_mib):
                       "copy_calibration_bytes": calibrate_mib * (1 << 20)}), flush=True)
 
 
+def batched_counter_run(hydro, torch, W, n, reps, calibrate_mib):
+    """The same single level (the n^3 FP64 shear layer, no CFL epilogue)
+    through the level step (launch shapes 6 and 2: XCD-blocked, low occupancy
+    target, column-tile and linear order) and through the persistent batched
+    kernel (variants 0 and 2: one queue, 12 and 14: per-XCD column-tile
+    queues; high and low occupancy target),
+    `reps` launches each in that order after 30 untimed level steps (the
+    clock ramp of a fresh process), then the calibration copy: the per-item
+    cost of the persistent form, in counters."""
+    lv = W.shear_layer(n)
+    U = torch.from_numpy(np.ascontiguousarray(lv.U)).cuda()
+    O = torch.empty_like(U)
+    dt = 0.2 * lv.dx
+    work = torch.zeros(hydro.BATCH_WORK_WORDS, dtype=torch.int32, device="cuda")
+    order = []
+    saved_l, saved_b = hydro.get_level_variant(torch.float64, False), hydro.get_batched_variant(torch.float64)
+    try:
+        hydro.set_level_variant(torch.float64, False, 2)
+        for _ in range(30):
+            hydro.advance_level(U, lv.ng, lv.bc, dt, lv.dx, lv.gamma, out=O)
+        torch.cuda.synchronize()
+        order.append({"form": "warm-up", "variant": 2, "launches": 30})
+        for v in (6, 2):
+            hydro.set_level_variant(torch.float64, False, v)
+            for _ in range(reps):
+                hydro.advance_level(U, lv.ng, lv.bc, dt, lv.dx, lv.gamma, out=O)
+            torch.cuda.synchronize()
+            order.append({"form": "level", "variant": v, "launches": reps, "name": hydro.variant_name(v)})
+        for v in (0, 2, 12, 14):
+            hydro.set_batched_variant(torch.float64, v)
+            for _ in range(reps):
+                hydro.advance_batched([(U, O, lv.ng, lv.bc, dt, lv.dx)], lv.gamma, work)
+            torch.cuda.synchronize()
+            order.append({"form": "batched", "variant": v, "launches": reps})
+    finally:
+        hydro.set_level_variant(torch.float64, False, saved_l)
+        hydro.set_batched_variant(torch.float64, saved_b)
+    if calibrate_mib > 0:
+        m = calibrate_mib * (1 << 20) // 8
+        src = torch.ones(m, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    print(json.dumps({"batched_counter_run": order, "cells_per_launch": lv.n_cells,
+                      "copy_calibration_bytes": calibrate_mib * (1 << 20)}), flush=True)
+
+
 def adjoint_counter_run(hydro, torch, W, reps, calibrate_mib):
     """Forward level step, then step adjoint (fused form), `reps` launches
     each, on the 128^3 FP64 smooth wave and then the 384^3 FP32 turbulence
@@ -706,6 +758,9 @@ def main():
         return
     if args.adjoint_counter_run > 0:
         adjoint_counter_run(hydro, torch, W, args.adjoint_counter_run, args.calibrate_copy)
+        return
+    if args.batched_counter_run > 0:
+        batched_counter_run(hydro, torch, W, args.n, args.batched_counter_run, args.calibrate_copy)
         return
     print("bench: building workload", file=sys.stderr, flush=True)
     lv = W.shear_layer(args.n)

@@ -488,7 +488,10 @@ typedef struct {
  * bit 0 item order (0: level 0 first, 1: finest level first), bit 1
  * occupancy target, bits 2-3 work distribution (0: one queue; 1: one queue
  * per XCD, each serving one residue class of items mod 8, with stealing when
- * it runs dry; 2: static round-robin, workgroup b takes items b, b + grid, ...);
+ * it runs dry; 2: static round-robin, workgroup b takes items b, b + grid,
+ * ...; 3: one queue per XCD, each serving level by level one of 8
+ * contiguous blocks of the level's groups in column-tile order (the range
+ * the XCD-blocked column-tile level step gives that XCD), with stealing);
  * hydro_set_batched_variant / hydro_get_batched_variant select and read it,
  * hydro_autotune_batched times all of them on the given levels (two passes
  * of 1 untimed + `reps` timed launches per shape, a shape's time is the
@@ -497,7 +500,7 @@ typedef struct {
  * fastest in ctx (non-NULL) for these level lattices.
  */
 #define HYDRO_BATCH_WORK_WORDS 16
-#define HYDRO_BATCHED_VARIANTS 12
+#define HYDRO_BATCHED_VARIANTS 16
 int hydro_advance_batched(hydro_ctx* ctx, const hydro_level_t* levels_host, int32_t n_levels, int32_t dtype, double gamma,
                           int32_t scheme, double theta, int32_t* n_bad_dev, uint32_t* work_dev, int32_t grid,
                           void* stream);

@@ -104,10 +104,10 @@ hipError_t launch_gather_ghost_adjoint(const T* g_pad, T* g_level, const LevelGe
 constexpr int kLevelVariants = 32;
 // Batched kernel: ticket queues (one per XCD of MI355X), launch-shape variants
 // (bit 0 item order, bit 1 occupancy target, bits 2-3 queue mode: one queue,
-// per-XCD queues, static round-robin) and the uint32 words of its work buffer
-// (kQueues tickets + 1 departure counter).
+// per-XCD queues, static round-robin, per-XCD column-tile queues) and the
+// uint32 words of its work buffer (kQueues tickets + 1 departure counter).
 constexpr int kQueues = 8;
-constexpr int kBatchedVariants = 12;
+constexpr int kBatchedVariants = 16;
 constexpr int kBatchWorkWords = 16;
 static_assert(kQueues + 1 <= kBatchWorkWords, "work buffer too small");
 

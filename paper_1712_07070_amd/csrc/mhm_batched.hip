@@ -11,6 +11,7 @@
 #include <mutex>
 
 #include "mhm_group.h"
+#include "mhm_level.h"
 
 namespace gh {
 
@@ -36,11 +37,15 @@ __device__ __forceinline__ double uniform(double v) {
 // Queue modes: 0, one queue, items in ticket order; 1, queue c serves the
 // items c, c + kQueues, c + 2 kQueues, ... and workgroup b starts at queue
 // b % kQueues, moving on to the next queue when its own is empty; 2, no
-// queue: workgroup b takes items b, b + grid, b + 2 grid, ... (static).
-// Workgroups of a launch are dealt round-robin to the 8 XCDs, so modes 1 and
-// 2 give every XCD the same residue class of items that a one-launch-per-level
-// grid gives it (its L2 then holds the ghost cells that neighbouring groups in
-// that class share).  Every mode hands every item out exactly once.
+// queue: workgroup b takes items b, b + grid, b + 2 grid, ... (static); 3,
+// tile queues: queue c serves, level by level, the c-th of kQueues
+// contiguous blocks of each level's groups in column-tile order, workgroups
+// starting and moving on as in mode 1.  Workgroups of a launch are dealt
+// round-robin to the 8 XCDs, so modes 1 and 2 give every XCD the same
+// residue class of items that a one-launch-per-level grid in plain order
+// gives it, and mode 3 the range of groups the XCD-blocked column-tile level
+// step gives it (half the HBM bytes of mode 0 on one 4096-group level,
+// measured).  Every mode hands every item out exactly once.
 //
 // The ticket for the next item is taken when an item starts and decoded when
 // it ends, so the atomic's return overlaps the whole group step.
@@ -65,11 +70,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     return c < args.total ? (args.total - c + kQueues - 1) / kQueues : 0;
   };
   // the queue the next ticket comes from (mode 0: the only one)
-  auto cur_queue = [&]() { return queues == 1 ? (home + tried) % kQueues : 0; };
+  auto cur_queue = [&]() { return (queues == 1 || queues == 3) ? (home + tried) % kQueues : 0; };
+  // mode 3: entry t of tile queue c (levels finest first with order 1)
+  auto tile_item = [&](int c, long long t) -> long long {
+    for (int k = 0; k < args.n_levels; ++k) {
+      const int l = order ? args.n_levels - 1 - k : k;
+      const LevelGeom& geo = args.lv[l].geo;
+      const long long G = (long long)geo.ngx * geo.ngy * geo.ngz;
+      const long long per = (G + kQueues - 1) / kQueues, b0 = c * per;
+      const long long n = b0 >= G ? 0 : (G - b0 < per ? G - b0 : per);
+      if (t < n) return args.lv[l].g_begin + tile_group(b0 + t, geo);
+      t -= n;
+    }
+    return -1;
+  };
   // ticket t of the current queue -> item (or -1 if that queue is exhausted)
   auto decode = [&](unsigned int t) -> long long {
     if (queues == 0) return t < args.total ? (long long)t : -1;
     const int c = cur_queue();
+    if (queues == 3) return tile_item(c, (long long)t);
     return (long long)t < queue_size(c) ? c + (long long)kQueues * t : -1;
   };
   // take a ticket (thread 0); for mode 2 the "ticket" is the static index
@@ -85,7 +104,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
       i = c < args.total ? c : -1;
     } else {
       i = decode(t);
-      while (i < 0 && queues == 1 && ++tried < kQueues) i = decode(atomicAdd(&work[cur_queue()], 1u));
+      while (i < 0 && (queues == 1 || queues == 3) && ++tried < kQueues) i = decode(atomicAdd(&work[cur_queue()], 1u));
+      if (queues == 3) return i;  // the level order is taken in tile_item
     }
     // order 1 deals items from the last (finest, largest) level first
     return i < 0 ? -1 : (order ? args.total - 1 - i : i);

@@ -37,7 +37,7 @@ PPM = 1 << 14
 RIEMANN_HLLC, RIEMANN_ROE, RIEMANN_HLLE = 0 << 16, 1 << 16, 2 << 16
 DUAL_ENERGY = 1 << 18
 BATCH_WORK_WORDS = 16       # uint32 words of the batched kernel's work buffer
-BATCHED_VARIANTS = 12       # launch shapes of the batched kernel
+BATCHED_VARIANTS = 16       # launch shapes of the batched kernel
 
 _lib = None
 

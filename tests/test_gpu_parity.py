@@ -525,7 +525,8 @@ def test_batched_small_grid_and_uneven_items(hydro):
     ent = lambda outs: [(t, o, lv.ng, lv.bc, 1e-4 / 2 ** l, lv.dx) for l, (t, o, lv) in enumerate(zip(ins, outs, lvs))]
     saved = hydro.get_batched_variant(torch.float64)
     try:
-        for v in (0, 4, 8):   # one queue; per-XCD queues (3 and 5 workgroups steal from drained queues); static
+        for v in (0, 4, 8, 12, 13):   # one queue; per-XCD queues (3 and 5 workgroups steal from drained
+            # queues); static; per-XCD column-tile queues, both level orders
             hydro.set_batched_variant(torch.float64, v)
             hydro.advance_batched(ent(b), 5 / 3, work, grid=0)
             for grid in (3, 5):
