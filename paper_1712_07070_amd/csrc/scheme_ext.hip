@@ -23,9 +23,10 @@
 // the upwind s/rho as its Riemann flux), and the update takes E from s where
 // E_th < xi E_kin and resets s from E elsewhere.
 // Per-group arrays are indexed (group, field, cell); face arrays by (axis,
-// field, face) with face = ((b * NB + a) * 17 + n): n the normal coordinate
-// 0..16 (the face between n-1 and n), a, b the transverse coordinates in
-// the cyclic order (axis+1, axis+2).
+// field, face), the face of axis D at cell (x, y, z) being the one between
+// that cell - e_D and it, laid out x fastest for every axis (face_idx,
+// face1_idx), so that the threads of a wave, which take consecutive x,
+// touch consecutive elements whatever the axis.
 
 #include "ext_device.h"
 #include "kernels.h"
@@ -43,6 +44,25 @@ __device__ __forceinline__ int64_t cell_p(int P, int gh, int x, int y, int z) {
   return (int64_t(z + gh) * P + (y + gh)) * P + (x + gh);
 }
 __device__ __forceinline__ int cell_s(int x, int y, int z) { return ((z + 1) * kS + (y + 1)) * kS + (x + 1); }
+
+// Face arrays, x fastest: interior faces of axis D (normal coordinate 0..16,
+// transverse 0..15) and first-solve faces (normal 0..16, transverse -1..16).
+__device__ __forceinline__ int face_idx(int D, int x, int y, int z) {
+  const int nx = D == 0 ? 17 : 16, ny = D == 1 ? 17 : 16;
+  return (z * ny + y) * nx + x;
+}
+__device__ __forceinline__ int face1_idx(int D, int x, int y, int z) {
+  const int nx = D == 0 ? 17 : 18, ny = D == 1 ? 17 : 18;
+  return ((z + (D == 2 ? 0 : 1)) * ny + (y + (D == 1 ? 0 : 1))) * nx + (x + (D == 0 ? 0 : 1));
+}
+// Cell coordinates of entry f of a box of cells, x fastest: extent m along
+// axis D and t across it, starting at lo (along D) and tlo (across).
+__device__ __forceinline__ void box_cell(int D, int f, int m, int lo, int t, int tlo, int& x, int& y, int& z) {
+  const int nx = D == 0 ? m : t, ny = D == 1 ? m : t;
+  x = f % nx + (D == 0 ? lo : tlo);
+  y = (f / nx) % ny + (D == 1 ? lo : tlo);
+  z = f / (nx * ny) + (D == 2 ? lo : tlo);
+}
 
 // Sum over the wave (the caller adds it to the counter once per wave).
 __device__ __forceinline__ int wave_sum(int v) {
@@ -165,14 +185,6 @@ __global__ __launch_bounds__(256) void ext_states_kernel(const T* __restrict__ W
   }
 }
 
-// Cell coordinates from (axis D, normal n, transverse a, b in cyclic order).
-template <int D>
-__device__ __forceinline__ void face_cell(int n, int a, int b, int& x, int& y, int& z) {
-  if (D == 0) { x = n; y = a; z = b; }
-  if (D == 1) { y = n; z = a; x = b; }
-  if (D == 2) { z = n; x = a; y = b; }
-}
-
 template <int D, int NF, typename T>
 __device__ __forceinline__ void load_state(const T* __restrict__ Sg, int x, int y, int z, int side, T U[NF]) {
   const int c = cell_s(x, y, z);
@@ -180,13 +192,11 @@ __device__ __forceinline__ void load_state(const T* __restrict__ Sg, int x, int 
   for (int q = 0; q < NF; ++q) U[q] = Sg[((D * 2 + side) * NF + q) * int64_t(kS3) + c];
 }
 
-// Riemann solve of the face (D, n, a, b) between cell - e_D (its high state)
-// and cell (its low state); returns the unphysical flag.
+// Riemann solve of the face of axis D at cell (x, y, z), between cell - e_D
+// (its high state) and the cell (its low state); returns the unphysical flag.
 template <int D, int NF, typename T>
-__device__ __forceinline__ int solve_face(const T* __restrict__ Sg, int n, int a, int b, const Gas<T>& gas,
+__device__ __forceinline__ int solve_face(const T* __restrict__ Sg, int x, int y, int z, const Gas<T>& gas,
                                           const ExtOpts& o, T F[NF]) {
-  int x, y, z;
-  face_cell<D>(n, a, b, x, y, z);
   T L[NF], R[NF];
   load_state<D, NF>(Sg, x - (D == 0), y - (D == 1), z - (D == 2), 1, L);
   load_state<D, NF>(Sg, x, y, z, 0, R);
@@ -198,14 +208,15 @@ __global__ __launch_bounds__(256) void ext_flux1_kernel(const T* __restrict__ S,
                                                         Gas<T> gas, ExtOpts o) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * kF1) return;
-  const int d = i / kF1, f = i % kF1;
-  const int n = f % 17, a = (f / 17) % 18 - 1, b = f / (17 * 18) - 1;
+  const int d = i / kF1, f = i % kF1;  // f = face1_idx(d, x, y, z)
+  int x, y, z;
+  box_cell(d, f, 17, 0, 18, -1, x, y, z);
   for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
     const T* Sg = S + g * 6 * NF * int64_t(kS3);
     T F[NF];
-    if (d == 0) solve_face<0, NF>(Sg, n, a, b, gas, o, F);
-    else if (d == 1) solve_face<1, NF>(Sg, n, a, b, gas, o, F);
-    else solve_face<2, NF>(Sg, n, a, b, gas, o, F);
+    if (d == 0) solve_face<0, NF>(Sg, x, y, z, gas, o, F);
+    else if (d == 1) solve_face<1, NF>(Sg, x, y, z, gas, o, F);
+    else solve_face<2, NF>(Sg, x, y, z, gas, o, F);
     T* out = F1 + g * 3 * NF * int64_t(kF1) + d * NF * int64_t(kF1) + f;
 #pragma unroll
     for (int q = 0; q < NF; ++q) out[q * int64_t(kF1)] = F[q];
@@ -216,11 +227,7 @@ __global__ __launch_bounds__(256) void ext_flux1_kernel(const T* __restrict__ S,
 // face between (x, y, z) - e_E and (x, y, z)).
 template <int NF, typename T>
 __device__ __forceinline__ const T* f1_at(const T* __restrict__ F1g, int E, int x, int y, int z) {
-  int n, a, b;
-  if (E == 0) { n = x; a = y; b = z; }
-  else if (E == 1) { n = y; a = z; b = x; }
-  else { n = z; a = x; b = y; }
-  return F1g + E * NF * int64_t(kF1) + ((b + 1) * 18 + (a + 1)) * 17 + n;
+  return F1g + E * NF * int64_t(kF1) + face1_idx(E, x, y, z);
 }
 
 template <typename T, int NF>
@@ -231,11 +238,8 @@ __global__ __launch_bounds__(256) void ext_correct_kernel(T* __restrict__ S, con
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * kPer) return;
   const int d = i / kPer, f = i % kPer;
-  const int n = f % 18 - 1, a = (f / 18) % 16, b = f / (18 * 16);
   int x, y, z;
-  if (d == 0) { x = n; y = a; z = b; }
-  else if (d == 1) { y = n; z = a; x = b; }
-  else { z = n; x = a; y = b; }
+  box_cell(d, f, 18, -1, 16, 0, x, y, z);
   for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
     const T* F1g = F1 + g * 3 * NF * int64_t(kF1);
     T corr[NF];
@@ -267,16 +271,17 @@ __global__ __launch_bounds__(256) void ext_flux_kernel(const T* __restrict__ S, 
                                                        Gas<T> gas, ExtOpts o, int* __restrict__ n_bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < 3 * kF;
-  const int d = live ? i / kF : 0, f = live ? i % kF : 0;
-  const int n = f % 17, a = (f / 17) % 16, b = f / (17 * 16);
+  const int d = live ? i / kF : 0, f = live ? i % kF : 0;  // f = face_idx(d, x, y, z)
+  int x, y, z;
+  box_cell(d, f, 17, 0, 16, 0, x, y, z);
   int bad = 0;
   for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
     if (!live) continue;
     const T* Sg = S + g * 6 * NF * int64_t(kS3);
     T Fv[NF];
-    if (d == 0) bad += solve_face<0, NF>(Sg, n, a, b, gas, o, Fv);
-    else if (d == 1) bad += solve_face<1, NF>(Sg, n, a, b, gas, o, Fv);
-    else bad += solve_face<2, NF>(Sg, n, a, b, gas, o, Fv);
+    if (d == 0) bad += solve_face<0, NF>(Sg, x, y, z, gas, o, Fv);
+    else if (d == 1) bad += solve_face<1, NF>(Sg, x, y, z, gas, o, Fv);
+    else bad += solve_face<2, NF>(Sg, x, y, z, gas, o, Fv);
     T* out = F + g * 3 * NF * int64_t(kF) + d * NF * int64_t(kF) + f;
 #pragma unroll
     for (int q = 0; q < NF; ++q) out[q * int64_t(kF)] = Fv[q];
@@ -301,10 +306,9 @@ __global__ __launch_bounds__(256) void ext_update_kernel(const T* __restrict__ U
   int bad = 0;
   for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
     const T* Fg = F + g * 3 * NF * int64_t(kF);
-    // face index of the low face of this cell along each axis
-    const int fx = (z * 16 + y) * 17 + x;   // axis 0: n = x, a = y, b = z
-    const int fy = (x * 16 + z) * 17 + y;   // axis 1: n = y, a = z, b = x
-    const int fz = (y * 16 + x) * 17 + z;   // axis 2: n = z, a = x, b = y
+    // the low face of this cell along each axis; the high one is the next
+    // entry along that axis (strides 1, 16, 256)
+    const int fx = face_idx(0, x, y, z), fy = face_idx(1, x, y, z), fz = face_idx(2, x, y, z);
     T Un[NF];
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
@@ -312,8 +316,8 @@ __global__ __launch_bounds__(256) void ext_update_kernel(const T* __restrict__ U
       const T* Fy = Fg + (1 * NF + q) * int64_t(kF);
       const T* Fz = Fg + (2 * NF + q) * int64_t(kF);
       T acc = Fx[fx + 1] - Fx[fx];
-      acc = acc + (Fy[fy + 1] - Fy[fy]);
-      acc = acc + (Fz[fz + 1] - Fz[fz]);
+      acc = acc + (Fy[fy + 16] - Fy[fy]);
+      acc = acc + (Fz[fz + 256] - Fz[fz]);
       Un[q] = Upad[g * NF * P3 + q * P3 + cell_p(P, gh, x, y, z)] - gas.dtdx * acc;
     }
     if constexpr (NF == 6) {
@@ -342,7 +346,8 @@ __global__ __launch_bounds__(256) void ext_face_flux_kernel(const T* __restrict_
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // < 9 * 256
   const int p = i >> 8, ab = i & 255, d = p / 3, k = p % 3;
   const int a = ab & 15, b = ab >> 4;
-  const int f = (b * 16 + a) * 17 + 8 * k;
+  // the face at normal coordinate 8 k, transverse (a, b) in cyclic order
+  const int f = d == 0 ? face_idx(0, 8 * k, a, b) : d == 1 ? face_idx(1, b, 8 * k, a) : face_idx(2, a, b, 8 * k);
   for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
 #pragma unroll
     for (int q = 0; q < 5; ++q)
