@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhydro.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["capi.hip", "mhm_fwd.hip", "mhm_fwd_g2.hip", "mhm_batched.hip", "mhm_adj.hip", "aux_kernels.hip", "scheme_ext.hip",
+SOURCES = ["capi.hip", "mhm_fwd.hip", "mhm_fwd_g2.hip", "mhm_fwd_ext.hip", "mhm_batched.hip", "mhm_adj.hip", "aux_kernels.hip", "scheme_ext.hip",
            "fallback.hip", "amr.hip"]
 
 HIPCC_FLAGS = [

@@ -65,24 +65,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
 }
 
-// The other MHM + PLM scheme words (limiters, characteristic variables,
-// Roe / HLLE, wave speeds, first order: run-time ExtOpts) through the same
-// march; optional patch-boundary face fluxes as in mhm_padded_kernel.
-template <typename T, int kWaves, bool kFlux>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves))) void mhm_padded_ext_kernel(
-    const T* __restrict__ Upad, T* __restrict__ Uout, int gh, Gas<T> gas, const double* __restrict__ dt_dev, double dx,
-    ExtOpts o, int* __restrict__ n_bad, T* __restrict__ face_flux) {
-  __shared__ Smem<T> sm;
-  set_dt(gas, dt_dev, dx);
-  const int P = 16 + 2 * gh;
-  const int64_t P3 = int64_t(P) * P * P;
-  PaddedSource<T> src{Upad + int64_t(blockIdx.x) * 5 * P3, P, gh};
-  T* ff = kFlux ? face_flux + int64_t(blockIdx.x) * 9 * 5 * 256 : nullptr;
-  const ExtScheme sch{o};
-  const int bad = process_group<T, (kWaves >= 4)>(src, Uout + int64_t(blockIdx.x) * 5 * 4096, gas, o.first_order,
-                                                  o.ws, sm, nullptr, 0.0, threadIdx.x, ff, nullptr, sch);
-  if (n_bad != nullptr && bad != 0) atomicAdd(n_bad, bad);
-}
 
 template <typename T, bool kCfl, typename Off>
 void launch_level_shape(const T* level, T* level_out, const LevelGeom& geo, const Gas<T>& gas,
@@ -172,34 +154,6 @@ hipError_t launch_mhm_level(const T* level, T* level_out, const LevelGeom& geo, 
                                         stream);
 }
 
-template <typename T>
-hipError_t launch_mhm_fwd_ext(const T* U_pad, T* U_out, int64_t n_groups, int ghost, const Gas<T>& gas,
-                              const double* dt_dev, double dx, const ExtOpts& o, int* n_bad, hipStream_t stream,
-                              T* face_flux) {
-  if (n_groups == 0) return hipSuccess;
-  const int64_t chunk = int64_t(1) << 30;
-  const int P = 16 + 2 * ghost;
-  const int64_t P3 = int64_t(P) * P * P;
-  for (int64_t g0 = 0; g0 < n_groups; g0 += chunk) {
-    const int64_t n = n_groups - g0 < chunk ? n_groups - g0 : chunk;
-    if (face_flux != nullptr)
-      hipLaunchKernelGGL((mhm_padded_ext_kernel<T, MinWaves<T>::value, true>), dim3(unsigned(n)), dim3(kThreads), 0,
-                         stream, U_pad + g0 * 5 * P3, U_out + g0 * 5 * 4096, ghost, gas, dt_dev, dx, o, n_bad,
-                         face_flux + g0 * 9 * 5 * 256);
-    else
-      hipLaunchKernelGGL((mhm_padded_ext_kernel<T, MinWaves<T>::value, false>), dim3(unsigned(n)), dim3(kThreads), 0,
-                         stream, U_pad + g0 * 5 * P3, U_out + g0 * 5 * 4096, ghost, gas, dt_dev, dx, o, n_bad,
-                         (T*)nullptr);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-template hipError_t launch_mhm_fwd_ext<double>(const double*, double*, int64_t, int, const Gas<double>&, const double*,
-                                               double, const ExtOpts&, int*, hipStream_t, double*);
-template hipError_t launch_mhm_fwd_ext<float>(const float*, float*, int64_t, int, const Gas<float>&, const double*,
-                                              double, const ExtOpts&, int*, hipStream_t, float*);
 
 hipError_t launch_mhm_record(const double* U_pad, double* U_out, int64_t n_groups, int ghost, const Gas<double>& gas,
                              const double* dt_dev, double dx, int first_order, int ws, int* n_bad, unsigned* record,

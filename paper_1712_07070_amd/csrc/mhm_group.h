@@ -105,9 +105,22 @@ struct Smem {
 //                  the same half step with the slopes of ext_slopes and the
 //                  fluxes of riemann_any.
 struct DefaultScheme {};
-struct ExtScheme {
+// kChr (0 / 1) fixes the characteristic projection at compile time and kRoe
+// the solver family (1: Roe, 0: HLLC or HLLE); -1 leaves either to run
+// time.  Each fixed combination is its own inlined copy, which carries only
+// the registers of its own options.
+template <int kChr = -1, int kRoe = -1>
+struct ExtSchemeT {
   ExtOpts o;
+  __device__ __forceinline__ ExtOpts opts() const {
+    ExtOpts r = o;
+    if (kChr >= 0) r.chr = kChr;
+    if (kRoe == 1) r.solver = 1;
+    if (kRoe == 0) r.solver = o.solver == 2 ? 2 : 0;
+    return r;
+  }
 };
+using ExtScheme = ExtSchemeT<>;
 
 template <typename T>
 __device__ __forceinline__ void scheme_half_step(const DefaultScheme&, const T Wc[5], const T Wn[3][2][5],
@@ -118,22 +131,23 @@ __device__ __forceinline__ void scheme_half_step(const DefaultScheme&, const T W
 // The half step with full limited slopes s: face states Wc -+ s/2 (as the
 // oracle's face values), then hancock_states' conserved form, fluxes and
 // flux differences.
-template <typename T>
-__device__ __forceinline__ void scheme_half_step(const ExtScheme& sch, const T Wc[5], const T Wn[3][2][5],
+template <typename T, int kChr, int kRoe>
+__device__ __forceinline__ void scheme_half_step(const ExtSchemeT<kChr, kRoe>& sch, const T Wc[5], const T Wn[3][2][5],
                                                  const Gas<T>& g, bool, T Ut[3][2][5], unsigned*) {
+  const ExtOpts o = sch.opts();
   T sum[5];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     T sl[5];
-    if (sch.o.first_order) {
+    if (o.first_order) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) sl[q] = T(0);
     } else if (d == 0) {
-      ext_slopes<0>(Wn[0][0], Wc, Wn[0][1], g, sch.o, sl);
+      ext_slopes<0>(Wn[0][0], Wc, Wn[0][1], g, o, sl);
     } else if (d == 1) {
-      ext_slopes<1>(Wn[1][0], Wc, Wn[1][1], g, sch.o, sl);
+      ext_slopes<1>(Wn[1][0], Wc, Wn[1][1], g, o, sl);
     } else {
-      ext_slopes<2>(Wn[2][0], Wc, Wn[2][1], g, sch.o, sl);
+      ext_slopes<2>(Wn[2][0], Wc, Wn[2][1], g, o, sl);
     }
     T dF[5];
 #pragma unroll
@@ -176,10 +190,10 @@ __device__ __forceinline__ bool scheme_flux(const DefaultScheme&, const T L[5], 
                                             T F[5], unsigned* rec) {
   return hllc_flux<D>(L, R, g, ws, F, rec);
 }
-template <int D, typename T>
-__device__ __forceinline__ bool scheme_flux(const ExtScheme& sch, const T L[5], const T R[5], const Gas<T>& g, int,
-                                            T F[5], unsigned*) {
-  return riemann_any<D>(L, R, g, sch.o, F);
+template <int D, typename T, int kChr, int kRoe>
+__device__ __forceinline__ bool scheme_flux(const ExtSchemeT<kChr, kRoe>& sch, const T L[5], const T R[5],
+                                            const Gas<T>& g, int, T F[5], unsigned*) {
+  return riemann_any<D>(L, R, g, sch.opts(), F);
 }
 // Two faces (normal axes D0, D1) at once; the default scheme interleaves
 // their solves.
@@ -188,10 +202,12 @@ __device__ __forceinline__ int scheme_flux2(const DefaultScheme&, const T L0[5],
                                             const T R1[5], const Gas<T>& g, int ws, T F0[5], T F1[5], unsigned* rec) {
   return hllc_flux2<D0, D1>(L0, R0, L1, R1, g, ws, F0, F1, rec);
 }
-template <int D0, int D1, typename T>
-__device__ __forceinline__ int scheme_flux2(const ExtScheme& sch, const T L0[5], const T R0[5], const T L1[5],
-                                            const T R1[5], const Gas<T>& g, int, T F0[5], T F1[5], unsigned*) {
-  return int(riemann_any<D0>(L0, R0, g, sch.o, F0)) + int(riemann_any<D1>(L1, R1, g, sch.o, F1));
+template <int D0, int D1, typename T, int kChr, int kRoe>
+__device__ __forceinline__ int scheme_flux2(const ExtSchemeT<kChr, kRoe>& sch, const T L0[5], const T R0[5],
+                                            const T L1[5], const T R1[5], const Gas<T>& g, int, T F0[5], T F1[5],
+                                            unsigned*) {
+  const ExtOpts o = sch.opts();
+  return int(riemann_any<D0>(L0, R0, g, o, F0)) + int(riemann_any<D1>(L1, R1, g, o, F1));
 }
 
 // ---------------------------------------------------- one patch group ----
